@@ -1,0 +1,21 @@
+"""CPU FP64 oracle of the edge-FEM CSEM secondary-field solve.
+
+TEST INFRASTRUCTURE ONLY. Only the tests, the smoke check and the benchmark's
+CPU-baseline leg may import this package. The product path (the HIP library
+and its binding) never imports, links or calls anything here, and this package
+shares no code with it: both take their inputs from the seeded generator
+module ``paper_1808_00186_amd.synth``, which holds none of the method's
+arithmetic.
+
+Every function is a plain, slow, direct statement of what the paper defines,
+in complex128 / float64, citing the passage it follows:
+
+* ``fem``       -- edges and signs (Appendix B, eq. B.15), Dirichlet elimination
+                   (Section 2), element matrices (eqs. B.13, B.14), assembly,
+                   right-hand side (eq. 9), receiver interpolation (eq. 8).
+* ``primary``   -- whole-space dipole primary field (Appendix A, repaired).
+* ``solve``     -- direct and GMRES solves of the assembled system.
+* ``network``   -- FP64 reference of the learned initial-guess network
+                   (not in the paper; its parity is "unpinned" by the paper and
+                   pinned by central finite differences instead).
+"""

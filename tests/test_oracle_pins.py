@@ -1,0 +1,444 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix,
+independently of the oracle's own formulas (CPU only).
+
+Each test names the property it checks and the passage it comes from. The
+properties are chosen so that a plausible slip (a dropped term, a wrong sign
+or index, a transposed operand, a missing mu0) fails at least one of them.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from paper_1808_00186_amd import synth
+from oracle import fem, primary, solve
+from quadrature_ref import (barycentric_by_solve, duffy_rule, tet_points,
+                            tet_volumes)
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _mesh(n, seed, lo=-1000.0, hi=1000.0):
+    return synth.kuhn_mesh(n, lo, hi, seed)
+
+
+def _gradient_matrix(xyz, topo, interior=True):
+    """Discrete gradient G[e, j] = (delta_{j,hi} - delta_{j,lo}) / l_e: the
+    tangential component of grad(phi_j) on edge e for the P1 hat phi_j."""
+    en = topo.edge_nodes
+    ell = np.linalg.norm(xyz[en[:, 1]] - xyz[en[:, 0]], axis=1)
+    if interior:
+        nodes = np.flatnonzero(~topo.boundary_node)
+        edges = np.flatnonzero(~topo.boundary_edge)
+        row_of = topo.dof_of_edge
+        nrow = topo.n_dof
+    else:
+        nodes = np.arange(len(xyz))
+        edges = np.arange(len(en))
+        row_of = np.arange(len(en))
+        nrow = len(en)
+    col = -np.ones(len(xyz), dtype=np.int64)
+    col[nodes] = np.arange(len(nodes))
+    r, c, v = [], [], []
+    for e in edges:
+        for node, s in ((en[e, 1], 1.0), (en[e, 0], -1.0)):
+            if col[node] >= 0:
+                r.append(row_of[e]); c.append(col[node]); v.append(s / ell[e])
+    return sp.csr_matrix((v, (r, c)), shape=(nrow, len(nodes))), nodes
+
+
+# ---------------------------------------------------------------- counts (V10)
+
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 8])
+def test_counts_closed_forms(n):
+    """Kuhn meshes: edges 3n(n+1)^2 + 3n^2(n+1) + n^3, boundary edges 18 n^2,
+    DOF = interior edges (Section 2 Dirichlet condition, Table 1 reading)."""
+    xyz, tets = _mesh(n, 7)
+    topo = fem.topology(xyz, tets)
+    E = 3 * n * (n + 1) ** 2 + 3 * n * n * (n + 1) + n ** 3
+    assert len(topo.edge_nodes) == E
+    assert topo.boundary_edge.sum() == 18 * n * n
+    assert topo.n_dof == E - 18 * n * n
+    # Euler for a ball, V - E + F - T = 1, gives the boundary edge count
+    T, V = len(tets), len(xyz)
+    F = E + T - V + 1
+    Fb = 2 * F - 4 * T
+    assert 3 * Fb // 2 == topo.boundary_edge.sum()
+
+
+def test_cfg1_sizes():
+    m = synth.config1()
+    s = fem.assemble(m.xyz, m.tets, m.sigma)
+    assert s.topo.n_dof == 3032 and s.K.nnz == 43688
+
+
+def test_table1_dof_is_interior_edges():
+    """Table 1 (Section 5.3): for every mesh A-H, edges - DOF equals the
+    number of boundary edges that Euler's relation gives from the element,
+    node and edge counts, so the paper's DOF are the interior edges."""
+    rows = [l.split() for l in open(os.path.join(GOLDEN, "table1_meshes.txt"))
+            if l.strip() and not l.startswith("#")]
+    assert len(rows) == 8
+    for lab, _f, T, V, E, dof in rows:
+        T, V, E, dof = int(T), int(V), int(E), int(dof)
+        F = E + T - V + 1
+        Fb = 2 * F - 4 * T
+        assert E - dof == 3 * Fb // 2 == 36204, lab
+
+
+# ------------------------------------------------------- element matrices (V1, V2, V8)
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+def test_curl_curl_gradient_null_space(seed):
+    """K G = 0 (discrete de Rham): the gradient of every P1 hat lies in the
+    lowest-order Nedelec space and has zero curl (Appendix B basis)."""
+    n = 2 + seed % 3
+    xyz, tets = _mesh(n, seed)
+    sigma = np.random.default_rng(seed).uniform(0.01, 3.3, len(tets))
+    for full in (False, True):
+        s = fem.assemble(xyz, tets, sigma, full=full)
+        G, _ = _gradient_matrix(xyz, s.topo, interior=not full)
+        assert abs(s.K @ G).max() <= 1e-13 * abs(s.K).max()
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_whitney_mass_is_p1_stiffness(seed):
+    """G^T M_sigma G = S_sigma, the sigma-weighted P1 Laplacian, exactly (the
+    mass matrix of eq. B.14 restricted to gradients). S is built from the
+    inverse of the [1 x y z] vertex matrix, not from the oracle's geometry."""
+    n = 2 + seed
+    xyz, tets = _mesh(n, 10 + seed)
+    sigma = np.random.default_rng(seed).uniform(0.01, 3.3, len(tets))
+    s = fem.assemble(xyz, tets, sigma, full=True)
+    G, nodes = _gradient_matrix(xyz, s.topo, interior=False)
+    X = xyz[tets]
+    P = np.concatenate([np.ones((len(tets), 4, 1)), X], axis=2)
+    C = np.linalg.inv(P)                        # columns: coefficients of lambda_j
+    grads = np.transpose(C[:, 1:, :], (0, 2, 1))  # [T][4][3]
+    vol = tet_volumes(X)
+    Se = sigma[:, None, None] * vol[:, None, None] * np.einsum("tik,tjk->tij", grads, grads)
+    r = np.repeat(tets[:, :, None], 4, 2); c = np.repeat(tets[:, None, :], 4, 1)
+    S = sp.coo_matrix((Se.ravel(), (r.ravel(), c.ravel())), shape=(len(xyz),) * 2).tocsr()
+    lhs = (G.T @ s.Ms @ G).toarray()
+    assert np.abs(lhs - S.toarray()).max() <= 1e-12 * np.abs(S).max()
+
+
+def test_element_matrices_by_brute_force_quadrature():
+    """K^e, M^e from their definitions (eqs. B.13, B.14) by a 125-point
+    conical rule, lambda from a pointwise linear solve and curl N by central
+    differences of N: no closed form involved."""
+    xyz, tets = _mesh(2, 3)
+    topo = fem.topology(xyz, tets)
+    K, M = fem.element_matrices(xyz, tets, topo.elem_sign)
+    X = xyz[tets]
+    lam, w = duffy_rule(5)
+    vol = tet_volumes(X)
+    ell = np.linalg.norm(X[:, fem.LOCAL_EDGES[:, 1]] - X[:, fem.LOCAL_EDGES[:, 0]], axis=2)
+
+    def basis(pts):   # pts [T][P][3] -> [T][P][6][3]
+        L = barycentric_by_solve(X, pts)
+        hstep = 1e-3 * ell.min()
+        out = np.empty(pts.shape[:2] + (6, 3))
+        gl = np.empty(pts.shape[:2] + (4, 3))
+        for k in range(3):
+            d = np.zeros(3); d[k] = hstep
+            gl[..., k] = (barycentric_by_solve(X, pts + d) - barycentric_by_solve(X, pts - d)) / (2 * hstep)
+        for i, (a, b) in enumerate(fem.LOCAL_EDGES):
+            out[:, :, i] = (L[..., a, None] * gl[..., b, :] - L[..., b, None] * gl[..., a, :])
+        return out * (topo.elem_sign * ell)[:, None, :, None]
+
+    pts = tet_points(X, lam)
+    N = basis(pts)
+    Mq = np.einsum("tpik,tpjk,p,t->tij", N, N, w, vol)
+    hstep = 1e-2 * ell.min()
+    curl = np.zeros_like(N)
+    for k in range(3):
+        d = np.zeros(3); d[k] = hstep
+        dN = (basis(pts + d) - basis(pts - d)) / (2 * hstep)   # d N / d x_k
+        # curl_x = dNz/dy - dNy/dz etc.
+        if k == 0:
+            curl[..., 2] += dN[..., 1]; curl[..., 1] -= dN[..., 2]
+        elif k == 1:
+            curl[..., 0] += dN[..., 2]; curl[..., 2] -= dN[..., 0]
+        else:
+            curl[..., 1] += dN[..., 0]; curl[..., 0] -= dN[..., 1]
+    Kq = np.einsum("tpik,tpjk,p,t->tij", curl, curl, w, vol)
+    assert np.abs(Mq - M).max() <= 1e-10 * np.abs(M).max()
+    assert np.abs(Kq - K).max() <= 1e-8 * np.abs(K).max()
+
+
+def test_mass_matrix_spd_and_symmetry():
+    """M^e is symmetric positive definite; the assembled A = A^T (complex
+    symmetric, not Hermitian) and diag(A) != 0."""
+    m = synth.config1()
+    topo = fem.topology(m.xyz, m.tets)
+    K, M = fem.element_matrices(m.xyz, m.tets, topo.elem_sign)
+    assert np.all(np.linalg.eigvalsh(M) > 0)
+    s = fem.assemble(m.xyz, m.tets, m.sigma, topo)
+    A = fem.system_matrix(s, 2.0)
+    assert abs(A - A.T).max() <= 1e-15 * abs(A).max()
+    assert np.all(A.diagonal() != 0)
+
+
+# ------------------------------------------------------- polynomial reproduction (V3)
+
+def _box_integral_u2(a, b, lo, hi):
+    """int over [lo,hi]^3 of |a + b x x|^2, in closed form."""
+    B = np.array([[0, -b[2], b[1]], [b[2], 0, -b[0]], [-b[1], b[0], 0]])
+    m0, m1, m2 = hi - lo, (hi ** 2 - lo ** 2) / 2, (hi ** 3 - lo ** 3) / 3
+    mom1 = np.full(3, m1 * m0 * m0)
+    mom2 = np.full((3, 3), m1 * m1 * m0)
+    np.fill_diagonal(mom2, m2 * m0 * m0)
+    BtB = B.T @ B
+    return a @ a * m0 ** 3 + 2 * a @ B @ mom1 + np.sum(BtB * mom2)
+
+
+@pytest.mark.parametrize("seed", [4, 5])
+def test_polynomial_reproduction(seed):
+    """For u = a + b x x (in the lowest-order space) the edge interpolant
+    u_e = u(mid_e) . t_e reproduces u exactly: e^T K e = 4|b|^2 Vol,
+    e^T M e = int |u|^2, and interpolation (eq. 8) returns u at any point."""
+    rng = np.random.default_rng(seed)
+    a, b = rng.normal(size=3), rng.normal(size=3) * 1e-3
+    lo, hi = -1000.0, 1000.0
+    xyz, tets = _mesh(3, seed)
+    s = fem.assemble(xyz, tets, np.ones(len(tets)), full=True)
+    en = s.topo.edge_nodes
+    t = xyz[en[:, 1]] - xyz[en[:, 0]]
+    t /= np.linalg.norm(t, axis=1)[:, None]
+    mid = 0.5 * (xyz[en[:, 1]] + xyz[en[:, 0]])
+    e = np.einsum("ek,ek->e", a + np.cross(b, mid), t)
+    vol = (hi - lo) ** 3
+    assert np.isclose(e @ s.K @ e, 4 * (b @ b) * vol, rtol=1e-11)
+    assert np.isclose(e @ s.Ms @ e, _box_integral_u2(a, b, lo, hi), rtol=1e-11)
+    topo_all = fem.Topology(**{**s.topo.__dict__,
+                               "dof_of_edge": np.arange(len(en)),
+                               "n_dof": len(en)})
+    pts = rng.uniform(lo + 1, hi - 1, size=(25, 3))
+    got = fem.interpolate(xyz, tets, topo_all, e.astype(complex), pts)
+    assert np.abs(got - (a + np.cross(b, pts))).max() <= 1e-11 * np.abs(a).max()
+
+
+# ---------------------------------------------------------------- quadrature (V4)
+
+def test_four_point_rule_degree_two_exact():
+    """The 4-point rule integrates every barycentric monomial of degree <= 2
+    exactly: int lambda1^a lambda2^b lambda3^c lambda4^d = 6V a!b!c!d!/(a+b+c+d+3)!."""
+    for exps in [(0, 0, 0, 0), (1, 0, 0, 0), (0, 0, 1, 0), (2, 0, 0, 0), (1, 1, 0, 0),
+                 (0, 1, 0, 1), (0, 0, 0, 2)]:
+        q = np.mean(np.prod(fem.QUAD4 ** np.array(exps), axis=1))
+        exact = 6 * np.prod([math.factorial(e) for e in exps]) / math.factorial(sum(exps) + 3)
+        assert abs(q - exact) <= 1e-15
+    q3 = np.mean(fem.QUAD4[:, 0] ** 3)
+    assert abs(q3 - 6 * 6 / math.factorial(6)) > 1e-4   # degree 3 is not exact
+
+
+# ---------------------------------------------------------------- primary field (V5)
+
+def test_primary_static_limit():
+    """k -> 0 gives the DC current-dipole field (3 r (r.p) - p)/(4 pi sigma r^3)."""
+    rng = np.random.default_rng(0)
+    x = rng.uniform(-500, 500, (20, 3))
+    src, p, sig = (10.0, -20.0, 30.0), np.array([0.6, 0.0, 0.8]), 2.0
+    E = primary.dipole_field(x, src, p, 1e-12, sig)
+    d = x - np.array(src)
+    r = np.linalg.norm(d, axis=1)
+    rh = d / r[:, None]
+    ref = (3 * rh * (rh @ p)[:, None] - p) / (4 * np.pi * sig * r[:, None] ** 3)
+    assert np.abs(E - ref).max() <= 1e-9 * np.abs(ref).max()
+
+
+def test_primary_reciprocity_and_conjugate_form():
+    """E_i(p = e_j) = E_j(p = e_i), and the appendix's rows (grouping
+    restored) with k -> -k coincide with the e^{-i omega t} field."""
+    rng = np.random.default_rng(1)
+    x = rng.uniform(-800, 800, (15, 3))
+    f, sig, src = 0.7, 3.3, (0.0, 0.0, 50.0)
+    Es = [primary.dipole_field(x, src, np.eye(3)[j], f, sig) for j in range(3)]
+    for i in range(3):
+        for j in range(3):
+            assert np.allclose(Es[j][:, i], Es[i][:, j], rtol=1e-13, atol=0)
+        Ea = primary.dipole_field_appendix_rows(x, src, i, f, sig)
+        assert np.allclose(Ea, Es[i], rtol=1e-12, atol=0)
+
+
+def test_primary_satisfies_helmholtz_and_divergence_free():
+    """Away from the source: curl curl E_p - k^2 E_p = 0 and div E_p = 0
+    (Section 2, eqs. 1-3 with J_s = 0), checked by central differences."""
+    f, sig, src, p = 1.0, 1.0, np.zeros(3), np.array([1.0, 0.0, 0.0])
+    k = primary.wavenumber(f, sig)
+    x0 = np.array([[300.0, 200.0, -100.0], [-150.0, 400.0, 250.0]])
+    hs = 0.2
+
+    def E(x):
+        return primary.dipole_field(x, src, p, f, sig)
+
+    def d(fn, x, k_):
+        e = np.zeros(3); e[k_] = hs
+        return (fn(x + e) - fn(x - e)) / (2 * hs)
+
+    def curl(fn):
+        def c(x):
+            dx, dy, dz = d(fn, x, 0), d(fn, x, 1), d(fn, x, 2)
+            return np.stack([dy[:, 2] - dz[:, 1], dz[:, 0] - dx[:, 2], dx[:, 1] - dy[:, 0]], -1)
+        return c
+
+    cc = curl(curl(E))(x0)
+    res = cc - k * k * E(x0)
+    assert np.abs(res).max() <= 1e-3 * np.abs(k * k * E(x0)).max()
+    div = sum(d(E, x0, i)[:, i] for i in range(3))
+    assert np.abs(div).max() <= 1e-5 * np.abs(d(E, x0, 0)).max()
+
+
+def test_skin_depth_worked_values():
+    """delta ~ 503/sqrt(f sigma) and ~275/sqrt(f) in 3.3 S/m sea water
+    (Section 5.3, eq. 12 and the text after eq. 13)."""
+    rows = {l.split()[0]: (float(l.split()[1]), float(l.split()[2]))
+            for l in open(os.path.join(GOLDEN, "skin_depth.txt")) if l[0] != "#"}
+    v, tol = rows["coef_503"]
+    assert abs(primary.skin_depth(1.0, 1.0) - v) <= tol * v
+    v, tol = rows["coef_sea_3.3"]
+    assert abs(primary.skin_depth(0.37, 3.3) * np.sqrt(0.37) - v) <= tol * v
+    k = primary.wavenumber(1.3, 0.8)
+    assert np.isclose(k, (1 + 1j) / primary.skin_depth(1.3, 0.8), rtol=1e-14)
+
+
+# ------------------------------------------------------- whole solve (V6, V7, V8, V9)
+
+def _born_secondary(xyz, tets, mask, dsig, src, p, f, sigma_bg, probes):
+    """First-order Born field of the anomaly: sum of dipoles with current
+    moments dsig E_p dV over the anomalous elements (high-order rule)."""
+    lam, w = duffy_rule(4)
+    X = xyz[tets[mask]]
+    pts = tet_points(X, lam).reshape(-1, 3)
+    wt = (tet_volumes(X)[:, None] * w[None]).ravel()
+    J = dsig * primary.dipole_field(pts, src, p, f, sigma_bg) * wt[:, None]
+    out = np.zeros((len(probes), 3), dtype=complex)
+    for a in range(3):
+        e = np.eye(3)[a]
+        for i, pr in enumerate(probes):
+            out[i] += (primary.dipole_field(pr[None], pts, e, f, sigma_bg) * J[:, a:a + 1]).sum(0)
+    return out
+
+
+@pytest.mark.slow
+def test_secondary_field_matches_born_limit_and_converges():
+    """Whole chain (eqs. 6, 9, 8 and Appendix A) against an independent
+    reference: for a weak anomaly (dsigma/sigma = -1e-4) the exact secondary
+    field is the Born sum of the induced current dipoles. The FEM field must
+    approach it under refinement (pointwise error of lowest-order elements is
+    O(h); a wrong sign, a conjugated primary field or a missing mu0 give
+    errors of order 100 %)."""
+    sb, f, ds = 1.0, 4.0, -1e-4
+    src, p = (0.0, 0.0, 250.0), np.array([1.0, 0.0, 0.0])
+    box = ((-400, 400), (-400, 400), (-300, -100))
+    probes = np.array([[x, y, z] for x in (-300, 0, 300) for y in (-300, 0, 300)
+                       for z in (-550, 100)], dtype=float)
+    errs = []
+    for n in (8, 16, 24):
+        xyz, tets = synth.kuhn_mesh(n, -1000.0, 1000.0, 11)
+        mask = synth._in_box(synth.centroids(xyz, tets), box)
+        sig = np.where(mask, sb + ds, sb)
+        topo = fem.topology(xyz, tets)
+        s = fem.assemble(xyz, tets, sig, topo)
+        A = fem.system_matrix(s, f)
+        b = fem.rhs(xyz, tets, sig, sb, topo, src, p, f)
+        x, res, _ = solve.solve_system(A, b)
+        assert res <= 1e-11
+        Es = fem.interpolate(xyz, tets, topo, x, probes)
+        Eb = _born_secondary(xyz, tets, mask, ds, src, p, f, sb, probes)
+        errs.append(np.linalg.norm(Es - Eb) / np.linalg.norm(Eb))
+    assert errs[0] > errs[1] > errs[2]
+    assert errs[2] < 0.3, errs
+
+
+def _mms_error(n, seed=5):
+    f = 1.0 / (2 * np.pi * primary.MU0)     # omega mu0 = 1
+
+    def Ex(pt):
+        x, y, z = (np.pi * pt[..., i] for i in range(3))
+        return np.stack([np.sin(y) * np.sin(z), np.sin(x) * np.sin(z), np.sin(x) * np.sin(y)], -1)
+
+    def cEx(pt):
+        x, y, z = (np.pi * pt[..., i] for i in range(3))
+        return np.pi * np.stack([np.sin(x) * (np.cos(y) - np.cos(z)),
+                                 np.sin(y) * (np.cos(z) - np.cos(x)),
+                                 np.sin(z) * (np.cos(x) - np.cos(y))], -1)
+
+    lam, w = duffy_rule(5)
+    xyz, tets = synth.kuhn_mesh(n, 0.0, 1.0, seed)
+    topo = fem.topology(xyz, tets)
+    s = fem.assemble(xyz, tets, np.ones(len(tets)), topo)
+    A = fem.system_matrix(s, f)
+    vol, g, X = fem.geometry(xyz, tets)
+    ell = fem.edge_lengths(X)
+    pts = tet_points(X, lam)
+    N = fem.basis_at(g, topo.elem_sign, ell, np.broadcast_to(lam, (len(tets),) + lam.shape))
+    # curl curl E* = 2 pi^2 E* and div E* = 0, so f = (2 pi^2 - i) E* for sigma = 1
+    Re = np.einsum("tpik,tpk,p->ti", N, (2 * np.pi ** 2 - 1j) * Ex(pts), w) * vol[:, None]
+    dof = topo.dof_of_edge[topo.elem_edge]
+    b = np.zeros(topo.n_dof, dtype=complex)
+    np.add.at(b, dof[dof >= 0], Re[dof >= 0])
+    x, _, _ = solve.solve_system(A, b)
+    vals = np.where(dof >= 0, x[np.maximum(dof, 0)], 0)
+    Eh = np.einsum("tpik,ti->tpk", N, vals)
+    ea, eb = fem.LOCAL_EDGES[:, 0], fem.LOCAL_EDGES[:, 1]
+    curlN = 2 * (topo.elem_sign * ell)[:, :, None] * np.cross(g[:, ea], g[:, eb])
+    cEh = np.einsum("tik,ti->tk", curlN, vals)[:, None, :]
+    e0 = np.einsum("tp,p,t->", np.sum(np.abs(Eh - Ex(pts)) ** 2, -1), w, vol)
+    e1 = np.einsum("tp,p,t->", np.sum(np.abs(cEh - cEx(pts)) ** 2, -1), w, vol)
+    return math.sqrt(e0 + e1)
+
+
+def test_manufactured_solution_converges_first_order():
+    """E* = (sin pi y sin pi z, sin pi x sin pi z, sin pi x sin pi y) on [0,1]^3
+    has zero tangential trace; with f = curl curl E* - i omega mu0 sigma E*
+    the discrete solution converges as O(h) in the H(curl) norm."""
+    errs = [_mms_error(n) for n in (4, 8, 16)]
+    slopes = np.diff(np.log(errs)) / np.log(0.5)
+    assert np.all(slopes >= 0.9), slopes
+
+
+def test_direct_and_gmres_agree():
+    """Dense LU, sparse LU and the oracle's GMRES (1e-12) give one solution."""
+    m = synth.config1()
+    s = fem.assemble(m.xyz, m.tets, m.sigma)
+    src = m.sources[0]
+    A = fem.system_matrix(s, src.freq)
+    b = fem.rhs(m.xyz, m.tets, m.sigma, m.sigma_bg, s.topo, src.pos, src.dir, src.freq)
+    xd = np.linalg.solve(A.toarray(), b)
+    import scipy.sparse.linalg as spla
+    xs = spla.spsolve(A.tocsc(), b)
+    xg, it, res = solve.gmres(A, b, rtol=1e-12)
+    assert res <= 1e-12 and it > 0
+    for x in (xs, xg):
+        assert np.linalg.norm(x - xd) <= 1e-9 * np.linalg.norm(xd)
+
+
+def test_invariance_under_renumbering():
+    """Renumbering nodes, permuting the vertex order of every element and
+    reordering the elements changes only round-off in the receiver field."""
+    m = synth.config1()
+    ref = solve.forward(m)["E"]
+    rng = np.random.default_rng(3)
+    perm = rng.permutation(len(m.xyz))
+    inv = np.empty_like(perm); inv[perm] = np.arange(len(perm))
+    tets = perm[m.tets]
+    tets = np.take_along_axis(tets, np.argsort(rng.random(tets.shape), axis=1), axis=1)
+    order = rng.permutation(len(tets))
+    m2 = synth.Model("p", m.xyz[inv], tets[order].astype(np.int32), m.sigma[order],
+                     m.sigma_bg, m.sources, m.receivers, m.n, m.box)
+    got = solve.forward(m2)["E"]
+    assert fem.receiver_error(got, ref) <= 1e-11
+
+
+def test_locate_tie_break_and_outside():
+    """A point on a face shared by two elements goes to the lower element id;
+    a point outside the mesh is reported as outside."""
+    xyz, tets = synth.kuhn_mesh(1, 0.0, 1.0, None)
+    # the main diagonal is shared by all six tetrahedra
+    elem, lam = fem.locate(xyz, tets, np.array([[0.3, 0.3, 0.3], [2.0, 0.5, 0.5]]))
+    assert elem[0] == 0 and elem[1] == -1
+    assert abs(lam[0].sum() - 1) < 1e-14
