@@ -1,0 +1,221 @@
+/*
+ * petgem.h -- C ABI of the MI355X (gfx950) edge-FEM CSEM secondary-field solver.
+ *
+ * The library solves, on one GPU, the secondary-field equation of marine
+ * controlled-source electromagnetics (Section 2, eq. 6, with the e^{-i w t}
+ * sign)
+ *
+ *     curl curl E_s - i w mu0 sigma E_s = i w mu0 (sigma - sigma_bg) E_p
+ *
+ * on unstructured tetrahedra with lowest-order Nedelec edge elements
+ * (Section 3, eqs. 7-9; Appendix B), E_s = 0 tangentially on the outer
+ * boundary (Dirichlet, Section 2), E_p the analytic whole-space dipole field
+ * (Appendix A), and returns the total field E_p + E_s at receivers (eq. 8).
+ *
+ * Conventions
+ *   - SI units; time dependence e^{-i w t}; mu0 = 4 pi 1e-7 H/m; w = 2 pi f.
+ *   - Complex numbers are interleaved (re, im) pairs of double ("complex128")
+ *     or float ("complex64").
+ *   - Host pointers are borrowed for the duration of the call only.
+ *     Device pointers ("_dev") are caller-owned device memory of the current
+ *     HIP device; the library never frees them.
+ *   - Handles own their device memory and are released by petgem_free_*.
+ *   - `stream` is a hipStream_t (NULL = the legacy default stream). Every
+ *     device operation is ordered on it; calls that return host data
+ *     synchronise it.
+ *   - Every function returning int returns PETGEM_OK (0) or a negative
+ *     error code; petgem_last_error() gives a thread-local message. No C++
+ *     exception crosses the ABI.
+ *   - Unknowns ("DOFs") are the interior edges, ordered by the library; each
+ *     DOF is the tangential component of E_s along its edge, directed from
+ *     the lower to the higher global node index (Appendix B, eq. B.15).
+ */
+#ifndef PETGEM_H
+#define PETGEM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+#pragma GCC visibility push(default)
+
+/* ---- status codes ------------------------------------------------------ */
+#define PETGEM_OK                   0
+#define PETGEM_INVALID_ARG         -1  /* null pointer, bad size, bad option   */
+#define PETGEM_DEGENERATE_ELEMENT  -2  /* |det J| <= 1e-14 h^3 for an element   */
+#define PETGEM_MESH_TOPOLOGY       -3  /* a face shared by more than two tets  */
+#define PETGEM_RECEIVER_OUTSIDE    -4  /* a receiver lies in no element        */
+#define PETGEM_SOURCE_SINGULAR     -5  /* source within 1e-9 h of a quadrature
+                                          point of an element with dsigma != 0 */
+#define PETGEM_NOT_CONVERGED       -6  /* max_iter reached; the best iterate is
+                                          still returned, stats are filled     */
+#define PETGEM_NONFINITE           -7  /* NaN/Inf in the right-hand side or in
+                                          the Krylov recurrence                */
+#define PETGEM_HIP_ERROR           -8  /* a HIP runtime call failed            */
+#define PETGEM_OUT_OF_MEMORY       -9
+
+/* ---- solver options ------------------------------------------------------ */
+#define PETGEM_GMRES   0  /* right-Jacobi GMRES(restart), one source at a time */
+#define PETGEM_COCG    1  /* multi-source conjugate-orthogonal CG with Jacobi,
+                             one sparse matrix pass per iteration for all
+                             sources and frequencies                          */
+#define PETGEM_FP64    0  /* every step in double precision                   */
+#define PETGEM_MIXED   1  /* complex64 Krylov solves inside a double-precision
+                             iterative-refinement loop                         */
+
+typedef struct petgem_system   petgem_system;    /* mesh, matrices, workspaces */
+typedef struct petgem_solution petgem_solution;  /* E_s DOFs of n_src sources  */
+
+typedef struct {
+    int32_t       n_nodes;
+    int32_t       n_tets;
+    const double*  xyz;     /* host [n_nodes][3], metres                       */
+    const int32_t* tets;    /* host [n_tets][4], 0-based node indices           */
+} petgem_mesh;
+
+/* A point electric dipole (Appendix A): moment I*dS along the unit vector
+ * dir at pos, frequency freq_hz. */
+typedef struct {
+    double freq_hz;
+    double pos[3];
+    double dir[3];
+    double moment;          /* I * dS, A*m                                     */
+} petgem_source;
+
+typedef struct {
+    int32_t method;         /* PETGEM_GMRES or PETGEM_COCG                      */
+    int32_t precision;      /* PETGEM_FP64 or PETGEM_MIXED                      */
+    int32_t restart;        /* GMRES restart length, 1..64 (default 30)         */
+    int32_t max_iter;       /* total Krylov iterations per source               */
+    double  rtol;           /* stop when |b - A x|_2 <= rtol |b|_2 (true
+                               residual, double precision)                      */
+    double  inner_rtol;     /* MIXED: relative tolerance of each inner solve    */
+    int32_t use_graph;      /* replay captured HIP graphs for the Krylov loop   */
+    int32_t profile;        /* time the sparse-matrix kernels with HIP events   */
+} petgem_opts;
+
+typedef struct {
+    int32_t iters;          /* Krylov iterations (inner ones for MIXED)         */
+    int32_t ir_steps;       /* refinement steps (MIXED), restarts (GMRES)       */
+    int32_t used_fallback;  /* 1 if the initial guess was rejected for zero     */
+    int32_t status;         /* PETGEM_OK or PETGEM_NOT_CONVERGED/NONFINITE      */
+    double  rel_residual;   /* final true |b - A x| / |b|                       */
+    double  x0_rel_residual;/* |b - A x0| / |b| of the supplied guess (or 1)    */
+    double  t_rhs_ms;
+    double  t_solve_ms;
+    double  spmv_ms;        /* profile: summed duration of sparse-matrix kernels */
+    int32_t spmv_launches;  /* profile: number of such launches                  */
+    int32_t pad;
+} petgem_stats;
+
+/* Fill *opts with the defaults: GMRES, FP64, restart 30, max_iter 20000,
+ * rtol 1e-8, inner_rtol 1e-4, use_graph 1, profile 0. */
+void petgem_default_opts(petgem_opts* opts);
+
+/* ---- assembly (Section 3, eq. 9; Section 4; Appendix B) -----------------
+ * Builds the mesh topology on the host (unique edges with the global
+ * orientation of eq. B.15, boundary faces and edges, interior DOF numbering,
+ * the CSR pattern and the deterministic nnz -> element-entry gather lists),
+ * uploads it, and assembles on the GPU the real matrices
+ *     K   = sum_e K^e              (eq. B.13, curl-curl)
+ *     M_s = sum_e sigma_e M^e      (eq. B.14, mass weighted by sigma)
+ * so that A(f) = K - i w mu0 M_s for any frequency.
+ *   sigma     host [n_tets] total conductivity, S/m, > 0
+ *   sigma_bg  conductivity of the primary field's whole space, > 0
+ * Errors: INVALID_ARG, DEGENERATE_ELEMENT, MESH_TOPOLOGY, HIP_ERROR,
+ * OUT_OF_MEMORY. On error *out is NULL. */
+int petgem_assemble(const petgem_mesh* mesh, const double* sigma, double sigma_bg,
+                    void* stream, petgem_system** out);
+
+/* Re-assembles K and M_s on the GPU for new conductivities of the same mesh.
+ * sigma_dev: device [n_tets] double. No host work, no allocation. */
+int petgem_reassemble(petgem_system* sys, const double* sigma_dev, double sigma_bg,
+                      void* stream);
+
+/* ---- right-hand side (Section 3, eq. 9; Appendix A) ----------------------
+ * b_i = i w mu0 sum_e (sigma_e - sigma_bg) sum_q (V_e/4) N_i(x_q) . E_p(x_q)
+ * with the 4-point degree-2 rule, for each source, written to
+ * b_dev: device complex128 [n_src][n_dof]. */
+int petgem_rhs(petgem_system* sys, const petgem_source* src, int32_t n_src,
+               void* b_dev, void* stream);
+
+/* ---- solve ----------------------------------------------------------------
+ * Solves A(f_s) x_s = b_s for every source s (each at its own frequency) to
+ * the true relative residual opts->rtol.
+ *   x0_dev  optional device complex128 [n_src][n_dof] initial guess (NULL =
+ *           zero). A guess that is non-finite or has |b - A x0| >= |b| is
+ *           replaced by zero (stats->used_fallback = 1).
+ *   *inout  NULL to allocate a new solution, or a solution from an earlier
+ *           call on the same system with the same n_src, which is reused.
+ *   stats   optional host [n_src].
+ * Returns PETGEM_OK, or NOT_CONVERGED / NONFINITE (the solution then holds
+ * the last iterate), or an error. */
+int petgem_solve(petgem_system* sys, const petgem_source* src, int32_t n_src,
+                 const petgem_opts* opts, const void* x0_dev, void* stream,
+                 petgem_solution** inout, petgem_stats* stats);
+
+/* Uneven batch: solves one source on each of n_sys independent systems
+ * (different meshes) with the multi-system COCG in mixed precision; the
+ * Krylov iterations of all systems run in the same kernel launches, captured
+ * once in a HIP graph and replayed until every system has converged.
+ *   sols[k] as for petgem_solve (n_src = 1), stats host [n_sys]. */
+int petgem_solve_many(petgem_system* const* systems, const petgem_source* src,
+                      int32_t n_sys, const petgem_opts* opts, void* stream,
+                      petgem_solution** sols, petgem_stats* stats);
+
+/* ---- receivers (Section 3, eq. 8; Section 2, eq. 4) ----------------------
+ * E(x_r) = E_p(x_r) + sum_{i=1..6} N_i(x_r) e_i in the element containing
+ * x_r (the lowest element id on faces; all barycentric coordinates
+ * >= -1e-12), boundary DOFs being zero.
+ *   rx      host [n_rx][3]; located on the host at the first call and cached
+ *           while the same coordinates are passed again.
+ *   E_dev   device complex128 [n_src][n_rx][3] total field.
+ *   Es_dev  optional device complex128 [n_src][n_rx][3] secondary field.
+ * Errors: RECEIVER_OUTSIDE, INVALID_ARG, HIP_ERROR. */
+int petgem_receivers(const petgem_solution* sol, const double* rx, int32_t n_rx,
+                     void* E_dev, void* Es_dev, void* stream);
+
+/* ---- accessors --------------------------------------------------------- */
+int32_t petgem_num_dofs(const petgem_system* sys);
+int64_t petgem_nnz(const petgem_system* sys);
+int32_t petgem_solution_nsrc(const petgem_solution* sol);
+/* Device pointer to the solution DOFs, complex128 [n_src][n_dof] (borrowed). */
+const void* petgem_solution_x(const petgem_solution* sol);
+/* Copies the solution DOFs into caller device memory x_dev, complex128
+ * [n_src][n_dof], ordered on `stream`. */
+int petgem_solution_copy(const petgem_solution* sol, void* x_dev, void* stream);
+/* Host copies: the global node pair (lo, hi) of every DOF, int32 [n_dof][2];
+ * the CSR arrays of K and M_s (row_ptr [n_dof+1], col [nnz], K [nnz],
+ * Ms [nnz]). Any output pointer may be NULL. Synchronises the stream. */
+int petgem_get_dof_edges(const petgem_system* sys, int32_t* edges);
+int petgem_get_csr(const petgem_system* sys, int32_t* row_ptr, int32_t* col,
+                   double* K, double* Ms, void* stream);
+/* y = A(freq) x for device complex128 vectors of length n_dof, with the
+ * kernel the double-precision solver uses. */
+int petgem_spmv(petgem_system* sys, double freq, const void* x_dev, void* y_dev,
+                void* stream);
+/* Host-only preprocessing (no GPU call): the interior-edge numbering and the
+ * CSR pattern petgem_assemble would build for this mesh. Call once with the
+ * array outputs NULL to get *n_dof and *nnz, then again with
+ * dof_edges int32 [n_dof][2] (global node pair lo < hi of each DOF),
+ * row_ptr int32 [n_dof+1] and col int32 [nnz]. Errors as petgem_assemble. */
+int petgem_mesh_pattern(const petgem_mesh* mesh, int32_t* n_dof, int64_t* nnz,
+                        int32_t* dof_edges, int32_t* row_ptr, int32_t* col);
+/* Host-only point location (no GPU call): for each point the lowest element
+ * id whose barycentric coordinates are all >= -tol, or -1 when the point lies
+ * in no element. pts host [n_pts][3], elem host [n_pts]. */
+int petgem_locate(const petgem_mesh* mesh, const double* pts, int32_t n_pts, double tol,
+                  int32_t* elem);
+/* Seconds spent in the host preprocessing of the last petgem_assemble. */
+double petgem_setup_seconds(const petgem_system* sys);
+
+void petgem_free_system(petgem_system* sys);
+void petgem_free_solution(petgem_solution* sol);
+const char* petgem_last_error(void);
+
+#pragma GCC visibility pop
+#ifdef __cplusplus
+}
+#endif
+#endif /* PETGEM_H */

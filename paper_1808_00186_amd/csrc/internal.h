@@ -1,0 +1,185 @@
+// Internal declarations of the HIP library: the system and solution handles,
+// device-side helpers and the kernel launchers shared by the .hip units.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/petgem.h"
+#include "mesh.h"
+
+namespace petgem {
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kMu0 = 4.0e-7 * kPi;
+constexpr int kMaxRestart = 64;
+
+void set_error(const std::string& msg);
+
+// ---------------------------------------------------------------- errors
+#define PG_HIP(call)                                                          \
+    do {                                                                      \
+        hipError_t e_ = (call);                                               \
+        if (e_ != hipSuccess) {                                               \
+            ::petgem::set_error(std::string(#call) + ": " + hipGetErrorString(e_)); \
+            return e_ == hipErrorOutOfMemory ? PETGEM_OUT_OF_MEMORY : PETGEM_HIP_ERROR; \
+        }                                                                     \
+    } while (0)
+
+#define PG_TRY(call)                      \
+    do {                                  \
+        int rc_ = (call);                 \
+        if (rc_ != PETGEM_OK) return rc_; \
+    } while (0)
+
+template <class T>
+inline int dalloc(T** p, size_t count) {
+    *p = nullptr;
+    if (count == 0) return PETGEM_OK;
+    hipError_t e = hipMalloc(reinterpret_cast<void**>(p), count * sizeof(T));
+    if (e != hipSuccess) {
+        set_error(std::string("hipMalloc of ") + std::to_string(count * sizeof(T)) + " bytes: " +
+                  hipGetErrorString(e));
+        return e == hipErrorOutOfMemory ? PETGEM_OUT_OF_MEMORY : PETGEM_HIP_ERROR;
+    }
+    return PETGEM_OK;
+}
+template <class T>
+inline void dfree(T*& p) {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+}
+
+// ------------------------------------------------------- GMRES control block
+// Small device-resident state of one GMRES cycle: the Hessenberg column in
+// progress, Givens rotations, the least-squares right-hand side g and flags
+// that let every later kernel of the cycle exit early once it has converged.
+struct GmresCtl {
+    double2 H[(kMaxRestart + 1) * kMaxRestart];  // column-major, ld = kMaxRestart+1
+    double2 cs[kMaxRestart], sn[kMaxRestart];
+    double2 g[kMaxRestart + 1];
+    double2 h[kMaxRestart + 1];                   // coefficients of the current pass
+    double2 y[kMaxRestart];
+    double nrm2;        // |w|^2 of the current pass
+    double scale;       // multiplier applied by the update kernel
+    double tol_abs;     // rtol * |b|
+    double rnorm;       // true residual norm at the start of the cycle
+    int done;           // cycle finished (converged estimate or breakdown)
+    int reorth;         // second Gram-Schmidt pass requested
+    int mdone;          // Arnoldi steps completed in this cycle
+    int nonfinite;
+};
+
+struct GmresWork {
+    int n = 0, m = 0, nb_dot = 0;
+    double2* V = nullptr;        // (m+1) x n basis
+    double2* u = nullptr;        // scaled iterate D x
+    double2* b = nullptr;        // right-hand side of the current source
+    double* partial = nullptr;   // [(m+2)][nb_dot] complex partial sums
+    GmresCtl* ctl = nullptr;
+    GmresCtl* ctl_host = nullptr;  // pinned mirror for the per-cycle readback
+    hipGraphExec_t graph = nullptr;  // one captured cycle
+    hipStream_t graph_stream = nullptr;
+    void release();
+};
+
+// ------------------------------------------------------- multi-RHS workspace
+struct BlockWork;   // defined in block.hip
+void release_block_work(BlockWork*& w);
+
+struct ReceiverCache {
+    std::vector<double> rx;     // host copy of the located coordinates
+    int32_t n_rx = 0;
+    int32_t* tet = nullptr;     // device [n_rx]
+    int32_t* dof = nullptr;     // device [n_rx][6]
+    double* xyz = nullptr;      // device [n_rx][3]
+    void release() { dfree(tet); dfree(dof); dfree(xyz); n_rx = 0; rx.clear(); }
+};
+
+}  // namespace petgem
+
+struct petgem_system {
+    int device = 0;
+    int32_t n_nodes = 0, n_tets = 0, n_dof = 0, n_edges = 0;
+    int64_t nnz = 0;
+    double h_mean = 0.0;
+    double sigma_bg = 1.0;
+    double setup_seconds = 0.0;
+    // host copies kept for receivers and accessors
+    std::vector<double> xyz_h;
+    std::vector<int32_t> tets_h;
+    std::vector<int32_t> elem_dof_h;      // [T][6] DOF or -1
+    std::vector<int32_t> dof_nodes_h;     // [n_dof][2]
+    std::vector<int32_t> row_ptr_h;       // kept for host-side tools
+    // device topology
+    double* xyz = nullptr;                // [N][3]
+    int32_t* tets = nullptr;              // [T][4]
+    double* sigma = nullptr;              // [T]
+    int32_t* row_ptr = nullptr;           // [n+1]
+    int32_t* col = nullptr;               // [nnz]
+    int32_t* diag_pos = nullptr;          // [n]
+    int32_t* cptr = nullptr;              // [nnz+1]
+    int32_t* cidx = nullptr;              // contributions
+    int32_t* iptr = nullptr;              // [n+1]
+    int32_t* islot = nullptr;             // incidence slots
+    // assembled real matrices (frequency independent)
+    double* Kst = nullptr;                // [21][T] staging
+    double* Mst = nullptr;                // [21][T] staging (sigma-weighted)
+    double* K = nullptr;                  // [nnz]
+    double* Ms = nullptr;                 // [nnz]
+    double* Kd = nullptr;                 // [n]
+    double* Msd = nullptr;                // [n]
+    // single-precision copies for the mixed-precision path
+    float* K32 = nullptr;
+    float* Ms32 = nullptr;
+    bool have32 = false;
+    // frequency-specific operator of the FP64 GMRES: Ahat = A D^{-1}
+    double cached_freq = -1.0;
+    double2* Ahat = nullptr;              // [nnz]
+    double2* dvec = nullptr;              // [n] D = diag(A)
+    double2* dinv = nullptr;              // [n]
+    // right-hand-side staging and error flag
+    double2* Rst = nullptr;               // [6][T]
+    int* dflag = nullptr;                 // device error flags
+    double2* tmp = nullptr;               // [n] scratch of petgem_spmv
+    int spmv_group = 8;                   // lanes per CSR row (autotuned)
+    petgem::GmresWork gw;
+    petgem::BlockWork* bw = nullptr;
+    petgem::ReceiverCache rxc;
+};
+
+struct petgem_solution {
+    petgem_system* sys = nullptr;
+    int32_t n_src = 0;
+    double2* x = nullptr;                 // [n_src][n_dof]
+    std::vector<petgem_source> src;
+    double sigma_bg = 1.0;
+};
+
+namespace petgem {
+
+// Launchers implemented in the .hip units; all ordered on `s`.
+int launch_assembly(petgem_system* sys, hipStream_t s);
+int launch_freq_prep(petgem_system* sys, double freq, hipStream_t s);
+int launch_rhs(petgem_system* sys, const petgem_source& src, double2* b, int b_stride,
+               hipStream_t s);
+int launch_spmv_ahat(petgem_system* sys, const double2* x, double2* y, hipStream_t s);
+int launch_spmv_unscaled(petgem_system* sys, const double2* x, double2* y, hipStream_t s);
+int launch_receivers(const petgem_solution* sol, int32_t n_rx, double2* E, double2* Es,
+                     hipStream_t s);
+int gmres_solve(petgem_system* sys, const petgem_source& src, const petgem_opts& o,
+                const double2* x0, double2* x_out, hipStream_t s, petgem_stats* st);
+int block_solve(petgem_system* sys, const petgem_source* src, int32_t n_src,
+                const petgem_opts& o, const double2* x0, double2* x_out, hipStream_t s,
+                petgem_stats* st);
+int batch_solve(petgem_system* const* systems, const petgem_source* src, int32_t n_sys,
+                const petgem_opts& o, petgem_solution** sols, hipStream_t s,
+                petgem_stats* st);
+int ensure_fp32(petgem_system* sys, hipStream_t s);
+
+// Grid helpers
+inline int ceil_div(int64_t a, int64_t b) { return int((a + b - 1) / b); }
+
+}  // namespace petgem

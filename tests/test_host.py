@@ -1,0 +1,104 @@
+"""CPU tests of the library's host side: the C ABI loads and exports every
+declared entry point, and the host preprocessing (edge numbering, boundary
+elimination, CSR pattern, point location) matches the oracle's own,
+independently computed topology exactly. No GPU call is made here."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1808_00186_amd import petgem, synth
+from oracle import fem
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "petgem.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(petgem_[a-z_0-9]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = petgem.lib()
+    names = _declared()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) >= set(petgem._SIGS), set(petgem._SIGS) - set(names)
+
+
+def _oracle_pattern(xyz, tets):
+    s = fem.assemble(xyz, tets, np.ones(len(tets)))
+    return s.topo, s.K.tocsr()
+
+
+@pytest.mark.parametrize("n,seed", [(1, 0), (2, 1), (3, 2), (5, 3), (8, 1)])
+def test_pattern_matches_oracle(n, seed):
+    xyz, tets = synth.kuhn_mesh(n, -1000.0, 1000.0, seed)
+    de, rp, col = petgem.mesh_pattern(xyz, tets)
+    topo, K = _oracle_pattern(xyz, tets)
+    assert len(de) == topo.n_dof
+    assert np.all(de[:, 0] < de[:, 1])
+    # map library DOFs to oracle DOFs through the global node pairs
+    N = len(xyz)
+    okey = topo.edge_nodes[:, 0] * N + topo.edge_nodes[:, 1]
+    lkey = de[:, 0].astype(np.int64) * N + de[:, 1]
+    eidx = np.searchsorted(okey, lkey)
+    assert np.all(okey[eidx] == lkey)
+    odof = topo.dof_of_edge[eidx]
+    assert np.all(odof >= 0) and len(np.unique(odof)) == topo.n_dof
+    rows = np.repeat(np.arange(len(de)), np.diff(rp))
+    assert np.all(np.diff(col)[np.diff(rows) == 0] > 0)       # sorted, unique per row
+    lib_pairs = set(zip(odof[rows].tolist(), odof[col].tolist()))
+    Kc = K.tocoo()
+    assert lib_pairs == set(zip(Kc.row.tolist(), Kc.col.tolist()))
+
+
+def test_config_sizes_exact():
+    for cfg, (ndof, nnz) in ((synth.config1(), (3032, 43688)),):
+        de, rp, col = petgem.mesh_pattern(cfg.xyz, cfg.tets)
+        assert (len(de), len(col)) == (ndof, nnz)
+
+
+@pytest.mark.slow
+def test_cfg2_sizes_exact():
+    m = synth.config2()
+    de, rp, col = petgem.mesh_pattern(m.xyz, m.tets)
+    assert (len(de), len(col)) == (433720, 6950152)
+
+
+def test_locate_matches_oracle():
+    m = synth.config1()
+    rng = np.random.default_rng(0)
+    pts = np.concatenate([m.receivers, rng.uniform(-999, 999, (30, 3))])
+    got = petgem.locate(m.xyz, m.tets, pts)
+    ref, _ = fem.locate(m.xyz, m.tets, pts)
+    assert np.array_equal(got, ref)
+
+
+def test_locate_tie_break_and_outside():
+    xyz, tets = synth.kuhn_mesh(1, 0.0, 1.0, None)
+    got = petgem.locate(xyz, tets, np.array([[0.3, 0.3, 0.3], [2.0, 0.5, 0.5], [0.0, 0.0, 0.0]]))
+    ref, _ = fem.locate(xyz, tets, np.array([[0.3, 0.3, 0.3], [2.0, 0.5, 0.5], [0.0, 0.0, 0.0]]))
+    assert got.tolist() == ref.tolist() == [0, -1, 0]
+
+
+def test_error_paths():
+    xyz, tets = synth.kuhn_mesh(2, 0.0, 1.0, 3)
+    bad = tets.copy()
+    bad[5, 3] = len(xyz) + 10
+    with pytest.raises(petgem.PetgemError) as e:
+        petgem.mesh_pattern(xyz, bad)
+    assert e.value.code == petgem.INVALID_ARG
+    flat = xyz.copy()
+    flat[tets[0]] = flat[tets[0, 0]] + np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [1, 1, 0]]) * 0.1
+    with pytest.raises(petgem.PetgemError) as e:
+        petgem.mesh_pattern(flat, tets)
+    assert e.value.code == petgem.DEGENERATE_ELEMENT
+    # a third element on an existing face
+    extra = np.concatenate([tets, tets[:1]])
+    with pytest.raises(petgem.PetgemError) as e:
+        petgem.mesh_pattern(xyz, extra)
+    assert e.value.code == petgem.MESH_TOPOLOGY
