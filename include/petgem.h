@@ -207,6 +207,10 @@ int petgem_mesh_pattern(const petgem_mesh* mesh, int32_t* n_dof, int64_t* nnz,
  * in no element. pts host [n_pts][3], elem host [n_pts]. */
 int petgem_locate(const petgem_mesh* mesh, const double* pts, int32_t n_pts, double tol,
                   int32_t* elem);
+/* Autotuner choices of a system: lanes per row of the double-precision CSR
+ * SpMV (4, 8 or 16; 0 before the first solve) and the measured per-launch
+ * times of the three variants in ms (host float [3], may be NULL). */
+int petgem_tuning(const petgem_system* sys, int32_t* spmv_group, float* spmv_ms);
 /* Seconds spent in the host preprocessing of the last petgem_assemble. */
 double petgem_setup_seconds(const petgem_system* sys);
 

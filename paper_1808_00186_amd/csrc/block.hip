@@ -1,11 +1,614 @@
-// Multi-source COCG and the uneven multi-system batch (mixed precision).
+// Multi-column Jacobi-preconditioned COCG in complex64 inside a complex128
+// iterative-refinement loop, for many sources and frequencies on one mesh
+// (petgem_solve with PETGEM_COCG) and for an uneven batch of meshes
+// (petgem_solve_many). Not in the paper, which solves one source at a time
+// with PETSc Krylov solvers (Sections 5.1-5.3); the discrete system is the
+// same, A_c = K - i w_c mu0 M_sigma for each column c.
+//
+// Operator. Every column c of a block vector X[n][C] (row-major, so the
+// C values gathered for one column index are contiguous) may have its own
+// frequency: the SpMM reads the real K and M_sigma once per iteration for all
+// columns and forms  y_c = K x_c - i (w_c mu0) M_sigma x_c.  Rows are cut into
+// tiles of kTR rows; a tile belongs to one "segment" (one mesh of an uneven
+// batch, the concatenated block-diagonal system of several meshes), and each
+// (segment, column) pair carries its own Krylov scalars.
+//
+// COCG (complex symmetric A = A^T, Jacobi D = diag A):
+//   r = b, z = D^-1 r, p = z, rho = r^T z
+//   repeat: q = A p; alpha = rho / p^T q; x += alpha p; r -= alpha q;
+//           z = D^-1 r; rho' = r^T z; beta = rho'/rho; p = z + beta p
+// The dots p^T q, r^T z and |r|^2 are accumulated in double precision from
+// complex64 data, per tile, and reduced per (segment, column) in a fixed order
+// (bitwise reproducible). Refinement: r64 = b - A x64 in double precision,
+// the inner solve runs on r64/|r64| in complex64 to inner_rtol, x64 += |r64| d.
+#include <algorithm>
+#include <chrono>
+#include <map>
+#include <tuple>
+
 #include "device.h"
 #include "internal.h"
 
 namespace petgem {
 
+namespace {
+
+constexpr int kTR = 256;        // rows per tile
+constexpr int kCheck = 8;       // inner iterations between host checks (one graph)
+
+__device__ __forceinline__ float2 f2(float x, float y) { return make_float2(x, y); }
+
+template <typename T> struct V2;
+template <> struct V2<float> { using t = float2; };
+template <> struct V2<double> { using t = double2; };
+
+struct ColState {
+    double2 rho, alpha, beta;
+    double rn2;        // inner |r|^2 (relative to the normalised start)
+    double scale;      // |r64| of the current refinement step
+    double bnorm;      // |b|
+    double rnorm64;    // true residual norm
+    double tol_abs;    // rtol |b|
+    double inner_tol2; // inner_rtol^2
+    int active;        // inner iteration running
+    int outer;         // not yet converged in double precision
+    int breakdown;
+    int iters;         // inner iterations (all refinement steps)
+};
+
+// Operator view shared by the kernels.
+struct Op {
+    int n;                 // rows including padding (multiple of kTR)
+    int C;                 // columns
+    int ntiles, nseg;
+    const int* tile_seg;   // [ntiles] or null (one segment)
+    const int* seg_tile;   // [nseg+1] first tile of each segment
+    const int32_t* rp;
+    const int32_t* col;
+    const float* K32;
+    const float* M32;
+    const double* K64;
+    const double* M64;
+    const double* Kd;      // [n]
+    const double* Md;      // [n]
+    const double* wmu;     // [nseg][C] w mu0
+    int nrow_valid;        // rows with a matrix row (rp[i] defined for i < nrow_valid)
+};
+
+// ------------------------------------------------------------------ SpMM
+// EPI 1: Y = A X and partial[tile][c] = sum_i X_ic Y_ic (unconjugated).
+// EPI 2: Y = B - A X and partial[tile][c] = sum_i |Y_ic|^2 (in .x).
+// Column-lane variant: LPR lanes per row, CPL consecutive columns per lane.
+template <typename T, int LPR, int CPL, int EPI>
+__global__ void __launch_bounds__(256)
+k_spmm_c(Op op, const typename V2<T>::t* __restrict__ X, const typename V2<T>::t* __restrict__ B,
+         typename V2<T>::t* __restrict__ Y, double2* __restrict__ partial) {
+    using T2 = typename V2<T>::t;
+    const T* __restrict__ Kv = nullptr;
+    const T* __restrict__ Mv = nullptr;
+    if constexpr (sizeof(T) == 4) { Kv = op.K32; Mv = op.M32; } else { Kv = op.K64; Mv = op.M64; }
+    constexpr int RPB = 256 / LPR;
+    __shared__ double2 red[RPB][LPR * CPL];
+    const int tile = blockIdx.x;
+    const int slot = threadIdx.x / LPR, l = threadIdx.x % LPR;
+    const int C = op.C;
+    const int seg = op.tile_seg ? op.tile_seg[tile] : 0;
+    T wmu[CPL];
+#pragma unroll
+    for (int u = 0; u < CPL; ++u) {
+        const int c = l * CPL + u;
+        wmu[u] = c < C ? (T)op.wmu[seg * C + c] : (T)0;
+    }
+    double2 pacc[CPL];
+#pragma unroll
+    for (int u = 0; u < CPL; ++u) pacc[u] = make_double2(0.0, 0.0);
+    for (int r0 = 0; r0 < kTR; r0 += RPB) {
+        const int i = tile * kTR + r0 + slot;
+        if (i >= op.nrow_valid) continue;
+        T2 ak[CPL], am[CPL];
+#pragma unroll
+        for (int u = 0; u < CPL; ++u) { ak[u].x = ak[u].y = (T)0; am[u].x = am[u].y = (T)0; }
+        const int32_t e = op.rp[i + 1];
+        for (int32_t k = op.rp[i]; k < e; ++k) {
+            const T kv = Kv[k], mv = Mv[k];
+            const T2* xr = X + (size_t)op.col[k] * C + l * CPL;
+#pragma unroll
+            for (int u = 0; u < CPL; ++u) {
+                if (l * CPL + u < C) {
+                    const T2 xv = xr[u];
+                    ak[u].x += kv * xv.x; ak[u].y += kv * xv.y;
+                    am[u].x += mv * xv.x; am[u].y += mv * xv.y;
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < CPL; ++u) {
+            const int c = l * CPL + u;
+            if (c >= C) continue;
+            T2 y;
+            y.x = ak[u].x + wmu[u] * am[u].y;   // K x - i wmu M x
+            y.y = ak[u].y - wmu[u] * am[u].x;
+            const size_t o = (size_t)i * C + c;
+            if constexpr (EPI == 2) {
+                const T2 bb = B[o];
+                y.x = bb.x - y.x;
+                y.y = bb.y - y.y;
+                pacc[u].x += (double)y.x * (double)y.x + (double)y.y * (double)y.y;
+            } else {
+                const T2 xo = X[o];
+                pacc[u].x += (double)xo.x * (double)y.x - (double)xo.y * (double)y.y;
+                pacc[u].y += (double)xo.x * (double)y.y + (double)xo.y * (double)y.x;
+            }
+            Y[o] = y;
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < CPL; ++u) red[slot][l * CPL + u] = pacc[u];
+    __syncthreads();
+    for (int c = threadIdx.x; c < C && c < LPR * CPL; c += 256) {
+        double2 s = make_double2(0.0, 0.0);
+        for (int q = 0; q < RPB; ++q) s = cadd(s, red[q][c]);
+        partial[(size_t)tile * C + c] = s;
+    }
+}
+
+// Nonzero-lane variant for few columns: G lanes share the nonzeros of a row,
+// each lane accumulates all (<= CM) columns, then a shuffle reduction.
+template <typename T, int G, int CM, int EPI>
+__global__ void __launch_bounds__(256)
+k_spmm_n(Op op, const typename V2<T>::t* __restrict__ X, const typename V2<T>::t* __restrict__ B,
+         typename V2<T>::t* __restrict__ Y, double2* __restrict__ partial) {
+    using T2 = typename V2<T>::t;
+    const T* __restrict__ Kv = nullptr;
+    const T* __restrict__ Mv = nullptr;
+    if constexpr (sizeof(T) == 4) { Kv = op.K32; Mv = op.M32; } else { Kv = op.K64; Mv = op.M64; }
+    constexpr int RPB = 256 / G;
+    __shared__ double2 red[4][CM];
+    const int tile = blockIdx.x;
+    const int slot = threadIdx.x / G, l = threadIdx.x % G;
+    const int C = op.C;
+    const int seg = op.tile_seg ? op.tile_seg[tile] : 0;
+    double2 pacc[CM];
+#pragma unroll
+    for (int u = 0; u < CM; ++u) pacc[u] = make_double2(0.0, 0.0);
+    for (int r0 = 0; r0 < kTR; r0 += RPB) {
+        const int i = tile * kTR + r0 + slot;
+        if (i >= op.nrow_valid) continue;   // whole G-lane group skips together
+        T2 ak[CM], am[CM];
+#pragma unroll
+        for (int u = 0; u < CM; ++u) { ak[u].x = ak[u].y = (T)0; am[u].x = am[u].y = (T)0; }
+        const int32_t e = op.rp[i + 1];
+        for (int32_t k = op.rp[i] + l; k < e; k += G) {
+            const T kv = Kv[k], mv = Mv[k];
+            const T2* xr = X + (size_t)op.col[k] * C;
+#pragma unroll
+            for (int u = 0; u < CM; ++u) {
+                if (u < C) {
+                    const T2 xv = xr[u];
+                    ak[u].x += kv * xv.x; ak[u].y += kv * xv.y;
+                    am[u].x += mv * xv.x; am[u].y += mv * xv.y;
+                }
+            }
+        }
+#pragma unroll
+        for (int off = G / 2; off > 0; off >>= 1) {
+#pragma unroll
+            for (int u = 0; u < CM; ++u) {
+                ak[u].x += __shfl_xor(ak[u].x, off, G); ak[u].y += __shfl_xor(ak[u].y, off, G);
+                am[u].x += __shfl_xor(am[u].x, off, G); am[u].y += __shfl_xor(am[u].y, off, G);
+            }
+        }
+        if (l == 0) {
+#pragma unroll
+            for (int u = 0; u < CM; ++u) {
+                if (u >= C) continue;
+                const T w = (T)op.wmu[seg * C + u];
+                T2 y;
+                y.x = ak[u].x + w * am[u].y;
+                y.y = ak[u].y - w * am[u].x;
+                const size_t o = (size_t)i * C + u;
+                if constexpr (EPI == 2) {
+                    const T2 bb = B[o];
+                    y.x = bb.x - y.x;
+                    y.y = bb.y - y.y;
+                    pacc[u].x += (double)y.x * (double)y.x + (double)y.y * (double)y.y;
+                } else {
+                    const T2 xo = X[o];
+                    pacc[u].x += (double)xo.x * (double)y.x - (double)xo.y * (double)y.y;
+                    pacc[u].y += (double)xo.x * (double)y.y + (double)xo.y * (double)y.x;
+                }
+                Y[o] = y;
+            }
+        }
+    }
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+    for (int u = 0; u < CM; ++u) {
+        const double sx = wave_sum(pacc[u].x), sy = wave_sum(pacc[u].y);
+        if (lane == 0) red[wave][u] = make_double2(sx, sy);
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < C && (int)threadIdx.x < CM) {
+        const int u = threadIdx.x;
+        double2 s = red[0][u];
+        s = cadd(s, red[1][u]);
+        s = cadd(s, red[2][u]);
+        s = cadd(s, red[3][u]);
+        partial[(size_t)tile * C + u] = s;
+    }
+}
+
+// ------------------------------------------------------------ reductions
+enum RedMode { RED_INIT = 0, RED_ALPHA = 1, RED_BETA = 2, RED_RES = 3 };
+
+// One block per (segment, column): fixed-order sum over the segment's tiles,
+// then the scalar recurrence of that column.
+__global__ void __launch_bounds__(256)
+k_reduce(Op op, const double2* __restrict__ p0, const double2* __restrict__ p1,
+         ColState* __restrict__ st, int mode, int first) {
+    __shared__ double2 sa[256], sb[256];
+    const int sc = blockIdx.x;
+    const int s = sc / op.C, c = sc % op.C;
+    ColState& S = st[sc];
+    if ((mode == RED_ALPHA || mode == RED_BETA) && !S.active) return;
+    const int t0 = op.seg_tile[s], t1 = op.seg_tile[s + 1];
+    double2 a = make_double2(0.0, 0.0), b = make_double2(0.0, 0.0);
+    for (int t = t0 + threadIdx.x; t < t1; t += 256) {
+        a = cadd(a, p0[(size_t)t * op.C + c]);
+        if (p1) b = cadd(b, p1[(size_t)t * op.C + c]);
+    }
+    sa[threadIdx.x] = a;
+    sb[threadIdx.x] = b;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            sa[threadIdx.x] = cadd(sa[threadIdx.x], sa[threadIdx.x + w]);
+            sb[threadIdx.x] = cadd(sb[threadIdx.x], sb[threadIdx.x + w]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x != 0) return;
+    a = sa[0];
+    b = sb[0];
+    if (mode == RED_INIT) {            // a = r^T z, b.x = |r|^2
+        S.rho = a;
+        S.rn2 = b.x;
+        S.active = S.outer && isfinite(a.x) && isfinite(a.y) && (a.x != 0.0 || a.y != 0.0);
+        S.breakdown = 0;
+    } else if (mode == RED_ALPHA) {    // a = p^T q
+        if (!(isfinite(a.x) && isfinite(a.y)) || (a.x == 0.0 && a.y == 0.0)) {
+            S.active = 0;
+            S.breakdown = 1;
+            S.alpha = make_double2(0.0, 0.0);
+        } else {
+            S.alpha = cdiv(S.rho, a);
+        }
+    } else if (mode == RED_BETA) {     // a = r^T z (new), b.x = |r|^2
+        S.iters += 1;
+        S.rn2 = b.x;
+        if (!(isfinite(b.x)) || !(isfinite(a.x) && isfinite(a.y))) {
+            S.active = 0;
+            S.breakdown = 1;
+        } else if (b.x <= S.inner_tol2) {
+            S.active = 0;
+        } else if (S.rho.x == 0.0 && S.rho.y == 0.0) {
+            S.active = 0;
+            S.breakdown = 1;
+        } else {
+            S.beta = cdiv(a, S.rho);
+            S.rho = a;
+        }
+    } else {                           // RED_RES: a.x = |b - A x|^2
+        const double rn = sqrt(a.x);
+        S.rnorm64 = rn;
+        if (first) S.bnorm = rn;
+        S.scale = rn;
+        S.outer = S.outer && !(rn <= S.tol_abs) && isfinite(rn);
+    }
+}
+
+// --------------------------------------------------------- vector updates
+// Thread mapping of the elementwise kernels: CP lanes (power of two >= C)
+// per row, 256 / CP rows per pass over a tile.
+struct Map {
+    int CP, RPB;
+};
+
+__device__ __forceinline__ float2 jacobi_z(float2 r, double kd, double md, double wmu) {
+    // z = r / (Kd - i wmu Md)
+    const double dr = kd, di = -wmu * md;
+    const double inv = 1.0 / (dr * dr + di * di);
+    return f2((float)(((double)r.x * dr + (double)r.y * di) * inv),
+              (float)(((double)r.y * dr - (double)r.x * di) * inv));
+}
+
+// r = (r64 / |r64|) in complex64, x = 0, z = D^-1 r, p = z; partials r^T z, |r|^2.
+__global__ void __launch_bounds__(256)
+k_inner_init(Op op, int CP, const double2* __restrict__ R64, const ColState* __restrict__ st,
+             float2* __restrict__ Xi, float2* __restrict__ R, float2* __restrict__ P,
+             double2* __restrict__ p0, double2* __restrict__ p1) {
+    __shared__ double2 ra[256], rb[256];
+    const int tile = blockIdx.x, C = op.C;
+    const int c = threadIdx.x % CP, slot = threadIdx.x / CP, RPB = 256 / CP;
+    const int seg = op.tile_seg ? op.tile_seg[tile] : 0;
+    double2 a = make_double2(0.0, 0.0), b = make_double2(0.0, 0.0);
+    if (c < C) {
+        const ColState& S = st[seg * C + c];
+        const double inv = S.scale > 0.0 ? 1.0 / S.scale : 0.0;
+        const double wmu = op.wmu[seg * C + c];
+        for (int r0 = 0; r0 < kTR; r0 += RPB) {
+            const int i = tile * kTR + r0 + slot;
+            const size_t o = (size_t)i * C + c;
+            float2 r = f2(0.f, 0.f), z = f2(0.f, 0.f);
+            if (S.outer && i < op.nrow_valid) {
+                const double2 rr = R64[o];
+                r = f2((float)(rr.x * inv), (float)(rr.y * inv));
+                z = jacobi_z(r, op.Kd[i], op.Md[i], wmu);
+            }
+            Xi[o] = f2(0.f, 0.f);
+            R[o] = r;
+            P[o] = z;
+            a.x += (double)r.x * z.x - (double)r.y * z.y;
+            a.y += (double)r.x * z.y + (double)r.y * z.x;
+            b.x += (double)r.x * r.x + (double)r.y * r.y;
+        }
+    }
+    ra[threadIdx.x] = a;
+    rb[threadIdx.x] = b;
+    __syncthreads();
+    if ((int)threadIdx.x < C && (int)threadIdx.x < CP) {
+        double2 sa = make_double2(0.0, 0.0), sb = make_double2(0.0, 0.0);
+        for (int q = 0; q < RPB; ++q) {
+            sa = cadd(sa, ra[q * CP + threadIdx.x]);
+            sb = cadd(sb, rb[q * CP + threadIdx.x]);
+        }
+        p0[(size_t)tile * C + threadIdx.x] = sa;
+        p1[(size_t)tile * C + threadIdx.x] = sb;
+    }
+}
+
+// x += alpha p; r -= alpha q; partials r^T z and |r|^2 with z = D^-1 r.
+__global__ void __launch_bounds__(256)
+k_update1(Op op, int CP, const ColState* __restrict__ st, float2* __restrict__ Xi,
+          float2* __restrict__ R, const float2* __restrict__ P, const float2* __restrict__ Q,
+          double2* __restrict__ p0, double2* __restrict__ p1) {
+    __shared__ double2 ra[256], rb[256];
+    const int tile = blockIdx.x, C = op.C;
+    const int c = threadIdx.x % CP, slot = threadIdx.x / CP, RPB = 256 / CP;
+    const int seg = op.tile_seg ? op.tile_seg[tile] : 0;
+    double2 a = make_double2(0.0, 0.0), b = make_double2(0.0, 0.0);
+    if (c < C) {
+        const ColState& S = st[seg * C + c];
+        if (S.active) {
+            const float ax = (float)S.alpha.x, ay = (float)S.alpha.y;
+            const double wmu = op.wmu[seg * C + c];
+            for (int r0 = 0; r0 < kTR; r0 += RPB) {
+                const int i = tile * kTR + r0 + slot;
+                if (i >= op.nrow_valid) break;
+                const size_t o = (size_t)i * C + c;
+                const float2 p = P[o], q = Q[o];
+                float2 x = Xi[o], r = R[o];
+                x.x += ax * p.x - ay * p.y;
+                x.y += ax * p.y + ay * p.x;
+                r.x -= ax * q.x - ay * q.y;
+                r.y -= ax * q.y + ay * q.x;
+                Xi[o] = x;
+                R[o] = r;
+                const float2 z = jacobi_z(r, op.Kd[i], op.Md[i], wmu);
+                a.x += (double)r.x * z.x - (double)r.y * z.y;
+                a.y += (double)r.x * z.y + (double)r.y * z.x;
+                b.x += (double)r.x * r.x + (double)r.y * r.y;
+            }
+        }
+    }
+    ra[threadIdx.x] = a;
+    rb[threadIdx.x] = b;
+    __syncthreads();
+    if ((int)threadIdx.x < C && (int)threadIdx.x < CP) {
+        double2 sa = make_double2(0.0, 0.0), sb = make_double2(0.0, 0.0);
+        for (int q = 0; q < RPB; ++q) {
+            sa = cadd(sa, ra[q * CP + threadIdx.x]);
+            sb = cadd(sb, rb[q * CP + threadIdx.x]);
+        }
+        p0[(size_t)tile * C + threadIdx.x] = sa;
+        p1[(size_t)tile * C + threadIdx.x] = sb;
+    }
+}
+
+// p = D^-1 r + beta p for the still active columns.
+__global__ void __launch_bounds__(256)
+k_update2(Op op, int CP, const ColState* __restrict__ st, const float2* __restrict__ R,
+          float2* __restrict__ P) {
+    const int tile = blockIdx.x, C = op.C;
+    const int c = threadIdx.x % CP, slot = threadIdx.x / CP, RPB = 256 / CP;
+    if (c >= C) return;
+    const int seg = op.tile_seg ? op.tile_seg[tile] : 0;
+    const ColState& S = st[seg * C + c];
+    if (!S.active) return;
+    const float bx = (float)S.beta.x, by = (float)S.beta.y;
+    const double wmu = op.wmu[seg * C + c];
+    for (int r0 = 0; r0 < kTR; r0 += RPB) {
+        const int i = tile * kTR + r0 + slot;
+        if (i >= op.nrow_valid) break;
+        const size_t o = (size_t)i * C + c;
+        const float2 z = jacobi_z(R[o], op.Kd[i], op.Md[i], wmu);
+        const float2 p = P[o];
+        P[o] = f2(z.x + bx * p.x - by * p.y, z.y + bx * p.y + by * p.x);
+    }
+}
+
+// x64 += |r64| d for the columns still refining.
+__global__ void __launch_bounds__(256)
+k_ir_update(Op op, int CP, const ColState* __restrict__ st, const float2* __restrict__ Xi,
+            double2* __restrict__ X64) {
+    const int tile = blockIdx.x, C = op.C;
+    const int c = threadIdx.x % CP, slot = threadIdx.x / CP, RPB = 256 / CP;
+    if (c >= C) return;
+    const int seg = op.tile_seg ? op.tile_seg[tile] : 0;
+    const ColState& S = st[seg * C + c];
+    if (!S.outer) return;
+    for (int r0 = 0; r0 < kTR; r0 += RPB) {
+        const int i = tile * kTR + r0 + slot;
+        if (i >= op.nrow_valid) break;
+        const size_t o = (size_t)i * C + c;
+        const float2 d = Xi[o];
+        double2 x = X64[o];
+        x.x += S.scale * (double)d.x;
+        x.y += S.scale * (double)d.y;
+        X64[o] = x;
+    }
+}
+
+// partial[tile][c].x = sum_i |B_ic|^2
+__global__ void __launch_bounds__(256)
+k_norm2(Op op, int CP, const double2* __restrict__ B, double2* __restrict__ p0) {
+    __shared__ double ra[256];
+    const int tile = blockIdx.x, C = op.C;
+    const int c = threadIdx.x % CP, slot = threadIdx.x / CP, RPB = 256 / CP;
+    double a = 0.0;
+    if (c < C)
+        for (int r0 = 0; r0 < kTR; r0 += RPB) {
+            const int i = tile * kTR + r0 + slot;
+            if (i >= op.nrow_valid) break;
+            const double2 b = B[(size_t)i * C + c];
+            a += b.x * b.x + b.y * b.y;
+        }
+    ra[threadIdx.x] = a;
+    __syncthreads();
+    if ((int)threadIdx.x < C && (int)threadIdx.x < CP) {
+        double sa = 0.0;
+        for (int q = 0; q < RPB; ++q) sa += ra[q * CP + threadIdx.x];
+        p0[(size_t)tile * C + threadIdx.x] = make_double2(sa, 0.0);
+    }
+}
+
+__global__ void k_fill_f2(size_t n, float2* __restrict__ a) {
+    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) a[i] = make_float2(0.f, 0.f);
+}
+
+__global__ void k_fill_z(size_t n, double2* __restrict__ a) {
+    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) a[i] = make_double2(0.0, 0.0);
+}
+
+// dst[c][i] = src[i][c] (row-major block -> per-column vectors), rows [r0, r0+nr)
+__global__ void k_cols_out(int nr, int C, size_t r0, const double2* __restrict__ src,
+                           double2* __restrict__ dst, size_t ldd) {
+    const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= (size_t)nr * C) return;
+    const size_t i = e / C, c = e % C;
+    dst[c * ldd + i] = src[(r0 + i) * C + c];
+}
+
+__global__ void k_cols_in(int nr, int C, size_t r0, const double2* __restrict__ src, size_t lds,
+                          double2* __restrict__ dst) {
+    const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= (size_t)nr * C) return;
+    const size_t i = e / C, c = e % C;
+    dst[(r0 + i) * C + c] = src[c * lds + i];
+}
+
+__global__ void k_init_state(ColState* st, int nsc, double rtol, double inner_rtol) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nsc) return;
+    ColState S;
+    S.rho = S.alpha = S.beta = make_double2(0.0, 0.0);
+    S.rn2 = 0.0;
+    S.scale = 0.0;
+    S.bnorm = 0.0;
+    S.rnorm64 = 0.0;
+    S.tol_abs = 0.0;
+    S.inner_tol2 = inner_rtol * inner_rtol;
+    S.active = 0;
+    S.outer = 1;
+    S.breakdown = 0;
+    S.iters = 0;
+    st[k] = S;
+}
+
+__global__ void k_set_tol(ColState* st, int nsc, double rtol) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nsc) return;
+    st[k].tol_abs = rtol * st[k].bnorm;
+    st[k].outer = st[k].bnorm > 0.0 && isfinite(st[k].bnorm);
+}
+
+// Builders of the concatenated (block-diagonal) operator of several meshes.
+__global__ void k_cat_rows(int n, int32_t nnz_off, int row_off, const int32_t* __restrict__ rp,
+                           int32_t* __restrict__ rp_cat) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i <= n) rp_cat[row_off + i] = rp[i] + nnz_off;
+}
+__global__ void k_fill_rp(int n, int32_t v, int32_t* __restrict__ a) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < n) a[i] = v;
+}
+__global__ void k_cat_cols(int64_t nnz, int row_off, const int32_t* __restrict__ col,
+                           const double* __restrict__ K, const double* __restrict__ M,
+                           int32_t* __restrict__ col_cat, double* __restrict__ K64,
+                           double* __restrict__ M64, float* __restrict__ K32, float* __restrict__ M32) {
+    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (k >= nnz) return;
+    col_cat[k] = col[k] + row_off;
+    K64[k] = K[k];
+    M64[k] = M[k];
+    K32[k] = (float)K[k];
+    M32[k] = (float)M[k];
+}
+__global__ void k_fill_d(int n, double v, double* __restrict__ a) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < n) a[i] = v;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- host side
+
+struct SpmmChoice {
+    int kind = 0;   // 0 = column lanes, 1 = nonzero lanes
+    int a = 8, b = 1;   // (LPR, CPL) or (G, CM)
+    float ms = 0.f;
+};
+
 struct BlockWork {
-    int dummy = 0;
+    size_t cap_rows = 0;
+    int cap_C = 0, cap_nsc = 0, cap_tiles = 0;
+    double2 *X64 = nullptr, *R64 = nullptr, *B64 = nullptr;
+    float2 *Xi = nullptr, *R = nullptr, *P = nullptr, *Q = nullptr;
+    double2 *p0 = nullptr, *p1 = nullptr;
+    ColState* st = nullptr;
+    ColState* st_h = nullptr;
+    double* wmu = nullptr;
+    int* seg_tile = nullptr;
+    int* tile_seg = nullptr;
+    // concatenated operator of an uneven batch
+    int32_t *rp = nullptr, *col = nullptr;
+    double *K64 = nullptr, *M64 = nullptr, *Kd = nullptr, *Md = nullptr;
+    float *K32 = nullptr, *M32 = nullptr;
+    size_t cat_rows = 0, cat_nnz = 0;
+    std::map<std::tuple<int, int64_t, int>, SpmmChoice> tuned;   // (n, nnz, C) -> choice
+    hipGraphExec_t graph = nullptr;
+    hipStream_t graph_stream = nullptr;
+    std::vector<char> graph_sig;   // bytes of every argument baked into the graph
+    ~BlockWork() { release(); }
+    void release_graph() {
+        if (graph) (void)hipGraphExecDestroy(graph);
+        graph = nullptr;
+        graph_sig.clear();
+    }
+    void release() {
+        release_graph();
+        if (graph_stream) (void)hipStreamDestroy(graph_stream);
+        graph_stream = nullptr;
+        dfree(X64); dfree(R64); dfree(B64); dfree(Xi); dfree(R); dfree(P); dfree(Q);
+        dfree(p0); dfree(p1); dfree(st); dfree(wmu); dfree(seg_tile); dfree(tile_seg);
+        dfree(rp); dfree(col); dfree(K64); dfree(M64); dfree(Kd); dfree(Md); dfree(K32); dfree(M32);
+        if (st_h) (void)hipHostFree(st_h);
+        st_h = nullptr;
+        cap_rows = 0; cap_C = cap_nsc = cap_tiles = 0;
+        cat_rows = cat_nnz = 0;
+    }
 };
 
 void release_block_work(BlockWork*& w) {
@@ -13,16 +616,498 @@ void release_block_work(BlockWork*& w) {
     w = nullptr;
 }
 
-int block_solve(petgem_system*, const petgem_source*, int32_t, const petgem_opts&, const double2*,
-                double2*, hipStream_t, petgem_stats*) {
-    set_error("COCG path not built");
-    return PETGEM_INVALID_ARG;
+namespace {
+
+using SpmmFn = void (*)(Op, const void*, const void*, void*, double2*);
+
+template <typename T, int A, int B, int EPI, bool COLS>
+void spmm_thunk(Op op, const void* X, const void* Bv, void* Y, double2* part, hipStream_t s) {
+    using T2 = typename V2<T>::t;
+    if constexpr (COLS)
+        hipLaunchKernelGGL((k_spmm_c<T, A, B, EPI>), dim3(op.ntiles), dim3(256), 0, s, op,
+                           (const T2*)X, (const T2*)Bv, (T2*)Y, part);
+    else
+        hipLaunchKernelGGL((k_spmm_n<T, A, B, EPI>), dim3(op.ntiles), dim3(256), 0, s, op,
+                           (const T2*)X, (const T2*)Bv, (T2*)Y, part);
 }
 
-int batch_solve(petgem_system* const*, const petgem_source*, int32_t, const petgem_opts&,
-                petgem_solution**, hipStream_t, petgem_stats*) {
-    set_error("batch path not built");
-    return PETGEM_INVALID_ARG;
+template <typename T, int EPI>
+bool spmm_dispatch_(const SpmmChoice& ch, Op op, const void* X, const void* Bv, void* Y,
+                   double2* part, hipStream_t s) {
+    if (ch.kind == 1) {
+#define PG_N(G, CM) if (ch.a == G && ch.b == CM) { spmm_thunk<T, G, CM, EPI, false>(op, X, Bv, Y, part, s); return true; }
+        PG_N(4, 1) PG_N(8, 1) PG_N(16, 1) PG_N(4, 2) PG_N(8, 2) PG_N(16, 2) PG_N(4, 4) PG_N(8, 4) PG_N(16, 4)
+#undef PG_N
+    } else {
+#define PG_C(L, P) if (ch.a == L && ch.b == P) { spmm_thunk<T, L, P, EPI, true>(op, X, Bv, Y, part, s); return true; }
+        PG_C(8, 1) PG_C(8, 2) PG_C(8, 4) PG_C(16, 1) PG_C(16, 2) PG_C(16, 3) PG_C(16, 4)
+        PG_C(32, 1) PG_C(32, 2) PG_C(32, 3) PG_C(32, 4) PG_C(64, 1) PG_C(64, 2) PG_C(64, 3) PG_C(64, 4)
+#undef PG_C
+    }
+    return false;
+}
+
+template <typename T, int EPI>
+void spmm_dispatch(const SpmmChoice& ch, Op op, const void* X, const void* Bv, void* Y,
+                   double2* part, hipStream_t s) {
+    if (!spmm_dispatch_<T, EPI>(ch, op, X, Bv, Y, part, s)) abort();   // candidates() lists only instantiated shapes
+}
+
+std::vector<SpmmChoice> candidates(int C) {
+    std::vector<SpmmChoice> v;
+    if (C <= 4) {
+        const int cm = C <= 1 ? 1 : (C <= 2 ? 2 : 4);
+        for (int g : {4, 8, 16}) v.push_back({1, g, cm});
+    }
+    if (C >= 4) {
+        for (int l : {8, 16, 32, 64})
+            for (int p : {1, 2, 3, 4}) {
+                if (l == 8 && p == 3) continue;
+                if (l * p < C) continue;
+                if (l * p >= 2 * C && l > 8) continue;   // more than half the lanes idle
+                v.push_back({0, l, p});
+            }
+        if (v.empty() || (C > 256)) v.push_back({0, 64, 4});
+    }
+    return v;
+}
+
+struct Timer {
+    std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
+    double ms() const {
+        return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
+};
+
+int ensure_work(BlockWork*& w, size_t rows, int C, int nsc, int ntiles) {
+    if (!w) w = new BlockWork();
+    if (w->cap_rows >= rows && w->cap_C == C && w->cap_nsc >= nsc && w->cap_tiles >= ntiles) return PETGEM_OK;
+    // keep the concatenated operator, reallocate the vectors
+    w->release_graph();
+    dfree(w->X64); dfree(w->R64); dfree(w->B64); dfree(w->Xi); dfree(w->R); dfree(w->P); dfree(w->Q);
+    dfree(w->p0); dfree(w->p1); dfree(w->st); dfree(w->wmu); dfree(w->seg_tile); dfree(w->tile_seg);
+    if (w->st_h) (void)hipHostFree(w->st_h);
+    w->st_h = nullptr;
+    const size_t e = rows * (size_t)C;
+    PG_TRY(dalloc(&w->X64, e));
+    PG_TRY(dalloc(&w->R64, e));
+    PG_TRY(dalloc(&w->B64, e));
+    PG_TRY(dalloc(&w->Xi, e));
+    PG_TRY(dalloc(&w->R, e));
+    PG_TRY(dalloc(&w->P, e));
+    PG_TRY(dalloc(&w->Q, e));
+    PG_TRY(dalloc(&w->p0, (size_t)ntiles * C));
+    PG_TRY(dalloc(&w->p1, (size_t)ntiles * C));
+    PG_TRY(dalloc(&w->st, (size_t)nsc));
+    PG_TRY(dalloc(&w->wmu, (size_t)nsc));
+    PG_TRY(dalloc(&w->seg_tile, (size_t)nsc + 1));
+    PG_TRY(dalloc(&w->tile_seg, (size_t)ntiles));
+    PG_HIP(hipHostMalloc(reinterpret_cast<void**>(&w->st_h), sizeof(ColState) * (size_t)nsc));
+    w->cap_rows = rows;
+    w->cap_C = C;
+    w->cap_nsc = nsc;
+    w->cap_tiles = ntiles;
+    return PETGEM_OK;
+}
+
+int cp_of(int C) {
+    int cp = 1;
+    while (cp < C && cp < 256) cp <<= 1;
+    return cp;
+}
+
+// Autotuner of the complex64 SpMM tile shape: every candidate (lanes per row x
+// columns per lane, or lanes sharing a row's nonzeros) runs 3 times on this
+// operator and block width; the fastest is kept per (rows, nnz, columns).
+int tune_spmm(BlockWork* w, const Op& op, int64_t nnz, hipStream_t s, SpmmChoice& out) {
+    auto key = std::make_tuple(op.n, nnz, op.C);
+    auto it = w->tuned.find(key);
+    if (it != w->tuned.end()) { out = it->second; return PETGEM_OK; }
+    auto cands = candidates(op.C);
+    hipEvent_t e0, e1;
+    PG_HIP(hipEventCreate(&e0));
+    PG_HIP(hipEventCreate(&e1));
+    SpmmChoice best = cands[0];
+    best.ms = 1e30f;
+    for (auto& c : cands) {
+        spmm_dispatch<float, 1>(c, op, w->P, nullptr, w->Q, w->p0, s);   // warm-up
+        PG_HIP(hipEventRecord(e0, s));
+        for (int r = 0; r < 3; ++r) spmm_dispatch<float, 1>(c, op, w->P, nullptr, w->Q, w->p0, s);
+        PG_HIP(hipEventRecord(e1, s));
+        PG_HIP(hipEventSynchronize(e1));
+        float ms = 0.f;
+        PG_HIP(hipEventElapsedTime(&ms, e0, e1));
+        c.ms = ms / 3.f;
+        if (c.ms < best.ms) best = c;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    w->tuned[key] = best;
+    out = best;
+    return PETGEM_OK;
+}
+
+// The driver shared by the multi-source and the uneven-batch solves.
+// On entry B64 holds the right-hand sides, X64 the initial guesses (or zero).
+int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hipStream_t s,
+               std::vector<petgem_stats*>& stv, bool have_x0) {
+    const int C = op.C, nsc = op.nseg * C, CP = cp_of(C);
+    Timer t_all;
+    SpmmChoice ch;
+    // P (complex64, rows x C) gets finite values for the tuning launches
+    hipLaunchKernelGGL(k_fill_f2, dim3(ceil_div((size_t)op.n * C, 256)), dim3(256), 0, s,
+                       (size_t)op.n * C, w->P);
+    PG_TRY(tune_spmm(w, op, nnz, s, ch));
+    hipLaunchKernelGGL(k_init_state, dim3(ceil_div(nsc, 64)), dim3(64), 0, s, w->st, nsc, o.rtol,
+                       o.inner_rtol);
+    const bool prof = o.profile != 0;
+    std::vector<hipEvent_t> evs;
+    auto ev = [&]() {
+        if (!prof) return;
+        hipEvent_t e;
+        (void)hipEventCreate(&e);
+        (void)hipEventRecord(e, s);
+        evs.push_back(e);
+    };
+    auto residual = [&](int first) -> int {
+        ev();
+        spmm_dispatch<double, 2>(ch, op, w->X64, w->B64, w->R64, w->p0, s);
+        ev();
+        hipLaunchKernelGGL(k_reduce, dim3(nsc), dim3(256), 0, s, op, w->p0, nullptr, w->st, (int)RED_RES, first);
+        PG_HIP(hipGetLastError());
+        return PETGEM_OK;
+    };
+    auto read_state = [&]() -> int {
+        PG_HIP(hipMemcpyAsync(w->st_h, w->st, sizeof(ColState) * nsc, hipMemcpyDeviceToHost, s));
+        PG_HIP(hipStreamSynchronize(s));
+        return PETGEM_OK;
+    };
+    // |b| of every (segment, column)
+    auto bnorms = [&]() -> int {
+        hipLaunchKernelGGL(k_norm2, dim3(op.ntiles), dim3(256), 0, s, op, CP, w->B64, w->p0);
+        hipLaunchKernelGGL(k_reduce, dim3(nsc), dim3(256), 0, s, op, w->p0, nullptr, w->st, (int)RED_RES, 1);
+        PG_HIP(hipGetLastError());
+        return PETGEM_OK;
+    };
+    PG_TRY(bnorms());
+    hipLaunchKernelGGL(k_set_tol, dim3(ceil_div(nsc, 64)), dim3(64), 0, s, w->st, nsc, o.rtol);
+    PG_TRY(residual(0));
+    PG_TRY(read_state());
+    std::vector<int> fallback(nsc, 0);
+    if (have_x0) {
+        bool redo = false;
+        for (int k = 0; k < nsc; ++k) {
+            const ColState& S = w->st_h[k];
+            if (!(S.rnorm64 < S.bnorm) && S.bnorm > 0.0) { fallback[k] = 1; redo = true; }
+        }
+        if (redo) {   // a rejected guess restarts every column from zero (simple and rare)
+            hipLaunchKernelGGL(k_fill_z, dim3(ceil_div((size_t)op.n * C, 256)), dim3(256), 0, s,
+                               (size_t)op.n * C, w->X64);
+            hipLaunchKernelGGL(k_init_state, dim3(ceil_div(nsc, 64)), dim3(64), 0, s, w->st, nsc,
+                               o.rtol, o.inner_rtol);
+            PG_TRY(bnorms());
+            hipLaunchKernelGGL(k_set_tol, dim3(ceil_div(nsc, 64)), dim3(64), 0, s, w->st, nsc, o.rtol);
+            PG_TRY(residual(0));
+            PG_TRY(read_state());
+        }
+    }
+    std::vector<double> x0res(nsc, 1.0);
+    for (int k = 0; k < nsc; ++k)
+        if (have_x0 && w->st_h[k].bnorm > 0) x0res[k] = fallback[k] ? 1.0 : w->st_h[k].rnorm64 / w->st_h[k].bnorm;
+
+    // one inner iteration, kCheck of them captured as a graph
+    auto iteration = [&]() {
+        ev();
+        spmm_dispatch<float, 1>(ch, op, w->P, nullptr, w->Q, w->p0, s);
+        ev();
+        hipLaunchKernelGGL(k_reduce, dim3(nsc), dim3(256), 0, s, op, w->p0, nullptr, w->st, (int)RED_ALPHA, 0);
+        hipLaunchKernelGGL(k_update1, dim3(op.ntiles), dim3(256), 0, s, op, CP, w->st, w->Xi, w->R, w->P,
+                           w->Q, w->p0, w->p1);
+        hipLaunchKernelGGL(k_reduce, dim3(nsc), dim3(256), 0, s, op, w->p0, w->p1, w->st, (int)RED_BETA, 0);
+        hipLaunchKernelGGL(k_update2, dim3(op.ntiles), dim3(256), 0, s, op, CP, w->st, w->R, w->P);
+    };
+    const bool use_graph = o.use_graph && !prof;
+    std::vector<char> sig;
+    {
+        auto put = [&](const void* p, size_t nb) {
+            const char* c = static_cast<const char*>(p);
+            sig.insert(sig.end(), c, c + nb);
+        };
+        put(&op, sizeof(op));
+        const void* ptrs[8] = {w->Xi, w->R, w->P, w->Q, w->p0, w->p1, w->st, nullptr};
+        put(ptrs, sizeof(ptrs));
+        int chv[3] = {ch.kind, ch.a, ch.b};
+        put(chv, sizeof(chv));
+    }
+    if (use_graph && (w->graph == nullptr || w->graph_sig != sig)) {
+        w->release_graph();
+        if (!w->graph_stream) PG_HIP(hipStreamCreateWithFlags(&w->graph_stream, hipStreamNonBlocking));
+        hipGraph_t g;
+        hipStream_t caller = s;
+        s = w->graph_stream;
+        PG_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        for (int k = 0; k < kCheck; ++k) iteration();
+        hipError_t ce = hipStreamEndCapture(s, &g);
+        s = caller;
+        if (ce != hipSuccess) {
+            set_error(std::string("graph capture: ") + hipGetErrorString(ce));
+            return PETGEM_HIP_ERROR;
+        }
+        hipError_t ie = hipGraphInstantiate(&w->graph, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (ie != hipSuccess) {
+            set_error(std::string("graph instantiate: ") + hipGetErrorString(ie));
+            return PETGEM_HIP_ERROR;
+        }
+        w->graph_sig = sig;
+    }
+
+    int total_inner = 0, steps = 0, strikes = 0;
+    int status = PETGEM_OK;
+    const int max_steps = 60;
+    double prev_worst = 1e300;
+    while (true) {
+        int n_outer = 0;
+        bool nonfinite = false;
+        for (int k = 0; k < nsc; ++k) {
+            n_outer += w->st_h[k].outer;
+            if (!std::isfinite(w->st_h[k].rnorm64)) nonfinite = true;
+        }
+        if (nonfinite) { status = PETGEM_NONFINITE; break; }
+        if (n_outer == 0) break;
+        // stagnation: the worst relative residual must at least halve per step
+        double worst = 0.0;
+        for (int k = 0; k < nsc; ++k)
+            if (w->st_h[k].outer && w->st_h[k].bnorm > 0)
+                worst = std::max(worst, w->st_h[k].rnorm64 / w->st_h[k].bnorm);
+        strikes = worst > 0.5 * prev_worst ? strikes + 1 : 0;
+        prev_worst = worst;
+        if (strikes >= 3) { status = PETGEM_NOT_CONVERGED; break; }
+        if (steps >= max_steps || total_inner >= o.max_iter) { status = PETGEM_NOT_CONVERGED; break; }
+        // inner complex64 COCG on A d = r64 / |r64|
+        hipLaunchKernelGGL(k_inner_init, dim3(op.ntiles), dim3(256), 0, s, op, CP, w->R64, w->st, w->Xi,
+                           w->R, w->P, w->p0, w->p1);
+        hipLaunchKernelGGL(k_reduce, dim3(nsc), dim3(256), 0, s, op, w->p0, w->p1, w->st, (int)RED_INIT, 0);
+        int inner = 0;
+        while (true) {
+            if (use_graph) {
+                PG_HIP(hipGraphLaunch(w->graph, s));
+            } else {
+                for (int k = 0; k < kCheck; ++k) iteration();
+            }
+            inner += kCheck;
+            PG_TRY(read_state());
+            int act = 0;
+            for (int k = 0; k < nsc; ++k) act += w->st_h[k].active;
+            if (act == 0 || total_inner + inner >= o.max_iter) break;
+        }
+        total_inner += inner;
+        hipLaunchKernelGGL(k_ir_update, dim3(op.ntiles), dim3(256), 0, s, op, CP, w->st, w->Xi, w->X64);
+        PG_TRY(residual(0));
+        PG_TRY(read_state());
+        ++steps;
+    }
+    double t_solve = t_all.ms();
+    double spmv_ms = 0.0;
+    int spmv_n = 0;
+    if (prof && !evs.empty()) {
+        (void)hipEventSynchronize(evs.back());
+        for (size_t i = 0; i + 1 < evs.size(); i += 2) {
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, evs[i], evs[i + 1]);
+            spmv_ms += ms;
+            ++spmv_n;
+        }
+        for (auto e : evs) (void)hipEventDestroy(e);
+    }
+    for (int k = 0; k < nsc; ++k) {
+        petgem_stats* st = stv[k];
+        if (!st) continue;
+        const ColState& S = w->st_h[k];
+        st->iters = S.iters;
+        st->ir_steps = steps;
+        st->used_fallback = fallback[k];
+        st->rel_residual = S.bnorm > 0 ? S.rnorm64 / S.bnorm : 0.0;
+        st->x0_rel_residual = x0res[k];
+        st->t_solve_ms = t_solve;
+        st->spmv_ms = spmv_ms;
+        st->spmv_launches = spmv_n;
+        st->status = S.outer ? (std::isfinite(S.rnorm64) ? PETGEM_NOT_CONVERGED : PETGEM_NONFINITE) : PETGEM_OK;
+        if (st->status != PETGEM_OK && status == PETGEM_OK) status = st->status;
+    }
+    if (status == PETGEM_NOT_CONVERGED) set_error("COCG refinement reached its iteration limit before rtol");
+    if (status == PETGEM_NONFINITE) set_error("non-finite value in the COCG recurrence");
+    return status;
+}
+
+}  // namespace
+
+int block_solve(petgem_system* sys, const petgem_source* src, int32_t n_src, const petgem_opts& o,
+                const double2* x0, double2* x_out, hipStream_t s, petgem_stats* st) {
+    const int n = sys->n_dof, C = n_src;
+    const int ntiles = ceil_div(n, kTR);
+    const size_t rows = (size_t)ntiles * kTR;
+    PG_TRY(ensure_fp32(sys, s));
+    PG_TRY(ensure_work(sys->bw, rows, C, C, ntiles));
+    BlockWork* w = sys->bw;
+    std::vector<double> wmu(C);
+    for (int c = 0; c < C; ++c) wmu[c] = 2.0 * kPi * src[c].freq_hz * kMu0;
+    int seg_tile[2] = {0, ntiles};
+    PG_HIP(hipMemcpyAsync(w->wmu, wmu.data(), sizeof(double) * C, hipMemcpyHostToDevice, s));
+    PG_HIP(hipMemcpyAsync(w->seg_tile, seg_tile, sizeof(seg_tile), hipMemcpyHostToDevice, s));
+    Op op;
+    op.n = (int)rows;
+    op.C = C;
+    op.ntiles = ntiles;
+    op.nseg = 1;
+    op.tile_seg = nullptr;
+    op.seg_tile = w->seg_tile;
+    op.rp = sys->row_ptr;
+    op.col = sys->col;
+    op.K32 = sys->K32;
+    op.M32 = sys->Ms32;
+    op.K64 = sys->K;
+    op.M64 = sys->Ms;
+    op.Kd = sys->Kd;
+    op.Md = sys->Msd;
+    op.wmu = w->wmu;
+    op.nrow_valid = n;
+    // right-hand sides into the block layout (padding rows stay zero)
+    Timer t_rhs;
+    hipLaunchKernelGGL(k_fill_z, dim3(ceil_div(rows * C, 256)), dim3(256), 0, s, rows * C, w->B64);
+    for (int c = 0; c < C; ++c) PG_TRY(launch_rhs(sys, src[c], w->B64 + c, C, s));
+    int flag = 0;
+    PG_HIP(hipMemcpyAsync(&flag, sys->dflag, sizeof(int), hipMemcpyDeviceToHost, s));
+    PG_HIP(hipStreamSynchronize(s));
+    if (flag) {
+        int zero = 0;
+        PG_HIP(hipMemcpy(sys->dflag, &zero, sizeof(int), hipMemcpyHostToDevice));
+        set_error("source within 1e-9 h of a quadrature point of an element with dsigma != 0");
+        return PETGEM_SOURCE_SINGULAR;
+    }
+    const double trhs = t_rhs.ms();
+    hipLaunchKernelGGL(k_fill_z, dim3(ceil_div(rows * C, 256)), dim3(256), 0, s, rows * C, w->X64);
+    if (x0)
+        hipLaunchKernelGGL(k_cols_in, dim3(ceil_div((size_t)n * C, 256)), dim3(256), 0, s, n, C, (size_t)0,
+                           x0, (size_t)n, w->X64);
+    std::vector<petgem_stats*> stv(C, nullptr);
+    if (st)
+        for (int c = 0; c < C; ++c) { stv[c] = st + c; st[c].t_rhs_ms = trhs; }
+    int rc = mrhs_solve(w, op, sys->nnz, o, s, stv, x0 != nullptr);
+    if (rc != PETGEM_OK && rc != PETGEM_NOT_CONVERGED && rc != PETGEM_NONFINITE) return rc;
+    hipLaunchKernelGGL(k_cols_out, dim3(ceil_div((size_t)n * C, 256)), dim3(256), 0, s, n, C, (size_t)0,
+                       w->X64, x_out, (size_t)n);
+    PG_HIP(hipGetLastError());
+    return rc;
+}
+
+int batch_solve(petgem_system* const* systems, const petgem_source* src, int32_t n_sys,
+                const petgem_opts& o, petgem_solution** sols, hipStream_t s, petgem_stats* st) {
+    // Row offsets of the concatenated block-diagonal operator: every mesh
+    // starts on a tile boundary, so each tile belongs to one mesh.
+    std::vector<int> row_off(n_sys + 1, 0), seg_tile(n_sys + 1, 0);
+    std::vector<int64_t> nnz_off(n_sys + 1, 0);
+    for (int k = 0; k < n_sys; ++k) {
+        const int nt = ceil_div(systems[k]->n_dof, kTR);
+        seg_tile[k + 1] = seg_tile[k] + nt;
+        row_off[k + 1] = row_off[k] + nt * kTR;
+        nnz_off[k + 1] = nnz_off[k] + systems[k]->nnz;
+    }
+    const int ntiles = seg_tile[n_sys];
+    const size_t rows = (size_t)row_off[n_sys];
+    const int64_t nnz = nnz_off[n_sys];
+    if (nnz >= (int64_t(1) << 31) || rows >= (size_t(1) << 31)) {
+        set_error("uneven batch too large for 32-bit CSR offsets");
+        return PETGEM_INVALID_ARG;
+    }
+    petgem_system* owner = systems[0];
+    PG_TRY(ensure_work(owner->bw, rows, 1, n_sys, ntiles));
+    BlockWork* w = owner->bw;
+    // (re)build the concatenated operator
+    if (w->cat_rows < rows || w->cat_nnz < (size_t)nnz) {
+        dfree(w->rp); dfree(w->col); dfree(w->K64); dfree(w->M64); dfree(w->K32); dfree(w->M32);
+        dfree(w->Kd); dfree(w->Md);
+        PG_TRY(dalloc(&w->rp, rows + 1));
+        PG_TRY(dalloc(&w->col, (size_t)nnz));
+        PG_TRY(dalloc(&w->K64, (size_t)nnz));
+        PG_TRY(dalloc(&w->M64, (size_t)nnz));
+        PG_TRY(dalloc(&w->K32, (size_t)nnz));
+        PG_TRY(dalloc(&w->M32, (size_t)nnz));
+        PG_TRY(dalloc(&w->Kd, rows));
+        PG_TRY(dalloc(&w->Md, rows));
+        w->cat_rows = rows;
+        w->cat_nnz = (size_t)nnz;
+    }
+    std::vector<int> tseg(ntiles);
+    std::vector<double> wmu(n_sys);
+    for (int k = 0; k < n_sys; ++k) {
+        petgem_system* sy = systems[k];
+        for (int t = seg_tile[k]; t < seg_tile[k + 1]; ++t) tseg[t] = k;
+        wmu[k] = 2.0 * kPi * src[k].freq_hz * kMu0;
+        const int n = sy->n_dof;
+        hipLaunchKernelGGL(k_cat_rows, dim3(ceil_div(n + 1, 256)), dim3(256), 0, s, n, (int32_t)nnz_off[k],
+                           row_off[k], sy->row_ptr, w->rp);
+        const int pad = row_off[k + 1] - row_off[k] - n;
+        if (pad > 0)
+            hipLaunchKernelGGL(k_fill_rp, dim3(ceil_div(pad, 256)), dim3(256), 0, s, pad,
+                               (int32_t)nnz_off[k + 1], w->rp + row_off[k] + n + 1);
+        hipLaunchKernelGGL(k_cat_cols, dim3(ceil_div(sy->nnz, 256)), dim3(256), 0, s, sy->nnz, row_off[k],
+                           sy->col, sy->K, sy->Ms, w->col + nnz_off[k], w->K64 + nnz_off[k],
+                           w->M64 + nnz_off[k], w->K32 + nnz_off[k], w->M32 + nnz_off[k]);
+        PG_HIP(hipMemcpyAsync(w->Kd + row_off[k], sy->Kd, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+        PG_HIP(hipMemcpyAsync(w->Md + row_off[k], sy->Msd, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+        if (pad > 0) {
+            hipLaunchKernelGGL(k_fill_d, dim3(ceil_div(pad, 256)), dim3(256), 0, s, pad, 1.0, w->Kd + row_off[k] + n);
+            hipLaunchKernelGGL(k_fill_d, dim3(ceil_div(pad, 256)), dim3(256), 0, s, pad, 0.0, w->Md + row_off[k] + n);
+        }
+    }
+    PG_HIP(hipGetLastError());
+    PG_HIP(hipMemcpyAsync(w->wmu, wmu.data(), sizeof(double) * n_sys, hipMemcpyHostToDevice, s));
+    PG_HIP(hipMemcpyAsync(w->seg_tile, seg_tile.data(), sizeof(int) * (n_sys + 1), hipMemcpyHostToDevice, s));
+    PG_HIP(hipMemcpyAsync(w->tile_seg, tseg.data(), sizeof(int) * ntiles, hipMemcpyHostToDevice, s));
+    Op op;
+    op.n = (int)rows;
+    op.C = 1;
+    op.ntiles = ntiles;
+    op.nseg = n_sys;
+    op.tile_seg = w->tile_seg;
+    op.seg_tile = w->seg_tile;
+    op.rp = w->rp;
+    op.col = w->col;
+    op.K32 = w->K32;
+    op.M32 = w->M32;
+    op.K64 = w->K64;
+    op.M64 = w->M64;
+    op.Kd = w->Kd;
+    op.Md = w->Md;
+    op.wmu = w->wmu;
+    op.nrow_valid = (int)rows;
+    Timer t_rhs;
+    hipLaunchKernelGGL(k_fill_z, dim3(ceil_div(rows, 256)), dim3(256), 0, s, rows, w->B64);
+    hipLaunchKernelGGL(k_fill_z, dim3(ceil_div(rows, 256)), dim3(256), 0, s, rows, w->X64);
+    for (int k = 0; k < n_sys; ++k) PG_TRY(launch_rhs(systems[k], src[k], w->B64 + row_off[k], 1, s));
+    for (int k = 0; k < n_sys; ++k) {
+        int flag = 0;
+        PG_HIP(hipMemcpyAsync(&flag, systems[k]->dflag, sizeof(int), hipMemcpyDeviceToHost, s));
+        PG_HIP(hipStreamSynchronize(s));
+        if (flag) {
+            int zero = 0;
+            PG_HIP(hipMemcpy(systems[k]->dflag, &zero, sizeof(int), hipMemcpyHostToDevice));
+            set_error("source within 1e-9 h of a quadrature point of an element with dsigma != 0 (system " +
+                      std::to_string(k) + ")");
+            return PETGEM_SOURCE_SINGULAR;
+        }
+    }
+    const double trhs = t_rhs.ms();
+    std::vector<petgem_stats*> stv(n_sys, nullptr);
+    if (st)
+        for (int k = 0; k < n_sys; ++k) { stv[k] = st + k; st[k].t_rhs_ms = trhs; }
+    int rc = mrhs_solve(w, op, nnz, o, s, stv, false);
+    if (rc != PETGEM_OK && rc != PETGEM_NOT_CONVERGED && rc != PETGEM_NONFINITE) return rc;
+    for (int k = 0; k < n_sys; ++k)
+        PG_HIP(hipMemcpyAsync(sols[k]->x, w->X64 + row_off[k], sizeof(double2) * systems[k]->n_dof,
+                              hipMemcpyDeviceToDevice, s));
+    return rc;
 }
 
 }  // namespace petgem

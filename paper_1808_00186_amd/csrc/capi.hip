@@ -211,6 +211,10 @@ int petgem_solve(petgem_system* sys, const petgem_source* src, int32_t n_src, co
     if (!src || n_src <= 0 || !inout) { set_error("sources and a solution handle are required"); return PETGEM_INVALID_ARG; }
     petgem_opts o;
     if (opts) o = *opts; else petgem_default_opts(&o);
+    if (o.method == PETGEM_COCG && n_src > 256) {
+        set_error("COCG solves at most 256 sources per call");
+        return PETGEM_INVALID_ARG;
+    }
     if (o.restart < 1 || o.restart > kMaxRestart || o.max_iter < 1 || !(o.rtol > 0.0) ||
         (o.method != PETGEM_GMRES && o.method != PETGEM_COCG) ||
         (o.precision != PETGEM_FP64 && o.precision != PETGEM_MIXED)) {
@@ -348,6 +352,14 @@ int petgem_locate(const petgem_mesh* mesh, const double* pts, int32_t n_pts, dou
     return PETGEM_OK;
 }
 
+int petgem_tuning(const petgem_system* sys, int32_t* spmv_group, float* spmv_ms) {
+    PG_TRY(check_sys(sys));
+    if (spmv_group) *spmv_group = sys->spmv_tuned ? sys->spmv_group : 0;
+    if (spmv_ms)
+        for (int i = 0; i < 3; ++i) spmv_ms[i] = sys->spmv_tune_ms[i];
+    return PETGEM_OK;
+}
+
 double petgem_setup_seconds(const petgem_system* sys) { return sys ? sys->setup_seconds : -1.0; }
 
 int petgem_get_dof_edges(const petgem_system* sys, int32_t* edges) {
@@ -375,6 +387,7 @@ int petgem_spmv(petgem_system* sys, double freq, const void* x_dev, void* y_dev,
     if (!x_dev || !y_dev || !(freq > 0.0)) { set_error("spmv needs x, y and a positive frequency"); return PETGEM_INVALID_ARG; }
     hipStream_t s = static_cast<hipStream_t>(stream);
     PG_TRY(launch_freq_prep(sys, freq, s));
+    PG_TRY(tune_spmv(sys, s));
     // A x = Ahat (D x) with the solver's CSR kernel
     PG_TRY(launch_spmv_unscaled(sys, static_cast<const double2*>(x_dev), static_cast<double2*>(y_dev), s));
     return PETGEM_OK;

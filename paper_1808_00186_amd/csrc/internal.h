@@ -145,6 +145,8 @@ struct petgem_system {
     int* dflag = nullptr;                 // device error flags
     double2* tmp = nullptr;               // [n] scratch of petgem_spmv
     int spmv_group = 8;                   // lanes per CSR row (autotuned)
+    bool spmv_tuned = false;
+    float spmv_tune_ms[3] = {0.f, 0.f, 0.f};  // measured 4/8/16-lane SpMV times
     petgem::GmresWork gw;
     petgem::BlockWork* bw = nullptr;
     petgem::ReceiverCache rxc;
@@ -166,6 +168,7 @@ int launch_freq_prep(petgem_system* sys, double freq, hipStream_t s);
 int launch_rhs(petgem_system* sys, const petgem_source& src, double2* b, int b_stride,
                hipStream_t s);
 int launch_spmv_ahat(petgem_system* sys, const double2* x, double2* y, hipStream_t s);
+int tune_spmv(petgem_system* sys, hipStream_t s);
 int launch_spmv_unscaled(petgem_system* sys, const double2* x, double2* y, hipStream_t s);
 int launch_receivers(const petgem_solution* sol, int32_t n_rx, double2* E, double2* Es,
                      hipStream_t s);

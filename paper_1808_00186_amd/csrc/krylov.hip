@@ -18,8 +18,10 @@
 // once the estimate has converged, which lets a whole cycle be captured in a
 // HIP graph and replayed without host round trips; the host reads back one
 // small record per cycle, after the true residual has been recomputed.
+#include <array>
 #include <chrono>
 #include <cstddef>
+#include <utility>
 
 #include "device.h"
 #include "internal.h"
@@ -28,7 +30,7 @@ namespace petgem {
 
 namespace {
 
-constexpr int kDotMaxBlocks = 512;
+constexpr int kDotMaxBlocks = 1024;
 constexpr int kChunk = 16;        // coefficients accumulated per pass of k_mdot
 constexpr double kEta = 1e-2;     // re-orthogonalise when beta^2 <= eta |w|^2
 
@@ -105,15 +107,67 @@ k_mdot(int n, int j, const double2* __restrict__ V, size_t ldv, const double2* _
     }
 }
 
-// Fixed-order sum of the block partials of coefficients 0..kmax into coef[].
+// Same as k_mdot with the number of dot products fixed at compile time
+// (NK = j + 1, plus |w|^2): straight-line loads of all basis vectors of a row.
+template <int NK>
+__global__ void __launch_bounds__(256)
+k_mdot_t(int n, const double2* __restrict__ V, size_t ldv, const double2* __restrict__ w,
+         double2* __restrict__ partial, const GmresCtl* __restrict__ ctl, int flags) {
+    if (flags >= 1 && ctl->done) return;
+    if (flags == 2 && !ctl->reorth) return;
+    __shared__ double2 red[4][NK + 1];
+    const int nb = gridDim.x;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    double2 acc[NK];
+    double nrm = 0.0;
+#pragma unroll
+    for (int q = 0; q < NK; ++q) acc[q] = make_double2(0.0, 0.0);
+    for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += nb * 256) {
+        const double2 wi = w[i];
+        double2 v[NK];
+#pragma unroll
+        for (int q = 0; q < NK; ++q) v[q] = V[(size_t)q * ldv + i];
+#pragma unroll
+        for (int q = 0; q < NK; ++q) {
+            acc[q].x += v[q].x * wi.x + v[q].y * wi.y;
+            acc[q].y += v[q].x * wi.y - v[q].y * wi.x;
+        }
+        nrm += wi.x * wi.x + wi.y * wi.y;
+    }
+#pragma unroll
+    for (int q = 0; q < NK; ++q) {
+        const double rx = wave_sum(acc[q].x), ry = wave_sum(acc[q].y);
+        if (lane == 0) red[wave][q] = make_double2(rx, ry);
+    }
+    nrm = wave_sum(nrm);
+    if (lane == 0) red[wave][NK] = make_double2(nrm, 0.0);
+    __syncthreads();
+    for (int q = threadIdx.x; q <= NK; q += blockDim.x) {
+        double2 s = red[0][q];
+        s = cadd(s, red[1][q]);
+        s = cadd(s, red[2][q]);
+        s = cadd(s, red[3][q]);
+        partial[(size_t)q * nb + blockIdx.x] = s;
+    }
+}
+
+// Fixed-order sum of the block partials of coefficients 0..kmax into coef[]
+// (nb <= 1024: every lane issues its up to 16 loads before summing).
 __device__ void reduce_partials(int kmax, int nb, const double2* __restrict__ partial, double2* coef) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    for (int k = wave; k <= kmax; k += 4) {
+    const int nw = blockDim.x >> 6;
+    for (int k = wave; k <= kmax; k += nw) {
+        double2 p[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int b = lane + 64 * u;
+            p[u] = b < nb ? partial[(size_t)k * nb + b] : make_double2(0.0, 0.0);
+        }
         double sx = 0.0, sy = 0.0;
-        for (int b = lane; b < nb; b += 64) {
-            double2 p = partial[(size_t)k * nb + b];
-            sx += p.x;
-            sy += p.y;
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            sx += p[u].x;
+            sy += p[u].y;
         }
         sx = wave_sum(sx);
         sy = wave_sum(sy);
@@ -124,63 +178,79 @@ __device__ void reduce_partials(int kmax, int nb, const double2* __restrict__ pa
 
 __device__ __forceinline__ double2& Hij(GmresCtl* c, int i, int j) { return c->H[j * (kMaxRestart + 1) + i]; }
 
-// One workgroup: finish the Gram-Schmidt pass of Arnoldi step j.
-__global__ void __launch_bounds__(256)
+// One workgroup: finish the Gram-Schmidt pass of Arnoldi step j. The
+// Hessenberg column, the previous rotations and g are staged in LDS so that
+// the sequential Givens recurrence runs on LDS, not on global memory.
+__global__ void __launch_bounds__(1024)
 k_fin(int j, int nb, const double2* __restrict__ partial, GmresCtl* __restrict__ ctl, int pass) {
     if (ctl->done) return;
     if (pass == 1 && !ctl->reorth) return;
     __shared__ double2 coef[kMaxRestart + 2];
-    reduce_partials(j + 1, nb, partial, coef);
-    if (threadIdx.x != 0) return;
+    __shared__ double2 col[kMaxRestart + 2];
+    __shared__ double2 rc[kMaxRestart], rs[kMaxRestart];
+    __shared__ int accept;
     GmresCtl* c = ctl;
-    const double nrm2 = coef[j + 1].x;
-    double hh = 0.0;
-    for (int k = 0; k <= j; ++k) {
-        c->h[k] = coef[k];
-        hh += cabs2(coef[k]);
-        if (pass == 0) Hij(c, k, j) = coef[k];
-        else Hij(c, k, j) = cadd(Hij(c, k, j), coef[k]);
+    reduce_partials(j + 1, nb, partial, coef);   // ends with __syncthreads
+    const int t = threadIdx.x;
+    if (t <= j) {
+        col[t] = pass == 0 ? coef[t] : cadd(Hij(c, t, j), coef[t]);
+        c->h[t] = coef[t];
     }
-    if (!isfinite(nrm2) || !isfinite(hh)) {
-        c->nonfinite = 1;
-        c->done = 1;
-        return;
+    if (t < j) {
+        rc[t] = c->cs[t];
+        rs[t] = c->sn[t];
     }
-    double beta2 = nrm2 - hh;
-    if (pass == 0 && beta2 <= kEta * nrm2) {   // cancellation: second pass
-        c->reorth = 1;
-        c->scale = 1.0;
-        return;
+    __syncthreads();
+    if (t == 0) {
+        accept = 0;
+        const double nrm2 = coef[j + 1].x;
+        double hh = 0.0;
+        for (int k = 0; k <= j; ++k) hh += cabs2(coef[k]);
+        if (!isfinite(nrm2) || !isfinite(hh)) {
+            c->nonfinite = 1;
+            c->done = 1;
+        } else if (pass == 0 && nrm2 - hh <= kEta * nrm2) {   // cancellation: second pass
+            c->reorth = 1;
+            c->scale = 1.0;
+            accept = 2;   // store the unrotated column for the second pass
+        } else {
+            const double beta2 = nrm2 - hh;
+            c->reorth = pass;   // pass 1 keeps the flag so that its update runs
+            const double beta = beta2 > 0.0 ? sqrt(beta2) : 0.0;
+            c->scale = beta > 0.0 ? 1.0 / beta : 0.0;
+            // previous rotations [[conj(c), conj(s)], [-s, c]] on rows (i, i+1)
+            for (int i = 0; i < j; ++i) {
+                const double2 a = col[i], b = col[i + 1];
+                col[i] = cadd(cmulc(rc[i], a), cmulc(rs[i], b));
+                col[i + 1] = csub(cmul(rc[i], b), cmul(rs[i], a));
+            }
+            const double2 a = col[j];
+            const double den = sqrt(cabs2(a) + beta * beta);
+            double2 cs, sn;
+            if (den > 0.0) {
+                cs = cscale(a, 1.0 / den);
+                sn = make_double2(beta / den, 0.0);
+            } else {
+                cs = make_double2(1.0, 0.0);
+                sn = make_double2(0.0, 0.0);
+            }
+            c->cs[j] = cs;
+            c->sn[j] = sn;
+            col[j] = make_double2(den, 0.0);
+            col[j + 1] = make_double2(0.0, 0.0);
+            const double2 gj = c->g[j];
+            const double2 g1 = cscale(cmul(sn, gj), -1.0);
+            c->g[j + 1] = g1;
+            c->g[j] = cmulc(cs, gj);
+            c->mdone = j + 1;
+            if (sqrt(cabs2(g1)) <= c->tol_abs || beta <= 1e-300) c->done = 1;
+            accept = 1;
+        }
     }
-    c->reorth = pass;   // pass 1 keeps the flag so that its update runs
-    const double beta = beta2 > 0.0 ? sqrt(beta2) : 0.0;
-    c->scale = beta > 0.0 ? 1.0 / beta : 0.0;
-    // apply the previous rotations, [[conj(c), conj(s)], [-s, c]] on rows (i, i+1)
-    for (int i = 0; i < j; ++i) {
-        double2 a = Hij(c, i, j), b = Hij(c, i + 1, j);
-        Hij(c, i, j) = cadd(cmulc(c->cs[i], a), cmulc(c->sn[i], b));
-        Hij(c, i + 1, j) = csub(cmul(c->cs[i], b), cmul(c->sn[i], a));
+    __syncthreads();
+    if (accept && t <= j + 1) {
+        if (accept == 1 || t <= j) Hij(c, t, j) = col[t];
     }
-    double2 a = Hij(c, j, j);
-    double den = sqrt(cabs2(a) + beta * beta);
-    double2 cs, sn;
-    if (den > 0.0) {
-        cs = cscale(a, 1.0 / den);
-        sn = make_double2(beta / den, 0.0);
-    } else {
-        cs = make_double2(1.0, 0.0);
-        sn = make_double2(0.0, 0.0);
-    }
-    c->cs[j] = cs;
-    c->sn[j] = sn;
-    Hij(c, j, j) = make_double2(den, 0.0);
-    Hij(c, j + 1, j) = make_double2(0.0, 0.0);
-    double2 gj = c->g[j];
-    c->g[j + 1] = cscale(cmul(sn, gj), -1.0);
-    c->g[j] = cmulc(cs, gj);
-    c->mdone = j + 1;
-    const double est = sqrt(cabs2(c->g[j + 1]));
-    if (est <= c->tol_abs || beta <= 1e-300) c->done = 1;
 }
 
 // v_{j+1} = (w - sum_k h_k v_k) * scale, in place in slot j+1.
@@ -201,14 +271,27 @@ k_update(int n, int j, double2* __restrict__ V, size_t ldv, const GmresCtl* __re
     V[(size_t)(j + 1) * ldv + i] = make_double2(w.x * s, w.y * s);
 }
 
-// Back substitution R y = g over the completed steps (one thread).
-__global__ void k_trisolve(GmresCtl* __restrict__ c) {
+// Back substitution R y = g over the completed steps; R and g are staged in
+// LDS by the whole workgroup, the recurrence runs on one thread.
+__global__ void __launch_bounds__(256) k_trisolve(GmresCtl* __restrict__ c) {
+    __shared__ double2 R[kMaxRestart * kMaxRestart];
+    __shared__ double2 y[kMaxRestart];
     const int m = c->mdone;
-    for (int i = m - 1; i >= 0; --i) {
-        double2 s = c->g[i];
-        for (int k = i + 1; k < m; ++k) s = csub(s, cmul(Hij(c, i, k), c->y[k]));
-        c->y[i] = cdiv(s, Hij(c, i, i));
+    for (int e = threadIdx.x; e < m * m; e += blockDim.x) {
+        const int i = e % m, k = e / m;
+        if (i <= k) R[k * kMaxRestart + i] = Hij(c, i, k);
     }
+    if ((int)threadIdx.x < m) y[threadIdx.x] = c->g[threadIdx.x];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = m - 1; i >= 0; --i) {
+            double2 s = y[i];
+            for (int k = i + 1; k < m; ++k) s = csub(s, cmul(R[k * kMaxRestart + i], y[k]));
+            y[i] = cdiv(s, R[i * kMaxRestart + i]);
+        }
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < m) c->y[threadIdx.x] = y[threadIdx.x];
 }
 
 // u += sum_{k < mdone} y_k v_k
@@ -230,7 +313,7 @@ struct CycleTail {   // mirrored to the host once per cycle
     int nonfinite;
 };
 
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(1024)
 k_cycle_start(int nb, const double2* __restrict__ partial, GmresCtl* __restrict__ c,
               CycleTail* __restrict__ tail) {
     __shared__ double2 coef[2];
@@ -290,6 +373,23 @@ void GmresWork::release() {
 }
 
 namespace {
+
+template <int... I>
+constexpr auto mdot_table(std::integer_sequence<int, I...>) {
+    using Fn = void (*)(int, const double2*, size_t, const double2*, double2*, const GmresCtl*, int);
+    return std::array<Fn, sizeof...(I)>{&k_mdot_t<I + 1>...};
+}
+constexpr int kMdotT = 32;
+const auto kMdotFns = mdot_table(std::make_integer_sequence<int, kMdotT>{});
+
+// Dots of w with v_0..v_j (and |w|^2) into `partial`; j = -1 gives |w|^2 only.
+void mdot_launch(int j, int nb, int n, const double2* V, size_t ldv, const double2* w,
+                 double2* partial, const GmresCtl* ctl, int flags, hipStream_t s) {
+    if (j >= 0 && j < kMdotT)
+        hipLaunchKernelGGL(kMdotFns[j], dim3(nb), dim3(256), 0, s, n, V, ldv, w, partial, ctl, flags);
+    else
+        hipLaunchKernelGGL(k_mdot, dim3(nb), dim3(256), 0, s, n, j, V, ldv, w, partial, ctl, flags);
+}
 
 template <bool RES>
 void spmv_launch(int G, int n, const int32_t* rp, const int32_t* col, const double2* val,
@@ -358,6 +458,44 @@ struct SpmvTimer {
 
 }  // namespace
 
+// Autotuner of the double-precision CSR SpMV: times the 4-, 8- and 16-lane
+// row groups on this system's operator (5 launches each, HIP events on the
+// caller's stream) and keeps the fastest. The choice is made once per system,
+// so every solve on a system uses one summation order (bitwise reproducible
+// within the system's lifetime).
+int tune_spmv(petgem_system* sys, hipStream_t s) {
+    if (sys->spmv_tuned) return PETGEM_OK;
+    const int n = sys->n_dof;
+    double2 *x = nullptr, *y = nullptr;
+    PG_TRY(dalloc(&x, (size_t)n));
+    PG_TRY(dalloc(&y, (size_t)n));
+    hipLaunchKernelGGL(k_fill0, dim3(ceil_div(n, 256)), dim3(256), 0, s, n, x);
+    hipEvent_t e0, e1;
+    PG_HIP(hipEventCreate(&e0));
+    PG_HIP(hipEventCreate(&e1));
+    float best = 1e30f;
+    int bestG = 8;
+    for (int G : {4, 8, 16}) {
+        spmv_launch<false>(G, n, sys->row_ptr, sys->col, sys->Ahat, x, nullptr, y, nullptr, s);  // warm
+        PG_HIP(hipEventRecord(e0, s));
+        for (int r = 0; r < 5; ++r)
+            spmv_launch<false>(G, n, sys->row_ptr, sys->col, sys->Ahat, x, nullptr, y, nullptr, s);
+        PG_HIP(hipEventRecord(e1, s));
+        PG_HIP(hipEventSynchronize(e1));
+        float ms = 0.f;
+        PG_HIP(hipEventElapsedTime(&ms, e0, e1));
+        sys->spmv_tune_ms[G == 4 ? 0 : (G == 8 ? 1 : 2)] = ms / 5.0f;
+        if (ms < best) { best = ms; bestG = G; }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    dfree(x);
+    dfree(y);
+    sys->spmv_group = bestG;
+    sys->spmv_tuned = true;
+    return PETGEM_OK;
+}
+
 int launch_spmv_ahat(petgem_system* sys, const double2* x, double2* y, hipStream_t s) {
     spmv_launch<false>(sys->spmv_group, sys->n_dof, sys->row_ptr, sys->col, sys->Ahat, x, nullptr, y,
                        nullptr, s);
@@ -378,6 +516,7 @@ int gmres_solve(petgem_system* sys, const petgem_source& src, const petgem_opts&
     const int m = o.restart;
     Timer t_all;
     PG_TRY(launch_freq_prep(sys, src.freq_hz, s));
+    PG_TRY(tune_spmv(sys, s));
     PG_TRY(ensure_gmres_work(sys, m));
     GmresWork& w = sys->gw;
     const int G = sys->spmv_group;
@@ -398,9 +537,8 @@ int gmres_solve(petgem_system* sys, const petgem_source& src, const petgem_opts&
         prof.start(s);
         spmv_launch<true>(G, n, sys->row_ptr, sys->col, sys->Ahat, w.u, w.b, w.V, nullptr, s);
         prof.stop(s);
-        hipLaunchKernelGGL(k_mdot, dim3(w.nb_dot), dim3(256), 0, s, n, -1, w.V, ldv, w.V,
-                           reinterpret_cast<double2*>(w.partial), w.ctl, 0);
-        hipLaunchKernelGGL(k_cycle_start, dim3(1), dim3(256), 0, s, w.nb_dot,
+        mdot_launch(-1, w.nb_dot, n, w.V, ldv, w.V, reinterpret_cast<double2*>(w.partial), w.ctl, 0, s);
+        hipLaunchKernelGGL(k_cycle_start, dim3(1), dim3(1024), 0, s, w.nb_dot,
                            reinterpret_cast<const double2*>(w.partial), w.ctl, tail_d);
         hipLaunchKernelGGL(k_scale_v0, dim3(nbv), dim3(256), 0, s, n, w.V, w.ctl);
         PG_HIP(hipGetLastError());
@@ -419,14 +557,14 @@ int gmres_solve(petgem_system* sys, const petgem_source& src, const petgem_opts&
             prof.start(s);
             spmv_launch<false>(G, n, sys->row_ptr, sys->col, sys->Ahat, vj, nullptr, vj1, &w.ctl->done, s);
             prof.stop(s);
-            hipLaunchKernelGGL(k_mdot, dim3(w.nb_dot), dim3(256), 0, s, n, j, w.V, ldv, vj1, part, w.ctl, 1);
-            hipLaunchKernelGGL(k_fin, dim3(1), dim3(256), 0, s, j, w.nb_dot, part, w.ctl, 0);
+            mdot_launch(j, w.nb_dot, n, w.V, ldv, vj1, part, w.ctl, 1, s);
+            hipLaunchKernelGGL(k_fin, dim3(1), dim3(1024), 0, s, j, w.nb_dot, part, w.ctl, 0);
             hipLaunchKernelGGL(k_update, dim3(nbv), dim3(256), 0, s, n, j, w.V, ldv, w.ctl, 0);
-            hipLaunchKernelGGL(k_mdot, dim3(w.nb_dot), dim3(256), 0, s, n, j, w.V, ldv, vj1, part, w.ctl, 2);
-            hipLaunchKernelGGL(k_fin, dim3(1), dim3(256), 0, s, j, w.nb_dot, part, w.ctl, 1);
+            mdot_launch(j, w.nb_dot, n, w.V, ldv, vj1, part, w.ctl, 2, s);
+            hipLaunchKernelGGL(k_fin, dim3(1), dim3(1024), 0, s, j, w.nb_dot, part, w.ctl, 1);
             hipLaunchKernelGGL(k_update, dim3(nbv), dim3(256), 0, s, n, j, w.V, ldv, w.ctl, 1);
         }
-        hipLaunchKernelGGL(k_trisolve, dim3(1), dim3(1), 0, s, w.ctl);
+        hipLaunchKernelGGL(k_trisolve, dim3(1), dim3(256), 0, s, w.ctl);
         hipLaunchKernelGGL(k_xupdate, dim3(nbv), dim3(256), 0, s, n, w.V, ldv, w.u, w.ctl);
         PG_HIP(hipGetLastError());
         return residual();

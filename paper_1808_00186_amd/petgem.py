@@ -86,6 +86,7 @@ _SIGS = {
                                  C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_void_p]),
     "petgem_spmv": (C.c_int, [C.c_void_p, C.c_double, C.c_void_p, C.c_void_p, C.c_void_p]),
     "petgem_setup_seconds": (C.c_double, [C.c_void_p]),
+    "petgem_tuning": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_float)]),
     "petgem_mesh_pattern": (C.c_int, [C.POINTER(Mesh), C.POINTER(C.c_int32), C.POINTER(C.c_int64),
                                       C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                       C.POINTER(C.c_int32)]),
@@ -260,6 +261,12 @@ class System:
         y = torch.empty_like(x)
         _check(lib().petgem_spmv(self.handle, freq, _ptr(x), _ptr(y), _stream(stream)))
         return y
+
+    def tuning(self) -> dict:
+        g = C.c_int32()
+        ms = (C.c_float * 3)()
+        _check(lib().petgem_tuning(self.handle, C.byref(g), ms))
+        return {"spmv_group": g.value, "spmv_ms_g4_g8_g16": [round(v, 5) for v in ms]}
 
     def free(self):
         if self.handle:
