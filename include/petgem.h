@@ -93,6 +93,9 @@ typedef struct {
     double  inner_rtol;     /* MIXED: relative tolerance of each inner solve    */
     int32_t use_graph;      /* replay captured HIP graphs for the Krylov loop   */
     int32_t profile;        /* time the sparse-matrix kernels with HIP events   */
+    int32_t verbose;        /* print one progress line per refinement step or
+                               per 10 GMRES cycles to stderr                    */
+    int32_t pad;
 } petgem_opts;
 
 typedef struct {
@@ -110,7 +113,7 @@ typedef struct {
 } petgem_stats;
 
 /* Fill *opts with the defaults: GMRES, FP64, restart 30, max_iter 20000,
- * rtol 1e-8, inner_rtol 1e-4, use_graph 1, profile 0. */
+ * rtol 1e-8, inner_rtol 1e-4, use_graph 1, profile 0, verbose 0. */
 void petgem_default_opts(petgem_opts* opts);
 
 /* ---- assembly (Section 3, eq. 9; Section 4; Appendix B) -----------------

@@ -23,6 +23,8 @@
 // the inner solve runs on r64/|r64| in complex64 to inner_rtol, x64 += |r64| d.
 #include <algorithm>
 #include <chrono>
+#include <cmath>
+#include <cstdio>
 #include <map>
 #include <tuple>
 
@@ -49,7 +51,8 @@ struct ColState {
     double bnorm;      // |b|
     double rnorm64;    // true residual norm
     double tol_abs;    // rtol |b|
-    double inner_tol2; // inner_rtol^2
+    double inner_tol2; // squared inner tolerance of the current refinement step
+    double inner_rtol; // requested inner tolerance
     int active;        // inner iteration running
     int outer;         // not yet converged in double precision
     int breakdown;
@@ -89,7 +92,7 @@ k_spmm_c(Op op, const typename V2<T>::t* __restrict__ X, const typename V2<T>::t
     if constexpr (sizeof(T) == 4) { Kv = op.K32; Mv = op.M32; } else { Kv = op.K64; Mv = op.M64; }
     constexpr int RPB = 256 / LPR;
     __shared__ double2 red[RPB][LPR * CPL];
-    const int tile = blockIdx.x;
+    const int tile = xcd_block(blockIdx.x, gridDim.x);
     const int slot = threadIdx.x / LPR, l = threadIdx.x % LPR;
     const int C = op.C;
     const int seg = op.tile_seg ? op.tile_seg[tile] : 0;
@@ -109,15 +112,28 @@ k_spmm_c(Op op, const typename V2<T>::t* __restrict__ X, const typename V2<T>::t
 #pragma unroll
         for (int u = 0; u < CPL; ++u) { ak[u].x = ak[u].y = (T)0; am[u].x = am[u].y = (T)0; }
         const int32_t e = op.rp[i + 1];
-        for (int32_t k = op.rp[i]; k < e; ++k) {
-            const T kv = Kv[k], mv = Mv[k];
-            const T2* xr = X + (size_t)op.col[k] * C + l * CPL;
+        // 4 nonzeros in flight: indices and values first, then the gathers
+        for (int32_t k0 = op.rp[i]; k0 < e; k0 += 4) {
+            int32_t cj[4];
+            T kv[4], mv[4];
 #pragma unroll
-            for (int u = 0; u < CPL; ++u) {
-                if (l * CPL + u < C) {
-                    const T2 xv = xr[u];
-                    ak[u].x += kv * xv.x; ak[u].y += kv * xv.y;
-                    am[u].x += mv * xv.x; am[u].y += mv * xv.y;
+            for (int q = 0; q < 4; ++q) {
+                const bool ok = k0 + q < e;
+                cj[q] = ok ? op.col[k0 + q] : -1;
+                kv[q] = ok ? Kv[k0 + q] : (T)0;
+                mv[q] = ok ? Mv[k0 + q] : (T)0;
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                if (cj[q] < 0) continue;
+                const T2* xr = X + (size_t)cj[q] * C + l * CPL;
+#pragma unroll
+                for (int u = 0; u < CPL; ++u) {
+                    if (l * CPL + u < C) {
+                        const T2 xv = xr[u];
+                        ak[u].x += kv[q] * xv.x; ak[u].y += kv[q] * xv.y;
+                        am[u].x += mv[q] * xv.x; am[u].y += mv[q] * xv.y;
+                    }
                 }
             }
         }
@@ -144,12 +160,15 @@ k_spmm_c(Op op, const typename V2<T>::t* __restrict__ X, const typename V2<T>::t
     }
 #pragma unroll
     for (int u = 0; u < CPL; ++u) red[slot][l * CPL + u] = pacc[u];
-    __syncthreads();
-    for (int c = threadIdx.x; c < C && c < LPR * CPL; c += 256) {
-        double2 s = make_double2(0.0, 0.0);
-        for (int q = 0; q < RPB; ++q) s = cadd(s, red[q][c]);
-        partial[(size_t)tile * C + c] = s;
+    for (int w = RPB >> 1; w > 0; w >>= 1) {
+        __syncthreads();
+        if (slot < w)
+#pragma unroll
+            for (int u = 0; u < CPL; ++u)
+                red[slot][l * CPL + u] = cadd(red[slot][l * CPL + u], red[slot + w][l * CPL + u]);
     }
+    __syncthreads();
+    for (int c = threadIdx.x; c < C && c < LPR * CPL; c += 256) partial[(size_t)tile * C + c] = red[0][c];
 }
 
 // Nonzero-lane variant for few columns: G lanes share the nonzeros of a row,
@@ -162,31 +181,46 @@ k_spmm_n(Op op, const typename V2<T>::t* __restrict__ X, const typename V2<T>::t
     const T* __restrict__ Kv = nullptr;
     const T* __restrict__ Mv = nullptr;
     if constexpr (sizeof(T) == 4) { Kv = op.K32; Mv = op.M32; } else { Kv = op.K64; Mv = op.M64; }
-    constexpr int RPB = 256 / G;
+    constexpr int RPB = 256 / G;      // rows per block: kTR / RPB = G blocks per tile
     __shared__ double2 red[4][CM];
-    const int tile = blockIdx.x;
+    const int bid = xcd_block(blockIdx.x, gridDim.x);
+    const int tile = bid / G, pass = bid % G;
     const int slot = threadIdx.x / G, l = threadIdx.x % G;
     const int C = op.C;
     const int seg = op.tile_seg ? op.tile_seg[tile] : 0;
     double2 pacc[CM];
 #pragma unroll
     for (int u = 0; u < CM; ++u) pacc[u] = make_double2(0.0, 0.0);
-    for (int r0 = 0; r0 < kTR; r0 += RPB) {
-        const int i = tile * kTR + r0 + slot;
-        if (i >= op.nrow_valid) continue;   // whole G-lane group skips together
+    {
+        const int i = tile * kTR + pass * RPB + slot;
+        if (i < op.nrow_valid) {   // the whole G-lane group shares i
         T2 ak[CM], am[CM];
 #pragma unroll
         for (int u = 0; u < CM; ++u) { ak[u].x = ak[u].y = (T)0; am[u].x = am[u].y = (T)0; }
         const int32_t e = op.rp[i + 1];
-        for (int32_t k = op.rp[i] + l; k < e; k += G) {
-            const T kv = Kv[k], mv = Mv[k];
-            const T2* xr = X + (size_t)op.col[k] * C;
+        // 4 nonzeros per lane in flight: all index and value loads first
+        for (int32_t k0 = op.rp[i] + l; k0 < e; k0 += 4 * G) {
+            int32_t cj[4];
+            T kv[4], mv[4];
 #pragma unroll
-            for (int u = 0; u < CM; ++u) {
-                if (u < C) {
-                    const T2 xv = xr[u];
-                    ak[u].x += kv * xv.x; ak[u].y += kv * xv.y;
-                    am[u].x += mv * xv.x; am[u].y += mv * xv.y;
+            for (int q = 0; q < 4; ++q) {
+                const int32_t k = k0 + q * G;
+                const bool ok = k < e;
+                cj[q] = ok ? op.col[k] : -1;
+                kv[q] = ok ? Kv[k] : (T)0;
+                mv[q] = ok ? Mv[k] : (T)0;
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                if (cj[q] < 0) continue;
+                const T2* xr = X + (size_t)cj[q] * C;
+#pragma unroll
+                for (int u = 0; u < CM; ++u) {
+                    if (u < C) {
+                        const T2 xv = xr[u];
+                        ak[u].x += kv[q] * xv.x; ak[u].y += kv[q] * xv.y;
+                        am[u].x += mv[q] * xv.x; am[u].y += mv[q] * xv.y;
+                    }
                 }
             }
         }
@@ -220,6 +254,7 @@ k_spmm_n(Op op, const typename V2<T>::t* __restrict__ X, const typename V2<T>::t
                 Y[o] = y;
             }
         }
+        }
     }
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
 #pragma unroll
@@ -234,33 +269,55 @@ k_spmm_n(Op op, const typename V2<T>::t* __restrict__ X, const typename V2<T>::t
         s = cadd(s, red[1][u]);
         s = cadd(s, red[2][u]);
         s = cadd(s, red[3][u]);
-        partial[(size_t)tile * C + u] = s;
+        partial[(size_t)bid * C + u] = s;
     }
 }
 
 // ------------------------------------------------------------ reductions
 enum RedMode { RED_INIT = 0, RED_ALPHA = 1, RED_BETA = 2, RED_RES = 3 };
 
-// One block per (segment, column): fixed-order sum over the segment's tiles,
-// then the scalar recurrence of that column.
-__global__ void __launch_bounds__(256)
-k_reduce(Op op, const double2* __restrict__ p0, const double2* __restrict__ p1,
+// One block per (segment, column): fixed-order sum over the segment's tiles
+// (pp0 / pp1 partial slots per tile), then the scalar recurrence of that column.
+__global__ void __launch_bounds__(1024)
+k_reduce(Op op, const double2* __restrict__ p0, int pp0, const double2* __restrict__ p1, int pp1,
          ColState* __restrict__ st, int mode, int first) {
-    __shared__ double2 sa[256], sb[256];
+    __shared__ double2 sa[1024], sb[1024];
     const int sc = blockIdx.x;
     const int s = sc / op.C, c = sc % op.C;
     ColState& S = st[sc];
     if ((mode == RED_ALPHA || mode == RED_BETA) && !S.active) return;
     const int t0 = op.seg_tile[s], t1 = op.seg_tile[s + 1];
     double2 a = make_double2(0.0, 0.0), b = make_double2(0.0, 0.0);
-    for (int t = t0 + threadIdx.x; t < t1; t += 256) {
-        a = cadd(a, p0[(size_t)t * op.C + c]);
-        if (p1) b = cadd(b, p1[(size_t)t * op.C + c]);
+    {
+        const int e0 = t0 * pp0, e1 = t1 * pp0;
+        for (int e = e0 + threadIdx.x; e < e1; e += 1024 * 8) {
+            double2 v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int k = e + 1024 * u;
+                v[u] = k < e1 ? p0[(size_t)k * op.C + c] : make_double2(0.0, 0.0);
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) a = cadd(a, v[u]);
+        }
+    }
+    if (p1) {
+        const int e0 = t0 * pp1, e1 = t1 * pp1;
+        for (int e = e0 + threadIdx.x; e < e1; e += 1024 * 8) {
+            double2 v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int k = e + 1024 * u;
+                v[u] = k < e1 ? p1[(size_t)k * op.C + c] : make_double2(0.0, 0.0);
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) b = cadd(b, v[u]);
+        }
     }
     sa[threadIdx.x] = a;
     sb[threadIdx.x] = b;
     __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
+    for (int w = 512; w > 0; w >>= 1) {
         if ((int)threadIdx.x < w) {
             sa[threadIdx.x] = cadd(sa[threadIdx.x], sa[threadIdx.x + w]);
             sb[threadIdx.x] = cadd(sb[threadIdx.x], sb[threadIdx.x + w]);
@@ -304,7 +361,23 @@ k_reduce(Op op, const double2* __restrict__ p0, const double2* __restrict__ p1,
         if (first) S.bnorm = rn;
         S.scale = rn;
         S.outer = S.outer && !(rn <= S.tol_abs) && isfinite(rn);
+        // no need to solve the correction more accurately than the target asks:
+        // a factor 0.3 below rtol |b| / |r64| leaves a safety margin
+        const double need = rn > 0.0 ? 0.3 * S.tol_abs / rn : 1.0;
+        const double it = fmax(S.inner_rtol, fmin(need, 0.5));
+        S.inner_tol2 = it * it;
     }
+}
+
+// Fixed-shape tree sum over the nslot row slots of a CP-lane row layout in
+// LDS (a[slot * CP + c]); the result for column c ends in a[c].
+__device__ __forceinline__ void slot_tree(double2* a, int CP, int nslot) {
+    for (int w = nslot >> 1; w > 0; w >>= 1) {
+        __syncthreads();
+        const int slot = threadIdx.x / CP, c = threadIdx.x % CP;
+        if (slot < w) a[slot * CP + c] = cadd(a[slot * CP + c], a[(slot + w) * CP + c]);
+    }
+    __syncthreads();
 }
 
 // --------------------------------------------------------- vector updates
@@ -355,15 +428,11 @@ k_inner_init(Op op, int CP, const double2* __restrict__ R64, const ColState* __r
     }
     ra[threadIdx.x] = a;
     rb[threadIdx.x] = b;
-    __syncthreads();
+    slot_tree(ra, CP, RPB);
+    slot_tree(rb, CP, RPB);
     if ((int)threadIdx.x < C && (int)threadIdx.x < CP) {
-        double2 sa = make_double2(0.0, 0.0), sb = make_double2(0.0, 0.0);
-        for (int q = 0; q < RPB; ++q) {
-            sa = cadd(sa, ra[q * CP + threadIdx.x]);
-            sb = cadd(sb, rb[q * CP + threadIdx.x]);
-        }
-        p0[(size_t)tile * C + threadIdx.x] = sa;
-        p1[(size_t)tile * C + threadIdx.x] = sb;
+        p0[(size_t)tile * C + threadIdx.x] = ra[threadIdx.x];
+        p1[(size_t)tile * C + threadIdx.x] = rb[threadIdx.x];
     }
 }
 
@@ -403,15 +472,11 @@ k_update1(Op op, int CP, const ColState* __restrict__ st, float2* __restrict__ X
     }
     ra[threadIdx.x] = a;
     rb[threadIdx.x] = b;
-    __syncthreads();
+    slot_tree(ra, CP, RPB);
+    slot_tree(rb, CP, RPB);
     if ((int)threadIdx.x < C && (int)threadIdx.x < CP) {
-        double2 sa = make_double2(0.0, 0.0), sb = make_double2(0.0, 0.0);
-        for (int q = 0; q < RPB; ++q) {
-            sa = cadd(sa, ra[q * CP + threadIdx.x]);
-            sb = cadd(sb, rb[q * CP + threadIdx.x]);
-        }
-        p0[(size_t)tile * C + threadIdx.x] = sa;
-        p1[(size_t)tile * C + threadIdx.x] = sb;
+        p0[(size_t)tile * C + threadIdx.x] = ra[threadIdx.x];
+        p1[(size_t)tile * C + threadIdx.x] = rb[threadIdx.x];
     }
 }
 
@@ -462,7 +527,7 @@ k_ir_update(Op op, int CP, const ColState* __restrict__ st, const float2* __rest
 // partial[tile][c].x = sum_i |B_ic|^2
 __global__ void __launch_bounds__(256)
 k_norm2(Op op, int CP, const double2* __restrict__ B, double2* __restrict__ p0) {
-    __shared__ double ra[256];
+    __shared__ double2 ra[256];
     const int tile = blockIdx.x, C = op.C;
     const int c = threadIdx.x % CP, slot = threadIdx.x / CP, RPB = 256 / CP;
     double a = 0.0;
@@ -473,13 +538,9 @@ k_norm2(Op op, int CP, const double2* __restrict__ B, double2* __restrict__ p0) 
             const double2 b = B[(size_t)i * C + c];
             a += b.x * b.x + b.y * b.y;
         }
-    ra[threadIdx.x] = a;
-    __syncthreads();
-    if ((int)threadIdx.x < C && (int)threadIdx.x < CP) {
-        double sa = 0.0;
-        for (int q = 0; q < RPB; ++q) sa += ra[q * CP + threadIdx.x];
-        p0[(size_t)tile * C + threadIdx.x] = make_double2(sa, 0.0);
-    }
+    ra[threadIdx.x] = make_double2(a, 0.0);
+    slot_tree(ra, CP, RPB);
+    if ((int)threadIdx.x < C && (int)threadIdx.x < CP) p0[(size_t)tile * C + threadIdx.x] = ra[threadIdx.x];
 }
 
 __global__ void k_fill_f2(size_t n, float2* __restrict__ a) {
@@ -520,6 +581,7 @@ __global__ void k_init_state(ColState* st, int nsc, double rtol, double inner_rt
     S.rnorm64 = 0.0;
     S.tol_abs = 0.0;
     S.inner_tol2 = inner_rtol * inner_rtol;
+    S.inner_rtol = inner_rtol;
     S.active = 0;
     S.outer = 1;
     S.breakdown = 0;
@@ -627,7 +689,7 @@ void spmm_thunk(Op op, const void* X, const void* Bv, void* Y, double2* part, hi
         hipLaunchKernelGGL((k_spmm_c<T, A, B, EPI>), dim3(op.ntiles), dim3(256), 0, s, op,
                            (const T2*)X, (const T2*)Bv, (T2*)Y, part);
     else
-        hipLaunchKernelGGL((k_spmm_n<T, A, B, EPI>), dim3(op.ntiles), dim3(256), 0, s, op,
+        hipLaunchKernelGGL((k_spmm_n<T, A, B, EPI>), dim3(op.ntiles * A), dim3(256), 0, s, op,
                            (const T2*)X, (const T2*)Bv, (T2*)Y, part);
 }
 
@@ -696,7 +758,7 @@ int ensure_work(BlockWork*& w, size_t rows, int C, int nsc, int ntiles) {
     PG_TRY(dalloc(&w->R, e));
     PG_TRY(dalloc(&w->P, e));
     PG_TRY(dalloc(&w->Q, e));
-    PG_TRY(dalloc(&w->p0, (size_t)ntiles * C));
+    PG_TRY(dalloc(&w->p0, (size_t)ntiles * C * (C <= 4 ? 16 : 1)));   // nonzero-lane SpMM: G slots per tile
     PG_TRY(dalloc(&w->p1, (size_t)ntiles * C));
     PG_TRY(dalloc(&w->st, (size_t)nsc));
     PG_TRY(dalloc(&w->wmu, (size_t)nsc));
@@ -758,6 +820,7 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
     hipLaunchKernelGGL(k_fill_f2, dim3(ceil_div((size_t)op.n * C, 256)), dim3(256), 0, s,
                        (size_t)op.n * C, w->P);
     PG_TRY(tune_spmm(w, op, nnz, s, ch));
+    const int ppS = ch.kind == 1 ? ch.a : 1;   // SpMM partial slots per tile
     hipLaunchKernelGGL(k_init_state, dim3(ceil_div(nsc, 64)), dim3(64), 0, s, w->st, nsc, o.rtol,
                        o.inner_rtol);
     const bool prof = o.profile != 0;
@@ -770,10 +833,8 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
         evs.push_back(e);
     };
     auto residual = [&](int first) -> int {
-        ev();
         spmm_dispatch<double, 2>(ch, op, w->X64, w->B64, w->R64, w->p0, s);
-        ev();
-        hipLaunchKernelGGL(k_reduce, dim3(nsc), dim3(256), 0, s, op, w->p0, nullptr, w->st, (int)RED_RES, first);
+        hipLaunchKernelGGL(k_reduce, dim3(nsc), dim3(1024), 0, s, op, w->p0, ppS, nullptr, 1, w->st, (int)RED_RES, first);
         PG_HIP(hipGetLastError());
         return PETGEM_OK;
     };
@@ -785,7 +846,7 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
     // |b| of every (segment, column)
     auto bnorms = [&]() -> int {
         hipLaunchKernelGGL(k_norm2, dim3(op.ntiles), dim3(256), 0, s, op, CP, w->B64, w->p0);
-        hipLaunchKernelGGL(k_reduce, dim3(nsc), dim3(256), 0, s, op, w->p0, nullptr, w->st, (int)RED_RES, 1);
+        hipLaunchKernelGGL(k_reduce, dim3(nsc), dim3(1024), 0, s, op, w->p0, 1, nullptr, 1, w->st, (int)RED_RES, 1);
         PG_HIP(hipGetLastError());
         return PETGEM_OK;
     };
@@ -820,10 +881,10 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
         ev();
         spmm_dispatch<float, 1>(ch, op, w->P, nullptr, w->Q, w->p0, s);
         ev();
-        hipLaunchKernelGGL(k_reduce, dim3(nsc), dim3(256), 0, s, op, w->p0, nullptr, w->st, (int)RED_ALPHA, 0);
+        hipLaunchKernelGGL(k_reduce, dim3(nsc), dim3(1024), 0, s, op, w->p0, ppS, nullptr, 1, w->st, (int)RED_ALPHA, 0);
         hipLaunchKernelGGL(k_update1, dim3(op.ntiles), dim3(256), 0, s, op, CP, w->st, w->Xi, w->R, w->P,
                            w->Q, w->p0, w->p1);
-        hipLaunchKernelGGL(k_reduce, dim3(nsc), dim3(256), 0, s, op, w->p0, w->p1, w->st, (int)RED_BETA, 0);
+        hipLaunchKernelGGL(k_reduce, dim3(nsc), dim3(1024), 0, s, op, w->p0, 1, w->p1, 1, w->st, (int)RED_BETA, 0);
         hipLaunchKernelGGL(k_update2, dim3(op.ntiles), dim3(256), 0, s, op, CP, w->st, w->R, w->P);
     };
     const bool use_graph = o.use_graph && !prof;
@@ -887,7 +948,7 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
         // inner complex64 COCG on A d = r64 / |r64|
         hipLaunchKernelGGL(k_inner_init, dim3(op.ntiles), dim3(256), 0, s, op, CP, w->R64, w->st, w->Xi,
                            w->R, w->P, w->p0, w->p1);
-        hipLaunchKernelGGL(k_reduce, dim3(nsc), dim3(256), 0, s, op, w->p0, w->p1, w->st, (int)RED_INIT, 0);
+        hipLaunchKernelGGL(k_reduce, dim3(nsc), dim3(1024), 0, s, op, w->p0, 1, w->p1, 1, w->st, (int)RED_INIT, 0);
         int inner = 0;
         while (true) {
             if (use_graph) {
@@ -899,6 +960,14 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
             PG_TRY(read_state());
             int act = 0;
             for (int k = 0; k < nsc; ++k) act += w->st_h[k].active;
+            if (o.verbose && inner % 512 == 0) {
+                double worst = 0.0;
+                for (int k = 0; k < nsc; ++k)
+                    if (w->st_h[k].active) worst = std::max(worst, w->st_h[k].rn2);
+                fprintf(stderr, "[petgem]   inner %d: %d active, worst inner residual %.3e, %.0f ms\n", inner, act,
+                        std::sqrt(worst), t_all.ms());
+                fflush(stderr);
+            }
             if (act == 0 || total_inner + inner >= o.max_iter) break;
         }
         total_inner += inner;
@@ -906,6 +975,17 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
         PG_TRY(residual(0));
         PG_TRY(read_state());
         ++steps;
+        if (o.verbose) {
+            double worst = 0.0;
+            int left = 0;
+            for (int k = 0; k < nsc; ++k) {
+                if (w->st_h[k].bnorm > 0) worst = std::max(worst, w->st_h[k].rnorm64 / w->st_h[k].bnorm);
+                left += w->st_h[k].outer;
+            }
+            fprintf(stderr, "[petgem] COCG refinement step %d: %d inner iterations, worst true residual "
+                            "%.3e, %d of %d columns left, %.0f ms\n", steps, inner, worst, left, nsc, t_all.ms());
+            fflush(stderr);
+        }
     }
     double t_solve = t_all.ms();
     double spmv_ms = 0.0;

@@ -21,6 +21,7 @@
 #include <array>
 #include <chrono>
 #include <cstddef>
+#include <cstdio>
 #include <utility>
 
 #include "device.h"
@@ -47,11 +48,19 @@ k_spmv(int n, const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
     if (row >= n) return;
     double2 acc = make_double2(0.0, 0.0);
     const int32_t e = rp[row + 1];
-    for (int32_t k = rp[row] + lane; k < e; k += G) {
-        double2 a = val[k];
-        double2 v = x[col[k]];
-        acc.x += a.x * v.x - a.y * v.y;
-        acc.y += a.x * v.y + a.y * v.x;
+    // 2 nonzeros per lane in flight
+    for (int32_t k0 = rp[row] + lane; k0 < e; k0 += 2 * G) {
+        const int32_t k1 = k0 + G;
+        const int32_t c0 = col[k0];
+        const int32_t c1 = k1 < e ? col[k1] : -1;
+        const double2 a0 = val[k0];
+        const double2 a1 = k1 < e ? val[k1] : make_double2(0.0, 0.0);
+        const double2 v0 = x[c0];
+        const double2 v1 = c1 >= 0 ? x[c1] : make_double2(0.0, 0.0);
+        acc.x += a0.x * v0.x - a0.y * v0.y;
+        acc.y += a0.x * v0.y + a0.y * v0.x;
+        acc.x += a1.x * v1.x - a1.y * v1.y;
+        acc.y += a1.x * v1.y + a1.y * v1.x;
     }
 #pragma unroll
     for (int off = G / 2; off > 0; off >>= 1) {
@@ -658,6 +667,11 @@ int gmres_solve(petgem_system* sys, const petgem_source& src, const petgem_opts&
         iters += tail->last_m;
         ++cycles;
         rnorm = tail->rnorm;
+        if (o.verbose && cycles % 10 == 0) {
+            fprintf(stderr, "[petgem] GMRES cycle %d: %d iterations, true residual %.3e, %.0f ms\n", cycles,
+                    iters, rnorm / bnorm, t_all.ms());
+            fflush(stderr);
+        }
         if (tail->nonfinite) { status = PETGEM_NONFINITE; break; }
         if (tail->last_m == 0) { status = PETGEM_NOT_CONVERGED; break; }   // stagnation
     }

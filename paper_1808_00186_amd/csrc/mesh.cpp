@@ -215,13 +215,39 @@ int build_topology(int32_t n_nodes, int32_t n_tets, const double* xyz,
             for (int32_t e : m) bnd[e] = 1;
     }
 
-    // ---- interior DOF numbering (edge order: lower node, then upper) -------
-    topo.dof_of_edge.assign(E, -1);
-    for (int32_t e = 0; e < E; ++e)
-        if (!bnd[e]) {
-            topo.dof_of_edge[e] = int32_t(topo.edge_of_dof.size());
-            topo.edge_of_dof.push_back(e);
+    // ---- interior DOF numbering along a Morton (Z-order) curve of the edge
+    //      midpoints: consecutive rows are spatially compact, so a tile of rows
+    //      gathers a small neighbourhood of x and shares it in cache ----------
+    {
+        double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+        for (int64_t v = 0; v < N; ++v)
+            for (int k = 0; k < 3; ++k) {
+                lo[k] = std::min(lo[k], xyz[3 * v + k]);
+                hi[k] = std::max(hi[k], xyz[3 * v + k]);
+            }
+        std::vector<std::pair<uint64_t, int32_t>> key;
+        key.reserve(E);
+        for (int32_t e = 0; e < E; ++e) {
+            if (bnd[e]) continue;
+            uint64_t code = 0;
+            uint32_t q[3];
+            for (int k = 0; k < 3; ++k) {
+                const double m = 0.5 * (xyz[3 * int64_t(topo.edge_lo[e]) + k] + xyz[3 * int64_t(topo.edge_hi[e]) + k]);
+                const double t = hi[k] > lo[k] ? (m - lo[k]) / (hi[k] - lo[k]) : 0.0;
+                q[k] = uint32_t(std::min(std::max(t, 0.0), 1.0) * double((1u << 21) - 1));
+            }
+            for (int b = 20; b >= 0; --b)
+                for (int k = 0; k < 3; ++k) code = (code << 1) | ((q[k] >> b) & 1u);
+            key.emplace_back(code, e);
         }
+        std::sort(key.begin(), key.end());
+        topo.dof_of_edge.assign(E, -1);
+        topo.edge_of_dof.resize(key.size());
+        for (size_t r = 0; r < key.size(); ++r) {
+            topo.edge_of_dof[r] = key[r].second;
+            topo.dof_of_edge[key[r].second] = int32_t(r);
+        }
+    }
     const int32_t n = int32_t(topo.edge_of_dof.size());
     topo.n_dof = n;
     if (n == 0) {

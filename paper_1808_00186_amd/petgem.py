@@ -47,7 +47,8 @@ class Source(C.Structure):
 class Opts(C.Structure):
     _fields_ = [("method", C.c_int32), ("precision", C.c_int32), ("restart", C.c_int32),
                 ("max_iter", C.c_int32), ("rtol", C.c_double), ("inner_rtol", C.c_double),
-                ("use_graph", C.c_int32), ("profile", C.c_int32)]
+                ("use_graph", C.c_int32), ("profile", C.c_int32), ("verbose", C.c_int32),
+                ("pad", C.c_int32)]
 
 
 class Stats(C.Structure):
