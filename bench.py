@@ -22,6 +22,9 @@ Other workloads (`--workload`):
           stated subset of the columns.
   cfg4 -- 48 independent models of 1e4..2e6 tetrahedra, one source each, in
           one uneven batch vs plain GMRES one model at a time.
+  cfg5 -- the learned initial guess: a network trained on 2000 solves of
+          config-1-sized random reservoir models, zero vs learned guess on 200
+          held-out seeds (plain GMRES and mixed COCG).
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload cfg2]
 
@@ -290,12 +293,62 @@ def bench_cfg4(args, petgem, synth, torch):
     }
 
 
+def bench_cfg5(args, petgem, synth, torch):
+    """Learned initial guess: train on solves of config-1-sized random
+    reservoir models generated by the library itself, then compare the zero
+    and the learned guess on held-out seeds at a true residual of 1e-8."""
+    from paper_1808_00186_amd import learned
+    mesh = synth.kuhn_mesh(8, -1000.0, 1000.0, 1)
+    S = petgem.System.from_model(synth.config5_sample(10000, mesh))
+    o_plain = petgem.default_opts(rtol=1e-8)
+    o_mix = petgem.default_opts(rtol=1e-8, method=petgem.COCG, precision=petgem.MIXED,
+                                inner_rtol=args.inner_rtol)
+    g = learned.pilot_scale(S, range(10000, 10016), mesh, o_plain)
+    train_seeds = list(synth.CFG5_TRAIN_SEEDS)[: args.n_train]
+    data = learned.generate(S, train_seeds, mesh, g, o_plain, progress=250)
+    net = petgem.Net(batch_max=16, seed=0)
+    t0 = time.perf_counter()
+    losses = learned.train(net, data, epochs=args.epochs, batch=16, lr=2e-3, progress=5)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    test = list(synth.CFG5_TEST_SEEDS)[: args.n_test]
+    forms = {}
+    for name, o in (("plain_fp64_gmres", o_plain), ("mixed_cocg", o_mix)):
+        r = learned.evaluate(S, net, test, mesh, g, o)
+        forms[name] = {
+            "zero_guess": {"solves_per_s": len(test) / r.t_zero, "iters_mean": float(np.mean(r.iters_zero))},
+            "learned_guess": {"solves_per_s": len(test) / r.t_learned,
+                              "iters_mean": float(np.mean(r.iters_learned)),
+                              "fallbacks": int(np.sum(r.fallback)),
+                              "x0_rel_residual_median": float(np.median(r.x0_residual))},
+            "max_rx_diff_learned_vs_zero": r.max_rx_diff,
+        }
+    plain = forms["plain_fp64_gmres"]["zero_guess"]["solves_per_s"]
+    best_name, best = max(((f"{k}/{kk}", v[kk]["solves_per_s"]) for k, v in forms.items()
+                           for kk in ("zero_guess", "learned_guess")), key=lambda t: t[1])
+    return {
+        "metric": "receiver-field solves/s at 1e-6 rel err: plain FP64 vs batched/mixed/learned",
+        "value": best, "unit": "solves/s", "n_gpus": 1, "steps": len(test), "warmup": 0,
+        "ms_per_step": 1e3 / best, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16 network / c64-f64 solve", "data": "synthetic",
+        "config": {"workload": f"cfg5: config-1 mesh with random reservoirs; network trained on {len(train_seeds)} "
+                               f"library solves, tested on {len(test)} held-out seeds at residual 1e-8",
+                   "best_form": best_name, "g": g, "train_data_s": round(data.seconds, 2),
+                   "train_s": round(t_train, 2), "epochs": args.epochs,
+                   "loss_first_last": [losses[0], losses[-1]], "parallelism": "1 GPU"},
+        "forms": forms, "speedup_vs_plain": best / plain,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="cfg2", choices=["cfg2", "cfg3", "cfg4"])
+    ap.add_argument("--workload", default="cfg2", choices=["cfg2", "cfg3", "cfg4", "cfg5"])
+    ap.add_argument("--n-train", type=int, default=2000)
+    ap.add_argument("--n-test", type=int, default=200)
+    ap.add_argument("--epochs", type=int, default=30)
     ap.add_argument("--inner-rtol", type=float, default=1e-4)
     ap.add_argument("--max-iter", type=int, default=20000)
     ap.add_argument("--verbose", action="store_true")
@@ -311,7 +364,7 @@ def main():
     import torch
     from paper_1808_00186_amd import petgem, synth
     torch.cuda.set_device(0)
-    fn = {"cfg2": bench_cfg2, "cfg3": bench_cfg3, "cfg4": bench_cfg4}[args.workload]
+    fn = {"cfg2": bench_cfg2, "cfg3": bench_cfg3, "cfg4": bench_cfg4, "cfg5": bench_cfg5}[args.workload]
     line = fn(args, petgem, synth, torch)
     print(json.dumps(line), flush=True)
 

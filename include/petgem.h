@@ -110,6 +110,7 @@ typedef struct {
     double  spmv_ms;        /* profile: summed duration of sparse-matrix kernels */
     int32_t spmv_launches;  /* profile: number of such launches                  */
     int32_t pad;
+    double  b_norm;         /* |b|_2 of the source's right-hand side            */
 } petgem_stats;
 
 /* Fill *opts with the defaults: GMRES, FP64, restart 30, max_iter 20000,
@@ -147,8 +148,9 @@ int petgem_rhs(petgem_system* sys, const petgem_source* src, int32_t n_src,
  * Solves A(f_s) x_s = b_s for every source s (each at its own frequency) to
  * the true relative residual opts->rtol.
  *   x0_dev  optional device complex128 [n_src][n_dof] initial guess (NULL =
- *           zero). A guess that is non-finite or has |b - A x0| >= |b| is
- *           replaced by zero (stats->used_fallback = 1).
+ *           zero). Each guess is first scaled by the complex alpha that
+ *           minimises |b - alpha A x0|; a guess that is non-finite or still
+ *           has |b - A x0| >= |b| is replaced by zero (stats->used_fallback).
  *   *inout  NULL to allocate a new solution, or a solution from an earlier
  *           call on the same system with the same n_src, which is reused.
  *   stats   optional host [n_src].
@@ -216,6 +218,50 @@ int petgem_locate(const petgem_mesh* mesh, const double* pts, int32_t n_pts, dou
 int petgem_tuning(const petgem_system* sys, int32_t* spmv_group, float* spmv_ms);
 /* Seconds spent in the host preprocessing of the last petgem_assemble. */
 double petgem_setup_seconds(const petgem_system* sys);
+
+/* ---- learned initial guess (not in the paper) -------------------------------
+ * A small 3D U-Net on a 32^3 voxel grid covering the mesh's bounding box
+ * (cubic cells of side max extent / 32) predicts the secondary field at the
+ * voxel centres, scaled by 1 / (g |b|); it is interpolated trilinearly to the
+ * edge midpoints and projected on the edge tangents to give an initial guess.
+ * Input tensor X: bf16 [B][32^3][16] (z-major voxels, channels last):
+ * log10 sigma of the containing element, (x - x_s)/L, (y - y_s)/L,
+ * (z - z_s)/L with L = half the box side, log10 f, then zeros. Output tensor
+ * Y: float [B][32^3][16], channels 0..5 = Re Ex, Im Ex, Re Ey, Im Ey, Re Ez,
+ * Im Ez (scaled). Targets T: float [B][32^3][6]. Parameters: float, layer by
+ * layer W[27][Cin][Cout] (tap = 9 (dz+1) + 3 (dy+1) + (dx+1)) then b[Cout],
+ * for (Cin, Cout) = (16,16), (16,32), (32,64), (64,64), (96,32), (48,16),
+ * (16,16). Loss: mean squared error over the 6 used channels. */
+typedef struct petgem_net petgem_net;
+int petgem_net_create(int32_t batch_max, uint64_t seed, petgem_net** out);
+int64_t petgem_net_num_params(const petgem_net* net);
+int petgem_net_get_params(const petgem_net* net, float* host);
+int petgem_net_set_params(petgem_net* net, const float* host);
+/* y_dev = network(x_dev) for `batch` samples (device pointers). */
+int petgem_net_forward(petgem_net* net, const void* x_dev, int32_t batch, void* y_dev, void* stream);
+/* Loss and its gradient with respect to every parameter (host copy if
+ * grad_host is not NULL); the parameters are not changed. */
+int petgem_net_loss_grad(petgem_net* net, const void* x_dev, const void* t_dev, int32_t batch,
+                         void* stream, double* loss, float* grad_host);
+/* One Adam step (beta 0.9, 0.999, eps 1e-8) on the batch's loss. */
+int petgem_net_train_step(petgem_net* net, const void* x_dev, const void* t_dev, int32_t batch,
+                          float lr, void* stream, double* loss);
+/* Network inputs of `batch` (conductivity model, source) pairs on a system's
+ * mesh: sigma_dev device double [batch][n_tets], or NULL for the system's
+ * current conductivities; x_dev as X above. */
+int petgem_voxelize(petgem_system* sys, const double* sigma_dev, const petgem_source* src,
+                    int32_t batch, void* x_dev, void* stream);
+/* Training targets from a solution: E_s at the voxel centres divided by
+ * scale[k] (host double [n_src]), t_dev as T above. */
+int petgem_vox_targets(const petgem_solution* sol, const double* scale, void* t_dev, void* stream);
+/* Initial guess for petgem_solve: computes |b| of every source, runs the
+ * network on the system's current conductivities and writes x0_dev
+ * (complex128 [batch][n_dof]) = g |b| (predicted field at the edge
+ * midpoint . edge tangent). bnorm_out (host [batch], may be NULL) receives
+ * |b|. */
+int petgem_learned_x0(petgem_system* sys, petgem_net* net, const petgem_source* src, int32_t batch,
+                      double g, void* x0_dev, double* bnorm_out, void* stream);
+void petgem_net_free(petgem_net* net);
 
 void petgem_free_system(petgem_system* sys);
 void petgem_free_solution(petgem_solution* sol);

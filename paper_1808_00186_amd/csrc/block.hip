@@ -274,7 +274,7 @@ k_spmm_n(Op op, const typename V2<T>::t* __restrict__ X, const typename V2<T>::t
 }
 
 // ------------------------------------------------------------ reductions
-enum RedMode { RED_INIT = 0, RED_ALPHA = 1, RED_BETA = 2, RED_RES = 3 };
+enum RedMode { RED_INIT = 0, RED_ALPHA = 1, RED_BETA = 2, RED_RES = 3, RED_X0 = 4 };
 
 // One block per (segment, column): fixed-order sum over the segment's tiles
 // (pp0 / pp1 partial slots per tile), then the scalar recurrence of that column.
@@ -355,6 +355,9 @@ k_reduce(Op op, const double2* __restrict__ p0, int pp0, const double2* __restri
             S.beta = cdiv(a, S.rho);
             S.rho = a;
         }
+    } else if (mode == RED_X0) {       // a = w^H b, b.x = |w|^2 for w = A x0
+        S.alpha = (b.x > 0.0 && isfinite(b.x) && isfinite(a.x) && isfinite(a.y)) ? cscale(a, 1.0 / b.x)
+                                                                                : make_double2(0.0, 0.0);
     } else {                           // RED_RES: a.x = |b - A x|^2
         const double rn = sqrt(a.x);
         S.rnorm64 = rn;
@@ -541,6 +544,50 @@ k_norm2(Op op, int CP, const double2* __restrict__ B, double2* __restrict__ p0) 
     ra[threadIdx.x] = make_double2(a, 0.0);
     slot_tree(ra, CP, RPB);
     if ((int)threadIdx.x < C && (int)threadIdx.x < CP) p0[(size_t)tile * C + threadIdx.x] = ra[threadIdx.x];
+}
+
+// partials of w^H b and |w|^2 per (tile, column) for w = B - R (= A x)
+__global__ void __launch_bounds__(256)
+k_x0_dots(Op op, int CP, const double2* __restrict__ B, const double2* __restrict__ R, double2* __restrict__ p0,
+          double2* __restrict__ p1) {
+    __shared__ double2 ra[256], rb[256];
+    const int tile = blockIdx.x, C = op.C;
+    const int c = threadIdx.x % CP, slot = threadIdx.x / CP, RPB = 256 / CP;
+    double2 a = make_double2(0.0, 0.0), b2 = make_double2(0.0, 0.0);
+    if (c < C)
+        for (int r0 = 0; r0 < kTR; r0 += RPB) {
+            const int i = tile * kTR + r0 + slot;
+            if (i >= op.nrow_valid) break;
+            const size_t o = (size_t)i * C + c;
+            const double2 bb = B[o];
+            const double2 w = csub(bb, R[o]);
+            a = cadd(a, cmulc(w, bb));
+            b2.x += cabs2(w);
+        }
+    ra[threadIdx.x] = a;
+    rb[threadIdx.x] = b2;
+    slot_tree(ra, CP, RPB);
+    slot_tree(rb, CP, RPB);
+    if ((int)threadIdx.x < C && (int)threadIdx.x < CP) {
+        p0[(size_t)tile * C + threadIdx.x] = ra[threadIdx.x];
+        p1[(size_t)tile * C + threadIdx.x] = rb[threadIdx.x];
+    }
+}
+
+// X *= alpha per column
+__global__ void __launch_bounds__(256)
+k_scale_cols(Op op, int CP, const ColState* __restrict__ st, double2* __restrict__ X) {
+    const int tile = blockIdx.x, C = op.C;
+    const int c = threadIdx.x % CP, slot = threadIdx.x / CP, RPB = 256 / CP;
+    if (c >= C) return;
+    const int seg = op.tile_seg ? op.tile_seg[tile] : 0;
+    const double2 al = st[seg * C + c].alpha;
+    for (int r0 = 0; r0 < kTR; r0 += RPB) {
+        const int i = tile * kTR + r0 + slot;
+        if (i >= op.nrow_valid) break;
+        const size_t o = (size_t)i * C + c;
+        X[o] = cmul(al, X[o]);
+    }
 }
 
 __global__ void k_fill_f2(size_t n, float2* __restrict__ a) {
@@ -852,6 +899,14 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
     };
     PG_TRY(bnorms());
     hipLaunchKernelGGL(k_set_tol, dim3(ceil_div(nsc, 64)), dim3(64), 0, s, w->st, nsc, o.rtol);
+    if (have_x0) {
+        // scale every guess by the alpha minimising |b - alpha A x0|
+        PG_TRY(residual(0));
+        hipLaunchKernelGGL(k_x0_dots, dim3(op.ntiles), dim3(256), 0, s, op, CP, w->B64, w->R64, w->p0, w->p1);
+        hipLaunchKernelGGL(k_reduce, dim3(nsc), dim3(1024), 0, s, op, w->p0, 1, w->p1, 1, w->st, (int)RED_X0, 0);
+        hipLaunchKernelGGL(k_scale_cols, dim3(op.ntiles), dim3(256), 0, s, op, CP, w->st, w->X64);
+        PG_HIP(hipGetLastError());
+    }
     PG_TRY(residual(0));
     PG_TRY(read_state());
     std::vector<int> fallback(nsc, 0);
@@ -1008,6 +1063,7 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
         st->ir_steps = steps;
         st->used_fallback = fallback[k];
         st->rel_residual = S.bnorm > 0 ? S.rnorm64 / S.bnorm : 0.0;
+        st->b_norm = S.bnorm;
         st->x0_rel_residual = x0res[k];
         st->t_solve_ms = t_solve;
         st->spmv_ms = spmv_ms;

@@ -79,6 +79,7 @@ void release_system(petgem_system* sys) {
     dfree(sys->Kst); dfree(sys->Mst); dfree(sys->K); dfree(sys->Ms); dfree(sys->Kd); dfree(sys->Msd);
     dfree(sys->K32); dfree(sys->Ms32); dfree(sys->Ahat); dfree(sys->dvec); dfree(sys->dinv);
     dfree(sys->Rst); dfree(sys->dflag); dfree(sys->tmp);
+    dfree(sys->vox_tet); dfree(sys->vox_dof); dfree(sys->dof_mid); dfree(sys->dof_tan);
     sys->gw.release();
     release_block_work(sys->bw);
     sys->rxc.release();

@@ -144,6 +144,13 @@ struct petgem_system {
     double2* Rst = nullptr;               // [6][T]
     int* dflag = nullptr;                 // device error flags
     double2* tmp = nullptr;               // [n] scratch of petgem_spmv
+    // voxel grid of the learned initial guess (cached at first use)
+    int32_t* vox_tet = nullptr;           // [32^3] element containing each voxel centre
+    int32_t* vox_dof = nullptr;           // [32^3][6]
+    double* dof_mid = nullptr;            // [n][3] edge midpoints
+    double* dof_tan = nullptr;            // [n][3] unit tangents (lo -> hi)
+    double vox_lo[3] = {0.0, 0.0, 0.0};
+    double vox_h = 0.0, vox_L = 0.0;
     int spmv_group = 8;                   // lanes per CSR row (autotuned)
     bool spmv_tuned = false;
     float spmv_tune_ms[3] = {0.f, 0.f, 0.f};  // measured 4/8/16-lane SpMV times

@@ -368,6 +368,50 @@ __global__ void k_scale_in(int n, const double2* __restrict__ d, const double2* 
     if (i < n) u[i] = cmul(d[i], x[i]);
 }
 
+// Minimal-residual scaling of a supplied guess: partials of w^H b and |w|^2
+// for w = A x0 (fixed block split).
+__global__ void __launch_bounds__(256)
+k_dots_wb(int n, const double2* __restrict__ w, const double2* __restrict__ b, double2* __restrict__ partial) {
+    __shared__ double2 red[4][2];
+    const int nb = gridDim.x, wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    double2 wb = make_double2(0.0, 0.0);
+    double ww = 0.0;
+    for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += nb * 256) {
+        const double2 wi = w[i], bi = b[i];
+        wb = cadd(wb, cmulc(wi, bi));
+        ww += cabs2(wi);
+    }
+    wb.x = wave_sum(wb.x);
+    wb.y = wave_sum(wb.y);
+    ww = wave_sum(ww);
+    if (lane == 0) { red[wave][0] = wb; red[wave][1] = make_double2(ww, 0.0); }
+    __syncthreads();
+    if (threadIdx.x < 2) {
+        double2 t = red[0][threadIdx.x];
+        t = cadd(t, red[1][threadIdx.x]);
+        t = cadd(t, red[2][threadIdx.x]);
+        t = cadd(t, red[3][threadIdx.x]);
+        partial[(size_t)threadIdx.x * nb + blockIdx.x] = t;
+    }
+}
+
+// u *= alpha with alpha = (w^H b) / |w|^2 (0 when w vanishes or is not finite)
+__global__ void __launch_bounds__(1024) k_x0_alpha(int nb, const double2* __restrict__ partial, double2* __restrict__ alpha) {
+    __shared__ double2 coef[2];
+    reduce_partials(1, nb, partial, coef);
+    if (threadIdx.x != 0) return;
+    const double2 wb = coef[0];
+    const double ww = coef[1].x;
+    double2 a = make_double2(0.0, 0.0);
+    if (ww > 0.0 && isfinite(ww) && isfinite(wb.x) && isfinite(wb.y)) a = cscale(wb, 1.0 / ww);
+    *alpha = a;
+}
+
+__global__ void k_scale_by(int n, const double2* __restrict__ alpha, double2* __restrict__ u) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < n) u[i] = cmul(*alpha, u[i]);
+}
+
 }  // namespace
 
 void GmresWork::release() {
@@ -594,6 +638,7 @@ int gmres_solve(petgem_system* sys, const petgem_source& src, const petgem_opts&
     }
     const double bnorm = tail->rnorm;
     if (st) {
+        st->b_norm = bnorm;
         st->iters = 0;
         st->ir_steps = 0;
         st->used_fallback = 0;
@@ -613,6 +658,15 @@ int gmres_solve(petgem_system* sys, const petgem_source& src, const petgem_opts&
     double rnorm = bnorm;
     if (x0) {
         hipLaunchKernelGGL(k_scale_in, dim3(nbv), dim3(256), 0, s, n, sys->dvec, x0, w.u);
+        // scale the guess by the alpha minimising |b - alpha A x0| (w = A x0 in slot 1)
+        double2* wv = w.V + ldv;
+        double2* part = reinterpret_cast<double2*>(w.partial);
+        spmv_launch<false>(G, n, sys->row_ptr, sys->col, sys->Ahat, w.u, nullptr, wv, nullptr, s);
+        hipLaunchKernelGGL(k_dots_wb, dim3(w.nb_dot), dim3(256), 0, s, n, wv, w.b, part);
+        // one scalar in the slack after the partial sums and the cycle record
+        double2* alpha = reinterpret_cast<double2*>(w.partial) + (size_t)(m + 2) * w.nb_dot + 4;
+        hipLaunchKernelGGL(k_x0_alpha, dim3(1), dim3(1024), 0, s, w.nb_dot, part, alpha);
+        hipLaunchKernelGGL(k_scale_by, dim3(nbv), dim3(256), 0, s, n, alpha, w.u);
         PG_TRY(residual());
         PG_TRY(read_tail());
         const double r0 = tail->rnorm;

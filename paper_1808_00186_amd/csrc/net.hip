@@ -1,0 +1,898 @@
+// Learned initial guess for the Krylov solve (not in the paper): a small 3D
+// U-Net on a 32^3 voxel grid over the mesh's bounding box maps
+//   [log10 sigma, (x - x_s)/L, (y - y_s)/L, (z - z_s)/L, log10 f]
+// to the secondary field E_s (Re/Im of x, y, z) at the voxel centres, scaled by
+// 1 / (g |b|). The prediction is interpolated trilinearly to the edge
+// midpoints and projected on the edge tangents (a DOF is the tangential
+// component of E, Section 3) to give x0. The plain zero guess remains the
+// fallback (petgem_solve rejects an x0 with |b - A x0| >= |b|).
+//
+// Layers (channels-last NDHWC, BF16 activations, FP32 accumulation):
+//   c1 16->16 @32^3 relu | pool | c2 16->32 @16^3 relu | pool |
+//   c3 32->64 @8^3 relu | c4 64->64 @8^3 relu | up, concat c2 |
+//   c5 96->32 @16^3 relu | up, concat c1 | c6 48->16 @32^3 relu |
+//   c7 16->16 @32^3 (linear; channels 0..5 are the output)
+// Every convolution is 3x3x3, stride 1, zero padding 1, computed as an
+// implicit GEMM on v_mfma_f32_16x16x16_bf16: M = voxels, N = output channels,
+// K = 27 taps x input channels (each 16-wide K chunk is one tap and 16
+// channels, so every lane's 4 K values are 8 contiguous bytes). The backward
+// data pass is the same kernel with the taps mirrored and the channel roles
+// swapped; the backward weight pass is an MFMA reduction over voxels.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "device.h"
+#include "internal.h"
+
+namespace petgem {
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+using bf16 = uint16_t;
+
+constexpr int kSide = 32;
+constexpr int kVox = kSide * kSide * kSide;
+constexpr int kIn = 16, kOut = 16, kOutUsed = 6;
+
+namespace {
+
+__device__ __forceinline__ bf16 f2bf(float f) {
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x7fffffu)) return 0x7fc0;   // NaN
+    u += 0x7fffu + ((u >> 16) & 1u);                                        // round to nearest even
+    return (bf16)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(bf16 h) { return __uint_as_float((uint32_t)h << 16); }
+
+// ---------------------------------------------------------------- conv
+// out[v][co] = sum_tap sum_ci in[v + off(tap)][ci] W[tap][ci][co] (+ bias, relu)
+// in bf16 [B][D^3][CIN], wt bf16 [COUT][27*CIN] (K-contiguous per output
+// channel), out bf16 or f32 [B][D^3][COUT]. One wave: 16 voxels x COUT.
+template <int CIN, int COUT, bool RELU, bool OUTF32>
+__global__ void __launch_bounds__(256)
+k_conv(const bf16* __restrict__ in, const bf16* __restrict__ wt, const float* __restrict__ bias,
+       void* __restrict__ out, int nvox, int D) {
+    constexpr int NT = COUT / 16;
+    constexpr int K = 27 * CIN;
+    const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int m = l & 15, kq = l >> 4;
+    const long vbase = ((long)blockIdx.x * 4 + wave) * 16;
+    const int Vs = D * D * D;
+    const long v = vbase + m;
+    const bool vok = v < nvox;
+    const int b = vok ? (int)(v / Vs) : 0;
+    const int r = vok ? (int)(v % Vs) : 0;
+    const int z = r / (D * D), y = (r / D) % D, x = r % D;
+    f32x4 acc[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int tap = 0; tap < 27; ++tap) {
+        const int nz = z + tap / 9 - 1, ny = y + (tap / 3) % 3 - 1, nx = x + tap % 3 - 1;
+        const bool ok = vok && nz >= 0 && nz < D && ny >= 0 && ny < D && nx >= 0 && nx < D;
+        const bf16* src = in + ((long)b * Vs + ((long)nz * D + ny) * D + nx) * CIN + 4 * kq;
+#pragma unroll
+        for (int c0 = 0; c0 < CIN; c0 += 16) {
+            bf16x4 a = {0, 0, 0, 0};
+            if (ok) a = *reinterpret_cast<const bf16x4*>(src + c0);
+            const int kk = tap * CIN + c0 + 4 * kq;
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                const bf16x4 w = *reinterpret_cast<const bf16x4*>(wt + (long)(t * 16 + m) * K + kk);
+                acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, w, acc[t], 0, 0, 0);
+            }
+        }
+    }
+    // lane holds D[row 4 kq + j][col m] of every output tile
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        const int co = t * 16 + m;
+        const float bb = bias ? bias[co] : 0.f;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const long vo = vbase + 4 * kq + j;
+            if (vo >= nvox) continue;
+            float val = acc[t][j] + bb;
+            if (RELU) val = fmaxf(val, 0.f);
+            if (OUTF32) reinterpret_cast<float*>(out)[vo * COUT + co] = val;
+            else reinterpret_cast<bf16*>(out)[vo * COUT + co] = f2bf(val);
+        }
+    }
+}
+
+// Backward weights: partial[s][k][co] = sum over the voxels of split s of
+// in[v + off(tap)][ci] * dz[v][co], k = tap * CIN + ci. One wave per
+// (16-row K tile, 16-column output tile, voxel split); rows of A are input
+// channels, its K index runs over voxels.
+template <int CIN, int COUT>
+__global__ void __launch_bounds__(64)
+k_conv_bwdw(const bf16* __restrict__ in, const bf16* __restrict__ dz, float* __restrict__ partial,
+            int nvox, int D, int nsplit) {
+    constexpr int KT = 27 * CIN / 16, NT = COUT / 16;
+    const int l = threadIdx.x & 63, m = l & 15, kq = l >> 4;
+    const int bid = blockIdx.x;
+    const int s = bid % nsplit, nt = (bid / nsplit) % NT, kt = bid / (nsplit * NT);
+    const int tap = (kt * 16) / CIN, c0 = (kt * 16) % CIN;
+    const int dzo = tap / 9 - 1, dyo = (tap / 3) % 3 - 1, dxo = tap % 3 - 1;
+    const int Vs = D * D * D;
+    const long chunk = ((long)nvox + nsplit - 1) / nsplit;
+    const long v0 = (long)s * chunk, v1 = v0 + chunk < nvox ? v0 + chunk : nvox;
+    f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (long vb = v0; vb < v1; vb += 16) {
+        bf16x4 a = {0, 0, 0, 0}, w = {0, 0, 0, 0};
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const long v = vb + 4 * kq + j;
+            if (v >= v1) continue;
+            const int b = (int)(v / Vs), r = (int)(v % Vs);
+            const int z = r / (D * D) + dzo, y = (r / D) % D + dyo, x = r % D + dxo;
+            if (z >= 0 && z < D && y >= 0 && y < D && x >= 0 && x < D)
+                a[j] = (short)in[((long)b * Vs + ((long)z * D + y) * D + x) * CIN + c0 + m];
+            w[j] = (short)dz[v * COUT + nt * 16 + m];
+        }
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, w, acc, 0, 0, 0);
+    }
+    // D[row = ci (4 kq + j)][col = co m]
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int k = tap * CIN + c0 + 4 * kq + j;
+        partial[((long)s * 27 * CIN + k) * COUT + nt * 16 + m] = acc[j];
+    }
+}
+
+__global__ void k_sum_splits(const float* __restrict__ partial, int nsplit, int n, float* __restrict__ out) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    float s = 0.f;
+    for (int k = 0; k < nsplit; ++k) s += partial[(long)k * n + i];
+    out[i] = s;
+}
+
+// db partials: partial[blk][c] = sum over a block of voxels of dz[v][c]
+__global__ void __launch_bounds__(256)
+k_bias_grad(const bf16* __restrict__ dz, int nvox, int C, float* __restrict__ partial) {
+    __shared__ float red[256];
+    const int c = threadIdx.x % C, slot = threadIdx.x / C, nslot = 256 / C;
+    const long v0 = (long)blockIdx.x * 1024;
+    float s = 0.f;
+    for (long v = v0 + slot; v < v0 + 1024 && v < nvox; v += nslot) s += bf2f(dz[v * C + c]);
+    red[threadIdx.x] = s;
+    __syncthreads();
+    if ((int)threadIdx.x < C) {
+        float t = 0.f;
+        for (int q = 0; q < nslot; ++q) t += red[q * C + threadIdx.x];
+        partial[(long)blockIdx.x * C + threadIdx.x] = t;
+    }
+}
+
+// 2x2x2 average pooling (fine side D), channel stride/offset for concatenation
+__global__ void k_pool(const bf16* __restrict__ in, int ldi, int B, int D, int C, bf16* __restrict__ out, int ldo) {
+    const long e = (long)blockIdx.x * 256 + threadIdx.x;
+    const int Dc = D / 2;
+    const long n = (long)B * Dc * Dc * Dc * C;
+    if (e >= n) return;
+    const int c = (int)(e % C);
+    const long vc = e / C;
+    const int b = (int)(vc / (Dc * Dc * Dc)), r = (int)(vc % (Dc * Dc * Dc));
+    const int z = r / (Dc * Dc), y = (r / Dc) % Dc, x = r % Dc;
+    float s = 0.f;
+    for (int q = 0; q < 8; ++q) {
+        const long vf = (long)b * D * D * D + ((long)(2 * z + (q >> 2)) * D + 2 * y + ((q >> 1) & 1)) * D + 2 * x + (q & 1);
+        s += bf2f(in[vf * ldi + c]);
+    }
+    out[vc * ldo + c] = f2bf(0.125f * s);
+}
+
+// nearest upsampling x2 into channels [off, off+C) of a wider tensor, and a
+// channel copy (for the skip half of a concatenation)
+__global__ void k_up(const bf16* __restrict__ in, int B, int Dc, int C, bf16* __restrict__ out, int ldo, int off) {
+    const long e = (long)blockIdx.x * 256 + threadIdx.x;
+    const int D = 2 * Dc;
+    const long n = (long)B * D * D * D * C;
+    if (e >= n) return;
+    const int c = (int)(e % C);
+    const long vf = e / C;
+    const int b = (int)(vf / (D * D * D)), r = (int)(vf % (D * D * D));
+    const int z = r / (D * D), y = (r / D) % D, x = r % D;
+    const long vc = (long)b * Dc * Dc * Dc + ((long)(z / 2) * Dc + y / 2) * Dc + x / 2;
+    out[vf * ldo + off + c] = in[vc * C + c];
+}
+__global__ void k_copy_ch(const bf16* __restrict__ in, long nvox, int C, bf16* __restrict__ out, int ldo, int off) {
+    const long e = (long)blockIdx.x * 256 + threadIdx.x;
+    if (e >= nvox * C) return;
+    out[(e / C) * ldo + off + e % C] = in[e];
+}
+
+// Backward of "nearest up into [0, C) of dq": dcoarse = sum of the 8 children
+__global__ void k_up_bwd(const float* __restrict__ dq, int ldq, int B, int Dc, int C, float* __restrict__ dout) {
+    const long e = (long)blockIdx.x * 256 + threadIdx.x;
+    const long n = (long)B * Dc * Dc * Dc * C;
+    if (e >= n) return;
+    const int c = (int)(e % C);
+    const long vc = e / C;
+    const int D = 2 * Dc;
+    const int b = (int)(vc / (Dc * Dc * Dc)), r = (int)(vc % (Dc * Dc * Dc));
+    const int z = r / (Dc * Dc), y = (r / Dc) % Dc, x = r % Dc;
+    float s = 0.f;
+    for (int q = 0; q < 8; ++q) {
+        const long vf = (long)b * D * D * D + ((long)(2 * z + (q >> 2)) * D + 2 * y + ((q >> 1) & 1)) * D + 2 * x + (q & 1);
+        s += dq[vf * ldq + c];
+    }
+    dout[vc * C + c] = s;
+}
+
+// dA (fine, C channels) = dq[:, off:off+C] (skip half of a concatenation) +
+// pooling backward of dp (coarse): dp[parent] / 8
+__global__ void k_skip_pool_bwd(const float* __restrict__ dq, int ldq, int off, const float* __restrict__ dp,
+                                int B, int D, int C, float* __restrict__ da) {
+    const long e = (long)blockIdx.x * 256 + threadIdx.x;
+    const long n = (long)B * D * D * D * C;
+    if (e >= n) return;
+    const int c = (int)(e % C);
+    const long vf = e / C;
+    const int Dc = D / 2;
+    const int b = (int)(vf / (D * D * D)), r = (int)(vf % (D * D * D));
+    const int z = r / (D * D), y = (r / D) % D, x = r % D;
+    const long vc = (long)b * Dc * Dc * Dc + ((long)(z / 2) * Dc + y / 2) * Dc + x / 2;
+    da[e] = dq[vf * ldq + off + c] + 0.125f * dp[vc * C + c];
+}
+
+// dz = dy * (y > 0) as bf16 (ReLU backward; y is the stored activation)
+__global__ void k_relu_bwd(const float* __restrict__ dy, const bf16* __restrict__ y, long n, bf16* __restrict__ dz) {
+    const long e = (long)blockIdx.x * 256 + threadIdx.x;
+    if (e >= n) return;
+    dz[e] = f2bf(bf2f(y[e]) > 0.f ? dy[e] : 0.f);
+}
+
+// Mean squared error over the used output channels; dY = d loss / d Y (bf16)
+__global__ void __launch_bounds__(256)
+k_mse(const float* __restrict__ Y, const float* __restrict__ T, long nvox, double inv_count,
+      bf16* __restrict__ dY, double* __restrict__ partial) {
+    __shared__ double red[256];
+    const long v = (long)blockIdx.x * 256 + threadIdx.x;
+    double s = 0.0;
+    if (v < nvox) {
+        for (int c = 0; c < kOut; ++c) {
+            float g = 0.f;
+            if (c < kOutUsed) {
+                const float d = Y[v * kOut + c] - T[v * kOutUsed + c];
+                s += (double)d * d;
+                g = (float)(2.0 * inv_count) * d;
+            }
+            dY[v * kOut + c] = f2bf(g);
+        }
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+__global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
+                       float* __restrict__ v, long n, float lr, float b1, float b2, float c1, float c2, float eps) {
+    const long i = (long)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+// FP32 master W[tap][ci][co] -> bf16 forward layout wt[co][tap*CIN+ci] and
+// backward-data layout wtb[ci][tap'*COUT+co] with tap' = 26 - tap (mirrored).
+__global__ void k_cast_w(const float* __restrict__ W, int CIN, int COUT, bf16* __restrict__ wt, bf16* __restrict__ wtb) {
+    const long e = (long)blockIdx.x * 256 + threadIdx.x;
+    const long n = 27L * CIN * COUT;
+    if (e >= n) return;
+    const int co = (int)(e % COUT);
+    const int ci = (int)((e / COUT) % CIN);
+    const int tap = (int)(e / ((long)COUT * CIN));
+    const bf16 h = f2bf(W[e]);
+    wt[(long)co * 27 * CIN + tap * CIN + ci] = h;
+    wtb[(long)ci * 27 * COUT + (26 - tap) * COUT + co] = h;
+}
+
+// Network input channels at the voxel centres.
+struct VoxSrc {
+    double pos[3];
+    double logf;
+};
+__global__ void k_voxelize(const double* __restrict__ sigma, long ldsig, const int32_t* __restrict__ vtet,
+                           const VoxSrc* __restrict__ src, int B, double lo0, double lo1, double lo2,
+                           double hv, double L, bf16* __restrict__ X) {
+    const long e = (long)blockIdx.x * 256 + threadIdx.x;
+    if (e >= (long)B * kVox) return;
+    const int b = (int)(e / kVox), r = (int)(e % kVox);
+    const int z = r / (kSide * kSide), y = (r / kSide) % kSide, x = r % kSide;
+    const double cx = lo0 + (x + 0.5) * hv, cy = lo1 + (y + 0.5) * hv, cz = lo2 + (z + 0.5) * hv;
+    bf16* o = X + e * kIn;
+    o[0] = f2bf((float)log10(sigma[(long)b * ldsig + vtet[r]]));
+    o[1] = f2bf((float)((cx - src[b].pos[0]) / L));
+    o[2] = f2bf((float)((cy - src[b].pos[1]) / L));
+    o[3] = f2bf((float)((cz - src[b].pos[2]) / L));
+    o[4] = f2bf((float)src[b].logf);
+    for (int c = 5; c < kIn; ++c) o[c] = 0;
+}
+
+// E_s at the voxel centres from solution DOFs, scaled: T[b][v][6] (training targets)
+__global__ void k_vox_field(const double* __restrict__ xyz, const int4* __restrict__ tets,
+                            const int32_t* __restrict__ vtet, const int32_t* __restrict__ vdof,
+                            const double2* __restrict__ sol, int n_dof, int B, const double* __restrict__ scale,
+                            double lo0, double lo1, double lo2, double hv, float* __restrict__ T) {
+    const long e = (long)blockIdx.x * 256 + threadIdx.x;
+    if (e >= (long)B * kVox) return;
+    const int b = (int)(e / kVox), r = (int)(e % kVox);
+    const int z = r / (kSide * kSide), y = (r / kSide) % kSide, x = r % kSide;
+    const double p[3] = {lo0 + (x + 0.5) * hv, lo1 + (y + 0.5) * hv, lo2 + (z + 0.5) * hv};
+    TetGeom G;
+    tet_geometry(xyz, tets[vtet[r]], G);
+    double lam[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int v = 1; v < 4; ++v)
+        for (int k = 0; k < 3; ++k) lam[v] += G.g[v][k] * (p[k] - G.X[0][k]);
+    lam[0] = 1.0 - lam[1] - lam[2] - lam[3];
+    constexpr int E0[6] = {0, 0, 0, 1, 3, 2};
+    constexpr int E1[6] = {1, 2, 3, 2, 1, 3};
+    double2 es[3] = {make_double2(0, 0), make_double2(0, 0), make_double2(0, 0)};
+    for (int i = 0; i < 6; ++i) {
+        const int d = vdof[6 * r + i];
+        if (d < 0) continue;
+        const double2 val = sol[(long)b * n_dof + d];
+        for (int k = 0; k < 3; ++k) {
+            const double nk = G.sl[i] * (lam[E0[i]] * G.g[E1[i]][k] - lam[E1[i]] * G.g[E0[i]][k]);
+            es[k].x += nk * val.x;
+            es[k].y += nk * val.y;
+        }
+    }
+    const double s = 1.0 / scale[b];
+    float* o = T + e * kOutUsed;
+    for (int k = 0; k < 3; ++k) {
+        o[2 * k] = (float)(es[k].x * s);
+        o[2 * k + 1] = (float)(es[k].y * s);
+    }
+}
+
+// x0[b][d] = scale_b * (E(mid_d) . t_d) with E trilinear in the voxel-centre grid
+__global__ void k_grid_to_edges(const float* __restrict__ Y, int B, int n_dof, const double* __restrict__ mid,
+                                const double* __restrict__ tan, const double* __restrict__ scale, double lo0,
+                                double lo1, double lo2, double hv, double2* __restrict__ x0) {
+    const long e = (long)blockIdx.x * 256 + threadIdx.x;
+    if (e >= (long)B * n_dof) return;
+    const int b = (int)(e / n_dof), d = (int)(e % n_dof);
+    const double lo[3] = {lo0, lo1, lo2};
+    int i0[3];
+    double w[3];
+    for (int k = 0; k < 3; ++k) {
+        double u = (mid[3 * d + k] - lo[k]) / hv - 0.5;
+        u = fmin(fmax(u, 0.0), (double)(kSide - 1));
+        int i = (int)floor(u);
+        if (i > kSide - 2) i = kSide - 2;
+        i0[k] = i;
+        w[k] = u - i;
+    }
+    double f[6] = {0, 0, 0, 0, 0, 0};
+    for (int q = 0; q < 8; ++q) {
+        const int dx = q & 1, dy = (q >> 1) & 1, dz = (q >> 2) & 1;
+        const double wt = (dx ? w[0] : 1 - w[0]) * (dy ? w[1] : 1 - w[1]) * (dz ? w[2] : 1 - w[2]);
+        const long v = (long)b * kVox + ((long)(i0[2] + dz) * kSide + i0[1] + dy) * kSide + i0[0] + dx;
+        for (int c = 0; c < 6; ++c) f[c] += wt * Y[v * kOut + c];
+    }
+    const double s = scale[b];
+    const double tx = tan[3 * d], ty = tan[3 * d + 1], tz = tan[3 * d + 2];
+    x0[e] = make_double2(s * (f[0] * tx + f[2] * ty + f[4] * tz), s * (f[1] * tx + f[3] * ty + f[5] * tz));
+}
+
+__global__ void __launch_bounds__(256) k_vnorm(const double2* __restrict__ b, int n, double* __restrict__ out) {
+    __shared__ double red[256];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += 256) s += cabs2(b[i]);
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[blockIdx.x] = sqrt(red[0]);
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ host
+
+struct NetLayer {
+    int cin, cout, side;
+    bool relu;
+    size_t w_off, b_off;   // offsets into the parameter vector (floats)
+    bf16* wt = nullptr;    // forward layout
+    bf16* wtb = nullptr;   // backward-data layout
+};
+
+}  // namespace petgem
+
+struct petgem_net {
+    int batch_max = 0;
+    std::vector<petgem::NetLayer> L;
+    size_t nparam = 0;
+    float *P = nullptr, *Gr = nullptr, *M = nullptr, *Vv = nullptr;
+    int step = 0;
+    // activations (bf16) and gradients (f32) for batch_max samples
+    petgem::bf16 *X0 = nullptr, *A1 = nullptr, *P1 = nullptr, *A2 = nullptr, *P2 = nullptr, *A3 = nullptr,
+                 *A4 = nullptr, *Q2 = nullptr, *A5 = nullptr, *Q1 = nullptr, *A6 = nullptr, *dzb = nullptr;
+    float* Y = nullptr;
+    float *g0 = nullptr, *g1 = nullptr, *g2 = nullptr;   // f32 gradient scratch
+    float* wpart = nullptr;                              // backward-weight partials
+    double* lpart = nullptr;
+    float* T = nullptr;       // targets of the current batch (caller-owned copy not needed)
+    double* scal = nullptr;   // per-sample scales on device
+    petgem::VoxSrc* vsrc = nullptr;
+    double* lpart_h = nullptr;
+    double2* bbuf = nullptr;   // right-hand side scratch of petgem_learned_x0
+    size_t bcap = 0;
+    double* bn = nullptr;      // [batch_max] |b|
+};
+
+namespace petgem {
+
+namespace {
+
+constexpr int kSplits = 64;
+
+size_t wpart_floats(int cin, int cout) { return (size_t)kSplits * 27 * cin * cout; }
+
+template <int CIN, int COUT, bool RELU, bool OUTF32>
+void conv_t(const bf16* in, const bf16* wt, const float* bias, void* out, int nvox, int D, hipStream_t s) {
+    hipLaunchKernelGGL((k_conv<CIN, COUT, RELU, OUTF32>), dim3(ceil_div(nvox, 64)), dim3(256), 0, s, in, wt,
+                       bias, out, nvox, D);
+}
+
+// forward/backward-data convolution dispatch on the (CIN, COUT) pairs used
+int conv(int cin, int cout, bool relu, bool outf32, const bf16* in, const bf16* wt, const float* bias, void* out,
+         int nvox, int D, hipStream_t s) {
+#define PG_CV(A, B)                                                                         \
+    if (cin == A && cout == B) {                                                            \
+        if (outf32) conv_t<A, B, false, true>(in, wt, bias, out, nvox, D, s);               \
+        else if (relu) conv_t<A, B, true, false>(in, wt, bias, out, nvox, D, s);            \
+        else conv_t<A, B, false, false>(in, wt, bias, out, nvox, D, s);                     \
+        return PETGEM_OK;                                                                   \
+    }
+    PG_CV(16, 16) PG_CV(16, 32) PG_CV(32, 16) PG_CV(32, 64) PG_CV(64, 32) PG_CV(64, 64)
+    PG_CV(96, 32) PG_CV(32, 96) PG_CV(48, 16) PG_CV(16, 48)
+#undef PG_CV
+    set_error("unsupported convolution shape");
+    return PETGEM_INVALID_ARG;
+}
+
+int conv_bwdw(int cin, int cout, const bf16* in, const bf16* dz, float* part, int nvox, int D, hipStream_t s) {
+    const int nb = (27 * cin / 16) * (cout / 16) * kSplits;
+#define PG_BW(A, B)                                                                                       \
+    if (cin == A && cout == B) {                                                                          \
+        hipLaunchKernelGGL((k_conv_bwdw<A, B>), dim3(nb), dim3(64), 0, s, in, dz, part, nvox, D, kSplits); \
+        return PETGEM_OK;                                                                                 \
+    }
+    PG_BW(16, 16) PG_BW(16, 32) PG_BW(32, 64) PG_BW(64, 64) PG_BW(96, 32) PG_BW(48, 16)
+#undef PG_BW
+    set_error("unsupported convolution shape");
+    return PETGEM_INVALID_ARG;
+}
+
+inline dim3 g1(long n) { return dim3((unsigned)((n + 255) / 256)); }
+
+// SplitMix64 + Box-Muller: seeded, platform-independent initial weights
+struct Rng {
+    uint64_t s;
+    uint64_t next() {
+        uint64_t z = (s += 0x9e3779b97f4a7c15ull);
+        z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+        z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+        return z ^ (z >> 31);
+    }
+    double uniform() { return ((next() >> 11) + 0.5) * (1.0 / 9007199254740992.0); }
+    double normal() {
+        const double u = uniform(), v = uniform();
+        return std::sqrt(-2.0 * std::log(u)) * std::cos(2.0 * kPi * v);
+    }
+};
+
+void release_net(petgem_net* n) {
+    for (auto& l : n->L) { dfree(l.wt); dfree(l.wtb); }
+    dfree(n->P); dfree(n->Gr); dfree(n->M); dfree(n->Vv);
+    dfree(n->X0); dfree(n->A1); dfree(n->P1); dfree(n->A2); dfree(n->P2); dfree(n->A3); dfree(n->A4);
+    dfree(n->Q2); dfree(n->A5); dfree(n->Q1); dfree(n->A6); dfree(n->dzb); dfree(n->Y);
+    dfree(n->g0); dfree(n->g1); dfree(n->g2); dfree(n->wpart); dfree(n->lpart); dfree(n->T);
+    dfree(n->scal); dfree(n->vsrc); dfree(n->bbuf); dfree(n->bn);
+    if (n->lpart_h) (void)hipHostFree(n->lpart_h);
+    n->lpart_h = nullptr;
+}
+
+int cast_weights(petgem_net* n, hipStream_t s) {
+    for (auto& l : n->L)
+        hipLaunchKernelGGL(k_cast_w, g1(27L * l.cin * l.cout), dim3(256), 0, s, n->P + l.w_off, l.cin, l.cout, l.wt,
+                           l.wtb);
+    PG_HIP(hipGetLastError());
+    return PETGEM_OK;
+}
+
+// Forward pass on X0 (already filled) for B samples; output Y f32 [B][32^3][16].
+int forward(petgem_net* n, int B, hipStream_t s) {
+    const int v32 = B * kVox, v16 = B * kVox / 8, v8 = B * kVox / 64;
+    auto& L = n->L;
+    PG_TRY(conv(16, 16, true, false, n->X0, L[0].wt, n->P + L[0].b_off, n->A1, v32, 32, s));
+    hipLaunchKernelGGL(k_pool, g1((long)v16 * 16), dim3(256), 0, s, n->A1, 16, B, 32, 16, n->P1, 16);
+    PG_TRY(conv(16, 32, true, false, n->P1, L[1].wt, n->P + L[1].b_off, n->A2, v16, 16, s));
+    hipLaunchKernelGGL(k_pool, g1((long)v8 * 32), dim3(256), 0, s, n->A2, 32, B, 16, 32, n->P2, 32);
+    PG_TRY(conv(32, 64, true, false, n->P2, L[2].wt, n->P + L[2].b_off, n->A3, v8, 8, s));
+    PG_TRY(conv(64, 64, true, false, n->A3, L[3].wt, n->P + L[3].b_off, n->A4, v8, 8, s));
+    hipLaunchKernelGGL(k_up, g1((long)v16 * 64), dim3(256), 0, s, n->A4, B, 8, 64, n->Q2, 96, 0);
+    hipLaunchKernelGGL(k_copy_ch, g1((long)v16 * 32), dim3(256), 0, s, n->A2, (long)v16, 32, n->Q2, 96, 64);
+    PG_TRY(conv(96, 32, true, false, n->Q2, L[4].wt, n->P + L[4].b_off, n->A5, v16, 16, s));
+    hipLaunchKernelGGL(k_up, g1((long)v32 * 32), dim3(256), 0, s, n->A5, B, 16, 32, n->Q1, 48, 0);
+    hipLaunchKernelGGL(k_copy_ch, g1((long)v32 * 16), dim3(256), 0, s, n->A1, (long)v32, 16, n->Q1, 48, 32);
+    PG_TRY(conv(48, 16, true, false, n->Q1, L[5].wt, n->P + L[5].b_off, n->A6, v32, 32, s));
+    PG_TRY(conv(16, 16, false, true, n->A6, L[6].wt, n->P + L[6].b_off, n->Y, v32, 32, s));
+    PG_HIP(hipGetLastError());
+    return PETGEM_OK;
+}
+
+// weight and bias gradients of layer li from its input `in` and dz (bf16)
+int layer_grads(petgem_net* n, int li, const bf16* in, const bf16* dz, int nvox, int D, hipStream_t s) {
+    const NetLayer& l = n->L[li];
+    PG_TRY(conv_bwdw(l.cin, l.cout, in, dz, n->wpart, nvox, D, s));
+    const int nw = 27 * l.cin * l.cout;
+    hipLaunchKernelGGL(k_sum_splits, g1(nw), dim3(256), 0, s, n->wpart, kSplits, nw, n->Gr + l.w_off);
+    const int nbb = ceil_div(nvox, 1024);
+    hipLaunchKernelGGL(k_bias_grad, dim3(nbb), dim3(256), 0, s, dz, nvox, l.cout, n->wpart);
+    hipLaunchKernelGGL(k_sum_splits, g1(l.cout), dim3(256), 0, s, n->wpart, nbb, l.cout, n->Gr + l.b_off);
+    PG_HIP(hipGetLastError());
+    return PETGEM_OK;
+}
+
+// Backward pass from dY (bf16 in n->dzb, layout [B][32^3][16]); fills n->Gr.
+int backward(petgem_net* n, int B, hipStream_t s) {
+    const int v32 = B * kVox, v16 = B * kVox / 8, v8 = B * kVox / 64;
+    auto& L = n->L;
+    bf16* dz = n->dzb;
+    float *g0 = n->g0, *g1b = n->g1, *g2 = n->g2;
+    // c7 (linear): dz = dY
+    PG_TRY(layer_grads(n, 6, n->A6, dz, v32, 32, s));
+    PG_TRY(conv(16, 16, false, true, dz, L[6].wtb, nullptr, g0, v32, 32, s));                  // dA6
+    hipLaunchKernelGGL(k_relu_bwd, g1((long)v32 * 16), dim3(256), 0, s, g0, n->A6, (long)v32 * 16, dz);
+    // c6
+    PG_TRY(layer_grads(n, 5, n->Q1, dz, v32, 32, s));
+    PG_TRY(conv(16, 48, false, true, dz, L[5].wtb, nullptr, g0, v32, 32, s));                  // dQ1 [v32][48]
+    hipLaunchKernelGGL(k_up_bwd, g1((long)v16 * 32), dim3(256), 0, s, g0, 48, B, 16, 32, g1b);  // dA5 [v16][32]
+    // keep dQ1's skip half for dA1: g0 stays alive until c2's backward
+    hipLaunchKernelGGL(k_relu_bwd, g1((long)v16 * 32), dim3(256), 0, s, g1b, n->A5, (long)v16 * 32, dz);
+    // c5
+    PG_TRY(layer_grads(n, 4, n->Q2, dz, v16, 16, s));
+    PG_TRY(conv(32, 96, false, true, dz, L[4].wtb, nullptr, g1b, v16, 16, s));                 // dQ2 [v16][96]
+    hipLaunchKernelGGL(k_up_bwd, g1((long)v8 * 64), dim3(256), 0, s, g1b, 96, B, 8, 64, g2);   // dA4 [v8][64]
+    hipLaunchKernelGGL(k_relu_bwd, g1((long)v8 * 64), dim3(256), 0, s, g2, n->A4, (long)v8 * 64, dz);
+    // c4
+    PG_TRY(layer_grads(n, 3, n->A3, dz, v8, 8, s));
+    PG_TRY(conv(64, 64, false, true, dz, L[3].wtb, nullptr, g2, v8, 8, s));                    // dA3
+    hipLaunchKernelGGL(k_relu_bwd, g1((long)v8 * 64), dim3(256), 0, s, g2, n->A3, (long)v8 * 64, dz);
+    // c3
+    PG_TRY(layer_grads(n, 2, n->P2, dz, v8, 8, s));
+    float* dP2 = g2;   // [v8][32]
+    PG_TRY(conv(64, 32, false, true, dz, L[2].wtb, nullptr, dP2, v8, 8, s));
+    // dA2 = skip half of dQ2 (channels 64..95) + pool backward of dP2; written after g1b's
+    // dQ2 is consumed, into a separate region of g2 (dP2 occupies its first v8*32 floats)
+    float* dA2 = g2 + (size_t)v8 * 32;
+    hipLaunchKernelGGL(k_skip_pool_bwd, g1((long)v16 * 32), dim3(256), 0, s, g1b, 96, 64, dP2, B, 16, 32, dA2);
+    hipLaunchKernelGGL(k_relu_bwd, g1((long)v16 * 32), dim3(256), 0, s, dA2, n->A2, (long)v16 * 32, dz);
+    // c2
+    PG_TRY(layer_grads(n, 1, n->P1, dz, v16, 16, s));
+    float* dP1 = g1b;  // [v16][16]
+    PG_TRY(conv(32, 16, false, true, dz, L[1].wtb, nullptr, dP1, v16, 16, s));
+    float* dA1 = g2;   // [v32][16]
+    hipLaunchKernelGGL(k_skip_pool_bwd, g1((long)v32 * 16), dim3(256), 0, s, g0, 48, 32, dP1, B, 32, 16, dA1);
+    hipLaunchKernelGGL(k_relu_bwd, g1((long)v32 * 16), dim3(256), 0, s, dA1, n->A1, (long)v32 * 16, dz);
+    // c1
+    PG_TRY(layer_grads(n, 0, n->X0, dz, v32, 32, s));
+    PG_HIP(hipGetLastError());
+    return PETGEM_OK;
+}
+
+int loss_and_grads(petgem_net* n, const float* T, int B, hipStream_t s, double* loss) {
+    PG_TRY(forward(n, B, s));
+    const long nv = (long)B * kVox;
+    const int nb = (int)((nv + 255) / 256);
+    hipLaunchKernelGGL(k_mse, dim3(nb), dim3(256), 0, s, n->Y, T, nv, 1.0 / ((double)nv * kOutUsed), n->dzb, n->lpart);
+    PG_TRY(backward(n, B, s));
+    PG_HIP(hipMemcpyAsync(n->lpart_h, n->lpart, sizeof(double) * nb, hipMemcpyDeviceToHost, s));
+    PG_HIP(hipStreamSynchronize(s));
+    double sum = 0.0;
+    for (int i = 0; i < nb; ++i) sum += n->lpart_h[i];
+    if (loss) *loss = sum / ((double)nv * kOutUsed);
+    return PETGEM_OK;
+}
+
+// Voxel -> element map and voxel DOFs of a system (host location, cached)
+int ensure_vox(petgem_system* sys) {
+    if (sys->vox_tet) return PETGEM_OK;
+    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+    for (int32_t v = 0; v < sys->n_nodes; ++v)
+        for (int k = 0; k < 3; ++k) {
+            lo[k] = std::min(lo[k], sys->xyz_h[3 * (size_t)v + k]);
+            hi[k] = std::max(hi[k], sys->xyz_h[3 * (size_t)v + k]);
+        }
+    const double side = std::max(hi[0] - lo[0], std::max(hi[1] - lo[1], hi[2] - lo[2]));
+    for (int k = 0; k < 3; ++k) sys->vox_lo[k] = lo[k];
+    sys->vox_h = side / kSide;
+    sys->vox_L = 0.5 * side;
+    std::vector<double> pts(3 * (size_t)kVox);
+    for (int r = 0; r < kVox; ++r) {
+        const int z = r / (kSide * kSide), y = (r / kSide) % kSide, x = r % kSide;
+        pts[3 * r] = lo[0] + (x + 0.5) * sys->vox_h;
+        pts[3 * r + 1] = lo[1] + (y + 0.5) * sys->vox_h;
+        pts[3 * r + 2] = lo[2] + (z + 0.5) * sys->vox_h;
+    }
+    std::vector<int32_t> tet(kVox);
+    locate_points(sys->n_tets, sys->xyz_h.data(), sys->tets_h.data(), pts.data(), kVox, 1e-12, tet.data());
+    std::vector<int32_t> dof(6 * (size_t)kVox);
+    for (int r = 0; r < kVox; ++r) {
+        if (tet[r] < 0) {
+            set_error("a voxel centre lies outside the mesh (the grid covers the bounding box)");
+            return PETGEM_RECEIVER_OUTSIDE;
+        }
+        for (int i = 0; i < 6; ++i) dof[6 * r + i] = sys->elem_dof_h[6 * (size_t)tet[r] + i];
+    }
+    // DOF midpoints and unit tangents for the grid -> edge interpolation
+    const int n = sys->n_dof;
+    std::vector<double> mid(3 * (size_t)n), tan(3 * (size_t)n);
+    for (int d = 0; d < n; ++d) {
+        const double* a = &sys->xyz_h[3 * (size_t)sys->dof_nodes_h[2 * d]];
+        const double* b = &sys->xyz_h[3 * (size_t)sys->dof_nodes_h[2 * d + 1]];
+        double t[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]};
+        const double ln = std::sqrt(t[0] * t[0] + t[1] * t[1] + t[2] * t[2]);
+        for (int k = 0; k < 3; ++k) {
+            mid[3 * d + k] = 0.5 * (a[k] + b[k]);
+            tan[3 * d + k] = t[k] / ln;
+        }
+    }
+    PG_TRY(dalloc(&sys->vox_tet, (size_t)kVox));
+    PG_TRY(dalloc(&sys->vox_dof, 6 * (size_t)kVox));
+    PG_TRY(dalloc(&sys->dof_mid, 3 * (size_t)n));
+    PG_TRY(dalloc(&sys->dof_tan, 3 * (size_t)n));
+    PG_HIP(hipMemcpy(sys->vox_tet, tet.data(), sizeof(int32_t) * kVox, hipMemcpyHostToDevice));
+    PG_HIP(hipMemcpy(sys->vox_dof, dof.data(), sizeof(int32_t) * 6 * kVox, hipMemcpyHostToDevice));
+    PG_HIP(hipMemcpy(sys->dof_mid, mid.data(), sizeof(double) * 3 * n, hipMemcpyHostToDevice));
+    PG_HIP(hipMemcpy(sys->dof_tan, tan.data(), sizeof(double) * 3 * n, hipMemcpyHostToDevice));
+    return PETGEM_OK;
+}
+
+int upload_vsrc(petgem_net* n, const petgem_source* src, int B, hipStream_t s) {
+    std::vector<VoxSrc> v(B);
+    for (int b = 0; b < B; ++b) {
+        for (int k = 0; k < 3; ++k) v[b].pos[k] = src[b].pos[k];
+        v[b].logf = std::log10(src[b].freq_hz);
+    }
+    PG_HIP(hipMemcpyAsync(n->vsrc, v.data(), sizeof(VoxSrc) * B, hipMemcpyHostToDevice, s));
+    PG_HIP(hipStreamSynchronize(s));
+    return PETGEM_OK;
+}
+
+}  // namespace
+
+}  // namespace petgem
+
+using namespace petgem;
+
+extern "C" {
+
+int petgem_net_create(int32_t batch_max, uint64_t seed, petgem_net** out) {
+    if (!out || batch_max <= 0 || batch_max > 256) {
+        set_error("net: 1 <= batch_max <= 256 and an output handle are required");
+        return PETGEM_INVALID_ARG;
+    }
+    *out = nullptr;
+    petgem_net* n = new (std::nothrow) petgem_net();
+    if (!n) { set_error("host allocation failed"); return PETGEM_OUT_OF_MEMORY; }
+    n->batch_max = batch_max;
+    const int spec[7][4] = {{16, 16, 32, 1}, {16, 32, 16, 1}, {32, 64, 8, 1}, {64, 64, 8, 1},
+                            {96, 32, 16, 1}, {48, 16, 32, 1}, {16, 16, 32, 0}};
+    size_t off = 0;
+    for (auto& sp : spec) {
+        NetLayer l;
+        l.cin = sp[0]; l.cout = sp[1]; l.side = sp[2]; l.relu = sp[3] != 0;
+        l.w_off = off;
+        off += 27 * (size_t)l.cin * l.cout;
+        l.b_off = off;
+        off += l.cout;
+        n->L.push_back(l);
+    }
+    n->nparam = off;
+    auto fail = [&](int rc) { release_net(n); delete n; return rc; };
+    int rc;
+    if ((rc = dalloc(&n->P, off)) || (rc = dalloc(&n->Gr, off)) || (rc = dalloc(&n->M, off)) ||
+        (rc = dalloc(&n->Vv, off)))
+        return fail(rc);
+    for (auto& l : n->L)
+        if ((rc = dalloc(&l.wt, 27 * (size_t)l.cin * l.cout)) || (rc = dalloc(&l.wtb, 27 * (size_t)l.cin * l.cout)))
+            return fail(rc);
+    const size_t v32 = (size_t)batch_max * kVox, v16 = v32 / 8, v8 = v32 / 64;
+    if ((rc = dalloc(&n->X0, v32 * 16)) || (rc = dalloc(&n->A1, v32 * 16)) || (rc = dalloc(&n->P1, v16 * 16)) ||
+        (rc = dalloc(&n->A2, v16 * 32)) || (rc = dalloc(&n->P2, v8 * 32)) || (rc = dalloc(&n->A3, v8 * 64)) ||
+        (rc = dalloc(&n->A4, v8 * 64)) || (rc = dalloc(&n->Q2, v16 * 96)) || (rc = dalloc(&n->A5, v16 * 32)) ||
+        (rc = dalloc(&n->Q1, v32 * 48)) || (rc = dalloc(&n->A6, v32 * 16)) || (rc = dalloc(&n->dzb, v32 * 48)) ||
+        (rc = dalloc(&n->Y, v32 * 16)) || (rc = dalloc(&n->g0, v32 * 48)) || (rc = dalloc(&n->g1, v16 * 96)) ||
+        (rc = dalloc(&n->g2, v32 * 16)) || (rc = dalloc(&n->T, v32 * kOutUsed)) ||
+        (rc = dalloc(&n->scal, (size_t)batch_max)) || (rc = dalloc(&n->vsrc, (size_t)batch_max)) ||
+        (rc = dalloc(&n->bn, (size_t)batch_max)))
+        return fail(rc);
+    size_t wp = 0;
+    for (auto& l : n->L) wp = std::max(wp, wpart_floats(l.cin, l.cout));
+    wp = std::max(wp, (size_t)ceil_div((int64_t)v32, 1024) * 96);
+    if ((rc = dalloc(&n->wpart, wp)) || (rc = dalloc(&n->lpart, (size_t)ceil_div((int64_t)v32, 256))))
+        return fail(rc);
+    if (hipHostMalloc(reinterpret_cast<void**>(&n->lpart_h), sizeof(double) * ceil_div((int64_t)v32, 256)) != hipSuccess)
+        return fail(PETGEM_OUT_OF_MEMORY);
+    // He-normal weights (the linear output layer scaled by 0.1, so that the
+    // untrained network predicts nearly zero), zero biases, zero Adam moments
+    std::vector<float> h(off, 0.f);
+    Rng rng{seed};
+    for (auto& l : n->L) {
+        const double sd = std::sqrt(2.0 / (27.0 * l.cin)) * (l.relu ? 1.0 : 0.1);
+        for (size_t i = 0; i < 27 * (size_t)l.cin * l.cout; ++i) h[l.w_off + i] = (float)(sd * rng.normal());
+    }
+    std::vector<float> z(off, 0.f);
+    if (hipMemcpy(n->P, h.data(), sizeof(float) * off, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(n->M, z.data(), sizeof(float) * off, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(n->Vv, z.data(), sizeof(float) * off, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(n->Gr, z.data(), sizeof(float) * off, hipMemcpyHostToDevice) != hipSuccess) {
+        set_error("net: upload failed");
+        return fail(PETGEM_HIP_ERROR);
+    }
+    if ((rc = cast_weights(n, nullptr)) != PETGEM_OK || hipDeviceSynchronize() != hipSuccess) return fail(rc ? rc : PETGEM_HIP_ERROR);
+    *out = n;
+    return PETGEM_OK;
+}
+
+int64_t petgem_net_num_params(const petgem_net* n) { return n ? (int64_t)n->nparam : -1; }
+
+int petgem_net_get_params(const petgem_net* n, float* host) {
+    if (!n || !host) { set_error("net and output are required"); return PETGEM_INVALID_ARG; }
+    PG_HIP(hipMemcpy(host, n->P, sizeof(float) * n->nparam, hipMemcpyDeviceToHost));
+    return PETGEM_OK;
+}
+
+int petgem_net_set_params(petgem_net* n, const float* host) {
+    if (!n || !host) { set_error("net and input are required"); return PETGEM_INVALID_ARG; }
+    PG_HIP(hipMemcpy(n->P, host, sizeof(float) * n->nparam, hipMemcpyHostToDevice));
+    PG_TRY(cast_weights(n, nullptr));
+    PG_HIP(hipDeviceSynchronize());
+    return PETGEM_OK;
+}
+
+int petgem_net_forward(petgem_net* n, const void* x_dev, int32_t B, void* y_dev, void* stream) {
+    if (!n || !x_dev || !y_dev || B <= 0 || B > n->batch_max) { set_error("net forward: bad arguments"); return PETGEM_INVALID_ARG; }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    PG_HIP(hipMemcpyAsync(n->X0, x_dev, sizeof(bf16) * (size_t)B * kVox * kIn, hipMemcpyDeviceToDevice, s));
+    PG_TRY(forward(n, B, s));
+    PG_HIP(hipMemcpyAsync(y_dev, n->Y, sizeof(float) * (size_t)B * kVox * kOut, hipMemcpyDeviceToDevice, s));
+    return PETGEM_OK;
+}
+
+int petgem_net_loss_grad(petgem_net* n, const void* x_dev, const void* t_dev, int32_t B, void* stream,
+                         double* loss, float* grad_host) {
+    if (!n || !x_dev || !t_dev || B <= 0 || B > n->batch_max) { set_error("net loss: bad arguments"); return PETGEM_INVALID_ARG; }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    PG_HIP(hipMemcpyAsync(n->X0, x_dev, sizeof(bf16) * (size_t)B * kVox * kIn, hipMemcpyDeviceToDevice, s));
+    PG_TRY(loss_and_grads(n, static_cast<const float*>(t_dev), B, s, loss));
+    if (grad_host) {
+        PG_HIP(hipMemcpyAsync(grad_host, n->Gr, sizeof(float) * n->nparam, hipMemcpyDeviceToHost, s));
+        PG_HIP(hipStreamSynchronize(s));
+    }
+    return PETGEM_OK;
+}
+
+int petgem_net_train_step(petgem_net* n, const void* x_dev, const void* t_dev, int32_t B, float lr, void* stream,
+                          double* loss) {
+    if (!n || !x_dev || !t_dev || B <= 0 || B > n->batch_max || !(lr > 0.f)) {
+        set_error("net train: bad arguments");
+        return PETGEM_INVALID_ARG;
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    PG_HIP(hipMemcpyAsync(n->X0, x_dev, sizeof(bf16) * (size_t)B * kVox * kIn, hipMemcpyDeviceToDevice, s));
+    PG_TRY(loss_and_grads(n, static_cast<const float*>(t_dev), B, s, loss));
+    n->step += 1;
+    const float b1 = 0.9f, b2 = 0.999f;
+    const float c1 = 1.f - std::pow(b1, (float)n->step), c2 = 1.f - std::pow(b2, (float)n->step);
+    hipLaunchKernelGGL(k_adam, g1((long)n->nparam), dim3(256), 0, s, n->P, n->Gr, n->M, n->Vv, (long)n->nparam, lr,
+                       b1, b2, c1, c2, 1e-8f);
+    PG_TRY(cast_weights(n, s));
+    return PETGEM_OK;
+}
+
+int petgem_voxelize(petgem_system* sys, const double* sigma_dev, const petgem_source* src, int32_t B,
+                    void* x_dev, void* stream) {
+    if (!sys || !src || B <= 0 || !x_dev) { set_error("voxelize: bad arguments"); return PETGEM_INVALID_ARG; }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    PG_TRY(ensure_vox(sys));
+    std::vector<VoxSrc> v(B);
+    for (int b = 0; b < B; ++b) {
+        for (int k = 0; k < 3; ++k) v[b].pos[k] = src[b].pos[k];
+        v[b].logf = std::log10(src[b].freq_hz);
+    }
+    VoxSrc* vd = nullptr;
+    PG_TRY(dalloc(&vd, (size_t)B));
+    PG_HIP(hipMemcpyAsync(vd, v.data(), sizeof(VoxSrc) * B, hipMemcpyHostToDevice, s));
+    const double* sg = sigma_dev ? sigma_dev : sys->sigma;
+    const long ld = sigma_dev ? sys->n_tets : 0;
+    hipLaunchKernelGGL(k_voxelize, g1((long)B * kVox), dim3(256), 0, s, sg, ld, sys->vox_tet, vd, B, sys->vox_lo[0],
+                       sys->vox_lo[1], sys->vox_lo[2], sys->vox_h, sys->vox_L, static_cast<bf16*>(x_dev));
+    PG_HIP(hipGetLastError());
+    PG_HIP(hipStreamSynchronize(s));
+    dfree(vd);
+    return PETGEM_OK;
+}
+
+int petgem_vox_targets(const petgem_solution* sol, const double* scale, void* t_dev, void* stream) {
+    if (!sol || !scale || !t_dev) { set_error("targets: bad arguments"); return PETGEM_INVALID_ARG; }
+    petgem_system* sys = sol->sys;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    PG_TRY(ensure_vox(sys));
+    const int B = sol->n_src;
+    double* sd = nullptr;
+    PG_TRY(dalloc(&sd, (size_t)B));
+    PG_HIP(hipMemcpyAsync(sd, scale, sizeof(double) * B, hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_vox_field, g1((long)B * kVox), dim3(256), 0, s, sys->xyz, reinterpret_cast<const int4*>(sys->tets),
+                       sys->vox_tet, sys->vox_dof, sol->x, sys->n_dof, B, sd, sys->vox_lo[0], sys->vox_lo[1],
+                       sys->vox_lo[2], sys->vox_h, static_cast<float*>(t_dev));
+    PG_HIP(hipGetLastError());
+    PG_HIP(hipStreamSynchronize(s));
+    dfree(sd);
+    return PETGEM_OK;
+}
+
+int petgem_learned_x0(petgem_system* sys, petgem_net* n, const petgem_source* src, int32_t B, double g,
+                      void* x0_dev, double* bnorm_out, void* stream) {
+    if (!sys || !n || !src || B <= 0 || B > n->batch_max || !x0_dev || !(g > 0.0)) {
+        set_error("learned x0: bad arguments");
+        return PETGEM_INVALID_ARG;
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    PG_TRY(ensure_vox(sys));
+    // |b| of every source (the prediction is scale-free)
+    if (n->bcap < (size_t)sys->n_dof) {
+        dfree(n->bbuf);
+        PG_TRY(dalloc(&n->bbuf, (size_t)sys->n_dof));
+        n->bcap = (size_t)sys->n_dof;
+    }
+    double2* b = n->bbuf;
+    double* bn = n->bn;
+    for (int k = 0; k < B; ++k) {
+        PG_TRY(launch_rhs(sys, src[k], b, 1, s));
+        hipLaunchKernelGGL(k_vnorm, dim3(1), dim3(256), 0, s, b, sys->n_dof, bn + k);
+    }
+    std::vector<double> h(B);
+    PG_HIP(hipMemcpyAsync(h.data(), bn, sizeof(double) * B, hipMemcpyDeviceToHost, s));
+    PG_HIP(hipStreamSynchronize(s));
+    for (int k = 0; k < B; ++k) {
+        if (bnorm_out) bnorm_out[k] = h[k];
+        h[k] *= g;
+    }
+    PG_HIP(hipMemcpyAsync(n->scal, h.data(), sizeof(double) * B, hipMemcpyHostToDevice, s));
+    PG_TRY(upload_vsrc(n, src, B, s));
+    hipLaunchKernelGGL(k_voxelize, g1((long)B * kVox), dim3(256), 0, s, sys->sigma, 0L, sys->vox_tet, n->vsrc, B,
+                       sys->vox_lo[0], sys->vox_lo[1], sys->vox_lo[2], sys->vox_h, sys->vox_L, n->X0);
+    PG_TRY(forward(n, B, s));
+    hipLaunchKernelGGL(k_grid_to_edges, g1((long)B * sys->n_dof), dim3(256), 0, s, n->Y, B, sys->n_dof, sys->dof_mid,
+                       sys->dof_tan, n->scal, sys->vox_lo[0], sys->vox_lo[1], sys->vox_lo[2], sys->vox_h,
+                       static_cast<double2*>(x0_dev));
+    PG_HIP(hipGetLastError());
+    return PETGEM_OK;
+}
+
+void petgem_net_free(petgem_net* n) {
+    if (!n) return;
+    release_net(n);
+    delete n;
+}
+
+}  // extern "C"

@@ -1,0 +1,147 @@
+"""Training and use of the learned initial guess (orchestration only: every
+arithmetic step -- solves, voxelisation, targets, network forward/backward,
+Adam, the grid-to-edge interpolation -- runs in libpetgem's kernels).
+
+Workload: the config-1 mesh (8^3 x 6 jittered tetrahedra over
+[-1000, 1000]^3) with a random resistive box per seed (see
+``synth.config5_sample``). Targets are the secondary field at the 32^3 voxel
+centres divided by g |b|, where |b| is the source's right-hand-side norm and g
+a dataset constant fixed from a pilot of the first samples.
+"""
+from __future__ import annotations
+
+import sys
+import time
+from dataclasses import dataclass, field
+from typing import List, Optional
+
+import numpy as np
+
+from . import petgem, synth
+
+
+@dataclass
+class Dataset:
+    X: "object"                 # bf16 CUDA [N][32^3][16]
+    T: "object"                 # f32 CUDA [N][32^3][6]
+    bnorm: np.ndarray
+    iters: np.ndarray
+    seeds: List[int]
+    seconds: float = 0.0
+
+
+def _sample(system, seed, mesh):
+    import torch
+    m = synth.config5_sample(seed, mesh)
+    sig = torch.tensor(m.sigma, device="cuda")
+    return m, sig
+
+
+def pilot_scale(system, seeds, mesh, opts) -> float:
+    """g: RMS of E_s / |b| at the voxel centres over a few samples."""
+    acc = []
+    for s in seeds:
+        m, sig = _sample(system, s, mesh)
+        system.reassemble(sig, m.sigma_bg)
+        sol, st, _ = system.solve(m.sources, opts)
+        if st[0]["b_norm"] == 0.0:
+            continue
+        t = petgem.vox_targets(sol, [st[0]["b_norm"]]).cpu().numpy()
+        acc.append(np.mean(t.astype(np.float64) ** 2))
+    return float(np.sqrt(np.mean(acc))) if acc else 1.0
+
+
+def generate(system, seeds, mesh, g: float, opts, progress=None) -> Dataset:
+    """Solve every sample with the plain path and store inputs and targets."""
+    import torch
+    t0 = time.perf_counter()
+    N = len(seeds)
+    X = torch.empty((N, petgem.NET_VOX, petgem.NET_IN), dtype=torch.bfloat16, device="cuda")
+    T = torch.empty((N, petgem.NET_VOX, petgem.NET_OUT_USED), dtype=torch.float32, device="cuda")
+    bn = np.zeros(N)
+    it = np.zeros(N, dtype=np.int64)
+    for k, s in enumerate(seeds):
+        m, sig = _sample(system, s, mesh)
+        system.reassemble(sig, m.sigma_bg)
+        sol, st, _ = system.solve(m.sources, opts)
+        bn[k] = st[0]["b_norm"]
+        it[k] = st[0]["iters"]
+        scale = bn[k] * g if bn[k] > 0 else 1.0
+        T[k:k + 1] = petgem.vox_targets(sol, [scale])
+        X[k:k + 1] = petgem.voxelize(system, m.sources, sigma_dev=sig)
+        if progress and (k + 1) % progress == 0:
+            print(f"[learned] generated {k + 1}/{N} samples, {time.perf_counter() - t0:.1f} s",
+                  file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    return Dataset(X, T, bn, it, list(seeds), time.perf_counter() - t0)
+
+
+def train(net, data: Dataset, epochs: int, batch: int = 16, lr: float = 2e-3, seed: int = 0,
+          progress=None) -> List[float]:
+    """Adam on shuffled mini-batches; cosine-decayed learning rate."""
+    N = data.X.shape[0]
+    rng = np.random.default_rng(seed)
+    losses = []
+    steps_total = epochs * ((N + batch - 1) // batch)
+    step = 0
+    for ep in range(epochs):
+        perm = rng.permutation(N)
+        tot, nb = 0.0, 0
+        for b0 in range(0, N, batch):
+            idx = perm[b0: b0 + batch]
+            import torch
+            ii = torch.as_tensor(idx, device="cuda")
+            x = data.X.index_select(0, ii).contiguous()
+            t = data.T.index_select(0, ii).contiguous()
+            a = lr * 0.5 * (1.0 + np.cos(np.pi * step / max(steps_total, 1)))
+            tot += net.train_step(x, t, max(a, lr * 0.02))
+            nb += 1
+            step += 1
+        losses.append(tot / nb)
+        if progress and (ep + 1) % progress == 0:
+            print(f"[learned] epoch {ep + 1}/{epochs} loss {losses[-1]:.4e}", file=sys.stderr, flush=True)
+    return losses
+
+
+@dataclass
+class EvalResult:
+    iters_zero: List[int] = field(default_factory=list)
+    iters_learned: List[int] = field(default_factory=list)
+    fallback: List[int] = field(default_factory=list)
+    x0_residual: List[float] = field(default_factory=list)
+    t_zero: float = 0.0
+    t_learned: float = 0.0
+    max_rx_diff: float = 0.0
+
+
+def evaluate(system, net, seeds, mesh, g: float, opts, receivers=None) -> EvalResult:
+    """Held-out comparison: zero guess vs learned guess (end-to-end time of
+    the learned path includes computing the guess)."""
+    import torch
+    r = EvalResult()
+    rx = receivers
+    for s in seeds:
+        m, sig = _sample(system, s, mesh)
+        system.reassemble(sig, m.sigma_bg)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sol0, st0, _ = system.solve(m.sources, opts)
+        E0 = sol0.receivers(m.receivers if rx is None else rx)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        x0, _ = petgem.learned_x0(system, net, m.sources, g)
+        sol1, st1, _ = system.solve(m.sources, opts, x0=x0)
+        E1 = sol1.receivers(m.receivers if rx is None else rx)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        r.t_zero += t1 - t0
+        r.t_learned += t2 - t1
+        r.iters_zero.append(st0[0]["iters"])
+        r.iters_learned.append(st1[0]["iters"])
+        r.fallback.append(st1[0]["used_fallback"])
+        r.x0_residual.append(st1[0]["x0_rel_residual"])
+        e0, e1 = E0.cpu().numpy(), E1.cpu().numpy()
+        num = np.sqrt(np.sum(np.abs(e1 - e0) ** 2, axis=-1))
+        den = np.sqrt(np.sum(np.abs(e0) ** 2, axis=-1))
+        r.max_rx_diff = max(r.max_rx_diff, float(np.max(num / den)))
+    return r

@@ -56,7 +56,7 @@ class Stats(C.Structure):
                 ("status", C.c_int32), ("rel_residual", C.c_double),
                 ("x0_rel_residual", C.c_double), ("t_rhs_ms", C.c_double),
                 ("t_solve_ms", C.c_double), ("spmv_ms", C.c_double),
-                ("spmv_launches", C.c_int32), ("pad", C.c_int32)]
+                ("spmv_launches", C.c_int32), ("pad", C.c_int32), ("b_norm", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad"}
@@ -96,6 +96,21 @@ _SIGS = {
     "petgem_free_system": (None, [C.c_void_p]),
     "petgem_free_solution": (None, [C.c_void_p]),
     "petgem_last_error": (C.c_char_p, []),
+    "petgem_net_create": (C.c_int, [C.c_int32, C.c_uint64, C.POINTER(C.c_void_p)]),
+    "petgem_net_num_params": (C.c_int64, [C.c_void_p]),
+    "petgem_net_get_params": (C.c_int, [C.c_void_p, C.POINTER(C.c_float)]),
+    "petgem_net_set_params": (C.c_int, [C.c_void_p, C.POINTER(C.c_float)]),
+    "petgem_net_forward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
+    "petgem_net_loss_grad": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p,
+                                       C.POINTER(C.c_double), C.POINTER(C.c_float)]),
+    "petgem_net_train_step": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_float,
+                                        C.c_void_p, C.POINTER(C.c_double)]),
+    "petgem_voxelize": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(Source), C.c_int32, C.c_void_p,
+                                  C.c_void_p]),
+    "petgem_vox_targets": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.c_void_p, C.c_void_p]),
+    "petgem_learned_x0": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(Source), C.c_int32, C.c_double,
+                                    C.c_void_p, C.POINTER(C.c_double), C.c_void_p]),
+    "petgem_net_free": (None, [C.c_void_p]),
 }
 
 
@@ -279,6 +294,94 @@ class System:
             self.free()
         except Exception:
             pass
+
+
+NET_SIDE = 32
+NET_VOX = NET_SIDE ** 3
+NET_IN, NET_OUT, NET_OUT_USED = 16, 16, 6
+NET_LAYERS = ((16, 16), (16, 32), (32, 64), (64, 64), (96, 32), (48, 16), (16, 16))
+
+
+class Net:
+    """The learned-initial-guess network (petgem_net_*). Tensors are CUDA
+    tensors: inputs bfloat16 [B][32^3][16], outputs float32 [B][32^3][16],
+    targets float32 [B][32^3][6]."""
+
+    def __init__(self, batch_max: int = 16, seed: int = 0):
+        h = C.c_void_p()
+        _check(lib().petgem_net_create(batch_max, seed, C.byref(h)))
+        self.handle = h
+        self.batch_max = batch_max
+        self.n_params = lib().petgem_net_num_params(h)
+
+    def params(self) -> np.ndarray:
+        out = np.empty(self.n_params, np.float32)
+        _check(lib().petgem_net_get_params(self.handle, out.ctypes.data_as(C.POINTER(C.c_float))))
+        return out
+
+    def set_params(self, p: np.ndarray):
+        p = np.ascontiguousarray(p, dtype=np.float32)
+        assert p.size == self.n_params
+        _check(lib().petgem_net_set_params(self.handle, p.ctypes.data_as(C.POINTER(C.c_float))))
+
+    def forward(self, x, stream=None):
+        import torch
+        y = torch.empty((x.shape[0], NET_VOX, NET_OUT), dtype=torch.float32, device="cuda")
+        _check(lib().petgem_net_forward(self.handle, _ptr(x), x.shape[0], _ptr(y), _stream(stream)))
+        return y
+
+    def loss_grad(self, x, t, stream=None):
+        loss = C.c_double()
+        g = np.empty(self.n_params, np.float32)
+        _check(lib().petgem_net_loss_grad(self.handle, _ptr(x), _ptr(t), x.shape[0], _stream(stream),
+                                          C.byref(loss), g.ctypes.data_as(C.POINTER(C.c_float))))
+        return loss.value, g
+
+    def train_step(self, x, t, lr: float, stream=None) -> float:
+        loss = C.c_double()
+        _check(lib().petgem_net_train_step(self.handle, _ptr(x), _ptr(t), x.shape[0], lr,
+                                           _stream(stream), C.byref(loss)))
+        return loss.value
+
+    def free(self):
+        if self.handle:
+            lib().petgem_net_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def voxelize(system: "System", dipoles, sigma_dev=None, stream=None):
+    import torch
+    src = make_sources(dipoles)
+    x = torch.empty((len(dipoles), NET_VOX, NET_IN), dtype=torch.bfloat16, device="cuda")
+    _check(lib().petgem_voxelize(system.handle, _ptr(sigma_dev), src, len(dipoles), _ptr(x),
+                                 _stream(stream)))
+    return x
+
+
+def vox_targets(solution: "Solution", scale, stream=None):
+    import torch
+    sc = np.ascontiguousarray(scale, dtype=np.float64)
+    t = torch.empty((solution.n_src, NET_VOX, NET_OUT_USED), dtype=torch.float32, device="cuda")
+    _check(lib().petgem_vox_targets(solution.handle, sc.ctypes.data_as(C.POINTER(C.c_double)),
+                                    _ptr(t), _stream(stream)))
+    return t
+
+
+def learned_x0(system: "System", net: Net, dipoles, g: float, stream=None):
+    """(x0 complex128 CUDA tensor [B][n_dof], |b| per source)."""
+    import torch
+    src = make_sources(dipoles)
+    x0 = torch.empty((len(dipoles), system.n_dof), dtype=torch.complex128, device="cuda")
+    bn = np.empty(len(dipoles), np.float64)
+    _check(lib().petgem_learned_x0(system.handle, net.handle, src, len(dipoles), g, _ptr(x0),
+                                   bn.ctypes.data_as(C.POINTER(C.c_double)), _stream(stream)))
+    return x0, bn
 
 
 def _mesh(xyz, tets):
