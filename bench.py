@@ -47,6 +47,10 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 RTOL = 1e-9
+# the high-frequency models of the uneven batch (f up to 2 Hz, receivers 4 km
+# out where the field has decayed by ~1e-8) need 1e-12: at 1e-10 their far
+# receivers still move by up to 1.4e-5, at 3e-11 by up to 2e-6
+RTOL_CFG4 = 1e-12
 GOLDEN_CFG2 = os.path.join(ROOT, "tests", "golden", "cfg2_receivers.npz")
 
 
@@ -256,7 +260,7 @@ def bench_cfg4(args, petgem, synth, torch):
     systems = [petgem.System.from_model(m) for m in models]
     setup_s = time.perf_counter() - t0
     srcs = [m.sources[0] for m in models]
-    o = petgem.default_opts(rtol=RTOL, method=petgem.COCG, precision=petgem.MIXED,
+    o = petgem.default_opts(rtol=RTOL_CFG4, method=petgem.COCG, precision=petgem.MIXED,
                             inner_rtol=args.inner_rtol)
 
     def step():
@@ -266,7 +270,10 @@ def bench_cfg4(args, petgem, synth, torch):
 
     dt, outs = timed(step, args.steps, args.warmup)
     st, Es = outs[-1]
-    o_plain = petgem.default_opts(rtol=RTOL)
+    o_plain = petgem.default_opts(rtol=RTOL_CFG4)
+    for Sy, m in zip(systems, models):   # untimed pass: the plain path's own autotuning
+        Sy.solve(m.sources, o_plain)
+    torch.cuda.synchronize()
     t1 = time.perf_counter()
     agree = 0.0
     plain_iters = []
@@ -284,7 +291,8 @@ def bench_cfg4(args, petgem, synth, torch):
         "ms_per_step": dt / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "c64 inner / f64 refinement", "data": "synthetic",
         "config": {"workload": "cfg4: 48 models, 1e4..2e6 tets (log-uniform), one source each, "
-                               "one uneven batch", "n_tets": [len(m.tets) for m in models],
+                               "one uneven batch, true relative residual 1e-12",
+                   "n_tets": [len(m.tets) for m in models],
                    "setup_s": round(setup_s, 3), "iters_max": max(s["iters"] for s in st),
                    "rel_residual_max": max(s["rel_residual"] for s in st), "parallelism": "1 GPU"},
         "plain_sequential": {"solves_per_s": len(models) / t_plain, "iters": plain_iters,
@@ -340,12 +348,26 @@ def bench_cfg5(args, petgem, synth, torch):
     }
 
 
+def copy_calibration(args, torch):
+    """A plain device copy of a known size (1 GiB read + 1 GiB written per
+    launch): the FETCH_SIZE / WRITE_SIZE counters of this kernel give the
+    factor that turns the counters of the solver kernels into HBM bytes."""
+    n = 1 << 30
+    a = torch.empty(n, dtype=torch.uint8, device="cuda").fill_(1)
+    b = torch.empty_like(a)
+    for _ in range(args.steps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    return {"metric": "copy calibration", "bytes_read_per_launch": n, "bytes_written_per_launch": n,
+            "launches": args.steps}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="cfg2", choices=["cfg2", "cfg3", "cfg4", "cfg5"])
+    ap.add_argument("--workload", default="cfg2", choices=["cfg2", "cfg3", "cfg4", "cfg5", "copy"])
     ap.add_argument("--n-train", type=int, default=2000)
     ap.add_argument("--n-test", type=int, default=200)
     ap.add_argument("--epochs", type=int, default=30)
@@ -364,6 +386,9 @@ def main():
     import torch
     from paper_1808_00186_amd import petgem, synth
     torch.cuda.set_device(0)
+    if args.workload == "copy":
+        print(json.dumps(copy_calibration(args, torch)), flush=True)
+        return
     fn = {"cfg2": bench_cfg2, "cfg3": bench_cfg3, "cfg4": bench_cfg4, "cfg5": bench_cfg5}[args.workload]
     line = fn(args, petgem, synth, torch)
     print(json.dumps(line), flush=True)

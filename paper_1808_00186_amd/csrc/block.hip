@@ -82,10 +82,16 @@ struct Op {
 // EPI 1: Y = A X and partial[tile][c] = sum_i X_ic Y_ic (unconjugated).
 // EPI 2: Y = B - A X and partial[tile][c] = sum_i |Y_ic|^2 (in .x).
 // Column-lane variant: LPR lanes per row, CPL consecutive columns per lane.
+// Columns whose Krylov solve has finished (EPI 1: inner `active` clear; EPI 2:
+// refinement `outer` clear) are skipped: no gathers, no writes, zero partials.
+__device__ __forceinline__ bool col_live(const ColState* st, int sc, int EPI_) {
+    return EPI_ == 2 ? st[sc].outer != 0 : st[sc].active != 0;
+}
+
 template <typename T, int LPR, int CPL, int EPI>
 __global__ void __launch_bounds__(256)
-k_spmm_c(Op op, const typename V2<T>::t* __restrict__ X, const typename V2<T>::t* __restrict__ B,
-         typename V2<T>::t* __restrict__ Y, double2* __restrict__ partial) {
+k_spmm_c(Op op, const ColState* __restrict__ st, const typename V2<T>::t* __restrict__ X,
+         const typename V2<T>::t* __restrict__ B, typename V2<T>::t* __restrict__ Y, double2* __restrict__ partial) {
     using T2 = typename V2<T>::t;
     const T* __restrict__ Kv = nullptr;
     const T* __restrict__ Mv = nullptr;
@@ -97,9 +103,11 @@ k_spmm_c(Op op, const typename V2<T>::t* __restrict__ X, const typename V2<T>::t
     const int C = op.C;
     const int seg = op.tile_seg ? op.tile_seg[tile] : 0;
     T wmu[CPL];
+    bool live[CPL];
 #pragma unroll
     for (int u = 0; u < CPL; ++u) {
         const int c = l * CPL + u;
+        live[u] = c < C && col_live(st, seg * C + c, EPI);
         wmu[u] = c < C ? (T)op.wmu[seg * C + c] : (T)0;
     }
     double2 pacc[CPL];
@@ -129,7 +137,7 @@ k_spmm_c(Op op, const typename V2<T>::t* __restrict__ X, const typename V2<T>::t
                 const T2* xr = X + (size_t)cj[q] * C + l * CPL;
 #pragma unroll
                 for (int u = 0; u < CPL; ++u) {
-                    if (l * CPL + u < C) {
+                    if (live[u]) {
                         const T2 xv = xr[u];
                         ak[u].x += kv[q] * xv.x; ak[u].y += kv[q] * xv.y;
                         am[u].x += mv[q] * xv.x; am[u].y += mv[q] * xv.y;
@@ -140,7 +148,7 @@ k_spmm_c(Op op, const typename V2<T>::t* __restrict__ X, const typename V2<T>::t
 #pragma unroll
         for (int u = 0; u < CPL; ++u) {
             const int c = l * CPL + u;
-            if (c >= C) continue;
+            if (!live[u]) continue;
             T2 y;
             y.x = ak[u].x + wmu[u] * am[u].y;   // K x - i wmu M x
             y.y = ak[u].y - wmu[u] * am[u].x;
@@ -175,8 +183,8 @@ k_spmm_c(Op op, const typename V2<T>::t* __restrict__ X, const typename V2<T>::t
 // each lane accumulates all (<= CM) columns, then a shuffle reduction.
 template <typename T, int G, int CM, int EPI>
 __global__ void __launch_bounds__(256)
-k_spmm_n(Op op, const typename V2<T>::t* __restrict__ X, const typename V2<T>::t* __restrict__ B,
-         typename V2<T>::t* __restrict__ Y, double2* __restrict__ partial) {
+k_spmm_n(Op op, const ColState* __restrict__ st, const typename V2<T>::t* __restrict__ X,
+         const typename V2<T>::t* __restrict__ B, typename V2<T>::t* __restrict__ Y, double2* __restrict__ partial) {
     using T2 = typename V2<T>::t;
     const T* __restrict__ Kv = nullptr;
     const T* __restrict__ Mv = nullptr;
@@ -189,11 +197,16 @@ k_spmm_n(Op op, const typename V2<T>::t* __restrict__ X, const typename V2<T>::t
     const int C = op.C;
     const int seg = op.tile_seg ? op.tile_seg[tile] : 0;
     double2 pacc[CM];
+    bool live[CM], any = false;
 #pragma unroll
-    for (int u = 0; u < CM; ++u) pacc[u] = make_double2(0.0, 0.0);
+    for (int u = 0; u < CM; ++u) {
+        pacc[u] = make_double2(0.0, 0.0);
+        live[u] = u < C && col_live(st, seg * C + u, EPI);
+        any = any || live[u];
+    }
     {
         const int i = tile * kTR + pass * RPB + slot;
-        if (i < op.nrow_valid) {   // the whole G-lane group shares i
+        if (any && i < op.nrow_valid) {   // the whole G-lane group shares i and seg
         T2 ak[CM], am[CM];
 #pragma unroll
         for (int u = 0; u < CM; ++u) { ak[u].x = ak[u].y = (T)0; am[u].x = am[u].y = (T)0; }
@@ -216,7 +229,7 @@ k_spmm_n(Op op, const typename V2<T>::t* __restrict__ X, const typename V2<T>::t
                 const T2* xr = X + (size_t)cj[q] * C;
 #pragma unroll
                 for (int u = 0; u < CM; ++u) {
-                    if (u < C) {
+                    if (live[u]) {
                         const T2 xv = xr[u];
                         ak[u].x += kv[q] * xv.x; ak[u].y += kv[q] * xv.y;
                         am[u].x += mv[q] * xv.x; am[u].y += mv[q] * xv.y;
@@ -235,7 +248,7 @@ k_spmm_n(Op op, const typename V2<T>::t* __restrict__ X, const typename V2<T>::t
         if (l == 0) {
 #pragma unroll
             for (int u = 0; u < CM; ++u) {
-                if (u >= C) continue;
+                if (!live[u]) continue;
                 const T w = (T)op.wmu[seg * C + u];
                 T2 y;
                 y.x = ak[u].x + w * am[u].y;
@@ -286,6 +299,7 @@ k_reduce(Op op, const double2* __restrict__ p0, int pp0, const double2* __restri
     const int s = sc / op.C, c = sc % op.C;
     ColState& S = st[sc];
     if ((mode == RED_ALPHA || mode == RED_BETA) && !S.active) return;
+    if (mode == RED_RES && !first && !S.outer) return;   // finished: keep its last residual
     const int t0 = op.seg_tile[s], t1 = op.seg_tile[s + 1];
     double2 a = make_double2(0.0, 0.0), b = make_double2(0.0, 0.0);
     {
@@ -356,8 +370,9 @@ k_reduce(Op op, const double2* __restrict__ p0, int pp0, const double2* __restri
             S.rho = a;
         }
     } else if (mode == RED_X0) {       // a = w^H b, b.x = |w|^2 for w = A x0
-        S.alpha = (b.x > 0.0 && isfinite(b.x) && isfinite(a.x) && isfinite(a.y)) ? cscale(a, 1.0 / b.x)
-                                                                                : make_double2(0.0, 0.0);
+        // a zero right-hand side (outer clear, its residual never formed) has x = 0
+        S.alpha = (S.outer && b.x > 0.0 && isfinite(b.x) && isfinite(a.x) && isfinite(a.y))
+                      ? cscale(a, 1.0 / b.x) : make_double2(0.0, 0.0);
     } else {                           // RED_RES: a.x = |b - A x|^2
         const double rn = sqrt(a.x);
         S.rnorm64 = rn;
@@ -636,6 +651,14 @@ __global__ void k_init_state(ColState* st, int nsc, double rtol, double inner_rt
     st[k] = S;
 }
 
+// every column live (for the autotuner's timing launches)
+__global__ void k_set_live(ColState* st, int nsc) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nsc) return;
+    st[k].active = 1;
+    st[k].outer = 1;
+}
+
 __global__ void k_set_tol(ColState* st, int nsc, double rtol) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= nsc) return;
@@ -727,28 +750,26 @@ void release_block_work(BlockWork*& w) {
 
 namespace {
 
-using SpmmFn = void (*)(Op, const void*, const void*, void*, double2*);
-
 template <typename T, int A, int B, int EPI, bool COLS>
-void spmm_thunk(Op op, const void* X, const void* Bv, void* Y, double2* part, hipStream_t s) {
+void spmm_thunk(Op op, const ColState* st, const void* X, const void* Bv, void* Y, double2* part, hipStream_t s) {
     using T2 = typename V2<T>::t;
     if constexpr (COLS)
-        hipLaunchKernelGGL((k_spmm_c<T, A, B, EPI>), dim3(op.ntiles), dim3(256), 0, s, op,
+        hipLaunchKernelGGL((k_spmm_c<T, A, B, EPI>), dim3(op.ntiles), dim3(256), 0, s, op, st,
                            (const T2*)X, (const T2*)Bv, (T2*)Y, part);
     else
-        hipLaunchKernelGGL((k_spmm_n<T, A, B, EPI>), dim3(op.ntiles * A), dim3(256), 0, s, op,
+        hipLaunchKernelGGL((k_spmm_n<T, A, B, EPI>), dim3(op.ntiles * A), dim3(256), 0, s, op, st,
                            (const T2*)X, (const T2*)Bv, (T2*)Y, part);
 }
 
 template <typename T, int EPI>
-bool spmm_dispatch_(const SpmmChoice& ch, Op op, const void* X, const void* Bv, void* Y,
+bool spmm_dispatch_(const SpmmChoice& ch, Op op, const ColState* st, const void* X, const void* Bv, void* Y,
                    double2* part, hipStream_t s) {
     if (ch.kind == 1) {
-#define PG_N(G, CM) if (ch.a == G && ch.b == CM) { spmm_thunk<T, G, CM, EPI, false>(op, X, Bv, Y, part, s); return true; }
+#define PG_N(G, CM) if (ch.a == G && ch.b == CM) { spmm_thunk<T, G, CM, EPI, false>(op, st, X, Bv, Y, part, s); return true; }
         PG_N(4, 1) PG_N(8, 1) PG_N(16, 1) PG_N(4, 2) PG_N(8, 2) PG_N(16, 2) PG_N(4, 4) PG_N(8, 4) PG_N(16, 4)
 #undef PG_N
     } else {
-#define PG_C(L, P) if (ch.a == L && ch.b == P) { spmm_thunk<T, L, P, EPI, true>(op, X, Bv, Y, part, s); return true; }
+#define PG_C(L, P) if (ch.a == L && ch.b == P) { spmm_thunk<T, L, P, EPI, true>(op, st, X, Bv, Y, part, s); return true; }
         PG_C(8, 1) PG_C(8, 2) PG_C(8, 4) PG_C(16, 1) PG_C(16, 2) PG_C(16, 3) PG_C(16, 4)
         PG_C(32, 1) PG_C(32, 2) PG_C(32, 3) PG_C(32, 4) PG_C(64, 1) PG_C(64, 2) PG_C(64, 3) PG_C(64, 4)
 #undef PG_C
@@ -757,9 +778,9 @@ bool spmm_dispatch_(const SpmmChoice& ch, Op op, const void* X, const void* Bv, 
 }
 
 template <typename T, int EPI>
-void spmm_dispatch(const SpmmChoice& ch, Op op, const void* X, const void* Bv, void* Y,
+void spmm_dispatch(const SpmmChoice& ch, Op op, const ColState* st, const void* X, const void* Bv, void* Y,
                    double2* part, hipStream_t s) {
-    if (!spmm_dispatch_<T, EPI>(ch, op, X, Bv, Y, part, s)) abort();   // candidates() lists only instantiated shapes
+    if (!spmm_dispatch_<T, EPI>(ch, op, st, X, Bv, Y, part, s)) abort();   // candidates() lists only instantiated shapes
 }
 
 std::vector<SpmmChoice> candidates(int C) {
@@ -839,9 +860,9 @@ int tune_spmm(BlockWork* w, const Op& op, int64_t nnz, hipStream_t s, SpmmChoice
     SpmmChoice best = cands[0];
     best.ms = 1e30f;
     for (auto& c : cands) {
-        spmm_dispatch<float, 1>(c, op, w->P, nullptr, w->Q, w->p0, s);   // warm-up
+        spmm_dispatch<float, 1>(c, op, w->st, w->P, nullptr, w->Q, w->p0, s);   // warm-up
         PG_HIP(hipEventRecord(e0, s));
-        for (int r = 0; r < 3; ++r) spmm_dispatch<float, 1>(c, op, w->P, nullptr, w->Q, w->p0, s);
+        for (int r = 0; r < 3; ++r) spmm_dispatch<float, 1>(c, op, w->st, w->P, nullptr, w->Q, w->p0, s);
         PG_HIP(hipEventRecord(e1, s));
         PG_HIP(hipEventSynchronize(e1));
         float ms = 0.f;
@@ -863,9 +884,11 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
     const int C = op.C, nsc = op.nseg * C, CP = cp_of(C);
     Timer t_all;
     SpmmChoice ch;
-    // P (complex64, rows x C) gets finite values for the tuning launches
+    // P (complex64, rows x C) gets finite values and every column is live
+    // for the tuning launches
     hipLaunchKernelGGL(k_fill_f2, dim3(ceil_div((size_t)op.n * C, 256)), dim3(256), 0, s,
                        (size_t)op.n * C, w->P);
+    hipLaunchKernelGGL(k_set_live, dim3(ceil_div(nsc, 64)), dim3(64), 0, s, w->st, nsc);
     PG_TRY(tune_spmm(w, op, nnz, s, ch));
     const int ppS = ch.kind == 1 ? ch.a : 1;   // SpMM partial slots per tile
     hipLaunchKernelGGL(k_init_state, dim3(ceil_div(nsc, 64)), dim3(64), 0, s, w->st, nsc, o.rtol,
@@ -880,7 +903,7 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
         evs.push_back(e);
     };
     auto residual = [&](int first) -> int {
-        spmm_dispatch<double, 2>(ch, op, w->X64, w->B64, w->R64, w->p0, s);
+        spmm_dispatch<double, 2>(ch, op, w->st, w->X64, w->B64, w->R64, w->p0, s);
         hipLaunchKernelGGL(k_reduce, dim3(nsc), dim3(1024), 0, s, op, w->p0, ppS, nullptr, 1, w->st, (int)RED_RES, first);
         PG_HIP(hipGetLastError());
         return PETGEM_OK;
@@ -934,7 +957,7 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
     // one inner iteration, kCheck of them captured as a graph
     auto iteration = [&]() {
         ev();
-        spmm_dispatch<float, 1>(ch, op, w->P, nullptr, w->Q, w->p0, s);
+        spmm_dispatch<float, 1>(ch, op, w->st, w->P, nullptr, w->Q, w->p0, s);
         ev();
         hipLaunchKernelGGL(k_reduce, dim3(nsc), dim3(1024), 0, s, op, w->p0, ppS, nullptr, 1, w->st, (int)RED_ALPHA, 0);
         hipLaunchKernelGGL(k_update1, dim3(op.ntiles), dim3(256), 0, s, op, CP, w->st, w->Xi, w->R, w->P,

@@ -148,3 +148,24 @@ def test_solve_many_uneven_batch_matches_oracle(pg):
     sols2, _, _ = pg.solve_many(systems, [mm.sources[0] for mm in models], o)
     for a, b in zip(sols, sols2):
         assert np.array_equal(a.x().cpu().numpy(), b.x().cpu().numpy())
+
+
+def test_uneven_batch_of_smallest_cfg4_models_matches_oracle(pg):
+    """The four smallest models of the 48-model uneven batch (coarse meshes,
+    h up to 833 m) and the smallest 1.8 Hz one, against the oracle at the true
+    residual the batch is run at, 1e-12 (1e-10 still leaves up to 1e-5 at the
+    far receivers of the high-frequency models)."""
+    models = synth.config4()
+    small = sorted(models, key=lambda m: len(m.tets))[:4]
+    small.append(min((m for m in models if m.sources[0].freq > 1.75), key=lambda m: len(m.tets)))
+    print(f"[case] cfg4 small models {[len(m.tets) for m in small]}", flush=True)
+    systems = [pg.System.from_model(m) for m in small]
+    o = pg.default_opts(method=pg.COCG, precision=pg.MIXED, rtol=1e-12)
+    sols, st, rc = pg.solve_many(systems, [m.sources[0] for m in small], o)
+    assert rc == pg.OK
+    for k, m in enumerate(small):
+        E = sols[k].receivers(m.receivers).cpu().numpy()[0]
+        err = fem.receiver_error(E, solve.forward(m)["E"])
+        print(f"  {m.name} tets {len(m.tets)} f {m.sources[0].freq:.2f} iters {st[k]['iters']} "
+              f"res {st[k]['rel_residual']:.1e} err {err:.1e}", flush=True)
+        assert st[k]["rel_residual"] <= 1e-12 and err <= 1e-6
