@@ -261,7 +261,7 @@ def bench_cfg4(args, petgem, synth, torch):
     setup_s = time.perf_counter() - t0
     srcs = [m.sources[0] for m in models]
     o = petgem.default_opts(rtol=RTOL_CFG4, method=petgem.COCG, precision=petgem.MIXED,
-                            inner_rtol=args.inner_rtol)
+                            inner_rtol=args.inner_rtol, verbose=int(args.verbose))
 
     def step():
         s_, st, _ = petgem.solve_many(systems, srcs, o)

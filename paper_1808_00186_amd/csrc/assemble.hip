@@ -165,6 +165,7 @@ int ensure_fp32(petgem_system* sys, hipStream_t s) {
                        sys->Ms, sys->K32, sys->Ms32);
     PG_HIP(hipGetLastError());
     sys->have32 = true;
+    sys->sell32.values = false;
     return PETGEM_OK;
 }
 

@@ -13,14 +13,29 @@
 // batch, the concatenated block-diagonal system of several meshes), and each
 // (segment, column) pair carries its own Krylov scalars.
 //
-// COCG (complex symmetric A = A^T, Jacobi D = diag A):
-//   r = b, z = D^-1 r, p = z, rho = r^T z
+// COCG (complex symmetric A = A^T, Jacobi D = diag A, bilinear form u^T v):
+//   r = b, x = 0, z = D^-1 r, p = z, rho = r^T z
 //   repeat: q = A p; alpha = rho / p^T q; x += alpha p; r -= alpha q;
-//           z = D^-1 r; rho' = r^T z; beta = rho'/rho; p = z + beta p
-// The dots p^T q, r^T z and |r|^2 are accumulated in double precision from
-// complex64 data, per tile, and reduced per (segment, column) in a fixed order
-// (bitwise reproducible). Refinement: r64 = b - A x64 in double precision,
-// the inner solve runs on r64/|r64| in complex64 to inner_rtol, x64 += |r64| d.
+//           z = D^-1 r; rho' = r^T z; stop if |r| <= tol;
+//           beta = rho' / rho; rho = rho'; p = z + beta p
+// Per iteration: the SpMM (partials of p^T q in its epilogue), a reduction,
+// the x / r / z update (partials of r^T z and |r|^2), a reduction, the p
+// update. For one mesh with few partials the two reductions move into the
+// prologues of the update kernels (see "reductions in the consumers"), so an
+// iteration is three kernels. Not used, after trial: the single-reduction
+// rearrangement of Chronopoulos and Gear, which carries A p by a recurrence,
+// loses convergence in complex64 on the harder marine models; folding the p
+// update into the SpMM (gathering z and p together) costs more than the pass
+// it saves; completing the reductions in the last block of each kernel needs
+// a device-wide cache write-back per block, which costs more than a reduction
+// kernel.
+// The SpMM shapes: CSR with nonzero lanes or column lanes, or a sliced
+// ELLPACK copy of the operator (one row per lane) for up to four columns;
+// the autotuner picks per operator and column count.
+// The dots are accumulated in double precision from complex64 data, per tile,
+// and reduced per (segment, column) in a fixed order (bitwise reproducible).
+// Refinement: r64 = b - A x64 in double precision, the inner solve runs on
+// r64/|r64| in complex64 to its tolerance, x64 += |r64| d.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -37,6 +52,9 @@ namespace {
 
 constexpr int kTR = 256;        // rows per tile
 constexpr int kCheck = 8;       // inner iterations between host checks (one graph)
+constexpr int64_t kConsumerMax = 8192;   // partials a vector kernel's block may sum itself
+constexpr int kConsumerTiles = 4;        // tiles per block of the in-consumer vector kernels
+constexpr int kMaxGroups = 8;            // iteration groups between two host checks
 
 __device__ __forceinline__ float2 f2(float x, float y) { return make_float2(x, y); }
 
@@ -57,6 +75,7 @@ struct ColState {
     int outer;         // not yet converged in double precision
     int breakdown;
     int iters;         // inner iterations (all refinement steps)
+    int kin;           // inner iterations of the current refinement step
 };
 
 // Operator view shared by the kernels.
@@ -76,11 +95,141 @@ struct Op {
     const double* Md;      // [n]
     const double* wmu;     // [nseg][C] w mu0
     int nrow_valid;        // rows with a matrix row (rp[i] defined for i < nrow_valid)
+    // sliced-ELLPACK copy of the complex64 operator (null when absent); its
+    // 64-row slices tile the kTR-row tiles exactly
+    const int32_t* sp;
+    const int32_t* sw;
+    const int32_t* scol;
+    const float* sK;
+    const float* sM;
 };
 
+// ------------------------------------------------------------ reductions
+enum RedMode { RED_INIT = 0, RED_ALPHA = 1, RED_BETA = 2, RED_RES = 3, RED_X0 = 4 };
+
+__device__ __forceinline__ bool cfinite(double2 a) { return isfinite(a.x) && isfinite(a.y); }
+__device__ __forceinline__ bool czero(double2 a) { return a.x == 0.0 && a.y == 0.0; }
+
+// alpha = rho / p^T q (or breakdown) for an active column
+__device__ __forceinline__ void step_alpha(ColState& S, double2 pq) {
+    if (!cfinite(pq) || czero(pq)) {
+        S.active = 0;
+        S.breakdown = 1;
+        S.alpha = make_double2(0.0, 0.0);
+    } else {
+        S.alpha = cdiv(S.rho, pq);
+    }
+}
+
+// convergence test on |r|^2 and beta = rho' / rho for an active column
+// (counting the update that produced r)
+__device__ __forceinline__ void step_beta(ColState& S, double2 rz, double r2) {
+    S.iters += 1;
+    S.kin += 1;
+    S.rn2 = r2;
+    if (!isfinite(r2) || !cfinite(rz)) {
+        S.active = 0;
+        S.breakdown = 1;
+    } else if (r2 <= S.inner_tol2) {
+        S.active = 0;
+    } else if (czero(S.rho)) {
+        S.active = 0;
+        S.breakdown = 1;
+    } else {
+        S.beta = cdiv(rz, S.rho);
+        S.rho = rz;
+    }
+}
+
+// The scalar step of one (segment, column) once its sums a, b are known.
+__device__ void apply_red(ColState& S, int mode, int first, double2 a, double2 b) {
+    if (mode == RED_INIT) {            // a = r^T z, b.x = |r|^2 of the normalised start
+        S.rho = a;
+        S.rn2 = b.x;
+        S.kin = 0;
+        S.beta = make_double2(0.0, 0.0);
+        S.active = S.outer && cfinite(a) && !czero(a);
+        S.breakdown = 0;
+    } else if (mode == RED_ALPHA) {    // a = p^T q
+        step_alpha(S, a);
+    } else if (mode == RED_BETA) {     // a = r^T z (new), b.x = |r|^2
+        step_beta(S, a, b.x);
+    } else if (mode == RED_X0) {       // a = w^H b, b.x = |w|^2 for w = A x0
+        // a zero right-hand side (outer clear, its residual never formed) has x = 0
+        S.alpha = (S.outer && b.x > 0.0 && isfinite(b.x) && cfinite(a)) ? cscale(a, 1.0 / b.x)
+                                                                       : make_double2(0.0, 0.0);
+    } else {                           // RED_RES: a.x = |b - A x|^2
+        const double rn = sqrt(a.x);
+        S.rnorm64 = rn;
+        if (first) S.bnorm = rn;
+        S.scale = rn;
+        S.outer = S.outer && !(rn <= S.tol_abs) && isfinite(rn);
+        // no need to solve the correction more accurately than the target asks:
+        // a factor 0.3 below rtol |b| / |r64| leaves a safety margin
+        const double need = rn > 0.0 ? 0.3 * S.tol_abs / rn : 1.0;
+        const double it = fmax(S.inner_rtol, fmin(need, 0.5));
+        S.inner_tol2 = it * it;
+    }
+}
+
+__device__ __forceinline__ bool red_skips(const ColState& S, int mode, int first) {
+    return ((mode == RED_ALPHA || mode == RED_BETA) && !S.active) || (mode == RED_RES && !first && !S.outer);
+}
+
+// One block per (segment, column): fixed-order sums over the segment's tiles
+// (pp0 / pp1 partial slots per tile), then the scalar step of that column.
+__global__ void __launch_bounds__(1024)
+k_reduce(Op op, const double2* __restrict__ p0, int pp0, const double2* __restrict__ p1, int pp1,
+         ColState* __restrict__ st, int mode, int first) {
+    __shared__ double2 sa[1024], sb[1024];
+    const int sc = blockIdx.x;
+    const int s = sc / op.C, c = sc % op.C;
+    ColState& S = st[sc];
+    if (red_skips(S, mode, first)) return;
+    const int t0 = op.seg_tile[s], t1 = op.seg_tile[s + 1];
+    double2 a = make_double2(0.0, 0.0), b = make_double2(0.0, 0.0);
+    {
+        const int e0 = t0 * pp0, e1 = t1 * pp0;
+        for (int e = e0 + threadIdx.x; e < e1; e += 1024 * 8) {
+            double2 v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int k = e + 1024 * u;
+                v[u] = k < e1 ? p0[(size_t)k * op.C + c] : make_double2(0.0, 0.0);
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) a = cadd(a, v[u]);
+        }
+    }
+    if (p1) {
+        const int e0 = t0 * pp1, e1 = t1 * pp1;
+        for (int e = e0 + threadIdx.x; e < e1; e += 1024 * 8) {
+            double2 v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int k = e + 1024 * u;
+                v[u] = k < e1 ? p1[(size_t)k * op.C + c] : make_double2(0.0, 0.0);
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) b = cadd(b, v[u]);
+        }
+    }
+    // fixed-shape tree: shuffles inside each wave, then the 16 wave sums
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    a.x = wave_sum(a.x); a.y = wave_sum(a.y);
+    b.x = wave_sum(b.x); b.y = wave_sum(b.y);
+    if (lane == 0) { sa[wave] = a; sb[wave] = b; }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    a = sa[0];
+    b = sb[0];
+    for (int k = 1; k < 16; ++k) { a = cadd(a, sa[k]); b = cadd(b, sb[k]); }
+    apply_red(S, mode, first, a, b);
+}
+
 // ------------------------------------------------------------------ SpMM
-// EPI 1: Y = A X and partial[tile][c] = sum_i X_ic Y_ic (unconjugated).
-// EPI 2: Y = B - A X and partial[tile][c] = sum_i |Y_ic|^2 (in .x).
+// EPI 2: Y = B - A X in the template type and partial[..][c].x = sum_i |Y_ic|^2.
+// EPI 1: Y = A X and partial[..][c] = sum_i X_ic Y_ic (unconjugated).
 // Column-lane variant: LPR lanes per row, CPL consecutive columns per lane.
 // Columns whose Krylov solve has finished (EPI 1: inner `active` clear; EPI 2:
 // refinement `outer` clear) are skipped: no gathers, no writes, zero partials.
@@ -91,7 +240,8 @@ __device__ __forceinline__ bool col_live(const ColState* st, int sc, int EPI_) {
 template <typename T, int LPR, int CPL, int EPI>
 __global__ void __launch_bounds__(256)
 k_spmm_c(Op op, const ColState* __restrict__ st, const typename V2<T>::t* __restrict__ X,
-         const typename V2<T>::t* __restrict__ B, typename V2<T>::t* __restrict__ Y, double2* __restrict__ partial) {
+         const typename V2<T>::t* __restrict__ B, typename V2<T>::t* __restrict__ Y,
+         double2* __restrict__ partial) {
     using T2 = typename V2<T>::t;
     const T* __restrict__ Kv = nullptr;
     const T* __restrict__ Mv = nullptr;
@@ -184,7 +334,8 @@ k_spmm_c(Op op, const ColState* __restrict__ st, const typename V2<T>::t* __rest
 template <typename T, int G, int CM, int EPI>
 __global__ void __launch_bounds__(256)
 k_spmm_n(Op op, const ColState* __restrict__ st, const typename V2<T>::t* __restrict__ X,
-         const typename V2<T>::t* __restrict__ B, typename V2<T>::t* __restrict__ Y, double2* __restrict__ partial) {
+         const typename V2<T>::t* __restrict__ B, typename V2<T>::t* __restrict__ Y,
+         double2* __restrict__ partial) {
     using T2 = typename V2<T>::t;
     const T* __restrict__ Kv = nullptr;
     const T* __restrict__ Mv = nullptr;
@@ -286,105 +437,133 @@ k_spmm_n(Op op, const ColState* __restrict__ st, const typename V2<T>::t* __rest
     }
 }
 
-// ------------------------------------------------------------ reductions
-enum RedMode { RED_INIT = 0, RED_ALPHA = 1, RED_BETA = 2, RED_RES = 3, RED_X0 = 4 };
-
-// One block per (segment, column): fixed-order sum over the segment's tiles
-// (pp0 / pp1 partial slots per tile), then the scalar recurrence of that column.
-__global__ void __launch_bounds__(1024)
-k_reduce(Op op, const double2* __restrict__ p0, int pp0, const double2* __restrict__ p1, int pp1,
-         ColState* __restrict__ st, int mode, int first) {
-    __shared__ double2 sa[1024], sb[1024];
-    const int sc = blockIdx.x;
-    const int s = sc / op.C, c = sc % op.C;
-    ColState& S = st[sc];
-    if ((mode == RED_ALPHA || mode == RED_BETA) && !S.active) return;
-    if (mode == RED_RES && !first && !S.outer) return;   // finished: keep its last residual
-    const int t0 = op.seg_tile[s], t1 = op.seg_tile[s + 1];
-    double2 a = make_double2(0.0, 0.0), b = make_double2(0.0, 0.0);
-    {
-        const int e0 = t0 * pp0, e1 = t1 * pp0;
-        for (int e = e0 + threadIdx.x; e < e1; e += 1024 * 8) {
-            double2 v[8];
+// Sliced-ELLPACK variant (EPI 1, complex64, C <= CM <= 4): one row per lane,
+// the block's four wavefronts take the four 64-row slices of one tile; U
+// slice columns (index and values) are loaded ahead of their gathers.
+template <int CM, int U>
+__global__ void __launch_bounds__(256)
+k_spmm_s(Op op, const ColState* __restrict__ st, const float2* __restrict__ X, float2* __restrict__ Y,
+         double2* __restrict__ partial) {
+    __shared__ double2 red[4][CM];
+    const int tile = xcd_block(blockIdx.x, gridDim.x);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int sl = tile * 4 + wave;
+    const int i = sl * 64 + lane;
+    const int C = op.C;
+    const int seg = op.tile_seg ? op.tile_seg[tile] : 0;
+    double2 pacc[CM];
+    float wmu[CM];
+    bool live[CM], any = false;
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int k = e + 1024 * u;
-                v[u] = k < e1 ? p0[(size_t)k * op.C + c] : make_double2(0.0, 0.0);
+    for (int u = 0; u < CM; ++u) {
+        pacc[u] = make_double2(0.0, 0.0);
+        live[u] = u < C && col_live(st, seg * C + u, 1);
+        any = any || live[u];
+        wmu[u] = u < C ? (float)op.wmu[seg * C + u] : 0.f;
+    }
+    if (any) {   // the same for the whole block (one segment)
+        float2 ak[CM], am[CM];
+#pragma unroll
+        for (int u = 0; u < CM; ++u) { ak[u] = f2(0.f, 0.f); am[u] = f2(0.f, 0.f); }
+        const int base = op.sp[sl], wd = op.sw[sl];
+        int k = 0;
+        for (; k + U <= wd; k += U) {
+            int32_t cj[U];
+            float kv[U], mv[U];
+#pragma unroll
+            for (int q = 0; q < U; ++q) {
+                const int e = base + (k + q) * 64 + lane;
+                cj[q] = op.scol[e];
+                kv[q] = op.sK[e];
+                mv[q] = op.sM[e];
             }
 #pragma unroll
-            for (int u = 0; u < 8; ++u) a = cadd(a, v[u]);
-        }
-    }
-    if (p1) {
-        const int e0 = t0 * pp1, e1 = t1 * pp1;
-        for (int e = e0 + threadIdx.x; e < e1; e += 1024 * 8) {
-            double2 v[8];
+            for (int q = 0; q < U; ++q) {
+                const float2* xr = X + (size_t)cj[q] * C;
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int k = e + 1024 * u;
-                v[u] = k < e1 ? p1[(size_t)k * op.C + c] : make_double2(0.0, 0.0);
+                for (int u = 0; u < CM; ++u) {
+                    if (live[u]) {
+                        const float2 xv = xr[u];
+                        ak[u].x += kv[q] * xv.x; ak[u].y += kv[q] * xv.y;
+                        am[u].x += mv[q] * xv.x; am[u].y += mv[q] * xv.y;
+                    }
+                }
             }
+        }
+        for (; k < wd; ++k) {
+            const int e = base + k * 64 + lane;
+            const float kv = op.sK[e], mv = op.sM[e];
+            const float2* xr = X + (size_t)op.scol[e] * C;
 #pragma unroll
-            for (int u = 0; u < 8; ++u) b = cadd(b, v[u]);
+            for (int u = 0; u < CM; ++u) {
+                if (live[u]) {
+                    const float2 xv = xr[u];
+                    ak[u].x += kv * xv.x; ak[u].y += kv * xv.y;
+                    am[u].x += mv * xv.x; am[u].y += mv * xv.y;
+                }
+            }
+        }
+        if (i < op.nrow_valid) {
+#pragma unroll
+            for (int u = 0; u < CM; ++u) {
+                if (!live[u]) continue;
+                float2 y;
+                y.x = ak[u].x + wmu[u] * am[u].y;   // K x - i wmu M x
+                y.y = ak[u].y - wmu[u] * am[u].x;
+                const size_t o = (size_t)i * C + u;
+                const float2 xo = X[o];
+                pacc[u].x += (double)xo.x * (double)y.x - (double)xo.y * (double)y.y;
+                pacc[u].y += (double)xo.x * (double)y.y + (double)xo.y * (double)y.x;
+                Y[o] = y;
+            }
         }
     }
-    sa[threadIdx.x] = a;
-    sb[threadIdx.x] = b;
+#pragma unroll
+    for (int u = 0; u < CM; ++u) {
+        const double sx = wave_sum(pacc[u].x), sy = wave_sum(pacc[u].y);
+        if (lane == 0) red[wave][u] = make_double2(sx, sy);
+    }
     __syncthreads();
-    for (int w = 512; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) {
-            sa[threadIdx.x] = cadd(sa[threadIdx.x], sa[threadIdx.x + w]);
-            sb[threadIdx.x] = cadd(sb[threadIdx.x], sb[threadIdx.x + w]);
+    if ((int)threadIdx.x < C && (int)threadIdx.x < CM) {
+        const int u = threadIdx.x;
+        partial[(size_t)tile * C + u] = cadd(cadd(red[0][u], red[1][u]), cadd(red[2][u], red[3][u]));
+    }
+}
+
+// Fixed-shape sums over the row slots of a CP-lane row layout (thread t holds
+// column t % CP of slot t / CP); the results for column c end in la[c], lb[c].
+// Below 64 lanes per row the slots inside a wave are folded by shuffles.
+__device__ __forceinline__ void cp_sum2(double2 a, double2 b, int CP, double2* la, double2* lb) {
+    const int RPB = 256 / CP;
+    if (CP < 64) {
+        for (int off = 32; off >= CP; off >>= 1) {
+            a.x += __shfl_xor(a.x, off, kWave); a.y += __shfl_xor(a.y, off, kWave);
+            b.x += __shfl_xor(b.x, off, kWave); b.y += __shfl_xor(b.y, off, kWave);
+        }
+        const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+        if (lane < CP) { la[wave * CP + lane] = a; lb[wave * CP + lane] = b; }
+        __syncthreads();
+        if ((int)threadIdx.x < CP) {
+            const int c = threadIdx.x;
+            a = cadd(cadd(la[c], la[CP + c]), cadd(la[2 * CP + c], la[3 * CP + c]));
+            b = cadd(cadd(lb[c], lb[CP + c]), cadd(lb[2 * CP + c], lb[3 * CP + c]));
         }
         __syncthreads();
+        if ((int)threadIdx.x < CP) { la[threadIdx.x] = a; lb[threadIdx.x] = b; }
+        __syncthreads();
+        return;
     }
-    if (threadIdx.x != 0) return;
-    a = sa[0];
-    b = sb[0];
-    if (mode == RED_INIT) {            // a = r^T z, b.x = |r|^2
-        S.rho = a;
-        S.rn2 = b.x;
-        S.active = S.outer && isfinite(a.x) && isfinite(a.y) && (a.x != 0.0 || a.y != 0.0);
-        S.breakdown = 0;
-    } else if (mode == RED_ALPHA) {    // a = p^T q
-        if (!(isfinite(a.x) && isfinite(a.y)) || (a.x == 0.0 && a.y == 0.0)) {
-            S.active = 0;
-            S.breakdown = 1;
-            S.alpha = make_double2(0.0, 0.0);
-        } else {
-            S.alpha = cdiv(S.rho, a);
+    la[threadIdx.x] = a;
+    lb[threadIdx.x] = b;
+    for (int w = RPB >> 1; w > 0; w >>= 1) {
+        __syncthreads();
+        const int slot = threadIdx.x / CP, c = threadIdx.x % CP;
+        if (slot < w) {
+            la[slot * CP + c] = cadd(la[slot * CP + c], la[(slot + w) * CP + c]);
+            lb[slot * CP + c] = cadd(lb[slot * CP + c], lb[(slot + w) * CP + c]);
         }
-    } else if (mode == RED_BETA) {     // a = r^T z (new), b.x = |r|^2
-        S.iters += 1;
-        S.rn2 = b.x;
-        if (!(isfinite(b.x)) || !(isfinite(a.x) && isfinite(a.y))) {
-            S.active = 0;
-            S.breakdown = 1;
-        } else if (b.x <= S.inner_tol2) {
-            S.active = 0;
-        } else if (S.rho.x == 0.0 && S.rho.y == 0.0) {
-            S.active = 0;
-            S.breakdown = 1;
-        } else {
-            S.beta = cdiv(a, S.rho);
-            S.rho = a;
-        }
-    } else if (mode == RED_X0) {       // a = w^H b, b.x = |w|^2 for w = A x0
-        // a zero right-hand side (outer clear, its residual never formed) has x = 0
-        S.alpha = (S.outer && b.x > 0.0 && isfinite(b.x) && isfinite(a.x) && isfinite(a.y))
-                      ? cscale(a, 1.0 / b.x) : make_double2(0.0, 0.0);
-    } else {                           // RED_RES: a.x = |b - A x|^2
-        const double rn = sqrt(a.x);
-        S.rnorm64 = rn;
-        if (first) S.bnorm = rn;
-        S.scale = rn;
-        S.outer = S.outer && !(rn <= S.tol_abs) && isfinite(rn);
-        // no need to solve the correction more accurately than the target asks:
-        // a factor 0.3 below rtol |b| / |r64| leaves a safety margin
-        const double need = rn > 0.0 ? 0.3 * S.tol_abs / rn : 1.0;
-        const double it = fmax(S.inner_rtol, fmin(need, 0.5));
-        S.inner_tol2 = it * it;
     }
+    __syncthreads();
 }
 
 // Fixed-shape tree sum over the nslot row slots of a CP-lane row layout in
@@ -401,9 +580,6 @@ __device__ __forceinline__ void slot_tree(double2* a, int CP, int nslot) {
 // --------------------------------------------------------- vector updates
 // Thread mapping of the elementwise kernels: CP lanes (power of two >= C)
 // per row, 256 / CP rows per pass over a tile.
-struct Map {
-    int CP, RPB;
-};
 
 __device__ __forceinline__ float2 jacobi_z(float2 r, double kd, double md, double wmu) {
     // z = r / (Kd - i wmu Md)
@@ -416,7 +592,7 @@ __device__ __forceinline__ float2 jacobi_z(float2 r, double kd, double md, doubl
 // r = (r64 / |r64|) in complex64, x = 0, z = D^-1 r, p = z; partials r^T z, |r|^2.
 __global__ void __launch_bounds__(256)
 k_inner_init(Op op, int CP, const double2* __restrict__ R64, const ColState* __restrict__ st,
-             float2* __restrict__ Xi, float2* __restrict__ R, float2* __restrict__ P,
+             float2* __restrict__ Xi, float2* __restrict__ R, float2* __restrict__ Z, float2* __restrict__ P,
              double2* __restrict__ p0, double2* __restrict__ p1) {
     __shared__ double2 ra[256], rb[256];
     const int tile = blockIdx.x, C = op.C;
@@ -438,27 +614,25 @@ k_inner_init(Op op, int CP, const double2* __restrict__ R64, const ColState* __r
             }
             Xi[o] = f2(0.f, 0.f);
             R[o] = r;
+            Z[o] = z;
             P[o] = z;
             a.x += (double)r.x * z.x - (double)r.y * z.y;
             a.y += (double)r.x * z.y + (double)r.y * z.x;
             b.x += (double)r.x * r.x + (double)r.y * r.y;
         }
     }
-    ra[threadIdx.x] = a;
-    rb[threadIdx.x] = b;
-    slot_tree(ra, CP, RPB);
-    slot_tree(rb, CP, RPB);
+    cp_sum2(a, b, CP, ra, rb);
     if ((int)threadIdx.x < C && (int)threadIdx.x < CP) {
         p0[(size_t)tile * C + threadIdx.x] = ra[threadIdx.x];
         p1[(size_t)tile * C + threadIdx.x] = rb[threadIdx.x];
     }
 }
 
-// x += alpha p; r -= alpha q; partials r^T z and |r|^2 with z = D^-1 r.
+// x += alpha p; r -= alpha q; z = D^-1 r; partials r^T z and |r|^2.
 __global__ void __launch_bounds__(256)
-k_update1(Op op, int CP, const ColState* __restrict__ st, float2* __restrict__ Xi,
-          float2* __restrict__ R, const float2* __restrict__ P, const float2* __restrict__ Q,
-          double2* __restrict__ p0, double2* __restrict__ p1) {
+k_update(Op op, int CP, const ColState* __restrict__ st, float2* __restrict__ Xi, float2* __restrict__ R,
+         float2* __restrict__ Z, const float2* __restrict__ P, const float2* __restrict__ Q,
+         double2* __restrict__ p0, double2* __restrict__ p1) {
     __shared__ double2 ra[256], rb[256];
     const int tile = blockIdx.x, C = op.C;
     const int c = threadIdx.x % CP, slot = threadIdx.x / CP, RPB = 256 / CP;
@@ -479,29 +653,26 @@ k_update1(Op op, int CP, const ColState* __restrict__ st, float2* __restrict__ X
                 x.y += ax * p.y + ay * p.x;
                 r.x -= ax * q.x - ay * q.y;
                 r.y -= ax * q.y + ay * q.x;
+                const float2 z = jacobi_z(r, op.Kd[i], op.Md[i], wmu);
                 Xi[o] = x;
                 R[o] = r;
-                const float2 z = jacobi_z(r, op.Kd[i], op.Md[i], wmu);
+                Z[o] = z;
                 a.x += (double)r.x * z.x - (double)r.y * z.y;
                 a.y += (double)r.x * z.y + (double)r.y * z.x;
                 b.x += (double)r.x * r.x + (double)r.y * r.y;
             }
         }
     }
-    ra[threadIdx.x] = a;
-    rb[threadIdx.x] = b;
-    slot_tree(ra, CP, RPB);
-    slot_tree(rb, CP, RPB);
+    cp_sum2(a, b, CP, ra, rb);
     if ((int)threadIdx.x < C && (int)threadIdx.x < CP) {
         p0[(size_t)tile * C + threadIdx.x] = ra[threadIdx.x];
         p1[(size_t)tile * C + threadIdx.x] = rb[threadIdx.x];
     }
 }
 
-// p = D^-1 r + beta p for the still active columns.
+// p = z + beta p for the columns still active.
 __global__ void __launch_bounds__(256)
-k_update2(Op op, int CP, const ColState* __restrict__ st, const float2* __restrict__ R,
-          float2* __restrict__ P) {
+k_pupdate(Op op, int CP, const ColState* __restrict__ st, const float2* __restrict__ Z, float2* __restrict__ P) {
     const int tile = blockIdx.x, C = op.C;
     const int c = threadIdx.x % CP, slot = threadIdx.x / CP, RPB = 256 / CP;
     if (c >= C) return;
@@ -509,14 +680,148 @@ k_update2(Op op, int CP, const ColState* __restrict__ st, const float2* __restri
     const ColState& S = st[seg * C + c];
     if (!S.active) return;
     const float bx = (float)S.beta.x, by = (float)S.beta.y;
-    const double wmu = op.wmu[seg * C + c];
     for (int r0 = 0; r0 < kTR; r0 += RPB) {
         const int i = tile * kTR + r0 + slot;
         if (i >= op.nrow_valid) break;
         const size_t o = (size_t)i * C + c;
-        const float2 z = jacobi_z(R[o], op.Kd[i], op.Md[i], wmu);
-        const float2 p = P[o];
+        const float2 z = Z[o], p = P[o];
         P[o] = f2(z.x + bx * p.x - by * p.y, z.y + bx * p.y + by * p.x);
+    }
+}
+
+// ------------------------------------------- reductions in the consumers
+// For one mesh whose partials are few, every block of the next vector kernel
+// sums them itself (the same fixed order in every block, so all blocks agree
+// bitwise) instead of a reduction kernel running in between: the iteration is
+// the SpMM, the update (which forms alpha first) and the direction update
+// (which tests convergence and forms beta first). Each kernel reads the
+// column state from one slot and its first block writes the advanced state to
+// the other slot, so no block reads a value another block of the same launch
+// may be writing. The two vector kernels take tpb tiles per block (fewer
+// blocks, fewer partials for the next consumer) and one partial slot per
+// block. (Folding the direction update into the SpMM, gathering an
+// interleaved {z, p}, measured slower than this arrangement.)
+
+// Sums over the partial slots [0, nslot) of every column, by all 256 threads
+// (thread t takes column t % CP); column c's sums end in la[c], lb[c].
+__device__ __forceinline__ void cols_sum2(const double2* __restrict__ p0, const double2* __restrict__ p1, int nslot,
+                                          int C, int CP, double2* la, double2* lb) {
+    const int c = threadIdx.x % CP, slot = threadIdx.x / CP, RPB = 256 / CP;
+    double2 a = make_double2(0.0, 0.0), b = make_double2(0.0, 0.0);
+    if (c < C) {
+        for (int e = slot; e < nslot; e += RPB) {
+            a = cadd(a, p0[(size_t)e * C + c]);
+            if (p1) b = cadd(b, p1[(size_t)e * C + c]);
+        }
+    }
+    cp_sum2(a, b, CP, la, lb);
+}
+
+// alpha from the nps SpMM partials of p^T q (state slot s1 -> s0), then as
+// k_update over tpb tiles: x += alpha p; r -= alpha q; z = D^-1 r; partials
+// r^T z, |r|^2 (one slot per block).
+__global__ void __launch_bounds__(256)
+k_update_p(Op op, int CP, int tpb, const ColState* __restrict__ s1, ColState* __restrict__ s0,
+           const double2* __restrict__ ps, int nps, float2* __restrict__ Xi, float2* __restrict__ R,
+           float2* __restrict__ Z, const float2* __restrict__ P, const float2* __restrict__ Q,
+           double2* __restrict__ p0, double2* __restrict__ p1) {
+    __shared__ double2 ra[256], rb[256];
+    const int C = op.C;
+    const int c = threadIdx.x % CP, slot = threadIdx.x / CP, RPB = 256 / CP;
+    // the two scalars the update needs are loaded ahead of the partial sums
+    int act0 = 0;
+    double2 rho = make_double2(0.0, 0.0);
+    if (c < C) {
+        act0 = s1[c].active;
+        rho = s1[c].rho;
+    }
+    cols_sum2(ps, nullptr, nps, C, CP, ra, rb);
+    bool act = false;
+    double2 alpha = make_double2(0.0, 0.0);
+    if (c < C) {
+        const double2 pq = ra[c];
+        act = act0 && cfinite(pq) && !czero(pq);
+        if (act) alpha = cdiv(rho, pq);
+        if (blockIdx.x == 0 && slot == 0) {
+            ColState S = s1[c];
+            if (S.active) step_alpha(S, pq);
+            s0[c] = S;
+        }
+    }
+    __syncthreads();   // ra is reused below
+    double2 a = make_double2(0.0, 0.0), b = make_double2(0.0, 0.0);
+    if (act) {
+        const float ax = (float)alpha.x, ay = (float)alpha.y;
+        const double wmu = op.wmu[c];
+        const int i0 = blockIdx.x * tpb * kTR, i1 = min(i0 + tpb * kTR, op.nrow_valid);
+        // four rows per thread in flight: all loads first
+        for (int ib = i0 + slot; ib < i1; ib += 4 * RPB) {
+            float2 p[4], q[4], x[4], r[4];
+            double kd[4], md[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int i = min(ib + u * RPB, i1 - 1);   // in range; the duplicates are not stored
+                const size_t o = (size_t)i * C + c;
+                p[u] = P[o]; q[u] = Q[o]; x[u] = Xi[o]; r[u] = R[o];
+                kd[u] = op.Kd[i]; md[u] = op.Md[i];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int i = ib + u * RPB;
+                if (i >= i1) break;
+                const size_t o = (size_t)i * C + c;
+                x[u].x += ax * p[u].x - ay * p[u].y;
+                x[u].y += ax * p[u].y + ay * p[u].x;
+                r[u].x -= ax * q[u].x - ay * q[u].y;
+                r[u].y -= ax * q[u].y + ay * q[u].x;
+                const float2 z = jacobi_z(r[u], kd[u], md[u], wmu);
+                Xi[o] = x[u];
+                R[o] = r[u];
+                Z[o] = z;
+                a.x += (double)r[u].x * z.x - (double)r[u].y * z.y;
+                a.y += (double)r[u].x * z.y + (double)r[u].y * z.x;
+                b.x += (double)r[u].x * r[u].x + (double)r[u].y * r[u].y;
+            }
+        }
+    }
+    cp_sum2(a, b, CP, ra, rb);
+    if ((int)threadIdx.x < C && (int)threadIdx.x < CP) {
+        p0[(size_t)blockIdx.x * C + threadIdx.x] = ra[threadIdx.x];
+        p1[(size_t)blockIdx.x * C + threadIdx.x] = rb[threadIdx.x];
+    }
+}
+
+// convergence test and beta from the npu partials of r^T z and |r|^2 (state
+// slot s0 -> s1), then p = z + beta p over tpb tiles for the columns still active.
+__global__ void __launch_bounds__(256)
+k_pupdate_p(Op op, int CP, int tpb, const ColState* __restrict__ s0, ColState* __restrict__ s1,
+            const double2* __restrict__ pg, const double2* __restrict__ pr, int npu, const float2* __restrict__ Z,
+            float2* __restrict__ P) {
+    __shared__ double2 ra[256], rb[256];
+    const int C = op.C;
+    const int c = threadIdx.x % CP, slot = threadIdx.x / CP, RPB = 256 / CP;
+    cols_sum2(pg, pr, npu, C, CP, ra, rb);
+    if (c >= C) return;
+    ColState S = s0[c];
+    if (S.active) step_beta(S, ra[c], rb[c].x);
+    if (blockIdx.x == 0 && slot == 0) s1[c] = S;
+    if (!S.active) return;
+    const float bx = (float)S.beta.x, by = (float)S.beta.y;
+    const int i0 = blockIdx.x * tpb * kTR, i1 = min(i0 + tpb * kTR, op.nrow_valid);
+    for (int ib = i0 + slot; ib < i1; ib += 4 * RPB) {
+        float2 z[4], p[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const size_t o = (size_t)min(ib + u * RPB, i1 - 1) * C + c;   // duplicates are not stored
+            z[u] = Z[o];
+            p[u] = P[o];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int i = ib + u * RPB;
+            if (i >= i1) break;
+            P[(size_t)i * C + c] = f2(z[u].x + bx * p[u].x - by * p[u].y, z[u].y + bx * p[u].y + by * p[u].x);
+        }
     }
 }
 
@@ -657,6 +962,9 @@ __global__ void k_set_live(ColState* st, int nsc) {
     if (k >= nsc) return;
     st[k].active = 1;
     st[k].outer = 1;
+    st[k].kin = 0;
+    st[k].beta = make_double2(0.0, 0.0);
+    st[k].rho = make_double2(1.0, 0.0);
 }
 
 __global__ void k_set_tol(ColState* st, int nsc, double rtol) {
@@ -693,23 +1001,68 @@ __global__ void k_fill_d(int n, double v, double* __restrict__ a) {
     if (i < n) a[i] = v;
 }
 
+// Sliced-ELLPACK builders: the width (longest row) of every 64-row slice,
+// then the column-major fill of every slice (padding: zero values pointing at
+// the row itself, or at row 0 past the last matrix row).
+__global__ void k_sell_width(int nsl, int nrow_valid, const int32_t* __restrict__ rp, int32_t* __restrict__ w) {
+    const int sl = blockIdx.x * blockDim.x + threadIdx.x;
+    if (sl >= nsl) return;
+    int m = 0;
+    for (int l = 0; l < 64; ++l) {
+        const int i = sl * 64 + l;
+        if (i < nrow_valid) m = max(m, rp[i + 1] - rp[i]);
+    }
+    w[sl] = m;
+}
+
+__global__ void k_sell_fill(int nsl, int nrow_valid, const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
+                            const float* __restrict__ K, const float* __restrict__ M, const int32_t* __restrict__ ptr,
+                            const int32_t* __restrict__ w, int32_t* __restrict__ scol, float* __restrict__ sK,
+                            float* __restrict__ sM, int values_only) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int sl = t >> 6, l = t & 63;
+    if (sl >= nsl) return;
+    const int i = sl * 64 + l;
+    const int b = i < nrow_valid ? rp[i] : 0;
+    const int len = i < nrow_valid ? rp[i + 1] - b : 0;
+    const int wd = w[sl];
+    for (int k = 0; k < wd; ++k) {
+        const size_t e = (size_t)ptr[sl] + (size_t)k * 64 + l;
+        if (k < len) {
+            if (!values_only) scol[e] = col[b + k];
+            sK[e] = K[b + k];
+            sM[e] = M[b + k];
+        } else {
+            if (!values_only) scol[e] = i < nrow_valid ? i : 0;
+            sK[e] = 0.f;
+            sM[e] = 0.f;
+        }
+    }
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------- host side
 
 struct SpmmChoice {
-    int kind = 0;   // 0 = column lanes, 1 = nonzero lanes
-    int a = 8, b = 1;   // (LPR, CPL) or (G, CM)
+    int kind = 0;   // 0 = column lanes, 1 = nonzero lanes, 2 = sliced ELLPACK
+    int a = 8, b = 1;   // (LPR, CPL), (G, CM) or (CM, U)
     float ms = 0.f;
+};
+
+struct SpmmTuned {
+    SpmmChoice best;   // fastest complex64 shape
+    SpmmChoice csr;    // fastest CSR shape (the double-precision residual uses it)
 };
 
 struct BlockWork {
     size_t cap_rows = 0;
     int cap_C = 0, cap_nsc = 0, cap_tiles = 0;
     double2 *X64 = nullptr, *R64 = nullptr, *B64 = nullptr;
-    float2 *Xi = nullptr, *R = nullptr, *P = nullptr, *Q = nullptr;
-    double2 *p0 = nullptr, *p1 = nullptr;
+    float2 *Xi = nullptr, *R = nullptr, *Z = nullptr, *P = nullptr, *Q = nullptr;
+    double2 *p0 = nullptr, *p1 = nullptr, *p2 = nullptr;
     ColState* st = nullptr;
+    ColState* st2 = nullptr;   // second state slot of the in-consumer reductions
     ColState* st_h = nullptr;
     double* wmu = nullptr;
     int* seg_tile = nullptr;
@@ -718,8 +1071,9 @@ struct BlockWork {
     int32_t *rp = nullptr, *col = nullptr;
     double *K64 = nullptr, *M64 = nullptr, *Kd = nullptr, *Md = nullptr;
     float *K32 = nullptr, *M32 = nullptr;
+    Sell cat_sell;
     size_t cat_rows = 0, cat_nnz = 0;
-    std::map<std::tuple<int, int64_t, int>, SpmmChoice> tuned;   // (n, nnz, C) -> choice
+    std::map<std::tuple<int, int64_t, int>, SpmmTuned> tuned;   // (n, nnz, C) -> choices
     hipGraphExec_t graph = nullptr;
     hipStream_t graph_stream = nullptr;
     std::vector<char> graph_sig;   // bytes of every argument baked into the graph
@@ -733,9 +1087,11 @@ struct BlockWork {
         release_graph();
         if (graph_stream) (void)hipStreamDestroy(graph_stream);
         graph_stream = nullptr;
-        dfree(X64); dfree(R64); dfree(B64); dfree(Xi); dfree(R); dfree(P); dfree(Q);
-        dfree(p0); dfree(p1); dfree(st); dfree(wmu); dfree(seg_tile); dfree(tile_seg);
+        dfree(X64); dfree(R64); dfree(B64); dfree(Xi); dfree(R); dfree(Z); dfree(P); dfree(Q);
+        dfree(p0); dfree(p1); dfree(p2); dfree(st); dfree(st2); dfree(wmu);
+        dfree(seg_tile); dfree(tile_seg);
         dfree(rp); dfree(col); dfree(K64); dfree(M64); dfree(Kd); dfree(Md); dfree(K32); dfree(M32);
+        cat_sell.release();
         if (st_h) (void)hipHostFree(st_h);
         st_h = nullptr;
         cap_rows = 0; cap_C = cap_nsc = cap_tiles = 0;
@@ -748,28 +1104,90 @@ void release_block_work(BlockWork*& w) {
     w = nullptr;
 }
 
+// (Re)build the sliced-ELLPACK copy of a complex64 operator of nrows rows
+// (a multiple of 64; rows from nrow_valid on are empty). The pattern is kept
+// when `pattern` is false and the slice count is unchanged; the values are
+// always refreshed.
+int build_sell(Sell& S, int nrows, int nrow_valid, const int32_t* rp, const int32_t* col, const float* K,
+               const float* M, bool pattern, hipStream_t s) {
+    const int nsl = nrows / 64;
+    if (pattern || S.nsl != nsl || !S.ptr) {
+        S.release();
+        PG_TRY(dalloc(&S.ptr, (size_t)nsl + 1));
+        PG_TRY(dalloc(&S.w, (size_t)nsl));
+        hipLaunchKernelGGL(k_sell_width, dim3(ceil_div(nsl, 256)), dim3(256), 0, s, nsl, nrow_valid, rp, S.w);
+        std::vector<int32_t> w(nsl), ptr(nsl + 1);
+        PG_HIP(hipMemcpyAsync(w.data(), S.w, sizeof(int32_t) * nsl, hipMemcpyDeviceToHost, s));
+        PG_HIP(hipStreamSynchronize(s));
+        int64_t tot = 0;
+        for (int k = 0; k < nsl; ++k) {
+            ptr[k] = (int32_t)tot;
+            tot += (int64_t)w[k] * 64;
+            if (tot >= (int64_t(1) << 31)) {
+                set_error("operator too large for 32-bit sliced-ELLPACK offsets");
+                return PETGEM_INVALID_ARG;
+            }
+        }
+        ptr[nsl] = (int32_t)tot;
+        PG_HIP(hipMemcpyAsync(S.ptr, ptr.data(), sizeof(int32_t) * (nsl + 1), hipMemcpyHostToDevice, s));
+        PG_TRY(dalloc(&S.col, (size_t)std::max<int64_t>(tot, 1)));
+        PG_TRY(dalloc(&S.K, (size_t)std::max<int64_t>(tot, 1)));
+        PG_TRY(dalloc(&S.M, (size_t)std::max<int64_t>(tot, 1)));
+        S.nsl = nsl;
+        S.elems = tot;
+        hipLaunchKernelGGL(k_sell_fill, dim3(ceil_div((size_t)nsl * 64, 256)), dim3(256), 0, s, nsl, nrow_valid, rp,
+                           col, K, M, S.ptr, S.w, S.col, S.K, S.M, 0);
+        // the host vectors above must outlive the copy
+        PG_HIP(hipStreamSynchronize(s));
+    } else {
+        hipLaunchKernelGGL(k_sell_fill, dim3(ceil_div((size_t)nsl * 64, 256)), dim3(256), 0, s, nsl, nrow_valid, rp,
+                           col, K, M, S.ptr, S.w, S.col, S.K, S.M, 1);
+    }
+    PG_HIP(hipGetLastError());
+    S.values = true;
+    return PETGEM_OK;
+}
+
 namespace {
 
+// Launch arguments of one SpMM (X, B, Y as described at the kernels).
+struct SpmmArgs {
+    const void* X;
+    const void* B;
+    void* Y;
+    double2* part;
+};
+
 template <typename T, int A, int B, int EPI, bool COLS>
-void spmm_thunk(Op op, const ColState* st, const void* X, const void* Bv, void* Y, double2* part, hipStream_t s) {
+void spmm_thunk(Op op, const ColState* st, const SpmmArgs& g, hipStream_t s) {
     using T2 = typename V2<T>::t;
     if constexpr (COLS)
         hipLaunchKernelGGL((k_spmm_c<T, A, B, EPI>), dim3(op.ntiles), dim3(256), 0, s, op, st,
-                           (const T2*)X, (const T2*)Bv, (T2*)Y, part);
+                           (const T2*)g.X, (const T2*)g.B, (T2*)g.Y, g.part);
     else
         hipLaunchKernelGGL((k_spmm_n<T, A, B, EPI>), dim3(op.ntiles * A), dim3(256), 0, s, op, st,
-                           (const T2*)X, (const T2*)Bv, (T2*)Y, part);
+                           (const T2*)g.X, (const T2*)g.B, (T2*)g.Y, g.part);
 }
 
 template <typename T, int EPI>
-bool spmm_dispatch_(const SpmmChoice& ch, Op op, const ColState* st, const void* X, const void* Bv, void* Y,
-                   double2* part, hipStream_t s) {
+bool spmm_dispatch_(const SpmmChoice& ch, Op op, const ColState* st, const SpmmArgs& g, hipStream_t s) {
+    if (ch.kind == 2) {
+        if constexpr (sizeof(T) == 4 && EPI == 1) {
+            if (!op.sp) return false;
+#define PG_S(CM, U) if (ch.a == CM && ch.b == U) { \
+            hipLaunchKernelGGL((k_spmm_s<CM, U>), dim3(op.ntiles), dim3(256), 0, s, op, st, (const float2*)g.X, \
+                               (float2*)g.Y, g.part); return true; }
+            PG_S(1, 4) PG_S(1, 8) PG_S(2, 4) PG_S(2, 8) PG_S(4, 4)
+#undef PG_S
+        }
+        return false;
+    }
     if (ch.kind == 1) {
-#define PG_N(G, CM) if (ch.a == G && ch.b == CM) { spmm_thunk<T, G, CM, EPI, false>(op, st, X, Bv, Y, part, s); return true; }
+#define PG_N(G, CM) if (ch.a == G && ch.b == CM) { spmm_thunk<T, G, CM, EPI, false>(op, st, g, s); return true; }
         PG_N(4, 1) PG_N(8, 1) PG_N(16, 1) PG_N(4, 2) PG_N(8, 2) PG_N(16, 2) PG_N(4, 4) PG_N(8, 4) PG_N(16, 4)
 #undef PG_N
     } else {
-#define PG_C(L, P) if (ch.a == L && ch.b == P) { spmm_thunk<T, L, P, EPI, true>(op, st, X, Bv, Y, part, s); return true; }
+#define PG_C(L, P) if (ch.a == L && ch.b == P) { spmm_thunk<T, L, P, EPI, true>(op, st, g, s); return true; }
         PG_C(8, 1) PG_C(8, 2) PG_C(8, 4) PG_C(16, 1) PG_C(16, 2) PG_C(16, 3) PG_C(16, 4)
         PG_C(32, 1) PG_C(32, 2) PG_C(32, 3) PG_C(32, 4) PG_C(64, 1) PG_C(64, 2) PG_C(64, 3) PG_C(64, 4)
 #undef PG_C
@@ -778,16 +1196,23 @@ bool spmm_dispatch_(const SpmmChoice& ch, Op op, const ColState* st, const void*
 }
 
 template <typename T, int EPI>
-void spmm_dispatch(const SpmmChoice& ch, Op op, const ColState* st, const void* X, const void* Bv, void* Y,
-                   double2* part, hipStream_t s) {
-    if (!spmm_dispatch_<T, EPI>(ch, op, st, X, Bv, Y, part, s)) abort();   // candidates() lists only instantiated shapes
+void spmm_dispatch(const SpmmChoice& ch, Op op, const ColState* st, const SpmmArgs& g, hipStream_t s) {
+    if (!spmm_dispatch_<T, EPI>(ch, op, st, g, s)) abort();   // candidates() lists only instantiated shapes
 }
 
-std::vector<SpmmChoice> candidates(int C) {
+// partial slots per tile of an SpMM shape
+int spmm_slots(const SpmmChoice& ch) { return ch.kind == 1 ? ch.a : 1; }
+
+
+std::vector<SpmmChoice> candidates(int C, bool sell) {
     std::vector<SpmmChoice> v;
     if (C <= 4) {
         const int cm = C <= 1 ? 1 : (C <= 2 ? 2 : 4);
         for (int g : {4, 8, 16}) v.push_back({1, g, cm});
+        if (sell) {
+            v.push_back({2, cm, 4});
+            if (cm < 4) v.push_back({2, cm, 8});
+        }
     }
     if (C >= 4) {
         for (int l : {8, 16, 32, 64})
@@ -814,8 +1239,9 @@ int ensure_work(BlockWork*& w, size_t rows, int C, int nsc, int ntiles) {
     if (w->cap_rows >= rows && w->cap_C == C && w->cap_nsc >= nsc && w->cap_tiles >= ntiles) return PETGEM_OK;
     // keep the concatenated operator, reallocate the vectors
     w->release_graph();
-    dfree(w->X64); dfree(w->R64); dfree(w->B64); dfree(w->Xi); dfree(w->R); dfree(w->P); dfree(w->Q);
-    dfree(w->p0); dfree(w->p1); dfree(w->st); dfree(w->wmu); dfree(w->seg_tile); dfree(w->tile_seg);
+    dfree(w->X64); dfree(w->R64); dfree(w->B64); dfree(w->Xi); dfree(w->R); dfree(w->Z); dfree(w->P);
+    dfree(w->Q);
+    dfree(w->p0); dfree(w->p1); dfree(w->p2); dfree(w->st); dfree(w->st2); dfree(w->wmu); dfree(w->seg_tile); dfree(w->tile_seg);
     if (w->st_h) (void)hipHostFree(w->st_h);
     w->st_h = nullptr;
     const size_t e = rows * (size_t)C;
@@ -824,11 +1250,15 @@ int ensure_work(BlockWork*& w, size_t rows, int C, int nsc, int ntiles) {
     PG_TRY(dalloc(&w->B64, e));
     PG_TRY(dalloc(&w->Xi, e));
     PG_TRY(dalloc(&w->R, e));
+    PG_TRY(dalloc(&w->Z, e));
     PG_TRY(dalloc(&w->P, e));
     PG_TRY(dalloc(&w->Q, e));
     PG_TRY(dalloc(&w->p0, (size_t)ntiles * C * (C <= 4 ? 16 : 1)));   // nonzero-lane SpMM: G slots per tile
     PG_TRY(dalloc(&w->p1, (size_t)ntiles * C));
+    PG_TRY(dalloc(&w->p2, (size_t)ntiles * C));
+
     PG_TRY(dalloc(&w->st, (size_t)nsc));
+    PG_TRY(dalloc(&w->st2, (size_t)nsc));
     PG_TRY(dalloc(&w->wmu, (size_t)nsc));
     PG_TRY(dalloc(&w->seg_tile, (size_t)nsc + 1));
     PG_TRY(dalloc(&w->tile_seg, (size_t)ntiles));
@@ -849,26 +1279,33 @@ int cp_of(int C) {
 // Autotuner of the complex64 SpMM tile shape: every candidate (lanes per row x
 // columns per lane, or lanes sharing a row's nonzeros) runs 3 times on this
 // operator and block width; the fastest is kept per (rows, nnz, columns).
-int tune_spmm(BlockWork* w, const Op& op, int64_t nnz, hipStream_t s, SpmmChoice& out) {
+int tune_spmm(BlockWork* w, const Op& op, int64_t nnz, hipStream_t s, SpmmTuned& out, bool verbose) {
     auto key = std::make_tuple(op.n, nnz, op.C);
     auto it = w->tuned.find(key);
     if (it != w->tuned.end()) { out = it->second; return PETGEM_OK; }
-    auto cands = candidates(op.C);
+    auto cands = candidates(op.C, op.sp != nullptr);
     hipEvent_t e0, e1;
     PG_HIP(hipEventCreate(&e0));
     PG_HIP(hipEventCreate(&e1));
-    SpmmChoice best = cands[0];
-    best.ms = 1e30f;
+    SpmmTuned best;
+    best.best.ms = best.csr.ms = 1e30f;
     for (auto& c : cands) {
-        spmm_dispatch<float, 1>(c, op, w->st, w->P, nullptr, w->Q, w->p0, s);   // warm-up
+        const SpmmArgs g{w->P, nullptr, w->Q, w->p0};
+        spmm_dispatch<float, 1>(c, op, w->st, g, s);   // warm-up
         PG_HIP(hipEventRecord(e0, s));
-        for (int r = 0; r < 3; ++r) spmm_dispatch<float, 1>(c, op, w->st, w->P, nullptr, w->Q, w->p0, s);
+        for (int r = 0; r < 3; ++r) spmm_dispatch<float, 1>(c, op, w->st, g, s);
         PG_HIP(hipEventRecord(e1, s));
         PG_HIP(hipEventSynchronize(e1));
         float ms = 0.f;
         PG_HIP(hipEventElapsedTime(&ms, e0, e1));
         c.ms = ms / 3.f;
-        if (c.ms < best.ms) best = c;
+        if (verbose) {
+            static const char* kinds[3] = {"column lanes", "nonzero lanes", "sliced ELLPACK"};
+            fprintf(stderr, "[petgem] SpMM tuning: %s %d x %d: %.1f us\n", kinds[c.kind], c.a, c.b, 1e3 * c.ms);
+            fflush(stderr);
+        }
+        if (c.ms < best.best.ms) best.best = c;
+        if (c.kind != 2 && c.ms < best.csr.ms) best.csr = c;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -883,14 +1320,19 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
                std::vector<petgem_stats*>& stv, bool have_x0) {
     const int C = op.C, nsc = op.nseg * C, CP = cp_of(C);
     Timer t_all;
-    SpmmChoice ch;
+    SpmmTuned tu;
     // P (complex64, rows x C) gets finite values and every column is live
     // for the tuning launches
     hipLaunchKernelGGL(k_fill_f2, dim3(ceil_div((size_t)op.n * C, 256)), dim3(256), 0, s,
                        (size_t)op.n * C, w->P);
     hipLaunchKernelGGL(k_set_live, dim3(ceil_div(nsc, 64)), dim3(64), 0, s, w->st, nsc);
-    PG_TRY(tune_spmm(w, op, nnz, s, ch));
-    const int ppS = ch.kind == 1 ? ch.a : 1;   // SpMM partial slots per tile
+    PG_TRY(tune_spmm(w, op, nnz, s, tu, o.verbose != 0));
+    const SpmmChoice ch = tu.best, ch64 = tu.csr;
+    const int ppS = spmm_slots(ch), pp64 = spmm_slots(ch64);
+    // the reductions run inside the vector kernels for one mesh whose
+    // partials are few enough for every block to sum
+    const bool in_consumer = op.nseg == 1 && (int64_t)op.ntiles * ppS * C <= kConsumerMax;
+    const int nbu = ceil_div(op.ntiles, kConsumerTiles);   // blocks of the two vector kernels
     hipLaunchKernelGGL(k_init_state, dim3(ceil_div(nsc, 64)), dim3(64), 0, s, w->st, nsc, o.rtol,
                        o.inner_rtol);
     const bool prof = o.profile != 0;
@@ -903,8 +1345,9 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
         evs.push_back(e);
     };
     auto residual = [&](int first) -> int {
-        spmm_dispatch<double, 2>(ch, op, w->st, w->X64, w->B64, w->R64, w->p0, s);
-        hipLaunchKernelGGL(k_reduce, dim3(nsc), dim3(1024), 0, s, op, w->p0, ppS, nullptr, 1, w->st, (int)RED_RES, first);
+        spmm_dispatch<double, 2>(ch64, op, w->st, SpmmArgs{w->X64, w->B64, w->R64, w->p0}, s);
+        hipLaunchKernelGGL(k_reduce, dim3(nsc), dim3(1024), 0, s, op, w->p0, pp64, nullptr, 1, w->st,
+                           (int)RED_RES, first);
         PG_HIP(hipGetLastError());
         return PETGEM_OK;
     };
@@ -916,7 +1359,8 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
     // |b| of every (segment, column)
     auto bnorms = [&]() -> int {
         hipLaunchKernelGGL(k_norm2, dim3(op.ntiles), dim3(256), 0, s, op, CP, w->B64, w->p0);
-        hipLaunchKernelGGL(k_reduce, dim3(nsc), dim3(1024), 0, s, op, w->p0, 1, nullptr, 1, w->st, (int)RED_RES, 1);
+        hipLaunchKernelGGL(k_reduce, dim3(nsc), dim3(1024), 0, s, op, w->p0, 1, nullptr, 1, w->st,
+                           (int)RED_RES, 1);
         PG_HIP(hipGetLastError());
         return PETGEM_OK;
     };
@@ -926,7 +1370,8 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
         // scale every guess by the alpha minimising |b - alpha A x0|
         PG_TRY(residual(0));
         hipLaunchKernelGGL(k_x0_dots, dim3(op.ntiles), dim3(256), 0, s, op, CP, w->B64, w->R64, w->p0, w->p1);
-        hipLaunchKernelGGL(k_reduce, dim3(nsc), dim3(1024), 0, s, op, w->p0, 1, w->p1, 1, w->st, (int)RED_X0, 0);
+        hipLaunchKernelGGL(k_reduce, dim3(nsc), dim3(1024), 0, s, op, w->p0, 1, w->p1, 1, w->st,
+                           (int)RED_X0, 0);
         hipLaunchKernelGGL(k_scale_cols, dim3(op.ntiles), dim3(256), 0, s, op, CP, w->st, w->X64);
         PG_HIP(hipGetLastError());
     }
@@ -954,16 +1399,28 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
     for (int k = 0; k < nsc; ++k)
         if (have_x0 && w->st_h[k].bnorm > 0) x0res[k] = fallback[k] ? 1.0 : w->st_h[k].rnorm64 / w->st_h[k].bnorm;
 
-    // one inner iteration, kCheck of them captured as a graph
+    // one inner iteration; a group of kCheck is captured as one graph
     auto iteration = [&]() {
         ev();
-        spmm_dispatch<float, 1>(ch, op, w->st, w->P, nullptr, w->Q, w->p0, s);
+        spmm_dispatch<float, 1>(ch, op, w->st, SpmmArgs{w->P, nullptr, w->Q, w->p0}, s);
         ev();
-        hipLaunchKernelGGL(k_reduce, dim3(nsc), dim3(1024), 0, s, op, w->p0, ppS, nullptr, 1, w->st, (int)RED_ALPHA, 0);
-        hipLaunchKernelGGL(k_update1, dim3(op.ntiles), dim3(256), 0, s, op, CP, w->st, w->Xi, w->R, w->P,
-                           w->Q, w->p0, w->p1);
-        hipLaunchKernelGGL(k_reduce, dim3(nsc), dim3(1024), 0, s, op, w->p0, 1, w->p1, 1, w->st, (int)RED_BETA, 0);
-        hipLaunchKernelGGL(k_update2, dim3(op.ntiles), dim3(256), 0, s, op, CP, w->st, w->R, w->P);
+        if (in_consumer) {
+            hipLaunchKernelGGL(k_update_p, dim3(nbu), dim3(256), 0, s, op, CP, kConsumerTiles, w->st, w->st2,
+                               w->p0, op.ntiles * ppS, w->Xi, w->R, w->Z, w->P, w->Q, w->p1, w->p2);
+            hipLaunchKernelGGL(k_pupdate_p, dim3(nbu), dim3(256), 0, s, op, CP, kConsumerTiles, w->st2, w->st,
+                               w->p1, w->p2, nbu, w->Z, w->P);
+        } else {
+            hipLaunchKernelGGL(k_reduce, dim3(nsc), dim3(1024), 0, s, op, w->p0, ppS, nullptr, 1, w->st,
+                               (int)RED_ALPHA, 0);
+            hipLaunchKernelGGL(k_update, dim3(op.ntiles), dim3(256), 0, s, op, CP, w->st, w->Xi, w->R, w->Z,
+                               w->P, w->Q, w->p1, w->p2);
+            hipLaunchKernelGGL(k_reduce, dim3(nsc), dim3(1024), 0, s, op, w->p1, 1, w->p2, 1, w->st,
+                               (int)RED_BETA, 0);
+            hipLaunchKernelGGL(k_pupdate, dim3(op.ntiles), dim3(256), 0, s, op, CP, w->st, w->Z, w->P);
+        }
+    };
+    auto group = [&]() {
+        for (int k = 0; k < kCheck; ++k) iteration();
     };
     const bool use_graph = o.use_graph && !prof;
     std::vector<char> sig;
@@ -973,9 +1430,9 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
             sig.insert(sig.end(), c, c + nb);
         };
         put(&op, sizeof(op));
-        const void* ptrs[8] = {w->Xi, w->R, w->P, w->Q, w->p0, w->p1, w->st, nullptr};
+        const void* ptrs[10] = {w->Xi, w->R, w->Z, w->P, w->Q, w->p0, w->p1, w->p2, w->st, w->st2};
         put(ptrs, sizeof(ptrs));
-        int chv[3] = {ch.kind, ch.a, ch.b};
+        int chv[4] = {ch.kind, ch.a, ch.b, (int)in_consumer};
         put(chv, sizeof(chv));
     }
     if (use_graph && (w->graph == nullptr || w->graph_sig != sig)) {
@@ -985,7 +1442,7 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
         hipStream_t caller = s;
         s = w->graph_stream;
         PG_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-        for (int k = 0; k < kCheck; ++k) iteration();
+        group();
         hipError_t ce = hipStreamEndCapture(s, &g);
         s = caller;
         if (ce != hipSuccess) {
@@ -1002,6 +1459,7 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
     }
 
     int total_inner = 0, steps = 0, strikes = 0;
+    const char* why = "";
     int status = PETGEM_OK;
     const int max_steps = 60;
     double prev_worst = 1e300;
@@ -1021,32 +1479,63 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
                 worst = std::max(worst, w->st_h[k].rnorm64 / w->st_h[k].bnorm);
         strikes = worst > 0.5 * prev_worst ? strikes + 1 : 0;
         prev_worst = worst;
-        if (strikes >= 3) { status = PETGEM_NOT_CONVERGED; break; }
-        if (steps >= max_steps || total_inner >= o.max_iter) { status = PETGEM_NOT_CONVERGED; break; }
+        if (strikes >= 3) {
+            status = PETGEM_NOT_CONVERGED;
+            why = "stagnated (the worst residual did not halve in 3 refinement steps)";
+            break;
+        }
+        if (steps >= max_steps || total_inner >= o.max_iter) {
+            status = PETGEM_NOT_CONVERGED;
+            why = steps >= max_steps ? "reached its refinement step limit" : "reached max_iter";
+            break;
+        }
         // inner complex64 COCG on A d = r64 / |r64|
         hipLaunchKernelGGL(k_inner_init, dim3(op.ntiles), dim3(256), 0, s, op, CP, w->R64, w->st, w->Xi,
-                           w->R, w->P, w->p0, w->p1);
-        hipLaunchKernelGGL(k_reduce, dim3(nsc), dim3(1024), 0, s, op, w->p0, 1, w->p1, 1, w->st, (int)RED_INIT, 0);
-        int inner = 0;
+                           w->R, w->Z, w->P, w->p1, w->p2);
+        hipLaunchKernelGGL(k_reduce, dim3(nsc), dim3(1024), 0, s, op, w->p1, 1, w->p2, 1, w->st,
+                           (int)RED_INIT, 0);
+        // Groups of kCheck iterations run between host checks; the number of
+        // groups in a row follows the observed decrease of the worst active
+        // residual (half the predicted need, at most kMaxGroups), so that the
+        // readbacks are few while little runs past convergence.
+        int inner = 0, groups = 1, next_print = 512;
+        double prev_gap = -1.0;
         while (true) {
-            if (use_graph) {
-                PG_HIP(hipGraphLaunch(w->graph, s));
-            } else {
-                for (int k = 0; k < kCheck; ++k) iteration();
+            for (int g = 0; g < groups; ++g) {
+                if (use_graph) {
+                    PG_HIP(hipGraphLaunch(w->graph, s));
+                } else {
+                    group();
+                }
             }
-            inner += kCheck;
+            inner += kCheck * groups;
             PG_TRY(read_state());
             int act = 0;
-            for (int k = 0; k < nsc; ++k) act += w->st_h[k].active;
-            if (o.verbose && inner % 512 == 0) {
+            double gap = 0.0;   // worst log(|r|^2 / tol^2) over the active columns
+            for (int k = 0; k < nsc; ++k) {
+                const ColState& S = w->st_h[k];
+                if (!S.active) continue;
+                ++act;
+                if (S.rn2 > 0.0 && S.inner_tol2 > 0.0) gap = std::max(gap, std::log(S.rn2 / S.inner_tol2));
+            }
+            if (o.verbose && inner >= next_print) {
                 double worst = 0.0;
                 for (int k = 0; k < nsc; ++k)
                     if (w->st_h[k].active) worst = std::max(worst, w->st_h[k].rn2);
                 fprintf(stderr, "[petgem]   inner %d: %d active, worst inner residual %.3e, %.0f ms\n", inner, act,
                         std::sqrt(worst), t_all.ms());
                 fflush(stderr);
+                next_print += 512;
             }
             if (act == 0 || total_inner + inner >= o.max_iter) break;
+            const int ran = groups;
+            groups = 1;
+            if (prev_gap > 0.0 && gap < prev_gap && std::isfinite(gap)) {
+                const double per_group = (prev_gap - gap) / ran;
+                groups = (int)std::min<double>(kMaxGroups, std::max(1.0, 0.5 * gap / per_group));
+            }
+            groups = std::max(1, std::min(groups, (o.max_iter - total_inner - inner) / kCheck));
+            prev_gap = gap;
         }
         total_inner += inner;
         hipLaunchKernelGGL(k_ir_update, dim3(op.ntiles), dim3(256), 0, s, op, CP, w->st, w->Xi, w->X64);
@@ -1094,7 +1583,20 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
         st->status = S.outer ? (std::isfinite(S.rnorm64) ? PETGEM_NOT_CONVERGED : PETGEM_NONFINITE) : PETGEM_OK;
         if (st->status != PETGEM_OK && status == PETGEM_OK) status = st->status;
     }
-    if (status == PETGEM_NOT_CONVERGED) set_error("COCG refinement reached its iteration limit before rtol");
+    if (status == PETGEM_NOT_CONVERGED) {
+        int kw = 0;
+        double worst = -1.0;
+        for (int k = 0; k < nsc; ++k)
+            if (w->st_h[k].outer && w->st_h[k].bnorm > 0 && w->st_h[k].rnorm64 / w->st_h[k].bnorm > worst) {
+                worst = w->st_h[k].rnorm64 / w->st_h[k].bnorm;
+                kw = k;
+            }
+        char msg[256];
+        snprintf(msg, sizeof msg, "COCG refinement %s before rtol %.1e: %d steps, %d inner iterations, "
+                 "worst relative residual %.3e (segment %d, column %d)", why, o.rtol, steps, total_inner,
+                 worst, kw / C, kw % C);
+        set_error(msg);
+    }
     if (status == PETGEM_NONFINITE) set_error("non-finite value in the COCG recurrence");
     return status;
 }
@@ -1114,7 +1616,7 @@ int block_solve(petgem_system* sys, const petgem_source* src, int32_t n_src, con
     int seg_tile[2] = {0, ntiles};
     PG_HIP(hipMemcpyAsync(w->wmu, wmu.data(), sizeof(double) * C, hipMemcpyHostToDevice, s));
     PG_HIP(hipMemcpyAsync(w->seg_tile, seg_tile, sizeof(seg_tile), hipMemcpyHostToDevice, s));
-    Op op;
+    Op op{};
     op.n = (int)rows;
     op.C = C;
     op.ntiles = ntiles;
@@ -1131,6 +1633,15 @@ int block_solve(petgem_system* sys, const petgem_source* src, int32_t n_src, con
     op.Md = sys->Msd;
     op.wmu = w->wmu;
     op.nrow_valid = n;
+    if (C <= 4) {   // the sliced-ELLPACK shapes serve up to four columns
+        Sell& S = sys->sell32;
+        if (!S.ptr || !S.values) PG_TRY(build_sell(S, (int)rows, n, sys->row_ptr, sys->col, sys->K32, sys->Ms32, false, s));
+        op.sp = S.ptr;
+        op.sw = S.w;
+        op.scol = S.col;
+        op.sK = S.K;
+        op.sM = S.M;
+    }
     // right-hand sides into the block layout (padding rows stay zero)
     Timer t_rhs;
     hipLaunchKernelGGL(k_fill_z, dim3(ceil_div(rows * C, 256)), dim3(256), 0, s, rows * C, w->B64);
@@ -1224,7 +1735,7 @@ int batch_solve(petgem_system* const* systems, const petgem_source* src, int32_t
     PG_HIP(hipMemcpyAsync(w->wmu, wmu.data(), sizeof(double) * n_sys, hipMemcpyHostToDevice, s));
     PG_HIP(hipMemcpyAsync(w->seg_tile, seg_tile.data(), sizeof(int) * (n_sys + 1), hipMemcpyHostToDevice, s));
     PG_HIP(hipMemcpyAsync(w->tile_seg, tseg.data(), sizeof(int) * ntiles, hipMemcpyHostToDevice, s));
-    Op op;
+    Op op{};
     op.n = (int)rows;
     op.C = 1;
     op.ntiles = ntiles;
@@ -1241,6 +1752,12 @@ int batch_solve(petgem_system* const* systems, const petgem_source* src, int32_t
     op.Md = w->Md;
     op.wmu = w->wmu;
     op.nrow_valid = (int)rows;
+    PG_TRY(build_sell(w->cat_sell, (int)rows, (int)rows, w->rp, w->col, w->K32, w->M32, true, s));
+    op.sp = w->cat_sell.ptr;
+    op.sw = w->cat_sell.w;
+    op.scol = w->cat_sell.col;
+    op.sK = w->cat_sell.K;
+    op.sM = w->cat_sell.M;
     Timer t_rhs;
     hipLaunchKernelGGL(k_fill_z, dim3(ceil_div(rows, 256)), dim3(256), 0, s, rows, w->B64);
     hipLaunchKernelGGL(k_fill_z, dim3(ceil_div(rows, 256)), dim3(256), 0, s, rows, w->X64);

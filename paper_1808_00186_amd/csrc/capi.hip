@@ -77,6 +77,7 @@ void release_system(petgem_system* sys) {
     dfree(sys->xyz); dfree(sys->tets); dfree(sys->sigma); dfree(sys->row_ptr); dfree(sys->col);
     dfree(sys->diag_pos); dfree(sys->cptr); dfree(sys->cidx); dfree(sys->iptr); dfree(sys->islot);
     dfree(sys->Kst); dfree(sys->Mst); dfree(sys->K); dfree(sys->Ms); dfree(sys->Kd); dfree(sys->Msd);
+    sys->sell32.release();
     dfree(sys->K32); dfree(sys->Ms32); dfree(sys->Ahat); dfree(sys->dvec); dfree(sys->dinv);
     dfree(sys->Rst); dfree(sys->dflag); dfree(sys->tmp);
     dfree(sys->vox_tet); dfree(sys->vox_dof); dfree(sys->dof_mid); dfree(sys->dof_tan);

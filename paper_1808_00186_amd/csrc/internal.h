@@ -52,6 +52,27 @@ inline void dfree(T*& p) {
     p = nullptr;
 }
 
+// Sliced-ELLPACK copy of the complex64 operator (the pattern and the real K,
+// M_sigma values): slices of 64 rows, stored column-major inside a slice so a
+// wavefront reads one entry of each of its 64 rows per load; rows are padded
+// to the slice's longest with zero values that point at the row itself.
+struct Sell {
+    int nsl = 0;
+    int64_t elems = 0;
+    int32_t* ptr = nullptr;   // [nsl + 1] first element of each slice
+    int32_t* w = nullptr;     // [nsl] slice width
+    int32_t* col = nullptr;   // [elems]
+    float* K = nullptr;       // [elems]
+    float* M = nullptr;       // [elems]
+    bool values = false;      // K, M current
+    void release() {
+        dfree(ptr); dfree(w); dfree(col); dfree(K); dfree(M);
+        nsl = 0;
+        elems = 0;
+        values = false;
+    }
+};
+
 // ------------------------------------------------------- GMRES control block
 // Small device-resident state of one GMRES cycle: the Hessenberg column in
 // progress, Givens rotations, the least-squares right-hand side g and flags
@@ -135,6 +156,7 @@ struct petgem_system {
     float* K32 = nullptr;
     float* Ms32 = nullptr;
     bool have32 = false;
+    petgem::Sell sell32;     // sliced-ELLPACK copy of K32 / Ms32 (built on first use)
     // frequency-specific operator of the FP64 GMRES: Ahat = A D^{-1}
     double cached_freq = -1.0;
     double2* Ahat = nullptr;              // [nnz]
