@@ -109,12 +109,18 @@ typedef struct {
     double  t_solve_ms;
     double  spmv_ms;        /* profile: summed duration of sparse-matrix kernels */
     int32_t spmv_launches;  /* profile: number of such launches                  */
-    int32_t pad;
+    int32_t spmv_shape;     /* COCG: the autotuned complex64 SpMM shape,
+                               10000 kind + 100 a + b with kind 0 = CSR column
+                               lanes (a lanes per row, b columns per lane),
+                               1 = CSR nonzero lanes (a lanes per row, b
+                               columns), 2 = sliced ELLPACK (a columns, b
+                               slice columns in flight); GMRES: the lanes per
+                               row of the complex128 CSR SpMV                   */
     double  b_norm;         /* |b|_2 of the source's right-hand side            */
 } petgem_stats;
 
 /* Fill *opts with the defaults: GMRES, FP64, restart 30, max_iter 20000,
- * rtol 1e-8, inner_rtol 1e-4, use_graph 1, profile 0, verbose 0. */
+ * rtol 1e-8, inner_rtol 3e-5, use_graph 1, profile 0, verbose 0. */
 void petgem_default_opts(petgem_opts* opts);
 
 /* ---- assembly (Section 3, eq. 9; Section 4; Appendix B) -----------------

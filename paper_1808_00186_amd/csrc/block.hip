@@ -43,6 +43,8 @@
 #include <map>
 #include <tuple>
 
+#include <hip/hip_ext.h>
+
 #include "device.h"
 #include "internal.h"
 
@@ -1150,23 +1152,36 @@ int build_sell(Sell& S, int nrows, int nrow_valid, const int32_t* rp, const int3
 
 namespace {
 
-// Launch arguments of one SpMM (X, B, Y as described at the kernels).
+// Launch arguments of one SpMM (X, B, Y as described at the kernels; e0 / e1
+// optional events the dispatch timestamps at the kernel's start and end).
 struct SpmmArgs {
     const void* X;
     const void* B;
     void* Y;
     double2* part;
+    hipEvent_t e0 = nullptr;
+    hipEvent_t e1 = nullptr;
 };
+
+// launch through the timestamping dispatch only when events are given (plain
+// launches are what the graphs capture)
+template <typename K, typename... Args>
+void launch_timed(K kernel, dim3 grid, hipStream_t s, hipEvent_t e0, hipEvent_t e1, Args... args) {
+    if (e0)
+        hipExtLaunchKernelGGL(kernel, grid, dim3(256), 0, s, e0, e1, 0, args...);
+    else
+        hipLaunchKernelGGL(kernel, grid, dim3(256), 0, s, args...);
+}
 
 template <typename T, int A, int B, int EPI, bool COLS>
 void spmm_thunk(Op op, const ColState* st, const SpmmArgs& g, hipStream_t s) {
     using T2 = typename V2<T>::t;
     if constexpr (COLS)
-        hipLaunchKernelGGL((k_spmm_c<T, A, B, EPI>), dim3(op.ntiles), dim3(256), 0, s, op, st,
-                           (const T2*)g.X, (const T2*)g.B, (T2*)g.Y, g.part);
+        launch_timed(k_spmm_c<T, A, B, EPI>, dim3(op.ntiles), s, g.e0, g.e1, op, st, (const T2*)g.X,
+                     (const T2*)g.B, (T2*)g.Y, g.part);
     else
-        hipLaunchKernelGGL((k_spmm_n<T, A, B, EPI>), dim3(op.ntiles * A), dim3(256), 0, s, op, st,
-                           (const T2*)g.X, (const T2*)g.B, (T2*)g.Y, g.part);
+        launch_timed(k_spmm_n<T, A, B, EPI>, dim3(op.ntiles * A), s, g.e0, g.e1, op, st, (const T2*)g.X,
+                     (const T2*)g.B, (T2*)g.Y, g.part);
 }
 
 template <typename T, int EPI>
@@ -1175,8 +1190,8 @@ bool spmm_dispatch_(const SpmmChoice& ch, Op op, const ColState* st, const SpmmA
         if constexpr (sizeof(T) == 4 && EPI == 1) {
             if (!op.sp) return false;
 #define PG_S(CM, U) if (ch.a == CM && ch.b == U) { \
-            hipLaunchKernelGGL((k_spmm_s<CM, U>), dim3(op.ntiles), dim3(256), 0, s, op, st, (const float2*)g.X, \
-                               (float2*)g.Y, g.part); return true; }
+            launch_timed(k_spmm_s<CM, U>, dim3(op.ntiles), s, g.e0, g.e1, op, st, (const float2*)g.X, \
+                         (float2*)g.Y, g.part); return true; }
             PG_S(1, 4) PG_S(1, 8) PG_S(2, 4) PG_S(2, 8) PG_S(4, 4)
 #undef PG_S
         }
@@ -1337,12 +1352,14 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
                        o.inner_rtol);
     const bool prof = o.profile != 0;
     std::vector<hipEvent_t> evs;
-    auto ev = [&]() {
-        if (!prof) return;
-        hipEvent_t e;
-        (void)hipEventCreate(&e);
-        (void)hipEventRecord(e, s);
-        evs.push_back(e);
+    // a (start, end) pair the next SpMM dispatch timestamps, or nulls
+    auto ev_pair = [&](SpmmArgs g) -> SpmmArgs {
+        if (!prof) return g;
+        (void)hipEventCreate(&g.e0);
+        (void)hipEventCreate(&g.e1);
+        evs.push_back(g.e0);
+        evs.push_back(g.e1);
+        return g;
     };
     auto residual = [&](int first) -> int {
         spmm_dispatch<double, 2>(ch64, op, w->st, SpmmArgs{w->X64, w->B64, w->R64, w->p0}, s);
@@ -1401,9 +1418,7 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
 
     // one inner iteration; a group of kCheck is captured as one graph
     auto iteration = [&]() {
-        ev();
-        spmm_dispatch<float, 1>(ch, op, w->st, SpmmArgs{w->P, nullptr, w->Q, w->p0}, s);
-        ev();
+        spmm_dispatch<float, 1>(ch, op, w->st, ev_pair(SpmmArgs{w->P, nullptr, w->Q, w->p0}), s);
         if (in_consumer) {
             hipLaunchKernelGGL(k_update_p, dim3(nbu), dim3(256), 0, s, op, CP, kConsumerTiles, w->st, w->st2,
                                w->p0, op.ntiles * ppS, w->Xi, w->R, w->Z, w->P, w->Q, w->p1, w->p2);
@@ -1580,6 +1595,7 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
         st->t_solve_ms = t_solve;
         st->spmv_ms = spmv_ms;
         st->spmv_launches = spmv_n;
+        st->spmv_shape = 10000 * ch.kind + 100 * ch.a + ch.b;
         st->status = S.outer ? (std::isfinite(S.rnorm64) ? PETGEM_NOT_CONVERGED : PETGEM_NONFINITE) : PETGEM_OK;
         if (st->status != PETGEM_OK && status == PETGEM_OK) status = st->status;
     }

@@ -106,7 +106,7 @@ void petgem_default_opts(petgem_opts* o) {
     o->restart = 30;
     o->max_iter = 20000;
     o->rtol = 1e-8;
-    o->inner_rtol = 1e-4;
+    o->inner_rtol = 3e-5;
     o->use_graph = 1;
     o->profile = 0;
     o->verbose = 0;

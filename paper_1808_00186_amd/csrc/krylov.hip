@@ -24,6 +24,8 @@
 #include <cstdio>
 #include <utility>
 
+#include <hip/hip_ext.h>
+
 #include "device.h"
 #include "internal.h"
 
@@ -444,14 +446,23 @@ void mdot_launch(int j, int nb, int n, const double2* V, size_t ldv, const doubl
         hipLaunchKernelGGL(k_mdot, dim3(nb), dim3(256), 0, s, n, j, V, ldv, w, partial, ctl, flags);
 }
 
+// e0 / e1 (optional): events the dispatch itself timestamps at the kernel's
+// start and end, for profiling without extra packets between kernels.
 template <bool RES>
 void spmv_launch(int G, int n, const int32_t* rp, const int32_t* col, const double2* val,
-                 const double2* x, const double2* b, double2* y, const int* done, hipStream_t s) {
+                 const double2* x, const double2* b, double2* y, const int* done, hipStream_t s,
+                 hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
     const int nblk = ceil_div((int64_t)n * G, 256);
+    auto go = [&](auto kernel) {   // the timestamping dispatch only when profiling
+        if (e0)
+            hipExtLaunchKernelGGL(kernel, dim3(nblk), dim3(256), 0, s, e0, e1, 0, n, rp, col, val, x, b, y, done);
+        else
+            hipLaunchKernelGGL(kernel, dim3(nblk), dim3(256), 0, s, n, rp, col, val, x, b, y, done);
+    };
     switch (G) {
-        case 4: hipLaunchKernelGGL((k_spmv<4, RES>), dim3(nblk), dim3(256), 0, s, n, rp, col, val, x, b, y, done); break;
-        case 16: hipLaunchKernelGGL((k_spmv<16, RES>), dim3(nblk), dim3(256), 0, s, n, rp, col, val, x, b, y, done); break;
-        default: hipLaunchKernelGGL((k_spmv<8, RES>), dim3(nblk), dim3(256), 0, s, n, rp, col, val, x, b, y, done); break;
+        case 4: go(k_spmv<4, RES>); break;
+        case 16: go(k_spmv<16, RES>); break;
+        default: go(k_spmv<8, RES>); break;
     }
 }
 
@@ -479,18 +490,21 @@ struct Timer {
     }
 };
 
-// Profiling: events around every sparse-matrix launch of the solve.
+// Profiling: a pair of events per sparse-matrix launch, timestamped by the
+// dispatch itself (start and end of the kernel).
 struct SpmvTimer {
     bool on = false;
     std::vector<hipEvent_t> ev;
-    void start(hipStream_t s) {
-        if (!on) return;
-        hipEvent_t a;
+    // the (start, end) events for the next launch, or nulls when off
+    std::pair<hipEvent_t, hipEvent_t> next() {
+        if (!on) return {nullptr, nullptr};
+        hipEvent_t a, b;
         (void)hipEventCreate(&a);
-        (void)hipEventRecord(a, s);
+        (void)hipEventCreate(&b);
         ev.push_back(a);
+        ev.push_back(b);
+        return {a, b};
     }
-    void stop(hipStream_t s) { start(s); }
     void collect(petgem_stats* st) {
         if (!on) return;
         (void)hipEventSynchronize(ev.empty() ? nullptr : ev.back());
@@ -587,9 +601,9 @@ int gmres_solve(petgem_system* sys, const petgem_source& src, const petgem_opts&
     if (st) st->t_rhs_ms = t_rhs.ms();
 
     auto residual = [&]() -> int {   // V0 = b - Ahat u, rnorm, g, flags
-        prof.start(s);
-        spmv_launch<true>(G, n, sys->row_ptr, sys->col, sys->Ahat, w.u, w.b, w.V, nullptr, s);
-        prof.stop(s);
+        const auto pe = prof.next();
+        spmv_launch<true>(G, n, sys->row_ptr, sys->col, sys->Ahat, w.u, w.b, w.V, nullptr, s, pe.first,
+                          pe.second);
         mdot_launch(-1, w.nb_dot, n, w.V, ldv, w.V, reinterpret_cast<double2*>(w.partial), w.ctl, 0, s);
         hipLaunchKernelGGL(k_cycle_start, dim3(1), dim3(1024), 0, s, w.nb_dot,
                            reinterpret_cast<const double2*>(w.partial), w.ctl, tail_d);
@@ -607,9 +621,9 @@ int gmres_solve(petgem_system* sys, const petgem_source& src, const petgem_opts&
         for (int j = 0; j < m; ++j) {
             double2* vj = w.V + (size_t)j * ldv;
             double2* vj1 = w.V + (size_t)(j + 1) * ldv;
-            prof.start(s);
-            spmv_launch<false>(G, n, sys->row_ptr, sys->col, sys->Ahat, vj, nullptr, vj1, &w.ctl->done, s);
-            prof.stop(s);
+            const auto pe = prof.next();
+            spmv_launch<false>(G, n, sys->row_ptr, sys->col, sys->Ahat, vj, nullptr, vj1, &w.ctl->done, s,
+                               pe.first, pe.second);
             mdot_launch(j, w.nb_dot, n, w.V, ldv, vj1, part, w.ctl, 1, s);
             hipLaunchKernelGGL(k_fin, dim3(1), dim3(1024), 0, s, j, w.nb_dot, part, w.ctl, 0);
             hipLaunchKernelGGL(k_update, dim3(nbv), dim3(256), 0, s, n, j, w.V, ldv, w.ctl, 0);
@@ -736,6 +750,7 @@ int gmres_solve(petgem_system* sys, const petgem_source& src, const petgem_opts&
     if (st) {
         st->iters = iters;
         st->ir_steps = cycles;
+        st->spmv_shape = sys->spmv_group;
         st->rel_residual = rnorm / bnorm;
         st->status = status;
         st->t_solve_ms = t_all.ms();

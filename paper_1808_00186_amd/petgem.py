@@ -56,7 +56,7 @@ class Stats(C.Structure):
                 ("status", C.c_int32), ("rel_residual", C.c_double),
                 ("x0_rel_residual", C.c_double), ("t_rhs_ms", C.c_double),
                 ("t_solve_ms", C.c_double), ("spmv_ms", C.c_double),
-                ("spmv_launches", C.c_int32), ("pad", C.c_int32), ("b_norm", C.c_double)]
+                ("spmv_launches", C.c_int32), ("spmv_shape", C.c_int32), ("b_norm", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad"}
