@@ -95,7 +95,10 @@ typedef struct {
     int32_t profile;        /* time the sparse-matrix kernels with HIP events   */
     int32_t verbose;        /* print one progress line per refinement step or
                                per 10 GMRES cycles to stderr                    */
-    int32_t pad;
+    int32_t spmm_shape;     /* COCG: 0 = autotune the complex64 SpMM shape;
+                               otherwise that shape, encoded as the
+                               spmv_shape statistic (PETGEM_INVALID_ARG if it
+                               is not a candidate for this column count)       */
 } petgem_opts;
 
 typedef struct {
@@ -120,7 +123,7 @@ typedef struct {
 } petgem_stats;
 
 /* Fill *opts with the defaults: GMRES, FP64, restart 30, max_iter 20000,
- * rtol 1e-8, inner_rtol 3e-5, use_graph 1, profile 0, verbose 0. */
+ * rtol 1e-8, inner_rtol 3e-5, use_graph 1, profile 0, verbose 0, spmm_shape 0. */
 void petgem_default_opts(petgem_opts* opts);
 
 /* ---- assembly (Section 3, eq. 9; Section 4; Appendix B) -----------------

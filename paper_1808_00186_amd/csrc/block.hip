@@ -711,9 +711,20 @@ __device__ __forceinline__ void cols_sum2(const double2* __restrict__ p0, const 
     const int c = threadIdx.x % CP, slot = threadIdx.x / CP, RPB = 256 / CP;
     double2 a = make_double2(0.0, 0.0), b = make_double2(0.0, 0.0);
     if (c < C) {
-        for (int e = slot; e < nslot; e += RPB) {
-            a = cadd(a, p0[(size_t)e * C + c]);
-            if (p1) b = cadd(b, p1[(size_t)e * C + c]);
+        // eight loads in flight, then the additions in the same order
+        for (int e0 = slot; e0 < nslot; e0 += 8 * RPB) {
+            double2 va[8], vb[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int e = e0 + u * RPB;
+                va[u] = e < nslot ? p0[(size_t)e * C + c] : make_double2(0.0, 0.0);
+                vb[u] = (p1 && e < nslot) ? p1[(size_t)e * C + c] : make_double2(0.0, 0.0);
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                a = cadd(a, va[u]);
+                b = cadd(b, vb[u]);
+            }
         }
     }
     cp_sum2(a, b, CP, la, lb);
@@ -730,13 +741,24 @@ k_update_p(Op op, int CP, int tpb, const ColState* __restrict__ s1, ColState* __
     __shared__ double2 ra[256], rb[256];
     const int C = op.C;
     const int c = threadIdx.x % CP, slot = threadIdx.x / CP, RPB = 256 / CP;
-    // the two scalars the update needs are loaded ahead of the partial sums
-    int act0 = 0;
-    double2 rho = make_double2(0.0, 0.0);
-    if (c < C) {
-        act0 = s1[c].active;
-        rho = s1[c].rho;
-    }
+    const int i0 = blockIdx.x * tpb * kTR, i1 = min(i0 + tpb * kTR, op.nrow_valid);
+    const int cc = min(c, C - 1);   // lanes past the last column load column C-1 and store nothing
+    // The first four rows' vectors and the two scalars the update needs are
+    // loaded ahead of the partial sums (none of them depends on alpha).
+    float2 p[4], q[4], x[4], r[4];
+    double kd[4], md[4];
+    auto load4 = [&](int ib) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int i = max(min(ib + u * RPB, i1 - 1), 0);   // in range; the duplicates are not stored
+            const size_t o = (size_t)i * C + cc;
+            p[u] = P[o]; q[u] = Q[o]; x[u] = Xi[o]; r[u] = R[o];
+            kd[u] = op.Kd[i]; md[u] = op.Md[i];
+        }
+    };
+    load4(i0 + slot);
+    const int act0 = s1[cc].active;
+    const double2 rho = s1[cc].rho;
     cols_sum2(ps, nullptr, nps, C, CP, ra, rb);
     bool act = false;
     double2 alpha = make_double2(0.0, 0.0);
@@ -755,18 +777,8 @@ k_update_p(Op op, int CP, int tpb, const ColState* __restrict__ s1, ColState* __
     if (act) {
         const float ax = (float)alpha.x, ay = (float)alpha.y;
         const double wmu = op.wmu[c];
-        const int i0 = blockIdx.x * tpb * kTR, i1 = min(i0 + tpb * kTR, op.nrow_valid);
-        // four rows per thread in flight: all loads first
         for (int ib = i0 + slot; ib < i1; ib += 4 * RPB) {
-            float2 p[4], q[4], x[4], r[4];
-            double kd[4], md[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int i = min(ib + u * RPB, i1 - 1);   // in range; the duplicates are not stored
-                const size_t o = (size_t)i * C + c;
-                p[u] = P[o]; q[u] = Q[o]; x[u] = Xi[o]; r[u] = R[o];
-                kd[u] = op.Kd[i]; md[u] = op.Md[i];
-            }
+            if (ib != i0 + slot) load4(ib);
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const int i = ib + u * RPB;
@@ -802,6 +814,19 @@ k_pupdate_p(Op op, int CP, int tpb, const ColState* __restrict__ s0, ColState* _
     __shared__ double2 ra[256], rb[256];
     const int C = op.C;
     const int c = threadIdx.x % CP, slot = threadIdx.x / CP, RPB = 256 / CP;
+    const int i0 = blockIdx.x * tpb * kTR, i1 = min(i0 + tpb * kTR, op.nrow_valid);
+    const int cc = min(c, C - 1);   // lanes past the last column load column C-1 and store nothing
+    // the first four rows of z and p are loaded ahead of the partial sums
+    float2 z[4], p[4];
+    auto load4 = [&](int ib) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const size_t o = (size_t)max(min(ib + u * RPB, i1 - 1), 0) * C + cc;   // duplicates are not stored
+            z[u] = Z[o];
+            p[u] = P[o];
+        }
+    };
+    load4(i0 + slot);
     cols_sum2(pg, pr, npu, C, CP, ra, rb);
     if (c >= C) return;
     ColState S = s0[c];
@@ -809,15 +834,8 @@ k_pupdate_p(Op op, int CP, int tpb, const ColState* __restrict__ s0, ColState* _
     if (blockIdx.x == 0 && slot == 0) s1[c] = S;
     if (!S.active) return;
     const float bx = (float)S.beta.x, by = (float)S.beta.y;
-    const int i0 = blockIdx.x * tpb * kTR, i1 = min(i0 + tpb * kTR, op.nrow_valid);
     for (int ib = i0 + slot; ib < i1; ib += 4 * RPB) {
-        float2 z[4], p[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const size_t o = (size_t)min(ib + u * RPB, i1 - 1) * C + c;   // duplicates are not stored
-            z[u] = Z[o];
-            p[u] = P[o];
-        }
+        if (ib != i0 + slot) load4(ib);
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int i = ib + u * RPB;
@@ -1342,6 +1360,20 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
                        (size_t)op.n * C, w->P);
     hipLaunchKernelGGL(k_set_live, dim3(ceil_div(nsc, 64)), dim3(64), 0, s, w->st, nsc);
     PG_TRY(tune_spmm(w, op, nnz, s, tu, o.verbose != 0));
+    if (o.spmm_shape != 0) {   // a caller-chosen shape instead of the tuned one
+        bool found = false;
+        for (const SpmmChoice& c : candidates(op.C, op.sp != nullptr))
+            if (10000 * c.kind + 100 * c.a + c.b == o.spmm_shape) {
+                tu.best = c;
+                if (c.kind != 2) tu.csr = c;
+                found = true;
+            }
+        if (!found) {
+            set_error("spmm_shape " + std::to_string(o.spmm_shape) + " is not a candidate for " +
+                      std::to_string(op.C) + " columns");
+            return PETGEM_INVALID_ARG;
+        }
+    }
     const SpmmChoice ch = tu.best, ch64 = tu.csr;
     const int ppS = spmm_slots(ch), pp64 = spmm_slots(ch64);
     // the reductions run inside the vector kernels for one mesh whose

@@ -110,6 +110,7 @@ void petgem_default_opts(petgem_opts* o) {
     o->use_graph = 1;
     o->profile = 0;
     o->verbose = 0;
+    o->spmm_shape = 0;
 }
 
 int petgem_assemble(const petgem_mesh* mesh, const double* sigma, double sigma_bg, void* stream,

@@ -48,7 +48,7 @@ class Opts(C.Structure):
     _fields_ = [("method", C.c_int32), ("precision", C.c_int32), ("restart", C.c_int32),
                 ("max_iter", C.c_int32), ("rtol", C.c_double), ("inner_rtol", C.c_double),
                 ("use_graph", C.c_int32), ("profile", C.c_int32), ("verbose", C.c_int32),
-                ("pad", C.c_int32)]
+                ("spmm_shape", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -59,7 +59,7 @@ class Stats(C.Structure):
                 ("spmv_launches", C.c_int32), ("spmv_shape", C.c_int32), ("b_norm", C.c_double)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad"}
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 _lib = None

@@ -116,6 +116,35 @@ def test_cocg_cfg2_single_source_matches_stored_oracle(pg):
     assert err <= 1e-6
 
 
+# every complex64 SpMM shape the autotuner can pick, per column count:
+# 10000 kind + 100 a + b (kind 0 CSR column lanes, 1 CSR nonzero lanes,
+# 2 sliced ELLPACK)
+SHAPES = {
+    1: [10401, 10801, 11601, 20104, 20108],
+    3: [10404, 10804, 11604, 20404],
+    33: [1603, 1604, 3202, 6401],
+}
+
+
+@pytest.mark.parametrize("C", sorted(SHAPES))
+def test_every_spmm_shape_matches_oracle(pg, C):
+    m = synth.config1()
+    srcs = _survey_sources(C, (1.5,)) if C < 33 else _survey_sources(11, (0.25, 1.0, 3.0))
+    ref = _oracle_fields(m, srcs)
+    S = pg.System.from_model(m)
+    for shape in SHAPES[C]:
+        print(f"[case] cfg1 C={C} shape {shape}", flush=True)
+        o = pg.default_opts(method=pg.COCG, precision=pg.MIXED, rtol=1e-8, spmm_shape=shape)
+        sol, st, rc = S.solve(srcs, o)
+        assert rc == pg.OK and all(s_["spmv_shape"] == shape for s_ in st)
+        E = sol.receivers(m.receivers).cpu().numpy()
+        err = max(fem.receiver_error(E[k], ref[k]) for k in range(len(srcs)))
+        print(f"  shape {shape}: iters {st[0]['iters']} err {err:.1e}", flush=True)
+        assert err <= 1e-6
+    with pytest.raises(pg.PetgemError):
+        S.solve(srcs, pg.default_opts(method=pg.COCG, precision=pg.MIXED, spmm_shape=99999))
+
+
 def _small_marine(seed, n, f):
     xyz, tets = synth.kuhn_mesh(n, -5000.0, 5000.0, seed)
     rng = np.random.default_rng(seed)
