@@ -249,8 +249,10 @@ def bench_cfg3(args, petgem, synth, torch):
     avg_ms = sum(o[0][0]["spmv_ms"] for o in outs) / n_launch if n_launch else float("nan")
     nbytes = spmm_bytes_fp32(S.n_dof, S.nnz, len(srcs))
     achieved = nbytes / (avg_ms * 1e-3) / 1e9 if n_launch else None
-    # plain GMRES on a stated subset: the first, centre and last dipole at every frequency
-    sub = [k for f in range(3) for k in (f * 32, f * 32 + 16, f * 32 + 31)]
+    # plain GMRES on a stated subset: the centre dipole at every frequency, or
+    # the first, centre and last with --plain-subset 9
+    picks = (16,) if args.plain_subset <= 3 else (0, 16, 31)
+    sub = [f * 32 + k for f in range(3) for k in picks]
     o_plain = petgem.default_opts(rtol=RTOL, max_iter=args.max_iter, verbose=int(args.verbose))
     t1 = time.perf_counter()
     psol, pst, _ = S.solve([srcs[k] for k in sub], o_plain, allow_not_converged=True)
@@ -403,6 +405,8 @@ def main():
     ap.add_argument("--n-test", type=int, default=200)
     ap.add_argument("--epochs", type=int, default=30)
     ap.add_argument("--inner-rtol", type=float, default=3e-5)
+    ap.add_argument("--plain-subset", type=int, default=3, choices=[3, 9],
+                    help="cfg3: sources solved by the plain path for the comparison")
     ap.add_argument("--max-iter", type=int, default=20000)
     ap.add_argument("--verbose", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
