@@ -104,7 +104,13 @@ struct Op {
     const int32_t* scol;
     const float* sK;
     const float* sM;
+    // inner-loop launches over a subset of the tiles (an uneven batch whose
+    // converged meshes drop out): block b takes tile tmap[b]; null = all
+    const int* tmap;
+    int nlaunch;           // tiles launched (ntiles when tmap is null)
 };
+
+__device__ __forceinline__ int tile_of(const Op& op, int b) { return op.tmap ? op.tmap[b] : b; }
 
 // ------------------------------------------------------------ reductions
 enum RedMode { RED_INIT = 0, RED_ALPHA = 1, RED_BETA = 2, RED_RES = 3, RED_X0 = 4 };
@@ -250,7 +256,7 @@ k_spmm_c(Op op, const ColState* __restrict__ st, const typename V2<T>::t* __rest
     if constexpr (sizeof(T) == 4) { Kv = op.K32; Mv = op.M32; } else { Kv = op.K64; Mv = op.M64; }
     constexpr int RPB = 256 / LPR;
     __shared__ double2 red[RPB][LPR * CPL];
-    const int tile = xcd_block(blockIdx.x, gridDim.x);
+    const int tile = tile_of(op, xcd_block(blockIdx.x, gridDim.x));
     const int slot = threadIdx.x / LPR, l = threadIdx.x % LPR;
     const int C = op.C;
     const int seg = op.tile_seg ? op.tile_seg[tile] : 0;
@@ -344,8 +350,9 @@ k_spmm_n(Op op, const ColState* __restrict__ st, const typename V2<T>::t* __rest
     if constexpr (sizeof(T) == 4) { Kv = op.K32; Mv = op.M32; } else { Kv = op.K64; Mv = op.M64; }
     constexpr int RPB = 256 / G;      // rows per block: kTR / RPB = G blocks per tile
     __shared__ double2 red[4][CM];
-    const int bid = xcd_block(blockIdx.x, gridDim.x);
-    const int tile = bid / G, pass = bid % G;
+    const int lb = xcd_block(blockIdx.x, gridDim.x);
+    const int tile = tile_of(op, lb / G), pass = lb % G;
+    const int bid = tile * G + pass;   // partial slot
     const int slot = threadIdx.x / G, l = threadIdx.x % G;
     const int C = op.C;
     const int seg = op.tile_seg ? op.tile_seg[tile] : 0;
@@ -447,7 +454,7 @@ __global__ void __launch_bounds__(256)
 k_spmm_s(Op op, const ColState* __restrict__ st, const float2* __restrict__ X, float2* __restrict__ Y,
          double2* __restrict__ partial) {
     __shared__ double2 red[4][CM];
-    const int tile = xcd_block(blockIdx.x, gridDim.x);
+    const int tile = tile_of(op, xcd_block(blockIdx.x, gridDim.x));
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int sl = tile * 4 + wave;
     const int i = sl * 64 + lane;
@@ -636,7 +643,7 @@ k_update(Op op, int CP, const ColState* __restrict__ st, float2* __restrict__ Xi
          float2* __restrict__ Z, const float2* __restrict__ P, const float2* __restrict__ Q,
          double2* __restrict__ p0, double2* __restrict__ p1) {
     __shared__ double2 ra[256], rb[256];
-    const int tile = blockIdx.x, C = op.C;
+    const int tile = tile_of(op, blockIdx.x), C = op.C;
     const int c = threadIdx.x % CP, slot = threadIdx.x / CP, RPB = 256 / CP;
     const int seg = op.tile_seg ? op.tile_seg[tile] : 0;
     double2 a = make_double2(0.0, 0.0), b = make_double2(0.0, 0.0);
@@ -675,7 +682,7 @@ k_update(Op op, int CP, const ColState* __restrict__ st, float2* __restrict__ Xi
 // p = z + beta p for the columns still active.
 __global__ void __launch_bounds__(256)
 k_pupdate(Op op, int CP, const ColState* __restrict__ st, const float2* __restrict__ Z, float2* __restrict__ P) {
-    const int tile = blockIdx.x, C = op.C;
+    const int tile = tile_of(op, blockIdx.x), C = op.C;
     const int c = threadIdx.x % CP, slot = threadIdx.x / CP, RPB = 256 / CP;
     if (c >= C) return;
     const int seg = op.tile_seg ? op.tile_seg[tile] : 0;
@@ -1084,6 +1091,7 @@ struct BlockWork {
     ColState* st = nullptr;
     ColState* st2 = nullptr;   // second state slot of the in-consumer reductions
     ColState* st_h = nullptr;
+    int* tmap = nullptr;       // launched tiles of a compacted uneven batch
     double* wmu = nullptr;
     int* seg_tile = nullptr;
     int* tile_seg = nullptr;
@@ -1108,7 +1116,7 @@ struct BlockWork {
         if (graph_stream) (void)hipStreamDestroy(graph_stream);
         graph_stream = nullptr;
         dfree(X64); dfree(R64); dfree(B64); dfree(Xi); dfree(R); dfree(Z); dfree(P); dfree(Q);
-        dfree(p0); dfree(p1); dfree(p2); dfree(st); dfree(st2); dfree(wmu);
+        dfree(p0); dfree(p1); dfree(p2); dfree(st); dfree(st2); dfree(tmap); dfree(wmu);
         dfree(seg_tile); dfree(tile_seg);
         dfree(rp); dfree(col); dfree(K64); dfree(M64); dfree(Kd); dfree(Md); dfree(K32); dfree(M32);
         cat_sell.release();
@@ -1195,10 +1203,10 @@ template <typename T, int A, int B, int EPI, bool COLS>
 void spmm_thunk(Op op, const ColState* st, const SpmmArgs& g, hipStream_t s) {
     using T2 = typename V2<T>::t;
     if constexpr (COLS)
-        launch_timed(k_spmm_c<T, A, B, EPI>, dim3(op.ntiles), s, g.e0, g.e1, op, st, (const T2*)g.X,
+        launch_timed(k_spmm_c<T, A, B, EPI>, dim3(op.nlaunch), s, g.e0, g.e1, op, st, (const T2*)g.X,
                      (const T2*)g.B, (T2*)g.Y, g.part);
     else
-        launch_timed(k_spmm_n<T, A, B, EPI>, dim3(op.ntiles * A), s, g.e0, g.e1, op, st, (const T2*)g.X,
+        launch_timed(k_spmm_n<T, A, B, EPI>, dim3(op.nlaunch * A), s, g.e0, g.e1, op, st, (const T2*)g.X,
                      (const T2*)g.B, (T2*)g.Y, g.part);
 }
 
@@ -1208,7 +1216,7 @@ bool spmm_dispatch_(const SpmmChoice& ch, Op op, const ColState* st, const SpmmA
         if constexpr (sizeof(T) == 4 && EPI == 1) {
             if (!op.sp) return false;
 #define PG_S(CM, U) if (ch.a == CM && ch.b == U) { \
-            launch_timed(k_spmm_s<CM, U>, dim3(op.ntiles), s, g.e0, g.e1, op, st, (const float2*)g.X, \
+            launch_timed(k_spmm_s<CM, U>, dim3(op.nlaunch), s, g.e0, g.e1, op, st, (const float2*)g.X, \
                          (float2*)g.Y, g.part); return true; }
             PG_S(1, 4) PG_S(1, 8) PG_S(2, 4) PG_S(2, 8) PG_S(4, 4)
 #undef PG_S
@@ -1274,7 +1282,7 @@ int ensure_work(BlockWork*& w, size_t rows, int C, int nsc, int ntiles) {
     w->release_graph();
     dfree(w->X64); dfree(w->R64); dfree(w->B64); dfree(w->Xi); dfree(w->R); dfree(w->Z); dfree(w->P);
     dfree(w->Q);
-    dfree(w->p0); dfree(w->p1); dfree(w->p2); dfree(w->st); dfree(w->st2); dfree(w->wmu); dfree(w->seg_tile); dfree(w->tile_seg);
+    dfree(w->p0); dfree(w->p1); dfree(w->p2); dfree(w->st); dfree(w->st2); dfree(w->tmap); dfree(w->wmu); dfree(w->seg_tile); dfree(w->tile_seg);
     if (w->st_h) (void)hipHostFree(w->st_h);
     w->st_h = nullptr;
     const size_t e = rows * (size_t)C;
@@ -1350,7 +1358,7 @@ int tune_spmm(BlockWork* w, const Op& op, int64_t nnz, hipStream_t s, SpmmTuned&
 // The driver shared by the multi-source and the uneven-batch solves.
 // On entry B64 holds the right-hand sides, X64 the initial guesses (or zero).
 int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hipStream_t s,
-               std::vector<petgem_stats*>& stv, bool have_x0) {
+               std::vector<petgem_stats*>& stv, bool have_x0, const std::vector<int>* seg_tile_h = nullptr) {
     const int C = op.C, nsc = op.nseg * C, CP = cp_of(C);
     Timer t_all;
     SpmmTuned tu;
@@ -1449,8 +1457,36 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
         if (have_x0 && w->st_h[k].bnorm > 0) x0res[k] = fallback[k] ? 1.0 : w->st_h[k].rnorm64 / w->st_h[k].bnorm;
 
     // one inner iteration; a group of kCheck is captured as one graph
+    // The inner-loop launches of an uneven batch cover only the tiles of the
+    // meshes still iterating: after a check that finds the launched tiles at
+    // least a quarter idle, the tile list is rebuilt from the active meshes
+    // (and the graph captured anew). The reductions read only active meshes'
+    // partials, all of which the list covers.
+    Op opi = op;
+    std::vector<int> tmap_h;
+    int tgen = 0;   // generation of the launched tile list
+    auto compact = [&]() -> int {
+        if (!seg_tile_h || op.nseg <= 1 || C != 1) return PETGEM_OK;
+        std::vector<int> list;
+        for (int k = 0; k < op.nseg; ++k)
+            if (w->st_h[k].active)
+                for (int t = (*seg_tile_h)[k]; t < (*seg_tile_h)[k + 1]; ++t) list.push_back(t);
+        if (list.empty() || 4 * (int64_t)list.size() > 3 * (int64_t)opi.nlaunch) return PETGEM_OK;
+        if (!w->tmap) PG_TRY(dalloc(&w->tmap, (size_t)op.ntiles));
+        tmap_h = std::move(list);
+        PG_HIP(hipMemcpyAsync(w->tmap, tmap_h.data(), sizeof(int) * tmap_h.size(), hipMemcpyHostToDevice, s));
+        PG_HIP(hipStreamSynchronize(s));   // tmap_h is reused by the next rebuild
+        opi.tmap = w->tmap;
+        opi.nlaunch = (int)tmap_h.size();
+        ++tgen;
+        return PETGEM_OK;
+    };
+    auto uncompact = [&]() {
+        opi.tmap = nullptr;
+        opi.nlaunch = op.ntiles;
+    };
     auto iteration = [&]() {
-        spmm_dispatch<float, 1>(ch, op, w->st, ev_pair(SpmmArgs{w->P, nullptr, w->Q, w->p0}), s);
+        spmm_dispatch<float, 1>(ch, opi, w->st, ev_pair(SpmmArgs{w->P, nullptr, w->Q, w->p0}), s);
         if (in_consumer) {
             hipLaunchKernelGGL(k_update_p, dim3(nbu), dim3(256), 0, s, op, CP, kConsumerTiles, w->st, w->st2,
                                w->p0, op.ntiles * ppS, w->Xi, w->R, w->Z, w->P, w->Q, w->p1, w->p2);
@@ -1459,30 +1495,31 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
         } else {
             hipLaunchKernelGGL(k_reduce, dim3(nsc), dim3(1024), 0, s, op, w->p0, ppS, nullptr, 1, w->st,
                                (int)RED_ALPHA, 0);
-            hipLaunchKernelGGL(k_update, dim3(op.ntiles), dim3(256), 0, s, op, CP, w->st, w->Xi, w->R, w->Z,
+            hipLaunchKernelGGL(k_update, dim3(opi.nlaunch), dim3(256), 0, s, opi, CP, w->st, w->Xi, w->R, w->Z,
                                w->P, w->Q, w->p1, w->p2);
             hipLaunchKernelGGL(k_reduce, dim3(nsc), dim3(1024), 0, s, op, w->p1, 1, w->p2, 1, w->st,
                                (int)RED_BETA, 0);
-            hipLaunchKernelGGL(k_pupdate, dim3(op.ntiles), dim3(256), 0, s, op, CP, w->st, w->Z, w->P);
+            hipLaunchKernelGGL(k_pupdate, dim3(opi.nlaunch), dim3(256), 0, s, opi, CP, w->st, w->Z, w->P);
         }
     };
     auto group = [&]() {
         for (int k = 0; k < kCheck; ++k) iteration();
     };
     const bool use_graph = o.use_graph && !prof;
-    std::vector<char> sig;
-    {
+    // (re)capture the group graph whenever an argument baked into it changed
+    auto ensure_graph = [&]() -> int {
+        if (!use_graph) return PETGEM_OK;
+        std::vector<char> sig;
         auto put = [&](const void* p, size_t nb) {
             const char* c = static_cast<const char*>(p);
             sig.insert(sig.end(), c, c + nb);
         };
-        put(&op, sizeof(op));
+        put(&opi, sizeof(opi));
         const void* ptrs[10] = {w->Xi, w->R, w->Z, w->P, w->Q, w->p0, w->p1, w->p2, w->st, w->st2};
         put(ptrs, sizeof(ptrs));
-        int chv[4] = {ch.kind, ch.a, ch.b, (int)in_consumer};
+        int chv[5] = {ch.kind, ch.a, ch.b, (int)in_consumer, opi.tmap ? tgen : 0};
         put(chv, sizeof(chv));
-    }
-    if (use_graph && (w->graph == nullptr || w->graph_sig != sig)) {
+        if (w->graph != nullptr && w->graph_sig == sig) return PETGEM_OK;
         w->release_graph();
         if (!w->graph_stream) PG_HIP(hipStreamCreateWithFlags(&w->graph_stream, hipStreamNonBlocking));
         hipGraph_t g;
@@ -1503,7 +1540,8 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
             return PETGEM_HIP_ERROR;
         }
         w->graph_sig = sig;
-    }
+        return PETGEM_OK;
+    };
 
     int total_inner = 0, steps = 0, strikes = 0;
     const char* why = "";
@@ -1547,7 +1585,9 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
         // readbacks are few while little runs past convergence.
         int inner = 0, groups = 1, next_print = 512;
         double prev_gap = -1.0;
+        uncompact();
         while (true) {
+            PG_TRY(ensure_graph());
             for (int g = 0; g < groups; ++g) {
                 if (use_graph) {
                     PG_HIP(hipGraphLaunch(w->graph, s));
@@ -1575,6 +1615,7 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
                 next_print += 512;
             }
             if (act == 0 || total_inner + inner >= o.max_iter) break;
+            PG_TRY(compact());
             const int ran = groups;
             groups = 1;
             if (prev_gap > 0.0 && gap < prev_gap && std::isfinite(gap)) {
@@ -1668,6 +1709,7 @@ int block_solve(petgem_system* sys, const petgem_source* src, int32_t n_src, con
     op.n = (int)rows;
     op.C = C;
     op.ntiles = ntiles;
+    op.nlaunch = ntiles;
     op.nseg = 1;
     op.tile_seg = nullptr;
     op.seg_tile = w->seg_tile;
@@ -1787,6 +1829,7 @@ int batch_solve(petgem_system* const* systems, const petgem_source* src, int32_t
     op.n = (int)rows;
     op.C = 1;
     op.ntiles = ntiles;
+    op.nlaunch = ntiles;
     op.nseg = n_sys;
     op.tile_seg = w->tile_seg;
     op.seg_tile = w->seg_tile;
@@ -1826,7 +1869,7 @@ int batch_solve(petgem_system* const* systems, const petgem_source* src, int32_t
     std::vector<petgem_stats*> stv(n_sys, nullptr);
     if (st)
         for (int k = 0; k < n_sys; ++k) { stv[k] = st + k; st[k].t_rhs_ms = trhs; }
-    int rc = mrhs_solve(w, op, nnz, o, s, stv, false);
+    int rc = mrhs_solve(w, op, nnz, o, s, stv, false, &seg_tile);
     if (rc != PETGEM_OK && rc != PETGEM_NOT_CONVERGED && rc != PETGEM_NONFINITE) return rc;
     for (int k = 0; k < n_sys; ++k)
         PG_HIP(hipMemcpyAsync(sols[k]->x, w->X64 + row_off[k], sizeof(double2) * systems[k]->n_dof,
