@@ -354,8 +354,11 @@ def bench_cfg5(args, petgem, synth, torch):
     t_train = time.perf_counter() - t0
     test = list(synth.CFG5_TEST_SEEDS)[: args.n_test]
     forms = {}
+    r_plain_E = None
     for name, o in (("plain_fp64_gmres", o_plain), ("mixed_cocg", o_mix)):
         r = learned.evaluate(S, net, test, mesh, g, o)
+        if name == "plain_fp64_gmres":
+            r_plain_E = r.E_zero
         forms[name] = {
             "zero_guess": {"solves_per_s": len(test) / r.t_zero, "iters_mean": float(np.mean(r.iters_zero))},
             "learned_guess": {"solves_per_s": len(test) / r.t_learned,
@@ -364,6 +367,20 @@ def bench_cfg5(args, petgem, synth, torch):
                               "x0_rel_residual_median": float(np.median(r.x0_residual))},
             "max_rx_diff_learned_vs_zero": r.max_rx_diff,
         }
+    # the same held-out seeds as one uneven batch (mixed COCG), zero and learned guesses
+    rb = learned.evaluate_batched(net, test, mesh, g, o_mix)
+    seq_E = r_plain_E
+    forms["batched_mixed_cocg"] = {
+        "zero_guess": {"solves_per_s": len(test) / rb.t_zero, "iters_mean": float(np.mean(rb.iters_zero)),
+                       "iters_max": int(np.max(rb.iters_zero))},
+        "learned_guess": {"solves_per_s": len(test) / rb.t_learned,
+                          "iters_mean": float(np.mean(rb.iters_learned)),
+                          "iters_max": int(np.max(rb.iters_learned)),
+                          "fallbacks": int(np.sum(rb.fallback)),
+                          "x0_rel_residual_median": float(np.median(rb.x0_residual))},
+        "max_rx_diff_learned_vs_zero": rb.max_rx_diff,
+        "max_rx_diff_vs_sequential_plain": max(rx_error(a, b) for a, b in zip(rb.E_zero, seq_E)),
+    }
     plain = forms["plain_fp64_gmres"]["zero_guess"]["solves_per_s"]
     best_name, best = max(((f"{k}/{kk}", v[kk]["solves_per_s"]) for k, v in forms.items()
                            for kk in ("zero_guess", "learned_guess")), key=lambda t: t[1])

@@ -173,10 +173,15 @@ int petgem_solve(petgem_system* sys, const petgem_source* src, int32_t n_src,
  * (different meshes) with the multi-system COCG in mixed precision; the
  * Krylov iterations of all systems run in the same kernel launches, captured
  * once in a HIP graph and replayed until every system has converged.
+ *   x0_dev  optional host array of n_sys device pointers, each NULL (zero
+ *           guess) or complex128 [n_dof of that system] in the library's DOF
+ *           order; every guess is scaled by the alpha minimising
+ *           |b - alpha A x0| and one no better than zero (or non-finite) is
+ *           replaced by zero for that system alone.
  *   sols[k] as for petgem_solve (n_src = 1), stats host [n_sys]. */
 int petgem_solve_many(petgem_system* const* systems, const petgem_source* src,
-                      int32_t n_sys, const petgem_opts* opts, void* stream,
-                      petgem_solution** sols, petgem_stats* stats);
+                      int32_t n_sys, const petgem_opts* opts, const void* const* x0_dev,
+                      void* stream, petgem_solution** sols, petgem_stats* stats);
 
 /* ---- receivers (Section 3, eq. 8; Section 2, eq. 4) ----------------------
  * E(x_r) = E_p(x_r) + sum_{i=1..6} N_i(x_r) e_i in the element containing

@@ -163,9 +163,10 @@ __device__ void apply_red(ColState& S, int mode, int first, double2 a, double2 b
     } else if (mode == RED_BETA) {     // a = r^T z (new), b.x = |r|^2
         step_beta(S, a, b.x);
     } else if (mode == RED_X0) {       // a = w^H b, b.x = |w|^2 for w = A x0
-        // a zero right-hand side (outer clear, its residual never formed) has x = 0
-        S.alpha = (S.outer && b.x > 0.0 && isfinite(b.x) && cfinite(a)) ? cscale(a, 1.0 / b.x)
-                                                                       : make_double2(0.0, 0.0);
+        // a zero right-hand side (its residual never formed) has x = 0; a guess
+        // that already meets the tolerance is scaled all the same
+        S.alpha = (S.bnorm > 0.0 && b.x > 0.0 && isfinite(b.x) && cfinite(a)) ? cscale(a, 1.0 / b.x)
+                                                                             : make_double2(0.0, 0.0);
     } else {                           // RED_RES: a.x = |b - A x|^2
         const double rn = sqrt(a.x);
         S.rnorm64 = rn;
@@ -921,6 +922,21 @@ k_x0_dots(Op op, int CP, const double2* __restrict__ B, const double2* __restric
     }
 }
 
+// X = 0 in the (segment, column) pairs flagged
+__global__ void __launch_bounds__(256)
+k_zero_cols(Op op, int CP, const int* __restrict__ flags, double2* __restrict__ X) {
+    const int tile = blockIdx.x, C = op.C;
+    const int c = threadIdx.x % CP, slot = threadIdx.x / CP, RPB = 256 / CP;
+    if (c >= C) return;
+    const int seg = op.tile_seg ? op.tile_seg[tile] : 0;
+    if (!flags[seg * C + c]) return;
+    for (int r0 = 0; r0 < kTR; r0 += RPB) {
+        const int i = tile * kTR + r0 + slot;
+        if (i >= op.nrow_valid) break;
+        X[(size_t)i * C + c] = make_double2(0.0, 0.0);
+    }
+}
+
 // X *= alpha per column
 __global__ void __launch_bounds__(256)
 k_scale_cols(Op op, int CP, const ColState* __restrict__ st, double2* __restrict__ X) {
@@ -1092,6 +1108,7 @@ struct BlockWork {
     ColState* st2 = nullptr;   // second state slot of the in-consumer reductions
     ColState* st_h = nullptr;
     int* tmap = nullptr;       // launched tiles of a compacted uneven batch
+    int* flags = nullptr;      // [nsc] per-column flags (rejected initial guesses)
     double* wmu = nullptr;
     int* seg_tile = nullptr;
     int* tile_seg = nullptr;
@@ -1116,7 +1133,7 @@ struct BlockWork {
         if (graph_stream) (void)hipStreamDestroy(graph_stream);
         graph_stream = nullptr;
         dfree(X64); dfree(R64); dfree(B64); dfree(Xi); dfree(R); dfree(Z); dfree(P); dfree(Q);
-        dfree(p0); dfree(p1); dfree(p2); dfree(st); dfree(st2); dfree(tmap); dfree(wmu);
+        dfree(p0); dfree(p1); dfree(p2); dfree(st); dfree(st2); dfree(tmap); dfree(flags); dfree(wmu);
         dfree(seg_tile); dfree(tile_seg);
         dfree(rp); dfree(col); dfree(K64); dfree(M64); dfree(Kd); dfree(Md); dfree(K32); dfree(M32);
         cat_sell.release();
@@ -1282,7 +1299,7 @@ int ensure_work(BlockWork*& w, size_t rows, int C, int nsc, int ntiles) {
     w->release_graph();
     dfree(w->X64); dfree(w->R64); dfree(w->B64); dfree(w->Xi); dfree(w->R); dfree(w->Z); dfree(w->P);
     dfree(w->Q);
-    dfree(w->p0); dfree(w->p1); dfree(w->p2); dfree(w->st); dfree(w->st2); dfree(w->tmap); dfree(w->wmu); dfree(w->seg_tile); dfree(w->tile_seg);
+    dfree(w->p0); dfree(w->p1); dfree(w->p2); dfree(w->st); dfree(w->st2); dfree(w->tmap); dfree(w->flags); dfree(w->wmu); dfree(w->seg_tile); dfree(w->tile_seg);
     if (w->st_h) (void)hipHostFree(w->st_h);
     w->st_h = nullptr;
     const size_t e = rows * (size_t)C;
@@ -1300,6 +1317,7 @@ int ensure_work(BlockWork*& w, size_t rows, int C, int nsc, int ntiles) {
 
     PG_TRY(dalloc(&w->st, (size_t)nsc));
     PG_TRY(dalloc(&w->st2, (size_t)nsc));
+    PG_TRY(dalloc(&w->flags, (size_t)nsc));
     PG_TRY(dalloc(&w->wmu, (size_t)nsc));
     PG_TRY(dalloc(&w->seg_tile, (size_t)nsc + 1));
     PG_TRY(dalloc(&w->tile_seg, (size_t)ntiles));
@@ -1357,8 +1375,11 @@ int tune_spmm(BlockWork* w, const Op& op, int64_t nnz, hipStream_t s, SpmmTuned&
 
 // The driver shared by the multi-source and the uneven-batch solves.
 // On entry B64 holds the right-hand sides, X64 the initial guesses (or zero).
+// has_x0: which (segment, column) pairs came with an initial guess (null:
+// all of them when have_x0); only those can be rejected.
 int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hipStream_t s,
-               std::vector<petgem_stats*>& stv, bool have_x0, const std::vector<int>* seg_tile_h = nullptr) {
+               std::vector<petgem_stats*>& stv, bool have_x0, const std::vector<int>* seg_tile_h = nullptr,
+               const std::vector<char>* has_x0 = nullptr) {
     const int C = op.C, nsc = op.nseg * C, CP = cp_of(C);
     Timer t_all;
     SpmmTuned tu;
@@ -1439,11 +1460,12 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
         bool redo = false;
         for (int k = 0; k < nsc; ++k) {
             const ColState& S = w->st_h[k];
+            if (has_x0 && !(*has_x0)[k]) continue;
             if (!(S.rnorm64 < S.bnorm) && S.bnorm > 0.0) { fallback[k] = 1; redo = true; }
         }
-        if (redo) {   // a rejected guess restarts every column from zero (simple and rare)
-            hipLaunchKernelGGL(k_fill_z, dim3(ceil_div((size_t)op.n * C, 256)), dim3(256), 0, s,
-                               (size_t)op.n * C, w->X64);
+        if (redo) {   // the rejected guesses restart from zero, the others stay
+            PG_HIP(hipMemcpyAsync(w->flags, fallback.data(), sizeof(int) * nsc, hipMemcpyHostToDevice, s));
+            hipLaunchKernelGGL(k_zero_cols, dim3(op.ntiles), dim3(256), 0, s, op, CP, w->flags, w->X64);
             hipLaunchKernelGGL(k_init_state, dim3(ceil_div(nsc, 64)), dim3(64), 0, s, w->st, nsc,
                                o.rtol, o.inner_rtol);
             PG_TRY(bnorms());
@@ -1454,7 +1476,8 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
     }
     std::vector<double> x0res(nsc, 1.0);
     for (int k = 0; k < nsc; ++k)
-        if (have_x0 && w->st_h[k].bnorm > 0) x0res[k] = fallback[k] ? 1.0 : w->st_h[k].rnorm64 / w->st_h[k].bnorm;
+        if (have_x0 && w->st_h[k].bnorm > 0 && (!has_x0 || (*has_x0)[k]))
+            x0res[k] = fallback[k] ? 1.0 : w->st_h[k].rnorm64 / w->st_h[k].bnorm;
 
     // one inner iteration; a group of kCheck is captured as one graph
     // The inner-loop launches of an uneven batch cover only the tiles of the
@@ -1762,7 +1785,8 @@ int block_solve(petgem_system* sys, const petgem_source* src, int32_t n_src, con
 }
 
 int batch_solve(petgem_system* const* systems, const petgem_source* src, int32_t n_sys,
-                const petgem_opts& o, petgem_solution** sols, hipStream_t s, petgem_stats* st) {
+                const petgem_opts& o, const void* const* x0, petgem_solution** sols, hipStream_t s,
+                petgem_stats* st) {
     // Row offsets of the concatenated block-diagonal operator: every mesh
     // starts on a tile boundary, so each tile belongs to one mesh.
     std::vector<int> row_off(n_sys + 1, 0), seg_tile(n_sys + 1, 0);
@@ -1852,6 +1876,15 @@ int batch_solve(petgem_system* const* systems, const petgem_source* src, int32_t
     Timer t_rhs;
     hipLaunchKernelGGL(k_fill_z, dim3(ceil_div(rows, 256)), dim3(256), 0, s, rows, w->B64);
     hipLaunchKernelGGL(k_fill_z, dim3(ceil_div(rows, 256)), dim3(256), 0, s, rows, w->X64);
+    bool have_x0 = false;
+    std::vector<char> has_x0(n_sys, 0);
+    for (int k = 0; x0 && k < n_sys; ++k)
+        if (x0[k]) {
+            has_x0[k] = 1;
+            PG_HIP(hipMemcpyAsync(w->X64 + row_off[k], x0[k], sizeof(double2) * systems[k]->n_dof,
+                                  hipMemcpyDeviceToDevice, s));
+            have_x0 = true;
+        }
     for (int k = 0; k < n_sys; ++k) PG_TRY(launch_rhs(systems[k], src[k], w->B64 + row_off[k], 1, s));
     for (int k = 0; k < n_sys; ++k) {
         int flag = 0;
@@ -1869,7 +1902,7 @@ int batch_solve(petgem_system* const* systems, const petgem_source* src, int32_t
     std::vector<petgem_stats*> stv(n_sys, nullptr);
     if (st)
         for (int k = 0; k < n_sys; ++k) { stv[k] = st + k; st[k].t_rhs_ms = trhs; }
-    int rc = mrhs_solve(w, op, nnz, o, s, stv, false, &seg_tile);
+    int rc = mrhs_solve(w, op, nnz, o, s, stv, have_x0, &seg_tile, &has_x0);
     if (rc != PETGEM_OK && rc != PETGEM_NOT_CONVERGED && rc != PETGEM_NONFINITE) return rc;
     for (int k = 0; k < n_sys; ++k)
         PG_HIP(hipMemcpyAsync(sols[k]->x, w->X64 + row_off[k], sizeof(double2) * systems[k]->n_dof,

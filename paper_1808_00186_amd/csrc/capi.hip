@@ -258,7 +258,8 @@ int petgem_solve(petgem_system* sys, const petgem_source* src, int32_t n_src, co
 }
 
 int petgem_solve_many(petgem_system* const* systems, const petgem_source* src, int32_t n_sys,
-                      const petgem_opts* opts, void* stream, petgem_solution** sols, petgem_stats* stats) {
+                      const petgem_opts* opts, const void* const* x0_dev, void* stream, petgem_solution** sols,
+                      petgem_stats* stats) {
     if (!systems || !src || n_sys <= 0 || !sols) { set_error("systems, sources and solutions are required"); return PETGEM_INVALID_ARG; }
     petgem_opts o;
     if (opts) o = *opts; else petgem_default_opts(&o);
@@ -281,7 +282,7 @@ int petgem_solve_many(petgem_system* const* systems, const petgem_source* src, i
         sol->sigma_bg = systems[k]->sigma_bg;
     }
     if (stats) std::memset(stats, 0, sizeof(petgem_stats) * (size_t)n_sys);
-    return batch_solve(systems, src, n_sys, o, sols, static_cast<hipStream_t>(stream), stats);
+    return batch_solve(systems, src, n_sys, o, x0_dev, sols, static_cast<hipStream_t>(stream), stats);
 }
 
 int petgem_receivers(const petgem_solution* sol, const double* rx, int32_t n_rx, void* E_dev,

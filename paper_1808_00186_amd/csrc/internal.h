@@ -207,7 +207,7 @@ int block_solve(petgem_system* sys, const petgem_source* src, int32_t n_src,
                 const petgem_opts& o, const double2* x0, double2* x_out, hipStream_t s,
                 petgem_stats* st);
 int batch_solve(petgem_system* const* systems, const petgem_source* src, int32_t n_sys,
-                const petgem_opts& o, petgem_solution** sols, hipStream_t s,
+                const petgem_opts& o, const void* const* x0, petgem_solution** sols, hipStream_t s,
                 petgem_stats* st);
 int ensure_fp32(petgem_system* sys, hipStream_t s);
 

@@ -73,8 +73,8 @@ _SIGS = {
     "petgem_solve": (C.c_int, [C.c_void_p, C.POINTER(Source), C.c_int32, C.POINTER(Opts),
                                C.c_void_p, C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(Stats)]),
     "petgem_solve_many": (C.c_int, [C.POINTER(C.c_void_p), C.POINTER(Source), C.c_int32,
-                                    C.POINTER(Opts), C.c_void_p, C.POINTER(C.c_void_p),
-                                    C.POINTER(Stats)]),
+                                    C.POINTER(Opts), C.POINTER(C.c_void_p), C.c_void_p,
+                                    C.POINTER(C.c_void_p), C.POINTER(Stats)]),
     "petgem_receivers": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.c_int32, C.c_void_p,
                                    C.c_void_p, C.c_void_p]),
     "petgem_num_dofs": (C.c_int32, [C.c_void_p]),
@@ -416,8 +416,9 @@ def locate(xyz, tets, pts, tol=1e-12):
 
 
 def solve_many(systems: Sequence[System], dipoles, opts: Optional[Opts] = None, stream=None,
-               allow_not_converged: bool = False):
-    """One source per system, all systems in shared launches (petgem_solve_many)."""
+               allow_not_converged: bool = False, x0=None):
+    """One source per system, all systems in shared launches (petgem_solve_many).
+    x0: None, or one complex128 CUDA tensor [n_dof] (or None) per system."""
     n = len(systems)
     hs = (C.c_void_p * n)(*[s.handle.value for s in systems])
     src = make_sources(dipoles)
@@ -425,6 +426,14 @@ def solve_many(systems: Sequence[System], dipoles, opts: Optional[Opts] = None, 
     st = (Stats * n)()
     o = opts if opts is not None else default_opts(method=COCG, precision=MIXED)
     allow = (NOT_CONVERGED, NONFINITE) if allow_not_converged else ()
-    rc = _check(lib().petgem_solve_many(hs, src, n, C.byref(o), _stream(stream), sols, st), allow)
+    x0p = None
+    if x0 is not None:
+        if len(x0) != n:
+            raise ValueError("one initial guess (or None) per system")
+        for k, t in enumerate(x0):
+            if t is not None and (t.numel() != systems[k].n_dof or not t.is_cuda):
+                raise ValueError(f"initial guess {k}: a CUDA tensor of {systems[k].n_dof} values")
+        x0p = (C.c_void_p * n)(*[None if t is None else _ptr(t).value for t in x0])
+    rc = _check(lib().petgem_solve_many(hs, src, n, C.byref(o), x0p, _stream(stream), sols, st), allow)
     out = [Solution(systems[k], C.c_void_p(sols[k]), 1) for k in range(n)]
     return out, [s.as_dict() for s in st], rc

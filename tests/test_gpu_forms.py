@@ -177,6 +177,22 @@ def test_solve_many_uneven_batch_matches_oracle(pg):
     sols2, _, _ = pg.solve_many(systems, [mm.sources[0] for mm in models], o)
     for a, b in zip(sols, sols2):
         assert np.array_equal(a.x().cpu().numpy(), b.x().cpu().numpy())
+    # initial guesses per system: the solution itself (no iterations), none,
+    # and a non-finite one (replaced by zero for that system alone)
+    import torch
+    xs = [s_.x()[0] for s_ in sols]
+    x0 = [xs[0], None, torch.full_like(xs[2], float("nan")), xs[3] * 1e3, xs[4]]
+    sols3, st3, rc3 = pg.solve_many(systems, [mm.sources[0] for mm in models], o, x0=x0)
+    assert rc3 == pg.OK
+    print(f"  x0 batch: iters {[s_['iters'] for s_ in st3]} fallback {[s_['used_fallback'] for s_ in st3]}",
+          flush=True)
+    assert st3[0]["iters"] == 0 and st3[4]["iters"] == 0 and st3[3]["iters"] == 0
+    assert [s_["used_fallback"] for s_ in st3] == [0, 0, 1, 0, 0]
+    assert st3[1]["iters"] > 0 and st3[2]["iters"] > 0
+    for k, mm in enumerate(models):
+        E = sols3[k].receivers(mm.receivers).cpu().numpy()[0]
+        assert st3[k]["rel_residual"] <= 1e-9
+        assert fem.receiver_error(E, solve.forward(mm)["E"]) <= 1e-6
 
 
 def test_uneven_batch_of_smallest_cfg4_models_matches_oracle(pg):

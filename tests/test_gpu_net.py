@@ -91,3 +91,11 @@ def test_learned_guess_trains_and_solves(env):
           f"x0 res {np.round(res.x0_residual, 3)} rx diff {res.max_rx_diff:.1e}", flush=True)
     # same answer at the same tolerance, whatever the guess
     assert res.max_rx_diff <= 1e-6
+    # the same seeds as one uneven batch, zero and learned guesses
+    rb = learned.evaluate_batched(net, list(range(20000, 20006)), mesh, g, opts)
+    print(f"batched eval: zero {rb.iters_zero} learned {rb.iters_learned} fallback {rb.fallback} "
+          f"rx diff {rb.max_rx_diff:.1e}", flush=True)
+    assert rb.max_rx_diff <= 1e-6
+    for a, b in zip(rb.E_zero, res.E_zero):
+        num = np.sqrt(np.sum(np.abs(a - b) ** 2, axis=-1))
+        assert np.max(num / np.sqrt(np.sum(np.abs(b) ** 2, axis=-1))) <= 1e-6
