@@ -17,9 +17,9 @@ stored oracle fields (tests/golden/cfg2_receivers.npz) when present.
 
 Other workloads (`--workload`):
   cfg3 -- the same layered model at 100^3 x 6 = 6,000,000 tetrahedra with
-          32 dipole positions x 3 frequencies: one 96-column COCG block
-          (complex64 SpMM inside complex128 refinement) vs plain GMRES on a
-          stated subset of the columns.
+          32 dipole positions x 3 frequencies: 96 sources in one call, solved
+          as one 32-column COCG block per frequency (complex64 SpMM inside
+          complex128 refinement) vs plain GMRES on a stated subset.
   cfg4 -- 48 independent models of 1e4..2e6 tetrahedra, one source each, in
           one uneven batch vs plain GMRES one model at a time.
   cfg5 -- the learned initial guess: a network trained on 2000 solves of
@@ -247,7 +247,9 @@ def bench_cfg3(args, petgem, synth, torch):
     st = outs[-1][0]
     n_launch = sum(o[0][0]["spmv_launches"] for o in outs)
     avg_ms = sum(o[0][0]["spmv_ms"] for o in outs) / n_launch if n_launch else float("nan")
-    nbytes = spmm_bytes_fp32(S.n_dof, S.nnz, len(srcs))
+    # the roofline kernel is the first block's SpMM: the sources of the first frequency
+    block = next((k for k, d in enumerate(srcs) if d.freq != srcs[0].freq), len(srcs))
+    nbytes = spmm_bytes_fp32(S.n_dof, S.nnz, block)
     achieved = nbytes / (avg_ms * 1e-3) / 1e9 if n_launch else None
     # plain GMRES on a stated subset: the centre dipole at every frequency, or
     # the first, centre and last with --plain-subset 9
@@ -271,7 +273,7 @@ def bench_cfg3(args, petgem, synth, torch):
         "scaling": "weak", "vs_baseline": None, "dtype": "c64 inner / f64 refinement",
         "data": "synthetic",
         "config": {"workload": "cfg3: 6000000 jittered tets, 6910300 DOF, 112409452 nnz, 32 dipoles x "
-                               "(0.25, 0.5, 1.25) Hz = 96 sources, one 96-column COCG block",
+                               "(0.25, 0.5, 1.25) Hz = 96 sources, a 32-column COCG block per frequency",
                    "n_dof": S.n_dof, "nnz": S.nnz, "setup_s": round(setup_s, 3),
                    "iters_max": max(s["iters"] for s in st), "ir_steps": st[0]["ir_steps"],
                    "rel_residual_max": max(s["rel_residual"] for s in st),

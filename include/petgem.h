@@ -163,6 +163,10 @@ int petgem_rhs(petgem_system* sys, const petgem_source* src, int32_t n_src,
  *   *inout  NULL to allocate a new solution, or a solution from an earlier
  *           call on the same system with the same n_src, which is reused.
  *   stats   optional host [n_src].
+ * GMRES solves the sources one after another; COCG solves them as one block
+ * (all columns in shared launches), except that a large block (n_dof x n_src
+ * >= 1e8) whose sources come in contiguous runs of one frequency is solved
+ * one run at a time.
  * Returns PETGEM_OK, or NOT_CONVERGED / NONFINITE (the solution then holds
  * the last iterate), or an error. */
 int petgem_solve(petgem_system* sys, const petgem_source* src, int32_t n_src,
