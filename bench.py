@@ -24,12 +24,18 @@ Other workloads (`--workload`):
           one uneven batch vs plain GMRES one model at a time.
   cfg5 -- the learned initial guess: a network trained on 2000 solves of
           config-1-sized random reservoir models, zero vs learned guess on 200
-          held-out seeds (plain GMRES and mixed COCG).
+          held-out seeds (plain GMRES and mixed COCG one seed at a time, and
+          the 200 seeds as one uneven batch).
+  net  -- the network alone: training steps and forward passes on a batch of
+          16, BF16 MFMA throughput against its peak.
+  copy -- a 1 GiB device copy (calibration of the rocprofv3 byte counters).
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload cfg2]
 
-Prints one JSON line. `roofline` reports the dominant sparse-matrix kernel of
-the reported form from HIP events around its launches inside the timed steps;
+Prints one JSON line. `value` comes from a pass over the timed steps as the
+solver runs in use (graph-captured iterations); `roofline` reports the
+dominant sparse-matrix kernel of the reported form from a second pass over
+the same steps in which its dispatches timestamp their own start and end;
 `cpu_baseline` times the CPU oracle on a bounded sample of the same workload.
 """
 from __future__ import annotations
@@ -400,6 +406,51 @@ def bench_cfg5(args, petgem, synth, torch):
     }
 
 
+NET_LAYERS = ((16, 16, 32), (16, 32, 16), (32, 64, 8), (64, 64, 8), (96, 32, 16), (48, 16, 32), (16, 16, 32))
+
+
+def bench_net(args, petgem, torch):
+    """The learned guess's network alone: training steps (forward, loss,
+    backward data and weights, Adam) on a batch of 16 synthetic 32^3 inputs,
+    and forward passes; dense BF16 MFMA throughput against the 2.5 PFLOP/s
+    peak. FLOPs: 2 x 27 x Cin x Cout x D^3 per convolution and sample; a
+    training step counts the forward pass, the weight gradients of every layer
+    and the data gradients of all but the first."""
+    B = 16
+    g = torch.Generator(device="cuda").manual_seed(0)
+    x = (torch.randn((B, petgem.NET_VOX, petgem.NET_IN), device="cuda", generator=g) * 0.5).to(torch.bfloat16)
+    t = torch.randn((B, petgem.NET_VOX, petgem.NET_OUT_USED), device="cuda", generator=g) * 0.3
+    net = petgem.Net(batch_max=B, seed=1)
+    conv = [2 * 27 * ci * co * d ** 3 for ci, co, d in NET_LAYERS]
+    f_fwd = B * sum(conv)
+    f_train = B * (2 * sum(conv) + sum(conv[1:]))
+    for _ in range(args.warmup):
+        net.train_step(x, t, 1e-4)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        net.train_step(x, t, 1e-4)
+    torch.cuda.synchronize()
+    dt_train = (time.perf_counter() - t0) / args.steps
+    for _ in range(args.warmup):
+        net.forward(x)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        net.forward(x)
+    torch.cuda.synchronize()
+    dt_fwd = (time.perf_counter() - t0) / args.steps
+    peak = 2500.0
+    return {"metric": "network training samples/s (BF16 MFMA)", "value": B / dt_train, "unit": "samples/s",
+            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt_train * 1e3,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16 (fp32 accumulate)",
+            "data": "synthetic", "config": {"workload": "3D U-Net on 32^3 voxels, batch 16", "parallelism": "1 GPU"},
+            "roofline": {"bound": "mfma", "unit": "TFLOP/s", "peak": peak,
+                         "train_achieved": f_train / dt_train / 1e12, "train_frac": f_train / dt_train / 1e12 / peak,
+                         "forward_achieved": f_fwd / dt_fwd / 1e12, "forward_frac": f_fwd / dt_fwd / 1e12 / peak,
+                         "forward_ms": dt_fwd * 1e3, "flop_per_train_step": f_train, "flop_per_forward": f_fwd}}
+
+
 def copy_calibration(args, torch):
     """A plain device copy of a known size (1 GiB read + 1 GiB written per
     launch): the FETCH_SIZE / WRITE_SIZE counters of this kernel give the
@@ -419,7 +470,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="cfg2", choices=["cfg2", "cfg3", "cfg4", "cfg5", "copy"])
+    ap.add_argument("--workload", default="cfg2", choices=["cfg2", "cfg3", "cfg4", "cfg5", "net", "copy"])
     ap.add_argument("--n-train", type=int, default=2000)
     ap.add_argument("--n-test", type=int, default=200)
     ap.add_argument("--epochs", type=int, default=30)
@@ -442,6 +493,9 @@ def main():
     torch.cuda.set_device(0)
     if args.workload == "copy":
         print(json.dumps(copy_calibration(args, torch)), flush=True)
+        return
+    if args.workload == "net":
+        print(json.dumps(bench_net(args, petgem, torch)), flush=True)
         return
     fn = {"cfg2": bench_cfg2, "cfg3": bench_cfg3, "cfg4": bench_cfg4, "cfg5": bench_cfg5}[args.workload]
     line = fn(args, petgem, synth, torch)

@@ -17,7 +17,8 @@
 // K = 27 taps x input channels (each 16-wide K chunk is one tap and 16
 // channels, so every lane's 4 K values are 8 contiguous bytes). The backward
 // data pass is the same kernel with the taps mirrored and the channel roles
-// swapped; the backward weight pass is an MFMA reduction over voxels.
+// swapped; the backward weight pass is an MFMA reduction over voxels on
+// channel-major copies of the layer input and its output gradient.
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -101,69 +102,150 @@ k_conv(const bf16* __restrict__ in, const bf16* __restrict__ wt, const float* __
     }
 }
 
-// Backward weights: partial[s][k][co] = sum over the voxels of split s of
-// in[v + off(tap)][ci] * dz[v][co], k = tap * CIN + ci. One wave per
-// (16-row K tile, 16-column output tile, voxel split); rows of A are input
-// channels, its K index runs over voxels.
-template <int CIN, int COUT>
-__global__ void __launch_bounds__(64)
-k_conv_bwdw(const bf16* __restrict__ in, const bf16* __restrict__ dz, float* __restrict__ partial,
-            int nvox, int D, int nsplit) {
-    constexpr int KT = 27 * CIN / 16, NT = COUT / 16;
-    const int l = threadIdx.x & 63, m = l & 15, kq = l >> 4;
-    const int bid = blockIdx.x;
-    const int s = bid % nsplit, nt = (bid / nsplit) % NT, kt = bid / (nsplit * NT);
-    const int tap = (kt * 16) / CIN, c0 = (kt * 16) % CIN;
-    const int dzo = tap / 9 - 1, dyo = (tap / 3) % 3 - 1, dxo = tap % 3 - 1;
-    const int Vs = D * D * D;
-    const long chunk = ((long)nvox + nsplit - 1) / nsplit;
-    const long v0 = (long)s * chunk, v1 = v0 + chunk < nvox ? v0 + chunk : nvox;
-    f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
-    for (long vb = v0; vb < v1; vb += 16) {
-        bf16x4 a = {0, 0, 0, 0}, w = {0, 0, 0, 0};
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const long v = vb + 4 * kq + j;
-            if (v >= v1) continue;
-            const int b = (int)(v / Vs), r = (int)(v % Vs);
-            const int z = r / (D * D) + dzo, y = (r / D) % D + dyo, x = r % D + dxo;
-            if (z >= 0 && z < D && y >= 0 && y < D && x >= 0 && x < D)
-                a[j] = (short)in[((long)b * Vs + ((long)z * D + y) * D + x) * CIN + c0 + m];
-            w[j] = (short)dz[v * COUT + nt * 16 + m];
-        }
-        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, w, acc, 0, 0, 0);
-    }
-    // D[row = ci (4 kq + j)][col = co m]
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const int k = tap * CIN + c0 + 4 * kq + j;
-        partial[((long)s * 27 * CIN + k) * COUT + nt * 16 + m] = acc[j];
-    }
-}
-
-__global__ void k_sum_splits(const float* __restrict__ partial, int nsplit, int n, float* __restrict__ out) {
-    const int i = blockIdx.x * 256 + threadIdx.x;
-    if (i >= n) return;
-    float s = 0.f;
-    for (int k = 0; k < nsplit; ++k) s += partial[(long)k * n + i];
-    out[i] = s;
-}
-
-// db partials: partial[blk][c] = sum over a block of voxels of dz[v][c]
+// Channel-major copy of an activation: out[b][c][r] = in[b][r][c] for
+// r < Vs (Vs a multiple of 64). One block moves 64 voxels x C channels
+// through LDS so that both sides are 8-byte vector accesses.
+template <int C>
 __global__ void __launch_bounds__(256)
-k_bias_grad(const bf16* __restrict__ dz, int nvox, int C, float* __restrict__ partial) {
-    __shared__ float red[256];
-    const int c = threadIdx.x % C, slot = threadIdx.x / C, nslot = 256 / C;
-    const long v0 = (long)blockIdx.x * 1024;
-    float s = 0.f;
-    for (long v = v0 + slot; v < v0 + 1024 && v < nvox; v += nslot) s += bf2f(dz[v * C + c]);
-    red[threadIdx.x] = s;
-    __syncthreads();
-    if ((int)threadIdx.x < C) {
-        float t = 0.f;
-        for (int q = 0; q < nslot; ++q) t += red[q * C + threadIdx.x];
-        partial[(long)blockIdx.x * C + threadIdx.x] = t;
+k_to_cmajor(const bf16* __restrict__ in, int Vs, bf16* __restrict__ out) {
+    __shared__ bf16 tile[64][C + 4];
+    const long v0 = (long)blockIdx.x * 64;
+    const int b = (int)(v0 / Vs), r0 = (int)(v0 % Vs);
+    const uint2* src = reinterpret_cast<const uint2*>(in + v0 * C);
+    for (int q = threadIdx.x; q < 16 * C; q += 256) {   // 4 channels of one voxel
+        const uint2 w = src[q];
+        const int vv = (4 * q) / C, c = (4 * q) % C;
+        tile[vv][c] = (bf16)(w.x & 0xffffu);
+        tile[vv][c + 1] = (bf16)(w.x >> 16);
+        tile[vv][c + 2] = (bf16)(w.y & 0xffffu);
+        tile[vv][c + 3] = (bf16)(w.y >> 16);
     }
+    __syncthreads();
+    for (int q = threadIdx.x; q < 16 * C; q += 256) {   // 4 voxels of one channel
+        const int c = q / 16, vv = 4 * (q % 16);
+        uint2 w;
+        w.x = (uint32_t)tile[vv][c] | ((uint32_t)tile[vv + 1][c] << 16);
+        w.y = (uint32_t)tile[vv + 2][c] | ((uint32_t)tile[vv + 3][c] << 16);
+        *reinterpret_cast<uint2*>(out + ((long)b * C + c) * Vs + r0 + vv) = w;
+    }
+}
+
+// Backward weights and bias from channel-major copies inT [B][CIN][D^3] and
+// dzT [B][COUT][D^3]:
+//   partial[s][tap * CIN + ci][co] = sum over the voxels of split s of
+//                                    in[v + off(tap)][ci] dz[v][co]
+//   partial[s][27 CIN][co]         = sum over the same voxels of dz[v][co].
+// The reduction index of v_mfma_f32_16x16x16_bf16 runs over voxels: a K step
+// is 16 consecutive voxels, 4 per lane, all in one x row (D % 4 == 0). A
+// block is one (16-channel input group, z offset) unit and one voxel split;
+// its 4 waves take alternate K steps and are summed through LDS in wave
+// order, so the result does not depend on timing. A wave keeps the 9 (y, x)
+// offsets x all output tiles in registers: one 16-byte load per input row
+// (x0-2 .. x0+5 of one channel) yields the three x shifts by funnel shifts.
+template <int CIN, int COUT>
+__global__ void __launch_bounds__(256)
+k_conv_bwdw(const bf16* __restrict__ inT, const bf16* __restrict__ dzT, float* __restrict__ partial,
+            int nvox, int D, int nsplit) {
+    constexpr int NT = COUT / 16, KW = 27 * CIN;
+    const int wave = threadIdx.x >> 6, l = threadIdx.x & 63, m = l & 15, kq = l >> 4;
+    const int s = blockIdx.x % nsplit, unit = blockIdx.x / nsplit;
+    const int g = unit / 3, pz = unit % 3;
+    const bool bias_unit = unit == 1;   // g = 0, z offset 0
+    const int Vs = D * D * D;
+    const int nK = nvox / 16, chunk = (nK + nsplit - 1) / nsplit;
+    const int k0 = s * chunk, k1 = min(nK, k0 + chunk);
+    f32x4 acc[3][3][NT], accb[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        accb[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) acc[a][c][t] = f32x4{0.f, 0.f, 0.f, 0.f};
+    }
+    const bf16x4 ones = {0x3f80, 0x3f80, 0x3f80, 0x3f80};
+    for (int k = k0 + wave; k < k1; k += 4) {
+        const int v = 16 * k + 4 * kq;
+        const int b = v / Vs, r = v % Vs;
+        const int z = r / (D * D), y = (r / D) % D, x0 = r % D;
+        bf16x4 w[NT];
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+            w[t] = *reinterpret_cast<const bf16x4*>(dzT + ((long)b * COUT + t * 16 + m) * Vs + r);
+        const int zz = z + pz - 1;
+        const long cbase = ((long)b * CIN + g * 16 + m) * Vs;
+#pragma unroll
+        for (int dy = 0; dy < 3; ++dy) {
+            const int yy = y + dy - 1;
+            uint32_t dp = 0, d0 = 0, d1 = 0, dn = 0;
+            if (zz >= 0 && zz < D && yy >= 0 && yy < D) {
+                const bf16* row = inT + cbase + ((long)zz * D + yy) * D + x0;
+                const uint2 c = *reinterpret_cast<const uint2*>(row);
+                d0 = c.x;
+                d1 = c.y;
+                if (x0 > 0) dp = *reinterpret_cast<const uint32_t*>(row - 2);
+                if (x0 + 4 < D) dn = *reinterpret_cast<const uint32_t*>(row + 4);
+            }
+            // voxels x0-1..x0+2, x0..x0+3, x0+1..x0+4 of this row
+            const uint32_t lo[3] = {(dp >> 16) | (d0 << 16), d0, (d0 >> 16) | (d1 << 16)};
+            const uint32_t hi[3] = {(d0 >> 16) | (d1 << 16), d1, (d1 >> 16) | (dn << 16)};
+#pragma unroll
+            for (int dx = 0; dx < 3; ++dx) {
+                typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+                const bf16x4 a = __builtin_bit_cast(bf16x4, (u32x2{lo[dx], hi[dx]}));
+#pragma unroll
+                for (int t = 0; t < NT; ++t)
+                    acc[dy][dx][t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, w[t], acc[dy][dx][t], 0, 0, 0);
+            }
+        }
+        if (bias_unit) {
+#pragma unroll
+            for (int t = 0; t < NT; ++t) accb[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ones, w[t], accb[t], 0, 0, 0);
+        }
+    }
+    // wave-ordered sum of the 4 waves, one output tile column at a time;
+    // lane holds D[row ci = 4 kq + j][col co = m]
+    __shared__ float red[4][10][256];
+    float* base = partial + (long)s * (KW + 1) * COUT;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) red[wave][3 * a + c][4 * l + j] = acc[a][c][t][j];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) red[wave][9][4 * l + j] = accb[t][j];
+        __syncthreads();
+        for (int e = threadIdx.x; e < 10 * 256; e += 256) {
+            const int tile = e / 256, ln = (e / 4) % 64, j = e % 4;
+            const float val = red[0][tile][e % 256] + red[1][tile][e % 256] + red[2][tile][e % 256] +
+                              red[3][tile][e % 256];
+            const int co = t * 16 + (ln & 15), ci = g * 16 + 4 * (ln >> 4) + j;
+            if (tile < 9) {
+                const int tap = pz * 9 + tile;   // (z, y, x) offsets in row-major order
+                base[(long)(tap * CIN + ci) * COUT + co] = val;
+            } else if (bias_unit && ci == 0) {
+                base[(long)KW * COUT + co] = val;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// out[i] = sum over the nsplit partials of entry i, in split order within
+// each of 4 interleaved groups and then in group order (deterministic)
+__global__ void __launch_bounds__(256)
+k_sum_splits(const float* __restrict__ partial, int nsplit, int n, float* __restrict__ out) {
+    __shared__ float red[4][64];
+    const int i = blockIdx.x * 64 + (threadIdx.x & 63), q = threadIdx.x >> 6;
+    float sum = 0.f;
+    if (i < n)
+        for (int k = q; k < nsplit; k += 4) sum += partial[(long)k * n + i];
+    red[q][threadIdx.x & 63] = sum;
+    __syncthreads();
+    if (q == 0 && i < n) out[i] = red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] + red[3][threadIdx.x];
 }
 
 // 2x2x2 average pooling (fine side D), channel stride/offset for concatenation
@@ -426,6 +508,7 @@ struct petgem_net {
     float* Y = nullptr;
     float *g0 = nullptr, *g1 = nullptr, *g2 = nullptr;   // f32 gradient scratch
     float* wpart = nullptr;                              // backward-weight partials
+    petgem::bf16 *tin = nullptr, *tdz = nullptr;         // channel-major copies for the weight pass
     double* lpart = nullptr;
     float* T = nullptr;       // targets of the current batch (caller-owned copy not needed)
     double* scal = nullptr;   // per-sample scales on device
@@ -440,9 +523,16 @@ namespace petgem {
 
 namespace {
 
-constexpr int kSplits = 64;
-
-size_t wpart_floats(int cin, int cout) { return (size_t)kSplits * 27 * cin * cout; }
+// voxel splits of the weight pass: enough blocks to fill the chip, at least
+// 8 K steps per wave
+int bwdw_splits(int cin, long nvox) {
+    const int units = 3 * (cin / 16);
+    const long cap = std::max(1L, nvox / 16 / 32);
+    return (int)std::min<long>(cap, std::max(1, ceil_div(512, units)));
+}
+size_t wpart_floats(int cin, int cout, long nvox) {
+    return (size_t)bwdw_splits(cin, nvox) * (27 * (size_t)cin + 1) * cout;
+}
 
 template <int CIN, int COUT, bool RELU, bool OUTF32>
 void conv_t(const bf16* in, const bf16* wt, const float* bias, void* out, int nvox, int D, hipStream_t s) {
@@ -467,12 +557,25 @@ int conv(int cin, int cout, bool relu, bool outf32, const bf16* in, const bf16* 
     return PETGEM_INVALID_ARG;
 }
 
-int conv_bwdw(int cin, int cout, const bf16* in, const bf16* dz, float* part, int nvox, int D, hipStream_t s) {
-    const int nb = (27 * cin / 16) * (cout / 16) * kSplits;
-#define PG_BW(A, B)                                                                                       \
-    if (cin == A && cout == B) {                                                                          \
-        hipLaunchKernelGGL((k_conv_bwdw<A, B>), dim3(nb), dim3(64), 0, s, in, dz, part, nvox, D, kSplits); \
-        return PETGEM_OK;                                                                                 \
+int to_cmajor(int c, const bf16* in, long nvox, int Vs, bf16* out, hipStream_t s) {
+#define PG_TC(C)                                                                                           \
+    if (c == C) {                                                                                          \
+        hipLaunchKernelGGL((k_to_cmajor<C>), dim3((unsigned)(nvox / 64)), dim3(256), 0, s, in, Vs, out);   \
+        return PETGEM_OK;                                                                                  \
+    }
+    PG_TC(16) PG_TC(32) PG_TC(48) PG_TC(64) PG_TC(96)
+#undef PG_TC
+    set_error("unsupported channel count");
+    return PETGEM_INVALID_ARG;
+}
+
+int conv_bwdw(int cin, int cout, const bf16* inT, const bf16* dzT, float* part, int nvox, int D, int nsplit,
+              hipStream_t s) {
+    const int nb = 3 * (cin / 16) * nsplit;
+#define PG_BW(A, B)                                                                                          \
+    if (cin == A && cout == B) {                                                                             \
+        hipLaunchKernelGGL((k_conv_bwdw<A, B>), dim3(nb), dim3(256), 0, s, inT, dzT, part, nvox, D, nsplit);  \
+        return PETGEM_OK;                                                                                    \
     }
     PG_BW(16, 16) PG_BW(16, 32) PG_BW(32, 64) PG_BW(64, 64) PG_BW(96, 32) PG_BW(48, 16)
 #undef PG_BW
@@ -503,7 +606,7 @@ void release_net(petgem_net* n) {
     dfree(n->P); dfree(n->Gr); dfree(n->M); dfree(n->Vv);
     dfree(n->X0); dfree(n->A1); dfree(n->P1); dfree(n->A2); dfree(n->P2); dfree(n->A3); dfree(n->A4);
     dfree(n->Q2); dfree(n->A5); dfree(n->Q1); dfree(n->A6); dfree(n->dzb); dfree(n->Y);
-    dfree(n->g0); dfree(n->g1); dfree(n->g2); dfree(n->wpart); dfree(n->lpart); dfree(n->T);
+    dfree(n->g0); dfree(n->g1); dfree(n->g2); dfree(n->wpart); dfree(n->tin); dfree(n->tdz); dfree(n->lpart); dfree(n->T);
     dfree(n->scal); dfree(n->vsrc); dfree(n->bbuf); dfree(n->bn);
     if (n->lpart_h) (void)hipHostFree(n->lpart_h);
     n->lpart_h = nullptr;
@@ -538,15 +641,18 @@ int forward(petgem_net* n, int B, hipStream_t s) {
     return PETGEM_OK;
 }
 
-// weight and bias gradients of layer li from its input `in` and dz (bf16)
+// weight and bias gradients of layer li from its input `in` and dz (bf16,
+// channels-last); the bias gradient lands right after the weights (b_off =
+// w_off + 27 cin cout)
 int layer_grads(petgem_net* n, int li, const bf16* in, const bf16* dz, int nvox, int D, hipStream_t s) {
     const NetLayer& l = n->L[li];
-    PG_TRY(conv_bwdw(l.cin, l.cout, in, dz, n->wpart, nvox, D, s));
-    const int nw = 27 * l.cin * l.cout;
-    hipLaunchKernelGGL(k_sum_splits, g1(nw), dim3(256), 0, s, n->wpart, kSplits, nw, n->Gr + l.w_off);
-    const int nbb = ceil_div(nvox, 1024);
-    hipLaunchKernelGGL(k_bias_grad, dim3(nbb), dim3(256), 0, s, dz, nvox, l.cout, n->wpart);
-    hipLaunchKernelGGL(k_sum_splits, g1(l.cout), dim3(256), 0, s, n->wpart, nbb, l.cout, n->Gr + l.b_off);
+    const int Vs = D * D * D;
+    PG_TRY(to_cmajor(l.cin, in, nvox, Vs, n->tin, s));
+    PG_TRY(to_cmajor(l.cout, dz, nvox, Vs, n->tdz, s));
+    const int ns = bwdw_splits(l.cin, nvox);
+    PG_TRY(conv_bwdw(l.cin, l.cout, n->tin, n->tdz, n->wpart, nvox, D, ns, s));
+    const int nw = (27 * l.cin + 1) * l.cout;
+    hipLaunchKernelGGL(k_sum_splits, dim3(ceil_div(nw, 64)), dim3(256), 0, s, n->wpart, ns, nw, n->Gr + l.w_off);
     PG_HIP(hipGetLastError());
     return PETGEM_OK;
 }
@@ -726,9 +832,11 @@ int petgem_net_create(int32_t batch_max, uint64_t seed, petgem_net** out) {
         (rc = dalloc(&n->bn, (size_t)batch_max)))
         return fail(rc);
     size_t wp = 0;
-    for (auto& l : n->L) wp = std::max(wp, wpart_floats(l.cin, l.cout));
-    wp = std::max(wp, (size_t)ceil_div((int64_t)v32, 1024) * 96);
-    if ((rc = dalloc(&n->wpart, wp)) || (rc = dalloc(&n->lpart, (size_t)ceil_div((int64_t)v32, 256))))
+    for (auto& l : n->L) {
+        const long nv = (long)batch_max * (l.side * l.side * l.side);
+        wp = std::max(wp, wpart_floats(l.cin, l.cout, nv));
+    }
+    if ((rc = dalloc(&n->wpart, wp)) || (rc = dalloc(&n->tin, v32 * 48)) || (rc = dalloc(&n->tdz, v32 * 16)) || (rc = dalloc(&n->lpart, (size_t)ceil_div((int64_t)v32, 256))))
         return fail(rc);
     if (hipHostMalloc(reinterpret_cast<void**>(&n->lpart_h), sizeof(double) * ceil_div((int64_t)v32, 256)) != hipSuccess)
         return fail(PETGEM_OUT_OF_MEMORY);
