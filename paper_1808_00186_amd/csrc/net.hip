@@ -18,7 +18,7 @@
 // channels, so every lane's 4 K values are 8 contiguous bytes). The backward
 // data pass is the same kernel with the taps mirrored and the channel roles
 // swapped; the backward weight pass is an MFMA reduction over voxels on
-// channel-major copies of the layer input and its output gradient.
+// voxel-quad interleaved copies of the layer input and its output gradient.
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -50,88 +50,136 @@ __device__ __forceinline__ float bf2f(bf16 h) { return __uint_as_float((uint32_t
 // ---------------------------------------------------------------- conv
 // out[v][co] = sum_tap sum_ci in[v + off(tap)][ci] W[tap][ci][co] (+ bias, relu)
 // in bf16 [B][D^3][CIN], wt bf16 [COUT][27*CIN] (K-contiguous per output
-// channel), out bf16 or f32 [B][D^3][COUT]. One wave: 16 voxels x COUT.
-template <int CIN, int COUT, bool RELU, bool OUTF32>
+// channel), out bf16 or f32 [B][D^3][COUT].
+// A block owns TY full x rows of one z plane (TY*D voxels, 16-voxel M tiles,
+// MT per wave) and NTB 16-wide output tiles. For each of the three z offsets
+// it stages in LDS the input rows y0-1 .. y0+TY of that plane (x padded by a
+// zero column on both sides) and the nine taps of weights of that plane; the
+// MFMA operands are then 8-byte LDS reads, each A fragment feeding NTB MFMAs
+// and each weight fragment MT.
+template <int CIN, int COUT, int D, int TY, int NTB>
+struct ConvTile {
+    static constexpr int MT = TY * D / 64;           // M tiles per wave
+    static constexpr int HC = CIN + 4;               // halo voxel stride (bf16)
+    static constexpr int WK = 9 * CIN + 4;           // weight row stride (bf16)
+    static constexpr int HALO = (TY + 2) * (D + 2) * HC;
+    static constexpr int WTS = 16 * NTB * WK;
+    static_assert(TY * D % 64 == 0 && D % TY == 0 && COUT % (16 * NTB) == 0 && CIN % 16 == 0, "tile shape");
+};
+
+template <int CIN, int COUT, int D, int TY, int NTB, bool RELU, bool OUTF32>
 __global__ void __launch_bounds__(256)
 k_conv(const bf16* __restrict__ in, const bf16* __restrict__ wt, const float* __restrict__ bias,
-       void* __restrict__ out, int nvox, int D) {
-    constexpr int NT = COUT / 16;
-    constexpr int K = 27 * CIN;
-    const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
-    const int m = l & 15, kq = l >> 4;
-    const long vbase = ((long)blockIdx.x * 4 + wave) * 16;
-    const int Vs = D * D * D;
-    const long v = vbase + m;
-    const bool vok = v < nvox;
-    const int b = vok ? (int)(v / Vs) : 0;
-    const int r = vok ? (int)(v % Vs) : 0;
-    const int z = r / (D * D), y = (r / D) % D, x = r % D;
-    f32x4 acc[NT];
+       void* __restrict__ out) {
+    using T = ConvTile<CIN, COUT, D, TY, NTB>;
+    constexpr int MT = T::MT, HC = T::HC, WK = T::WK, K = 27 * CIN, Vs = D * D * D;
+    __shared__ __align__(16) bf16 halo[T::HALO];
+    __shared__ __align__(16) bf16 wl[T::WTS];
+    const int wave = threadIdx.x >> 6, l = threadIdx.x & 63, m = l & 15, kq = l >> 4;
+    const long v0 = (long)blockIdx.x * TY * D;
+    const int b = (int)(v0 / Vs), r0 = (int)(v0 % Vs);
+    const int z = r0 / (D * D), y0 = (r0 / D) % D;
+    const int co0 = blockIdx.y * 16 * NTB;
+    // LDS offsets of this lane's voxel in each of its M tiles (tile wave + 4 i)
+    int aoff[MT];
 #pragma unroll
-    for (int t = 0; t < NT; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
-    for (int tap = 0; tap < 27; ++tap) {
-        const int nz = z + tap / 9 - 1, ny = y + (tap / 3) % 3 - 1, nx = x + tap % 3 - 1;
-        const bool ok = vok && nz >= 0 && nz < D && ny >= 0 && ny < D && nx >= 0 && nx < D;
-        const bf16* src = in + ((long)b * Vs + ((long)nz * D + ny) * D + nx) * CIN + 4 * kq;
+    for (int i = 0; i < MT; ++i) {
+        const int vb = (wave + 4 * i) * 16 + m;
+        aoff[i] = ((vb / D) * (D + 2) + vb % D) * HC + 4 * kq;
+    }
+    f32x4 acc[MT][NTB];
 #pragma unroll
-        for (int c0 = 0; c0 < CIN; c0 += 16) {
-            bf16x4 a = {0, 0, 0, 0};
-            if (ok) a = *reinterpret_cast<const bf16x4*>(src + c0);
-            const int kk = tap * CIN + c0 + 4 * kq;
+    for (int i = 0; i < MT; ++i)
 #pragma unroll
-            for (int t = 0; t < NT; ++t) {
-                const bf16x4 w = *reinterpret_cast<const bf16x4*>(wt + (long)(t * 16 + m) * K + kk);
-                acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, w, acc[t], 0, 0, 0);
+        for (int t = 0; t < NTB; ++t) acc[i][t] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int pz = 0; pz < 3; ++pz) {
+        const int zz = z + pz - 1;
+        // input rows y0-1 .. y0+TY of plane zz, 4 channels per store
+        constexpr int Q = CIN / 4;
+        for (int e = threadIdx.x; e < (TY + 2) * (D + 2) * Q; e += 256) {
+            const int q = e % Q, vx = e / Q;
+            const int rx = vx % (D + 2), ry = vx / (D + 2);
+            const int yy = y0 - 1 + ry, xx = rx - 1;
+            uint2 val = make_uint2(0u, 0u);
+            if (zz >= 0 && zz < D && yy >= 0 && yy < D && xx >= 0 && xx < D)
+                val = *reinterpret_cast<const uint2*>(in + ((long)b * Vs + ((long)zz * D + yy) * D + xx) * CIN + 4 * q);
+            *reinterpret_cast<uint2*>(halo + vx * HC + 4 * q) = val;
+        }
+        // weights of taps 9 pz .. 9 pz + 8 for this block's output channels
+        constexpr int WQ = 9 * CIN / 4;
+        for (int e = threadIdx.x; e < 16 * NTB * WQ; e += 256) {
+            const int q = e % WQ, c = e / WQ;
+            *reinterpret_cast<uint2*>(wl + c * WK + 4 * q) =
+                *reinterpret_cast<const uint2*>(wt + (long)(co0 + c) * K + pz * 9 * CIN + 4 * q);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int t9 = 0; t9 < 9; ++t9) {
+            const int sh = ((t9 / 3) * (D + 2) + t9 % 3) * HC;   // (dy, dx) shift in the halo
+#pragma unroll
+            for (int c0 = 0; c0 < CIN; c0 += 16) {
+                bf16x4 a[MT], w[NTB];
+#pragma unroll
+                for (int i = 0; i < MT; ++i) a[i] = *reinterpret_cast<const bf16x4*>(halo + aoff[i] + sh + c0);
+#pragma unroll
+                for (int t = 0; t < NTB; ++t)
+                    w[t] = *reinterpret_cast<const bf16x4*>(wl + (t * 16 + m) * WK + t9 * CIN + c0 + 4 * kq);
+#pragma unroll
+                for (int i = 0; i < MT; ++i)
+#pragma unroll
+                    for (int t = 0; t < NTB; ++t)
+                        acc[i][t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], w[t], acc[i][t], 0, 0, 0);
             }
         }
+        __syncthreads();
     }
-    // lane holds D[row 4 kq + j][col m] of every output tile
+    // lane holds D[row voxel 4 kq + j][col co m] of every (M tile, output tile)
 #pragma unroll
-    for (int t = 0; t < NT; ++t) {
-        const int co = t * 16 + m;
+    for (int t = 0; t < NTB; ++t) {
+        const int co = co0 + t * 16 + m;
         const float bb = bias ? bias[co] : 0.f;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const long vo = vbase + 4 * kq + j;
-            if (vo >= nvox) continue;
-            float val = acc[t][j] + bb;
-            if (RELU) val = fmaxf(val, 0.f);
-            if (OUTF32) reinterpret_cast<float*>(out)[vo * COUT + co] = val;
-            else reinterpret_cast<bf16*>(out)[vo * COUT + co] = f2bf(val);
-        }
+        for (int i = 0; i < MT; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const long vo = v0 + (wave + 4 * i) * 16 + 4 * kq + j;
+                float val = acc[i][t][j] + bb;
+                if (RELU) val = fmaxf(val, 0.f);
+                if (OUTF32) reinterpret_cast<float*>(out)[vo * COUT + co] = val;
+                else reinterpret_cast<bf16*>(out)[vo * COUT + co] = f2bf(val);
+            }
     }
 }
 
-// Channel-major copy of an activation: out[b][c][r] = in[b][r][c] for
-// r < Vs (Vs a multiple of 64). One block moves 64 voxels x C channels
-// through LDS so that both sides are 8-byte vector accesses.
+// Voxel-quad interleaved copy of an activation: out[((v/4) C + c) 4 + v%4] =
+// in[v][c]. A lane of the weight pass then reads 4 consecutive voxels of one
+// channel as 8 contiguous bytes, and the 16 channels of a wave's fragment
+// are adjacent. One thread moves 4 voxels x 4 channels.
 template <int C>
 __global__ void __launch_bounds__(256)
-k_to_cmajor(const bf16* __restrict__ in, int Vs, bf16* __restrict__ out) {
-    __shared__ bf16 tile[64][C + 4];
-    const long v0 = (long)blockIdx.x * 64;
-    const int b = (int)(v0 / Vs), r0 = (int)(v0 % Vs);
-    const uint2* src = reinterpret_cast<const uint2*>(in + v0 * C);
-    for (int q = threadIdx.x; q < 16 * C; q += 256) {   // 4 channels of one voxel
-        const uint2 w = src[q];
-        const int vv = (4 * q) / C, c = (4 * q) % C;
-        tile[vv][c] = (bf16)(w.x & 0xffffu);
-        tile[vv][c + 1] = (bf16)(w.x >> 16);
-        tile[vv][c + 2] = (bf16)(w.y & 0xffffu);
-        tile[vv][c + 3] = (bf16)(w.y >> 16);
-    }
-    __syncthreads();
-    for (int q = threadIdx.x; q < 16 * C; q += 256) {   // 4 voxels of one channel
-        const int c = q / 16, vv = 4 * (q % 16);
-        uint2 w;
-        w.x = (uint32_t)tile[vv][c] | ((uint32_t)tile[vv + 1][c] << 16);
-        w.y = (uint32_t)tile[vv + 2][c] | ((uint32_t)tile[vv + 3][c] << 16);
-        *reinterpret_cast<uint2*>(out + ((long)b * C + c) * Vs + r0 + vv) = w;
+k_to_quads(const bf16* __restrict__ in, long nvox, bf16* __restrict__ out) {
+    const long e = (long)blockIdx.x * 256 + threadIdx.x;
+    if (e >= nvox / 4 * (C / 4)) return;
+    const long q = e / (C / 4);
+    const int c = 4 * (int)(e % (C / 4));
+    uint2 w[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) w[j] = *reinterpret_cast<const uint2*>(in + (4 * q + j) * C + c);
+    // channel c + i of voxel 4q + j is half (i & 1) of word (i >> 1) of w[j]
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        uint32_t h[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint32_t word = (i >> 1) ? w[j].y : w[j].x;
+            h[j] = (i & 1) ? (word >> 16) : (word & 0xffffu);
+        }
+        *reinterpret_cast<uint2*>(out + (q * C + c + i) * 4) = make_uint2(h[0] | (h[1] << 16), h[2] | (h[3] << 16));
     }
 }
 
-// Backward weights and bias from channel-major copies inT [B][CIN][D^3] and
-// dzT [B][COUT][D^3]:
+// Backward weights and bias from voxel-quad interleaved copies inQ
+// [B D^3 / 4][CIN][4] and dzQ [B D^3 / 4][COUT][4]:
 //   partial[s][tap * CIN + ci][co] = sum over the voxels of split s of
 //                                    in[v + off(tap)][ci] dz[v][co]
 //   partial[s][27 CIN][co]         = sum over the same voxels of dz[v][co].
@@ -142,16 +190,15 @@ k_to_cmajor(const bf16* __restrict__ in, int Vs, bf16* __restrict__ out) {
 // order, so the result does not depend on timing. A wave keeps the 9 (y, x)
 // offsets x all output tiles in registers: one 16-byte load per input row
 // (x0-2 .. x0+5 of one channel) yields the three x shifts by funnel shifts.
-template <int CIN, int COUT>
+template <int CIN, int COUT, int D>
 __global__ void __launch_bounds__(256)
-k_conv_bwdw(const bf16* __restrict__ inT, const bf16* __restrict__ dzT, float* __restrict__ partial,
-            int nvox, int D, int nsplit) {
-    constexpr int NT = COUT / 16, KW = 27 * CIN;
+k_conv_bwdw(const bf16* __restrict__ inQ, const bf16* __restrict__ dzQ, float* __restrict__ partial,
+            int nvox, int nsplit) {
+    constexpr int NT = COUT / 16, KW = 27 * CIN, Vs = D * D * D;
     const int wave = threadIdx.x >> 6, l = threadIdx.x & 63, m = l & 15, kq = l >> 4;
     const int s = blockIdx.x % nsplit, unit = blockIdx.x / nsplit;
     const int g = unit / 3, pz = unit % 3;
     const bool bias_unit = unit == 1;   // g = 0, z offset 0
-    const int Vs = D * D * D;
     const int nK = nvox / 16, chunk = (nK + nsplit - 1) / nsplit;
     const int k0 = s * chunk, k1 = min(nK, k0 + chunk);
     f32x4 acc[3][3][NT], accb[NT];
@@ -164,28 +211,38 @@ k_conv_bwdw(const bf16* __restrict__ inT, const bf16* __restrict__ dzT, float* _
             for (int c = 0; c < 3; ++c) acc[a][c][t] = f32x4{0.f, 0.f, 0.f, 0.f};
     }
     const bf16x4 ones = {0x3f80, 0x3f80, 0x3f80, 0x3f80};
-    for (int k = k0 + wave; k < k1; k += 4) {
+    // operands of one K step: dz fragments and, per y offset, the row words
+    // x0-2 .. x0+5 of this lane's input channel
+    struct Step {
+        bf16x4 w[NT];
+        uint32_t dp[3], d0[3], d1[3], dn[3];
+    };
+    auto load = [&](int k, Step& st) {
         const int v = 16 * k + 4 * kq;
         const int b = v / Vs, r = v % Vs;
         const int z = r / (D * D), y = (r / D) % D, x0 = r % D;
-        bf16x4 w[NT];
 #pragma unroll
         for (int t = 0; t < NT; ++t)
-            w[t] = *reinterpret_cast<const bf16x4*>(dzT + ((long)b * COUT + t * 16 + m) * Vs + r);
-        const int zz = z + pz - 1;
-        const long cbase = ((long)b * CIN + g * 16 + m) * Vs;
+            st.w[t] = *reinterpret_cast<const bf16x4*>(dzQ + ((long)(v / 4) * COUT + t * 16 + m) * 4);
+        const int zz = z + pz - 1, ci = g * 16 + m;
 #pragma unroll
         for (int dy = 0; dy < 3; ++dy) {
             const int yy = y + dy - 1;
-            uint32_t dp = 0, d0 = 0, d1 = 0, dn = 0;
+            st.dp[dy] = st.d0[dy] = st.d1[dy] = st.dn[dy] = 0;
             if (zz >= 0 && zz < D && yy >= 0 && yy < D) {
-                const bf16* row = inT + cbase + ((long)zz * D + yy) * D + x0;
-                const uint2 c = *reinterpret_cast<const uint2*>(row);
-                d0 = c.x;
-                d1 = c.y;
-                if (x0 > 0) dp = *reinterpret_cast<const uint32_t*>(row - 2);
-                if (x0 + 4 < D) dn = *reinterpret_cast<const uint32_t*>(row + 4);
+                const long q = ((long)b * Vs + ((long)zz * D + yy) * D + x0) / 4;   // quad of x0 .. x0+3
+                const uint2 c = *reinterpret_cast<const uint2*>(inQ + (q * CIN + ci) * 4);
+                st.d0[dy] = c.x;
+                st.d1[dy] = c.y;
+                if (x0 > 0) st.dp[dy] = *reinterpret_cast<const uint32_t*>(inQ + ((q - 1) * CIN + ci) * 4 + 2);
+                if (x0 + 4 < D) st.dn[dy] = *reinterpret_cast<const uint32_t*>(inQ + ((q + 1) * CIN + ci) * 4);
             }
+        }
+    };
+    auto compute = [&](const Step& st) {
+#pragma unroll
+        for (int dy = 0; dy < 3; ++dy) {
+            const uint32_t dp = st.dp[dy], d0 = st.d0[dy], d1 = st.d1[dy], dn = st.dn[dy];
             // voxels x0-1..x0+2, x0..x0+3, x0+1..x0+4 of this row
             const uint32_t lo[3] = {(dp >> 16) | (d0 << 16), d0, (d0 >> 16) | (d1 << 16)};
             const uint32_t hi[3] = {(d0 >> 16) | (d1 << 16), d1, (d1 >> 16) | (dn << 16)};
@@ -195,13 +252,24 @@ k_conv_bwdw(const bf16* __restrict__ inT, const bf16* __restrict__ dzT, float* _
                 const bf16x4 a = __builtin_bit_cast(bf16x4, (u32x2{lo[dx], hi[dx]}));
 #pragma unroll
                 for (int t = 0; t < NT; ++t)
-                    acc[dy][dx][t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, w[t], acc[dy][dx][t], 0, 0, 0);
+                    acc[dy][dx][t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, st.w[t], acc[dy][dx][t], 0, 0, 0);
             }
         }
         if (bias_unit) {
 #pragma unroll
-            for (int t = 0; t < NT; ++t) accb[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ones, w[t], accb[t], 0, 0, 0);
+            for (int t = 0; t < NT; ++t)
+                accb[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ones, st.w[t], accb[t], 0, 0, 0);
         }
+    };
+    // the loads of the next K step are issued before the MFMAs of this one
+    Step cur;
+    int k = k0 + wave;
+    if (k < k1) load(k, cur);
+    for (; k < k1; k += 4) {
+        Step nxt = cur;
+        if (k + 4 < k1) load(k + 4, nxt);
+        compute(cur);
+        cur = nxt;
     }
     // wave-ordered sum of the 4 waves, one output tile column at a time;
     // lane holds D[row ci = 4 kq + j][col co = m]
@@ -248,83 +316,106 @@ k_sum_splits(const float* __restrict__ partial, int nsplit, int n, float* __rest
     if (q == 0 && i < n) out[i] = red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] + red[3][threadIdx.x];
 }
 
-// 2x2x2 average pooling (fine side D), channel stride/offset for concatenation
-__global__ void k_pool(const bf16* __restrict__ in, int ldi, int B, int D, int C, bf16* __restrict__ out, int ldo) {
-    const long e = (long)blockIdx.x * 256 + threadIdx.x;
+// Elementwise kernels move 4 channels (8 bytes of bf16, 16 of f32) per
+// thread; every channel count and offset is a multiple of 4.
+__device__ __forceinline__ float4 ld_bf4(const bf16* p) {
+    const uint2 w = *reinterpret_cast<const uint2*>(p);
+    return make_float4(__uint_as_float(w.x << 16), __uint_as_float(w.x & 0xffff0000u), __uint_as_float(w.y << 16),
+                       __uint_as_float(w.y & 0xffff0000u));
+}
+__device__ __forceinline__ void st_bf4(bf16* p, float4 v) {
+    *reinterpret_cast<uint2*>(p) = make_uint2((uint32_t)f2bf(v.x) | ((uint32_t)f2bf(v.y) << 16),
+                                              (uint32_t)f2bf(v.z) | ((uint32_t)f2bf(v.w) << 16));
+}
+// parent (coarse) voxel of fine voxel vf on a grid of side D
+__device__ __forceinline__ long parent_of(long vf, int D) {
     const int Dc = D / 2;
-    const long n = (long)B * Dc * Dc * Dc * C;
-    if (e >= n) return;
-    const int c = (int)(e % C);
-    const long vc = e / C;
-    const int b = (int)(vc / (Dc * Dc * Dc)), r = (int)(vc % (Dc * Dc * Dc));
-    const int z = r / (Dc * Dc), y = (r / Dc) % Dc, x = r % Dc;
-    float s = 0.f;
-    for (int q = 0; q < 8; ++q) {
-        const long vf = (long)b * D * D * D + ((long)(2 * z + (q >> 2)) * D + 2 * y + ((q >> 1) & 1)) * D + 2 * x + (q & 1);
-        s += bf2f(in[vf * ldi + c]);
-    }
-    out[vc * ldo + c] = f2bf(0.125f * s);
-}
-
-// nearest upsampling x2 into channels [off, off+C) of a wider tensor, and a
-// channel copy (for the skip half of a concatenation)
-__global__ void k_up(const bf16* __restrict__ in, int B, int Dc, int C, bf16* __restrict__ out, int ldo, int off) {
-    const long e = (long)blockIdx.x * 256 + threadIdx.x;
-    const int D = 2 * Dc;
-    const long n = (long)B * D * D * D * C;
-    if (e >= n) return;
-    const int c = (int)(e % C);
-    const long vf = e / C;
-    const int b = (int)(vf / (D * D * D)), r = (int)(vf % (D * D * D));
+    const long b = vf / ((long)D * D * D);
+    const int r = (int)(vf % ((long)D * D * D));
     const int z = r / (D * D), y = (r / D) % D, x = r % D;
-    const long vc = (long)b * Dc * Dc * Dc + ((long)(z / 2) * Dc + y / 2) * Dc + x / 2;
-    out[vf * ldo + off + c] = in[vc * C + c];
+    return b * Dc * Dc * Dc + ((long)(z / 2) * Dc + y / 2) * Dc + x / 2;
 }
-__global__ void k_copy_ch(const bf16* __restrict__ in, long nvox, int C, bf16* __restrict__ out, int ldo, int off) {
-    const long e = (long)blockIdx.x * 256 + threadIdx.x;
-    if (e >= nvox * C) return;
-    out[(e / C) * ldo + off + e % C] = in[e];
-}
-
-// Backward of "nearest up into [0, C) of dq": dcoarse = sum of the 8 children
-__global__ void k_up_bwd(const float* __restrict__ dq, int ldq, int B, int Dc, int C, float* __restrict__ dout) {
-    const long e = (long)blockIdx.x * 256 + threadIdx.x;
-    const long n = (long)B * Dc * Dc * Dc * C;
-    if (e >= n) return;
-    const int c = (int)(e % C);
-    const long vc = e / C;
+// q-th of the 8 children of coarse voxel vc (side Dc) on the fine grid
+__device__ __forceinline__ long child_of(long vc, int Dc, int q) {
     const int D = 2 * Dc;
-    const int b = (int)(vc / (Dc * Dc * Dc)), r = (int)(vc % (Dc * Dc * Dc));
+    const long b = vc / ((long)Dc * Dc * Dc);
+    const int r = (int)(vc % ((long)Dc * Dc * Dc));
     const int z = r / (Dc * Dc), y = (r / Dc) % Dc, x = r % Dc;
-    float s = 0.f;
-    for (int q = 0; q < 8; ++q) {
-        const long vf = (long)b * D * D * D + ((long)(2 * z + (q >> 2)) * D + 2 * y + ((q >> 1) & 1)) * D + 2 * x + (q & 1);
-        s += dq[vf * ldq + c];
-    }
-    dout[vc * C + c] = s;
+    return b * D * D * D + ((long)(2 * z + (q >> 2)) * D + 2 * y + ((q >> 1) & 1)) * D + 2 * x + (q & 1);
 }
 
-// dA (fine, C channels) = dq[:, off:off+C] (skip half of a concatenation) +
-// pooling backward of dp (coarse): dp[parent] / 8
-__global__ void k_skip_pool_bwd(const float* __restrict__ dq, int ldq, int off, const float* __restrict__ dp,
-                                int B, int D, int C, float* __restrict__ da) {
+// 2x2x2 average pooling (fine side D), C channels
+__global__ void k_pool(const bf16* __restrict__ in, int B, int D, int C, bf16* __restrict__ out) {
     const long e = (long)blockIdx.x * 256 + threadIdx.x;
-    const long n = (long)B * D * D * D * C;
-    if (e >= n) return;
-    const int c = (int)(e % C);
-    const long vf = e / C;
-    const int Dc = D / 2;
-    const int b = (int)(vf / (D * D * D)), r = (int)(vf % (D * D * D));
-    const int z = r / (D * D), y = (r / D) % D, x = r % D;
-    const long vc = (long)b * Dc * Dc * Dc + ((long)(z / 2) * Dc + y / 2) * Dc + x / 2;
-    da[e] = dq[vf * ldq + off + c] + 0.125f * dp[vc * C + c];
+    const int Dc = D / 2, C4 = C / 4;
+    if (e >= (long)B * Dc * Dc * Dc * C4) return;
+    const int c = 4 * (int)(e % C4);
+    const long vc = e / C4;
+    float4 s = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int q = 0; q < 8; ++q) {
+        const float4 v = ld_bf4(in + child_of(vc, Dc, q) * C + c);
+        s.x += v.x; s.y += v.y; s.z += v.z; s.w += v.w;
+    }
+    st_bf4(out + vc * C + c, make_float4(0.125f * s.x, 0.125f * s.y, 0.125f * s.z, 0.125f * s.w));
+}
+
+// concatenation [nearest x2 upsampling of the coarse tensor (C1 channels) |
+// skip tensor (C2 channels)] on the fine grid of side D
+__global__ void k_up_concat(const bf16* __restrict__ coarse, int C1, const bf16* __restrict__ skip, int C2, int B,
+                            int D, bf16* __restrict__ out) {
+    const long e = (long)blockIdx.x * 256 + threadIdx.x;
+    const int W4 = (C1 + C2) / 4;
+    if (e >= (long)B * D * D * D * W4) return;
+    const int c = 4 * (int)(e % W4);
+    const long vf = e / W4;
+    const uint2 w = c < C1 ? *reinterpret_cast<const uint2*>(coarse + parent_of(vf, D) * C1 + c)
+                           : *reinterpret_cast<const uint2*>(skip + vf * C2 + (c - C1));
+    *reinterpret_cast<uint2*>(out + vf * (C1 + C2) + c) = w;
+}
+
+// ReLU backward of the coarse half of an upsampling concatenation:
+// dz[vc][c] = (y[vc][c] > 0) * sum over the 8 children of dq[child][c], c < C
+__global__ void k_up_bwd_relu(const float* __restrict__ dq, int ldq, int B, int Dc, int C,
+                              const bf16* __restrict__ y, bf16* __restrict__ dz) {
+    const long e = (long)blockIdx.x * 256 + threadIdx.x;
+    const int C4 = C / 4;
+    if (e >= (long)B * Dc * Dc * Dc * C4) return;
+    const int c = 4 * (int)(e % C4);
+    const long vc = e / C4;
+    float4 s = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int q = 0; q < 8; ++q) {
+        const float4 v = *reinterpret_cast<const float4*>(dq + child_of(vc, Dc, q) * ldq + c);
+        s.x += v.x; s.y += v.y; s.z += v.z; s.w += v.w;
+    }
+    const float4 a = ld_bf4(y + vc * C + c);
+    st_bf4(dz + vc * C + c, make_float4(a.x > 0.f ? s.x : 0.f, a.y > 0.f ? s.y : 0.f, a.z > 0.f ? s.z : 0.f,
+                                        a.w > 0.f ? s.w : 0.f));
+}
+
+// ReLU backward of a pooled activation that also feeds a skip connection:
+// dz = (y > 0) * (dq[:, off:off+C] + dp[parent] / 8)
+__global__ void k_skip_pool_bwd_relu(const float* __restrict__ dq, int ldq, int off, const float* __restrict__ dp,
+                                     int B, int D, int C, const bf16* __restrict__ y, bf16* __restrict__ dz) {
+    const long e = (long)blockIdx.x * 256 + threadIdx.x;
+    const int C4 = C / 4;
+    if (e >= (long)B * D * D * D * C4) return;
+    const int c = 4 * (int)(e % C4);
+    const long vf = e / C4;
+    const float4 u = *reinterpret_cast<const float4*>(dq + vf * ldq + off + c);
+    const float4 p = *reinterpret_cast<const float4*>(dp + parent_of(vf, D) * C + c);
+    const float4 a = ld_bf4(y + vf * C + c);
+    st_bf4(dz + vf * C + c, make_float4(a.x > 0.f ? u.x + 0.125f * p.x : 0.f, a.y > 0.f ? u.y + 0.125f * p.y : 0.f,
+                                        a.z > 0.f ? u.z + 0.125f * p.z : 0.f, a.w > 0.f ? u.w + 0.125f * p.w : 0.f));
 }
 
 // dz = dy * (y > 0) as bf16 (ReLU backward; y is the stored activation)
 __global__ void k_relu_bwd(const float* __restrict__ dy, const bf16* __restrict__ y, long n, bf16* __restrict__ dz) {
     const long e = (long)blockIdx.x * 256 + threadIdx.x;
-    if (e >= n) return;
-    dz[e] = f2bf(bf2f(y[e]) > 0.f ? dy[e] : 0.f);
+    if (e >= n / 4) return;
+    const float4 d = *reinterpret_cast<const float4*>(dy + 4 * e);
+    const float4 a = ld_bf4(y + 4 * e);
+    st_bf4(dz + 4 * e, make_float4(a.x > 0.f ? d.x : 0.f, a.y > 0.f ? d.y : 0.f, a.z > 0.f ? d.z : 0.f,
+                                   a.w > 0.f ? d.w : 0.f));
 }
 
 // Mean squared error over the used output channels; dY = d loss / d Y (bf16)
@@ -508,7 +599,7 @@ struct petgem_net {
     float* Y = nullptr;
     float *g0 = nullptr, *g1 = nullptr, *g2 = nullptr;   // f32 gradient scratch
     float* wpart = nullptr;                              // backward-weight partials
-    petgem::bf16 *tin = nullptr, *tdz = nullptr;         // channel-major copies for the weight pass
+    petgem::bf16 *tin = nullptr, *tdz = nullptr;         // voxel-quad copies for the weight pass
     double* lpart = nullptr;
     float* T = nullptr;       // targets of the current batch (caller-owned copy not needed)
     double* scal = nullptr;   // per-sample scales on device
@@ -523,67 +614,70 @@ namespace petgem {
 
 namespace {
 
+inline dim3 g1(long n) { return dim3((unsigned)((n + 255) / 256)); }
+
 // voxel splits of the weight pass: enough blocks to fill the chip, at least
 // 8 K steps per wave
 int bwdw_splits(int cin, long nvox) {
     const int units = 3 * (cin / 16);
     const long cap = std::max(1L, nvox / 16 / 32);
-    return (int)std::min<long>(cap, std::max(1, ceil_div(512, units)));
+    return (int)std::min<long>(cap, std::max(1, ceil_div(1024, units)));
 }
 size_t wpart_floats(int cin, int cout, long nvox) {
     return (size_t)bwdw_splits(cin, nvox) * (27 * (size_t)cin + 1) * cout;
 }
 
-template <int CIN, int COUT, bool RELU, bool OUTF32>
-void conv_t(const bf16* in, const bf16* wt, const float* bias, void* out, int nvox, int D, hipStream_t s) {
-    hipLaunchKernelGGL((k_conv<CIN, COUT, RELU, OUTF32>), dim3(ceil_div(nvox, 64)), dim3(256), 0, s, in, wt,
-                       bias, out, nvox, D);
+template <int CIN, int COUT, int D, int TY, int NTB>
+void conv_t(bool relu, bool outf32, const bf16* in, const bf16* wt, const float* bias, void* out, int nvox,
+            hipStream_t s) {
+    const dim3 grid((unsigned)(nvox / (TY * D)), COUT / (16 * NTB));
+    if (outf32) hipLaunchKernelGGL((k_conv<CIN, COUT, D, TY, NTB, false, true>), grid, dim3(256), 0, s, in, wt, bias, out);
+    else if (relu) hipLaunchKernelGGL((k_conv<CIN, COUT, D, TY, NTB, true, false>), grid, dim3(256), 0, s, in, wt, bias, out);
+    else hipLaunchKernelGGL((k_conv<CIN, COUT, D, TY, NTB, false, false>), grid, dim3(256), 0, s, in, wt, bias, out);
 }
 
-// forward/backward-data convolution dispatch on the (CIN, COUT) pairs used
+// forward/backward-data convolution dispatch on the (CIN, COUT, side) triples
+// of the network; nvox = B side^3
 int conv(int cin, int cout, bool relu, bool outf32, const bf16* in, const bf16* wt, const float* bias, void* out,
          int nvox, int D, hipStream_t s) {
-#define PG_CV(A, B)                                                                         \
-    if (cin == A && cout == B) {                                                            \
-        if (outf32) conv_t<A, B, false, true>(in, wt, bias, out, nvox, D, s);               \
-        else if (relu) conv_t<A, B, true, false>(in, wt, bias, out, nvox, D, s);            \
-        else conv_t<A, B, false, false>(in, wt, bias, out, nvox, D, s);                     \
-        return PETGEM_OK;                                                                   \
+#define PG_CV(A, B, SIDE, TY, NTB)                                                     \
+    if (cin == A && cout == B && D == SIDE) {                                          \
+        conv_t<A, B, SIDE, TY, NTB>(relu, outf32, in, wt, bias, out, nvox, s);         \
+        return PETGEM_OK;                                                              \
     }
-    PG_CV(16, 16) PG_CV(16, 32) PG_CV(32, 16) PG_CV(32, 64) PG_CV(64, 32) PG_CV(64, 64)
-    PG_CV(96, 32) PG_CV(32, 96) PG_CV(48, 16) PG_CV(16, 48)
+    PG_CV(16, 16, 32, 8, 1) PG_CV(48, 16, 32, 8, 1) PG_CV(16, 48, 32, 8, 3)
+    PG_CV(16, 32, 16, 8, 2) PG_CV(96, 32, 16, 8, 1) PG_CV(32, 96, 16, 8, 3) PG_CV(32, 16, 16, 8, 1)
+    PG_CV(32, 64, 8, 8, 1) PG_CV(64, 64, 8, 8, 1) PG_CV(64, 32, 8, 8, 1)
 #undef PG_CV
     set_error("unsupported convolution shape");
     return PETGEM_INVALID_ARG;
 }
 
-int to_cmajor(int c, const bf16* in, long nvox, int Vs, bf16* out, hipStream_t s) {
-#define PG_TC(C)                                                                                           \
-    if (c == C) {                                                                                          \
-        hipLaunchKernelGGL((k_to_cmajor<C>), dim3((unsigned)(nvox / 64)), dim3(256), 0, s, in, Vs, out);   \
-        return PETGEM_OK;                                                                                  \
+int to_quads(int c, const bf16* in, long nvox, bf16* out, hipStream_t s) {
+#define PG_TQ(C)                                                                                    \
+    if (c == C) {                                                                                   \
+        hipLaunchKernelGGL((k_to_quads<C>), g1(nvox / 4 * (C / 4)), dim3(256), 0, s, in, nvox, out); \
+        return PETGEM_OK;                                                                           \
     }
-    PG_TC(16) PG_TC(32) PG_TC(48) PG_TC(64) PG_TC(96)
-#undef PG_TC
+    PG_TQ(16) PG_TQ(32) PG_TQ(48) PG_TQ(64) PG_TQ(96)
+#undef PG_TQ
     set_error("unsupported channel count");
     return PETGEM_INVALID_ARG;
 }
 
-int conv_bwdw(int cin, int cout, const bf16* inT, const bf16* dzT, float* part, int nvox, int D, int nsplit,
+int conv_bwdw(int cin, int cout, const bf16* inQ, const bf16* dzQ, float* part, int nvox, int D, int nsplit,
               hipStream_t s) {
     const int nb = 3 * (cin / 16) * nsplit;
-#define PG_BW(A, B)                                                                                          \
-    if (cin == A && cout == B) {                                                                             \
-        hipLaunchKernelGGL((k_conv_bwdw<A, B>), dim3(nb), dim3(256), 0, s, inT, dzT, part, nvox, D, nsplit);  \
-        return PETGEM_OK;                                                                                    \
+#define PG_BW(A, B, SIDE)                                                                                     \
+    if (cin == A && cout == B && D == SIDE) {                                                                 \
+        hipLaunchKernelGGL((k_conv_bwdw<A, B, SIDE>), dim3(nb), dim3(256), 0, s, inQ, dzQ, part, nvox, nsplit); \
+        return PETGEM_OK;                                                                                     \
     }
-    PG_BW(16, 16) PG_BW(16, 32) PG_BW(32, 64) PG_BW(64, 64) PG_BW(96, 32) PG_BW(48, 16)
+    PG_BW(16, 16, 32) PG_BW(16, 32, 16) PG_BW(32, 64, 8) PG_BW(64, 64, 8) PG_BW(96, 32, 16) PG_BW(48, 16, 32)
 #undef PG_BW
     set_error("unsupported convolution shape");
     return PETGEM_INVALID_ARG;
 }
-
-inline dim3 g1(long n) { return dim3((unsigned)((n + 255) / 256)); }
 
 // SplitMix64 + Box-Muller: seeded, platform-independent initial weights
 struct Rng {
@@ -625,16 +719,14 @@ int forward(petgem_net* n, int B, hipStream_t s) {
     const int v32 = B * kVox, v16 = B * kVox / 8, v8 = B * kVox / 64;
     auto& L = n->L;
     PG_TRY(conv(16, 16, true, false, n->X0, L[0].wt, n->P + L[0].b_off, n->A1, v32, 32, s));
-    hipLaunchKernelGGL(k_pool, g1((long)v16 * 16), dim3(256), 0, s, n->A1, 16, B, 32, 16, n->P1, 16);
+    hipLaunchKernelGGL(k_pool, g1((long)v16 * 4), dim3(256), 0, s, n->A1, B, 32, 16, n->P1);
     PG_TRY(conv(16, 32, true, false, n->P1, L[1].wt, n->P + L[1].b_off, n->A2, v16, 16, s));
-    hipLaunchKernelGGL(k_pool, g1((long)v8 * 32), dim3(256), 0, s, n->A2, 32, B, 16, 32, n->P2, 32);
+    hipLaunchKernelGGL(k_pool, g1((long)v8 * 8), dim3(256), 0, s, n->A2, B, 16, 32, n->P2);
     PG_TRY(conv(32, 64, true, false, n->P2, L[2].wt, n->P + L[2].b_off, n->A3, v8, 8, s));
     PG_TRY(conv(64, 64, true, false, n->A3, L[3].wt, n->P + L[3].b_off, n->A4, v8, 8, s));
-    hipLaunchKernelGGL(k_up, g1((long)v16 * 64), dim3(256), 0, s, n->A4, B, 8, 64, n->Q2, 96, 0);
-    hipLaunchKernelGGL(k_copy_ch, g1((long)v16 * 32), dim3(256), 0, s, n->A2, (long)v16, 32, n->Q2, 96, 64);
+    hipLaunchKernelGGL(k_up_concat, g1((long)v16 * 24), dim3(256), 0, s, n->A4, 64, n->A2, 32, B, 16, n->Q2);
     PG_TRY(conv(96, 32, true, false, n->Q2, L[4].wt, n->P + L[4].b_off, n->A5, v16, 16, s));
-    hipLaunchKernelGGL(k_up, g1((long)v32 * 32), dim3(256), 0, s, n->A5, B, 16, 32, n->Q1, 48, 0);
-    hipLaunchKernelGGL(k_copy_ch, g1((long)v32 * 16), dim3(256), 0, s, n->A1, (long)v32, 16, n->Q1, 48, 32);
+    hipLaunchKernelGGL(k_up_concat, g1((long)v32 * 12), dim3(256), 0, s, n->A5, 32, n->A1, 16, B, 32, n->Q1);
     PG_TRY(conv(48, 16, true, false, n->Q1, L[5].wt, n->P + L[5].b_off, n->A6, v32, 32, s));
     PG_TRY(conv(16, 16, false, true, n->A6, L[6].wt, n->P + L[6].b_off, n->Y, v32, 32, s));
     PG_HIP(hipGetLastError());
@@ -646,9 +738,8 @@ int forward(petgem_net* n, int B, hipStream_t s) {
 // w_off + 27 cin cout)
 int layer_grads(petgem_net* n, int li, const bf16* in, const bf16* dz, int nvox, int D, hipStream_t s) {
     const NetLayer& l = n->L[li];
-    const int Vs = D * D * D;
-    PG_TRY(to_cmajor(l.cin, in, nvox, Vs, n->tin, s));
-    PG_TRY(to_cmajor(l.cout, dz, nvox, Vs, n->tdz, s));
+    PG_TRY(to_quads(l.cin, in, nvox, n->tin, s));
+    PG_TRY(to_quads(l.cout, dz, nvox, n->tdz, s));
     const int ns = bwdw_splits(l.cin, nvox);
     PG_TRY(conv_bwdw(l.cin, l.cout, n->tin, n->tdz, n->wpart, nvox, D, ns, s));
     const int nw = (27 * l.cin + 1) * l.cout;
@@ -666,38 +757,35 @@ int backward(petgem_net* n, int B, hipStream_t s) {
     // c7 (linear): dz = dY
     PG_TRY(layer_grads(n, 6, n->A6, dz, v32, 32, s));
     PG_TRY(conv(16, 16, false, true, dz, L[6].wtb, nullptr, g0, v32, 32, s));                  // dA6
-    hipLaunchKernelGGL(k_relu_bwd, g1((long)v32 * 16), dim3(256), 0, s, g0, n->A6, (long)v32 * 16, dz);
+    hipLaunchKernelGGL(k_relu_bwd, g1((long)v32 * 4), dim3(256), 0, s, g0, n->A6, (long)v32 * 16, dz);
     // c6
     PG_TRY(layer_grads(n, 5, n->Q1, dz, v32, 32, s));
     PG_TRY(conv(16, 48, false, true, dz, L[5].wtb, nullptr, g0, v32, 32, s));                  // dQ1 [v32][48]
-    hipLaunchKernelGGL(k_up_bwd, g1((long)v16 * 32), dim3(256), 0, s, g0, 48, B, 16, 32, g1b);  // dA5 [v16][32]
-    // keep dQ1's skip half for dA1: g0 stays alive until c2's backward
-    hipLaunchKernelGGL(k_relu_bwd, g1((long)v16 * 32), dim3(256), 0, s, g1b, n->A5, (long)v16 * 32, dz);
+    // dA5 from the upsampled half of dQ1; g0 keeps dQ1's skip half for dA1
+    // until c2's backward
+    hipLaunchKernelGGL(k_up_bwd_relu, g1((long)v16 * 8), dim3(256), 0, s, g0, 48, B, 16, 32, n->A5, dz);
     // c5
     PG_TRY(layer_grads(n, 4, n->Q2, dz, v16, 16, s));
     PG_TRY(conv(32, 96, false, true, dz, L[4].wtb, nullptr, g1b, v16, 16, s));                 // dQ2 [v16][96]
-    hipLaunchKernelGGL(k_up_bwd, g1((long)v8 * 64), dim3(256), 0, s, g1b, 96, B, 8, 64, g2);   // dA4 [v8][64]
-    hipLaunchKernelGGL(k_relu_bwd, g1((long)v8 * 64), dim3(256), 0, s, g2, n->A4, (long)v8 * 64, dz);
+    hipLaunchKernelGGL(k_up_bwd_relu, g1((long)v8 * 16), dim3(256), 0, s, g1b, 96, B, 8, 64, n->A4, dz);   // dA4
     // c4
     PG_TRY(layer_grads(n, 3, n->A3, dz, v8, 8, s));
     PG_TRY(conv(64, 64, false, true, dz, L[3].wtb, nullptr, g2, v8, 8, s));                    // dA3
-    hipLaunchKernelGGL(k_relu_bwd, g1((long)v8 * 64), dim3(256), 0, s, g2, n->A3, (long)v8 * 64, dz);
+    hipLaunchKernelGGL(k_relu_bwd, g1((long)v8 * 16), dim3(256), 0, s, g2, n->A3, (long)v8 * 64, dz);
     // c3
     PG_TRY(layer_grads(n, 2, n->P2, dz, v8, 8, s));
     float* dP2 = g2;   // [v8][32]
     PG_TRY(conv(64, 32, false, true, dz, L[2].wtb, nullptr, dP2, v8, 8, s));
-    // dA2 = skip half of dQ2 (channels 64..95) + pool backward of dP2; written after g1b's
-    // dQ2 is consumed, into a separate region of g2 (dP2 occupies its first v8*32 floats)
-    float* dA2 = g2 + (size_t)v8 * 32;
-    hipLaunchKernelGGL(k_skip_pool_bwd, g1((long)v16 * 32), dim3(256), 0, s, g1b, 96, 64, dP2, B, 16, 32, dA2);
-    hipLaunchKernelGGL(k_relu_bwd, g1((long)v16 * 32), dim3(256), 0, s, dA2, n->A2, (long)v16 * 32, dz);
+    // dA2 = skip half of dQ2 (channels 64..95) + pool backward of dP2
+    hipLaunchKernelGGL(k_skip_pool_bwd_relu, g1((long)v16 * 8), dim3(256), 0, s, g1b, 96, 64, dP2, B, 16, 32, n->A2,
+                       dz);
     // c2
     PG_TRY(layer_grads(n, 1, n->P1, dz, v16, 16, s));
     float* dP1 = g1b;  // [v16][16]
     PG_TRY(conv(32, 16, false, true, dz, L[1].wtb, nullptr, dP1, v16, 16, s));
-    float* dA1 = g2;   // [v32][16]
-    hipLaunchKernelGGL(k_skip_pool_bwd, g1((long)v32 * 16), dim3(256), 0, s, g0, 48, 32, dP1, B, 32, 16, dA1);
-    hipLaunchKernelGGL(k_relu_bwd, g1((long)v32 * 16), dim3(256), 0, s, dA1, n->A1, (long)v32 * 16, dz);
+    // dA1 = skip half of dQ1 (channels 32..47) + pool backward of dP1
+    hipLaunchKernelGGL(k_skip_pool_bwd_relu, g1((long)v32 * 4), dim3(256), 0, s, g0, 48, 32, dP1, B, 32, 16, n->A1,
+                       dz);
     // c1
     PG_TRY(layer_grads(n, 0, n->X0, dz, v32, 32, s));
     PG_HIP(hipGetLastError());
