@@ -302,18 +302,23 @@ k_conv_bwdw(const bf16* __restrict__ inQ, const bf16* __restrict__ dzQ, float* _
     }
 }
 
-// out[i] = sum over the nsplit partials of entry i, in split order within
-// each of 4 interleaved groups and then in group order (deterministic)
-__global__ void __launch_bounds__(256)
+// out[i] = sum over the nsplit partials of entry i: 16 interleaved groups of
+// splits summed in split order, then the groups in a fixed tree order
+// (deterministic). A block covers 64 entries with 1024 threads.
+__global__ void __launch_bounds__(1024)
 k_sum_splits(const float* __restrict__ partial, int nsplit, int n, float* __restrict__ out) {
-    __shared__ float red[4][64];
-    const int i = blockIdx.x * 64 + (threadIdx.x & 63), q = threadIdx.x >> 6;
+    __shared__ float red[16][64];
+    const int e = threadIdx.x & 63, q = threadIdx.x >> 6, i = blockIdx.x * 64 + e;
     float sum = 0.f;
     if (i < n)
-        for (int k = q; k < nsplit; k += 4) sum += partial[(long)k * n + i];
-    red[q][threadIdx.x & 63] = sum;
+        for (int k = q; k < nsplit; k += 16) sum += partial[(long)k * n + i];
+    red[q][e] = sum;
     __syncthreads();
-    if (q == 0 && i < n) out[i] = red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] + red[3][threadIdx.x];
+    for (int h = 8; h > 0; h >>= 1) {
+        if (q < h) red[q][e] += red[q + h][e];
+        __syncthreads();
+    }
+    if (q == 0 && i < n) out[i] = red[0][e];
 }
 
 // Elementwise kernels move 4 channels (8 bytes of bf16, 16 of f32) per
@@ -743,7 +748,7 @@ int layer_grads(petgem_net* n, int li, const bf16* in, const bf16* dz, int nvox,
     const int ns = bwdw_splits(l.cin, nvox);
     PG_TRY(conv_bwdw(l.cin, l.cout, n->tin, n->tdz, n->wpart, nvox, D, ns, s));
     const int nw = (27 * l.cin + 1) * l.cout;
-    hipLaunchKernelGGL(k_sum_splits, dim3(ceil_div(nw, 64)), dim3(256), 0, s, n->wpart, ns, nw, n->Gr + l.w_off);
+    hipLaunchKernelGGL(k_sum_splits, dim3(ceil_div(nw, 64)), dim3(1024), 0, s, n->wpart, ns, nw, n->Gr + l.w_off);
     PG_HIP(hipGetLastError());
     return PETGEM_OK;
 }
