@@ -380,12 +380,13 @@ def bench_cfg5(args, petgem, synth, torch):
     seq_E = r_plain_E
     forms["batched_mixed_cocg"] = {
         "zero_guess": {"solves_per_s": len(test) / rb.t_zero, "iters_mean": float(np.mean(rb.iters_zero)),
-                       "iters_max": int(np.max(rb.iters_zero))},
+                       "iters_max": int(np.max(rb.iters_zero)), "pass_ms": [round(t * 1e3, 2) for t in rb.t_zero_runs]},
         "learned_guess": {"solves_per_s": len(test) / rb.t_learned,
                           "iters_mean": float(np.mean(rb.iters_learned)),
                           "iters_max": int(np.max(rb.iters_learned)),
                           "fallbacks": int(np.sum(rb.fallback)),
-                          "x0_rel_residual_median": float(np.median(rb.x0_residual))},
+                          "x0_rel_residual_median": float(np.median(rb.x0_residual)),
+                          "pass_ms": [round(t * 1e3, 2) for t in rb.t_learned_runs]},
         "max_rx_diff_learned_vs_zero": rb.max_rx_diff,
         "max_rx_diff_vs_sequential_plain": max(rx_error(a, b) for a, b in zip(rb.E_zero, seq_E)),
     }

@@ -279,6 +279,14 @@ int petgem_vox_targets(const petgem_solution* sol, const double* scale, void* t_
  * |b|. */
 int petgem_learned_x0(petgem_system* sys, petgem_net* net, const petgem_source* src, int32_t batch,
                       double g, void* x0_dev, double* bnorm_out, void* stream);
+/* petgem_learned_x0 for n_sys systems with one source each, run as one
+ * network batch (n_sys <= the network's batch_max): sample k is system k's
+ * conductivities on its own voxel grid with src[k]. x0_dev[k] is caller-owned
+ * device complex128 [n_dof of system k]; bnorm_out (host [n_sys], may be
+ * NULL) receives |b| of every system. Each guess equals what
+ * petgem_learned_x0 gives for that system and source alone. */
+int petgem_learned_x0_many(petgem_system* const* systems, petgem_net* net, const petgem_source* src,
+                           int32_t n_sys, double g, void* const* x0_dev, double* bnorm_out, void* stream);
 void petgem_net_free(petgem_net* net);
 
 void petgem_free_system(petgem_system* sys);

@@ -1062,6 +1062,7 @@ int petgem_learned_x0(petgem_system* sys, petgem_net* n, const petgem_source* sr
     // |b| of every source (the prediction is scale-free)
     if (n->bcap < (size_t)sys->n_dof) {
         dfree(n->bbuf);
+        n->bcap = 0;
         PG_TRY(dalloc(&n->bbuf, (size_t)sys->n_dof));
         n->bcap = (size_t)sys->n_dof;
     }
@@ -1086,6 +1087,61 @@ int petgem_learned_x0(petgem_system* sys, petgem_net* n, const petgem_source* sr
     hipLaunchKernelGGL(k_grid_to_edges, g1((long)B * sys->n_dof), dim3(256), 0, s, n->Y, B, sys->n_dof, sys->dof_mid,
                        sys->dof_tan, n->scal, sys->vox_lo[0], sys->vox_lo[1], sys->vox_lo[2], sys->vox_h,
                        static_cast<double2*>(x0_dev));
+    PG_HIP(hipGetLastError());
+    return PETGEM_OK;
+}
+
+int petgem_learned_x0_many(petgem_system* const* systems, petgem_net* n, const petgem_source* src, int32_t n_sys,
+                           double g, void* const* x0_dev, double* bnorm_out, void* stream) {
+    if (!systems || !n || !src || n_sys <= 0 || n_sys > n->batch_max || !x0_dev || !(g > 0.0)) {
+        set_error("learned x0 (many systems): bad arguments");
+        return PETGEM_INVALID_ARG;
+    }
+    for (int k = 0; k < n_sys; ++k)
+        if (!systems[k] || !x0_dev[k]) {
+            set_error("learned x0 (many systems): system or guess " + std::to_string(k) + " is NULL");
+            return PETGEM_INVALID_ARG;
+        }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    size_t nmax = 0;
+    for (int k = 0; k < n_sys; ++k) {
+        PG_TRY(ensure_vox(systems[k]));
+        nmax = std::max(nmax, (size_t)systems[k]->n_dof);
+    }
+    if (n->bcap < nmax) {
+        dfree(n->bbuf);
+        n->bcap = 0;
+        PG_TRY(dalloc(&n->bbuf, nmax));
+        n->bcap = nmax;
+    }
+    // |b| of every system's source
+    for (int k = 0; k < n_sys; ++k) {
+        PG_TRY(launch_rhs(systems[k], src[k], n->bbuf, 1, s));
+        hipLaunchKernelGGL(k_vnorm, dim3(1), dim3(256), 0, s, n->bbuf, systems[k]->n_dof, n->bn + k);
+    }
+    std::vector<double> h(n_sys);
+    PG_HIP(hipMemcpyAsync(h.data(), n->bn, sizeof(double) * n_sys, hipMemcpyDeviceToHost, s));
+    PG_HIP(hipStreamSynchronize(s));
+    for (int k = 0; k < n_sys; ++k) {
+        if (bnorm_out) bnorm_out[k] = h[k];
+        h[k] *= g;
+    }
+    PG_HIP(hipMemcpyAsync(n->scal, h.data(), sizeof(double) * n_sys, hipMemcpyHostToDevice, s));
+    PG_TRY(upload_vsrc(n, src, n_sys, s));
+    // sample k of the batch is system k on its own voxel grid
+    for (int k = 0; k < n_sys; ++k) {
+        const petgem_system* sys = systems[k];
+        hipLaunchKernelGGL(k_voxelize, g1(kVox), dim3(256), 0, s, sys->sigma, 0L, sys->vox_tet, n->vsrc + k, 1,
+                           sys->vox_lo[0], sys->vox_lo[1], sys->vox_lo[2], sys->vox_h, sys->vox_L,
+                           n->X0 + (size_t)k * kVox * kIn);
+    }
+    PG_TRY(forward(n, n_sys, s));
+    for (int k = 0; k < n_sys; ++k) {
+        const petgem_system* sys = systems[k];
+        hipLaunchKernelGGL(k_grid_to_edges, g1(sys->n_dof), dim3(256), 0, s, n->Y + (size_t)k * kVox * kOut, 1,
+                           sys->n_dof, sys->dof_mid, sys->dof_tan, n->scal + k, sys->vox_lo[0], sys->vox_lo[1],
+                           sys->vox_lo[2], sys->vox_h, static_cast<double2*>(x0_dev[k]));
+    }
     PG_HIP(hipGetLastError());
     return PETGEM_OK;
 }

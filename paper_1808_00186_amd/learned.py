@@ -111,6 +111,8 @@ class EvalResult:
     x0_residual: List[float] = field(default_factory=list)
     t_zero: float = 0.0
     t_learned: float = 0.0
+    t_zero_runs: List[float] = field(default_factory=list)
+    t_learned_runs: List[float] = field(default_factory=list)
     max_rx_diff: float = 0.0
     E_zero: list = field(default_factory=list)
 
@@ -161,12 +163,14 @@ class BatchEvalResult:
     E_zero: list = field(default_factory=list)
 
 
-def evaluate_batched(net, seeds, mesh, g: float, opts) -> BatchEvalResult:
+def evaluate_batched(net, seeds, mesh, g: float, opts, reps: int = 5) -> BatchEvalResult:
     """The held-out seeds as one uneven batch (petgem_solve_many): every seed's
     model is its own system (built once, outside the timings); a timed pass
     re-assembles every system from its conductivities, solves all sources in
     shared launches and interpolates the receivers, first with zero guesses,
-    then with the learned ones (whose computation is timed with it)."""
+    then with the learned ones (computed one network batch per chunk of
+    batch_max systems, and timed with the solve). The two forms alternate for
+    `reps` timed passes each, and the median time of each is reported."""
     import torch
     models = [synth.config5_sample(s, mesh) for s in seeds]
     systems = [petgem.System.from_model(m) for m in models]
@@ -181,25 +185,38 @@ def evaluate_batched(net, seeds, mesh, g: float, opts) -> BatchEvalResult:
     def receivers(sols):
         return [sols[k].receivers(models[k].receivers) for k in range(len(models))]
 
-    # one untimed pass of each form (autotuning, graph capture)
-    reassemble()
-    petgem.solve_many(systems, srcs, opts)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    reassemble()
-    sols0, st0, _ = petgem.solve_many(systems, srcs, opts)
-    E0 = receivers(sols0)
-    torch.cuda.synchronize()
-    t_zero = time.perf_counter() - t0
-    for _ in range(2):   # the first pass warms the learned path up, the second is timed
-        t1 = time.perf_counter()
+    def zero_pass():
         reassemble()
-        x0 = [petgem.learned_x0(S, net, [src], g)[0][0] for S, src in zip(systems, srcs)]
-        sols1, st1, _ = petgem.solve_many(systems, srcs, opts, x0=x0)
-        E1 = receivers(sols1)
+        sols, st, _ = petgem.solve_many(systems, srcs, opts)
+        E = receivers(sols)
         torch.cuda.synchronize()
-    t2 = time.perf_counter()
-    r.t_zero, r.t_learned = t_zero, t2 - t1
+        return st, E
+
+    def learned_pass():
+        reassemble()
+        x0 = []
+        for c0 in range(0, len(systems), net.batch_max):   # one network batch per chunk of systems
+            x0 += petgem.learned_x0_many(systems[c0:c0 + net.batch_max], net, srcs[c0:c0 + net.batch_max], g)[0]
+        sols, st, _ = petgem.solve_many(systems, srcs, opts, x0=x0)
+        E = receivers(sols)
+        torch.cuda.synchronize()
+        return st, E
+
+    # one untimed pass of each form (autotuning, graph capture), then
+    # alternating timed passes; the median of each form is reported
+    zero_pass()
+    learned_pass()
+    tz, tl = [], []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        st0, E0 = zero_pass()
+        t1 = time.perf_counter()
+        st1, E1 = learned_pass()
+        t2 = time.perf_counter()
+        tz.append(t1 - t0)
+        tl.append(t2 - t1)
+    r.t_zero, r.t_learned = float(np.median(tz)), float(np.median(tl))
+    r.t_zero_runs, r.t_learned_runs = tz, tl
     r.iters_zero = [s["iters"] for s in st0]
     r.iters_learned = [s["iters"] for s in st1]
     r.fallback = [s["used_fallback"] for s in st1]

@@ -110,6 +110,8 @@ _SIGS = {
     "petgem_vox_targets": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.c_void_p, C.c_void_p]),
     "petgem_learned_x0": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(Source), C.c_int32, C.c_double,
                                     C.c_void_p, C.POINTER(C.c_double), C.c_void_p]),
+    "petgem_learned_x0_many": (C.c_int, [C.POINTER(C.c_void_p), C.c_void_p, C.POINTER(Source), C.c_int32,
+                                         C.c_double, C.POINTER(C.c_void_p), C.POINTER(C.c_double), C.c_void_p]),
     "petgem_net_free": (None, [C.c_void_p]),
 }
 
@@ -381,6 +383,23 @@ def learned_x0(system: "System", net: Net, dipoles, g: float, stream=None):
     bn = np.empty(len(dipoles), np.float64)
     _check(lib().petgem_learned_x0(system.handle, net.handle, src, len(dipoles), g, _ptr(x0),
                                    bn.ctypes.data_as(C.POINTER(C.c_double)), _stream(stream)))
+    return x0, bn
+
+
+def learned_x0_many(systems, net: Net, dipoles, g: float, stream=None):
+    """One guess per system (dipoles[k] on systems[k]) from one network batch:
+    ([x0 complex128 CUDA tensor [n_dof_k]], |b| per system)."""
+    import torch
+    n = len(systems)
+    if len(dipoles) != n:
+        raise ValueError("one dipole per system")
+    src = make_sources(dipoles)
+    x0 = [torch.empty(S.n_dof, dtype=torch.complex128, device="cuda") for S in systems]
+    hs = (C.c_void_p * n)(*[S.handle.value for S in systems])
+    ps = (C.c_void_p * n)(*[_ptr(t).value for t in x0])
+    bn = np.empty(n, np.float64)
+    _check(lib().petgem_learned_x0_many(hs, net.handle, src, n, g, ps,
+                                        bn.ctypes.data_as(C.POINTER(C.c_double)), _stream(stream)))
     return x0, bn
 
 

@@ -70,6 +70,43 @@ def test_gradients_match_reference(env):
         off += n + cout
 
 
+def test_gradients_are_bitwise_reproducible(env):
+    """The weight pass sums voxel splits in a fixed order: two evaluations of
+    the same batch give identical gradients (batch 3 also exercises a batch
+    that is not a power of two)."""
+    torch, petgem, _ = env
+    net = petgem.Net(batch_max=3, seed=13)
+    x, _ = _bf16_input(torch, 3, 4)
+    t = torch.tensor(np.random.default_rng(5).normal(size=(3, network.SIDE ** 3, network.USED)) * 0.3,
+                     dtype=torch.float32, device="cuda")
+    l1, g1 = net.loss_grad(x, t)
+    l2, g2 = net.loss_grad(x, t)
+    assert l1 == l2
+    assert np.array_equal(g1, g2)
+
+
+def test_learned_x0_many_matches_one_system_at_a_time(env):
+    """Guesses of systems on different meshes from one network batch equal the
+    per-system guesses bitwise (the forward pass has no cross-sample terms)."""
+    torch, petgem, _ = env
+    meshes = [synth.kuhn_mesh(8, -1000.0, 1000.0, 1), synth.kuhn_mesh(6, -1000.0, 1000.0, 2),
+              synth.kuhn_mesh(8, -1000.0, 1000.0, 1)]
+    models = [synth.config5_sample(30000 + k, m) for k, m in enumerate(meshes)]
+    systems = [petgem.System.from_model(m) for m in models]
+    srcs = [m.sources[0] for m in models]
+    net = petgem.Net(batch_max=4, seed=17)
+    g = 0.5
+    many, bn_many = petgem.learned_x0_many(systems, net, srcs, g)
+    for k, (S, src) in enumerate(zip(systems, srcs)):
+        one, bn_one = petgem.learned_x0(S, net, [src], g)
+        assert many[k].shape == (S.n_dof,)
+        assert torch.isfinite(torch.view_as_real(many[k])).all()
+        assert torch.equal(many[k], one[0])
+        assert bn_many[k] == bn_one[0]
+    with pytest.raises(petgem.PetgemError):
+        petgem.learned_x0_many(systems * 2, net, srcs * 2, g)   # more systems than batch_max
+
+
 def test_learned_guess_trains_and_solves(env):
     torch, petgem, learned = env
     mesh = synth.kuhn_mesh(8, -1000.0, 1000.0, 1)
