@@ -92,27 +92,50 @@ k_conv(const bf16* __restrict__ in, const bf16* __restrict__ wt, const float* __
     for (int i = 0; i < MT; ++i)
 #pragma unroll
         for (int t = 0; t < NTB; ++t) acc[i][t] = f32x4{0.f, 0.f, 0.f, 0.f};
-    for (int pz = 0; pz < 3; ++pz) {
+    // Staging of one z plane: the input rows y0-1 .. y0+TY of plane z+pz-1
+    // (4 channels per uint2) and the weights of taps 9 pz .. 9 pz + 8 for this
+    // block's output channels. The next plane's loads are issued into
+    // registers before the current plane's MFMAs, so their latency overlaps
+    // the compute; they go to LDS after the barrier that ends it.
+    constexpr int Q = CIN / 4, HQ = (TY + 2) * (D + 2) * Q, NH = (HQ + 255) / 256;
+    constexpr int WQ = 9 * CIN / 4, WQT = 16 * NTB * WQ, NW = (WQT + 255) / 256;
+    uint2 hreg[NH], wreg[NW];
+    auto fetch = [&](int pz) {
         const int zz = z + pz - 1;
-        // input rows y0-1 .. y0+TY of plane zz, 4 channels per store
-        constexpr int Q = CIN / 4;
-        for (int e = threadIdx.x; e < (TY + 2) * (D + 2) * Q; e += 256) {
+#pragma unroll
+        for (int j = 0; j < NH; ++j) {
+            const int e = threadIdx.x + 256 * j;
             const int q = e % Q, vx = e / Q;
             const int rx = vx % (D + 2), ry = vx / (D + 2);
             const int yy = y0 - 1 + ry, xx = rx - 1;
-            uint2 val = make_uint2(0u, 0u);
-            if (zz >= 0 && zz < D && yy >= 0 && yy < D && xx >= 0 && xx < D)
-                val = *reinterpret_cast<const uint2*>(in + ((long)b * Vs + ((long)zz * D + yy) * D + xx) * CIN + 4 * q);
-            *reinterpret_cast<uint2*>(halo + vx * HC + 4 * q) = val;
+            hreg[j] = make_uint2(0u, 0u);
+            if (e < HQ && zz >= 0 && zz < D && yy >= 0 && yy < D && xx >= 0 && xx < D)
+                hreg[j] = *reinterpret_cast<const uint2*>(in + ((long)b * Vs + ((long)zz * D + yy) * D + xx) * CIN + 4 * q);
         }
-        // weights of taps 9 pz .. 9 pz + 8 for this block's output channels
-        constexpr int WQ = 9 * CIN / 4;
-        for (int e = threadIdx.x; e < 16 * NTB * WQ; e += 256) {
-            const int q = e % WQ, c = e / WQ;
-            *reinterpret_cast<uint2*>(wl + c * WK + 4 * q) =
-                *reinterpret_cast<const uint2*>(wt + (long)(co0 + c) * K + pz * 9 * CIN + 4 * q);
+#pragma unroll
+        for (int j = 0; j < NW; ++j) {
+            const int e = threadIdx.x + 256 * j;
+            if (e < WQT)
+                wreg[j] = *reinterpret_cast<const uint2*>(wt + (long)(co0 + e / WQ) * K + pz * 9 * CIN + 4 * (e % WQ));
         }
-        __syncthreads();
+    };
+    auto stage = [&]() {
+#pragma unroll
+        for (int j = 0; j < NH; ++j) {
+            const int e = threadIdx.x + 256 * j;
+            if (e < HQ) *reinterpret_cast<uint2*>(halo + (e / Q) * HC + 4 * (e % Q)) = hreg[j];
+        }
+#pragma unroll
+        for (int j = 0; j < NW; ++j) {
+            const int e = threadIdx.x + 256 * j;
+            if (e < WQT) *reinterpret_cast<uint2*>(wl + (e / WQ) * WK + 4 * (e % WQ)) = wreg[j];
+        }
+    };
+    fetch(0);
+    stage();
+    __syncthreads();
+    for (int pz = 0; pz < 3; ++pz) {
+        if (pz < 2) fetch(pz + 1);
 #pragma unroll
         for (int t9 = 0; t9 < 9; ++t9) {
             const int sh = ((t9 / 3) * (D + 2) + t9 % 3) * HC;   // (dy, dx) shift in the halo
@@ -132,6 +155,10 @@ k_conv(const bf16* __restrict__ in, const bf16* __restrict__ wt, const float* __
             }
         }
         __syncthreads();
+        if (pz < 2) {
+            stage();
+            __syncthreads();
+        }
     }
     // lane holds D[row voxel 4 kq + j][col co m] of every (M tile, output tile)
 #pragma unroll
