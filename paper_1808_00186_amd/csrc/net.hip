@@ -184,14 +184,13 @@ k_conv(const bf16* __restrict__ in, const bf16* __restrict__ wt, const float* __
 // are adjacent. One thread moves 4 voxels x 4 channels.
 template <int C>
 __global__ void __launch_bounds__(256)
-k_to_quads(const bf16* __restrict__ in, long nvox, bf16* __restrict__ out) {
-    const long e = (long)blockIdx.x * 256 + threadIdx.x;
+k_to_quads(const bf16* __restrict__ in, int nvox, bf16* __restrict__ out) {
+    const int e = blockIdx.x * 256 + threadIdx.x;
     if (e >= nvox / 4 * (C / 4)) return;
-    const long q = e / (C / 4);
-    const int c = 4 * (int)(e % (C / 4));
+    const int q = e / (C / 4), c = 4 * (e % (C / 4));
     uint2 w[4];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) w[j] = *reinterpret_cast<const uint2*>(in + (4 * q + j) * C + c);
+    for (int j = 0; j < 4; ++j) w[j] = *reinterpret_cast<const uint2*>(in + (size_t)(4 * q + j) * C + c);
     // channel c + i of voxel 4q + j is half (i & 1) of word (i >> 1) of w[j]
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -201,7 +200,7 @@ k_to_quads(const bf16* __restrict__ in, long nvox, bf16* __restrict__ out) {
             const uint32_t word = (i >> 1) ? w[j].y : w[j].x;
             h[j] = (i & 1) ? (word >> 16) : (word & 0xffffu);
         }
-        *reinterpret_cast<uint2*>(out + (q * C + c + i) * 4) = make_uint2(h[0] | (h[1] << 16), h[2] | (h[3] << 16));
+        *reinterpret_cast<uint2*>(out + ((size_t)q * C + c + i) * 4) = make_uint2(h[0] | (h[1] << 16), h[2] | (h[3] << 16));
     }
 }
 
@@ -288,15 +287,17 @@ k_conv_bwdw(const bf16* __restrict__ inQ, const bf16* __restrict__ dzQ, float* _
                 accb[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ones, st.w[t], accb[t], 0, 0, 0);
         }
     };
-    // the loads of the next K step are issued before the MFMAs of this one
-    Step cur;
+    // the loads of the next two K steps are in flight during the MFMAs of this one
+    Step s0, s1;
     int k = k0 + wave;
-    if (k < k1) load(k, cur);
+    if (k < k1) load(k, s0);
+    if (k + 4 < k1) load(k + 4, s1);
     for (; k < k1; k += 4) {
-        Step nxt = cur;
-        if (k + 4 < k1) load(k + 4, nxt);
-        compute(cur);
-        cur = nxt;
+        Step s2 = s1;
+        if (k + 8 < k1) load(k + 8, s2);
+        compute(s0);
+        s0 = s1;
+        s1 = s2;
     }
     // wave-ordered sum of the 4 waves, one output tile column at a time;
     // lane holds D[row ci = 4 kq + j][col co = m]
@@ -322,6 +323,117 @@ k_conv_bwdw(const bf16* __restrict__ inQ, const bf16* __restrict__ dzQ, float* _
                 const int tap = pz * 9 + tile;   // (z, y, x) offsets in row-major order
                 base[(long)(tap * CIN + ci) * COUT + co] = val;
             } else if (bias_unit && ci == 0) {
+                base[(long)KW * COUT + co] = val;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// The same weight and bias partials at side 32, with input rows reused
+// along y. A column is (sample, z, 16-voxel x segment); a wave walks a
+// column's D output rows and keeps the input rows y-1, y, y+1 of its z plane
+// in registers, so each step loads one new input row (and the next row of
+// dz) instead of three. Same units, splits, LDS reduction and partial layout
+// as k_conv_bwdw; the bias unit adds the ones-operand MFMA.
+template <int CIN, int COUT, int D>
+__global__ void __launch_bounds__(256)
+k_conv_bwdw_col(const bf16* __restrict__ inQ, const bf16* __restrict__ dzQ, float* __restrict__ partial,
+                int ncol, int nsplit, int chunk) {
+    constexpr int NT = COUT / 16, KW = 27 * CIN, Vs = D * D * D, XS = D / 16;
+    static_assert(D % 16 == 0, "a column step is 16 voxels of one x row");
+    const int wave = threadIdx.x >> 6, l = threadIdx.x & 63, m = l & 15, kq = l >> 4;
+    const int s = blockIdx.x % nsplit, unit = blockIdx.x / nsplit;
+    const int g = unit / 3, pz = unit % 3, ci = g * 16 + m;
+    const bool bias_unit = unit == 1;   // g = 0, z offset 0
+    const int c0 = s * chunk, c1 = min(ncol, c0 + chunk);   // chunk: columns per split, a multiple of 4
+    f32x4 acc[3][3][NT], accb[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        accb[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) acc[a][c][t] = f32x4{0.f, 0.f, 0.f, 0.f};
+    }
+    const bf16x4 ones = {0x3f80, 0x3f80, 0x3f80, 0x3f80};
+    struct Row { uint32_t dp, d0, d1, dn; };   // x0-2 .. x0+5 of this lane's channel
+    struct Frag { bf16x4 w[NT]; };
+    for (int col = c0 + wave; col < c1; col += 4) {
+        const int xs = col % XS, bz = col / XS, z = bz % D, b = bz / D;
+        const int x0 = xs * 16 + 4 * kq, zz = z + pz - 1;
+        const bool zok = zz >= 0 && zz < D;
+        auto row = [&](int yy) {
+            Row r{0u, 0u, 0u, 0u};
+            if (zok && yy >= 0 && yy < D) {
+                const long q = ((long)b * Vs + ((long)zz * D + yy) * D + x0) / 4;   // quad of x0 .. x0+3
+                const uint2 c = *reinterpret_cast<const uint2*>(inQ + (q * CIN + ci) * 4);
+                r.d0 = c.x;
+                r.d1 = c.y;
+                if (x0 > 0) r.dp = *reinterpret_cast<const uint32_t*>(inQ + ((q - 1) * CIN + ci) * 4 + 2);
+                if (x0 + 4 < D) r.dn = *reinterpret_cast<const uint32_t*>(inQ + ((q + 1) * CIN + ci) * 4);
+            }
+            return r;
+        };
+        auto frag = [&](int y) {
+            Frag f;
+            const long q = ((long)b * Vs + ((long)z * D + y) * D + x0) / 4;
+#pragma unroll
+            for (int t = 0; t < NT; ++t) f.w[t] = *reinterpret_cast<const bf16x4*>(dzQ + (q * COUT + t * 16 + m) * 4);
+            return f;
+        };
+        Row ra{0u, 0u, 0u, 0u}, rb = row(0), rc = row(1);
+        Frag fc = frag(0);
+        for (int y = 0; y < D; ++y) {
+            const Row rn = row(y + 2);                        // zero past the last row
+            const Frag fn = y + 1 < D ? frag(y + 1) : fc;
+            const Row* rows[3] = {&ra, &rb, &rc};             // input rows y-1, y, y+1
+#pragma unroll
+            for (int dy = 0; dy < 3; ++dy) {
+                const uint32_t dp = rows[dy]->dp, d0 = rows[dy]->d0, d1 = rows[dy]->d1, dn = rows[dy]->dn;
+                const uint32_t lo[3] = {(dp >> 16) | (d0 << 16), d0, (d0 >> 16) | (d1 << 16)};
+                const uint32_t hi[3] = {(d0 >> 16) | (d1 << 16), d1, (d1 >> 16) | (dn << 16)};
+#pragma unroll
+                for (int dx = 0; dx < 3; ++dx) {
+                    typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+                    const bf16x4 a = __builtin_bit_cast(bf16x4, (u32x2{lo[dx], hi[dx]}));
+#pragma unroll
+                    for (int t = 0; t < NT; ++t)
+                        acc[dy][dx][t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, fc.w[t], acc[dy][dx][t], 0, 0, 0);
+                }
+            }
+            if (bias_unit) {
+#pragma unroll
+                for (int t = 0; t < NT; ++t)
+                    accb[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ones, fc.w[t], accb[t], 0, 0, 0);
+            }
+            ra = rb;
+            rb = rc;
+            rc = rn;
+            fc = fn;
+        }
+    }
+    __shared__ float red[4][10][256];
+    float* base = partial + (long)s * (KW + 1) * COUT;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) red[wave][3 * a + c][4 * l + j] = acc[a][c][t][j];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) red[wave][9][4 * l + j] = accb[t][j];
+        __syncthreads();
+        for (int e = threadIdx.x; e < 10 * 256; e += 256) {
+            const int tile = e / 256, ln = (e / 4) % 64, j = e % 4;
+            const float val = red[0][tile][e % 256] + red[1][tile][e % 256] + red[2][tile][e % 256] +
+                              red[3][tile][e % 256];
+            const int co = t * 16 + (ln & 15), cr = g * 16 + 4 * (ln >> 4) + j;
+            if (tile < 9) {
+                base[(long)((pz * 9 + tile) * CIN + cr) * COUT + co] = val;
+            } else if (bias_unit && cr == 0) {
                 base[(long)KW * COUT + co] = val;
             }
         }
@@ -360,29 +472,28 @@ __device__ __forceinline__ void st_bf4(bf16* p, float4 v) {
                                               (uint32_t)f2bf(v.z) | ((uint32_t)f2bf(v.w) << 16));
 }
 // parent (coarse) voxel of fine voxel vf on a grid of side D
-__device__ __forceinline__ long parent_of(long vf, int D) {
-    const int Dc = D / 2;
-    const long b = vf / ((long)D * D * D);
-    const int r = (int)(vf % ((long)D * D * D));
+// (voxel and element counts stay below 2^31 for batch_max <= 256, so the
+// index arithmetic of these kernels is 32-bit)
+__device__ __forceinline__ int parent_of(int vf, int D) {
+    const int Dc = D / 2, V = D * D * D;
+    const int b = vf / V, r = vf % V;
     const int z = r / (D * D), y = (r / D) % D, x = r % D;
-    return b * Dc * Dc * Dc + ((long)(z / 2) * Dc + y / 2) * Dc + x / 2;
+    return b * Dc * Dc * Dc + ((z / 2) * Dc + y / 2) * Dc + x / 2;
 }
 // q-th of the 8 children of coarse voxel vc (side Dc) on the fine grid
-__device__ __forceinline__ long child_of(long vc, int Dc, int q) {
-    const int D = 2 * Dc;
-    const long b = vc / ((long)Dc * Dc * Dc);
-    const int r = (int)(vc % ((long)Dc * Dc * Dc));
+__device__ __forceinline__ int child_of(int vc, int Dc, int q) {
+    const int D = 2 * Dc, Vc = Dc * Dc * Dc;
+    const int b = vc / Vc, r = vc % Vc;
     const int z = r / (Dc * Dc), y = (r / Dc) % Dc, x = r % Dc;
-    return b * D * D * D + ((long)(2 * z + (q >> 2)) * D + 2 * y + ((q >> 1) & 1)) * D + 2 * x + (q & 1);
+    return b * D * D * D + ((2 * z + (q >> 2)) * D + 2 * y + ((q >> 1) & 1)) * D + 2 * x + (q & 1);
 }
 
 // 2x2x2 average pooling (fine side D), C channels
 __global__ void k_pool(const bf16* __restrict__ in, int B, int D, int C, bf16* __restrict__ out) {
-    const long e = (long)blockIdx.x * 256 + threadIdx.x;
+    const int e = blockIdx.x * 256 + threadIdx.x;
     const int Dc = D / 2, C4 = C / 4;
-    if (e >= (long)B * Dc * Dc * Dc * C4) return;
-    const int c = 4 * (int)(e % C4);
-    const long vc = e / C4;
+    if (e >= B * Dc * Dc * Dc * C4) return;
+    const int c = 4 * (e % C4), vc = e / C4;
     float4 s = make_float4(0.f, 0.f, 0.f, 0.f);
     for (int q = 0; q < 8; ++q) {
         const float4 v = ld_bf4(in + child_of(vc, Dc, q) * C + c);
@@ -395,11 +506,10 @@ __global__ void k_pool(const bf16* __restrict__ in, int B, int D, int C, bf16* _
 // skip tensor (C2 channels)] on the fine grid of side D
 __global__ void k_up_concat(const bf16* __restrict__ coarse, int C1, const bf16* __restrict__ skip, int C2, int B,
                             int D, bf16* __restrict__ out) {
-    const long e = (long)blockIdx.x * 256 + threadIdx.x;
+    const int e = blockIdx.x * 256 + threadIdx.x;
     const int W4 = (C1 + C2) / 4;
-    if (e >= (long)B * D * D * D * W4) return;
-    const int c = 4 * (int)(e % W4);
-    const long vf = e / W4;
+    if (e >= B * D * D * D * W4) return;
+    const int c = 4 * (e % W4), vf = e / W4;
     const uint2 w = c < C1 ? *reinterpret_cast<const uint2*>(coarse + parent_of(vf, D) * C1 + c)
                            : *reinterpret_cast<const uint2*>(skip + vf * C2 + (c - C1));
     *reinterpret_cast<uint2*>(out + vf * (C1 + C2) + c) = w;
@@ -409,11 +519,10 @@ __global__ void k_up_concat(const bf16* __restrict__ coarse, int C1, const bf16*
 // dz[vc][c] = (y[vc][c] > 0) * sum over the 8 children of dq[child][c], c < C
 __global__ void k_up_bwd_relu(const float* __restrict__ dq, int ldq, int B, int Dc, int C,
                               const bf16* __restrict__ y, bf16* __restrict__ dz) {
-    const long e = (long)blockIdx.x * 256 + threadIdx.x;
+    const int e = blockIdx.x * 256 + threadIdx.x;
     const int C4 = C / 4;
-    if (e >= (long)B * Dc * Dc * Dc * C4) return;
-    const int c = 4 * (int)(e % C4);
-    const long vc = e / C4;
+    if (e >= B * Dc * Dc * Dc * C4) return;
+    const int c = 4 * (e % C4), vc = e / C4;
     float4 s = make_float4(0.f, 0.f, 0.f, 0.f);
     for (int q = 0; q < 8; ++q) {
         const float4 v = *reinterpret_cast<const float4*>(dq + child_of(vc, Dc, q) * ldq + c);
@@ -428,11 +537,10 @@ __global__ void k_up_bwd_relu(const float* __restrict__ dq, int ldq, int B, int 
 // dz = (y > 0) * (dq[:, off:off+C] + dp[parent] / 8)
 __global__ void k_skip_pool_bwd_relu(const float* __restrict__ dq, int ldq, int off, const float* __restrict__ dp,
                                      int B, int D, int C, const bf16* __restrict__ y, bf16* __restrict__ dz) {
-    const long e = (long)blockIdx.x * 256 + threadIdx.x;
+    const int e = blockIdx.x * 256 + threadIdx.x;
     const int C4 = C / 4;
-    if (e >= (long)B * D * D * D * C4) return;
-    const int c = 4 * (int)(e % C4);
-    const long vf = e / C4;
+    if (e >= B * D * D * D * C4) return;
+    const int c = 4 * (e % C4), vf = e / C4;
     const float4 u = *reinterpret_cast<const float4*>(dq + vf * ldq + off + c);
     const float4 p = *reinterpret_cast<const float4*>(dp + parent_of(vf, D) * C + c);
     const float4 a = ld_bf4(y + vf * C + c);
@@ -441,8 +549,8 @@ __global__ void k_skip_pool_bwd_relu(const float* __restrict__ dq, int ldq, int 
 }
 
 // dz = dy * (y > 0) as bf16 (ReLU backward; y is the stored activation)
-__global__ void k_relu_bwd(const float* __restrict__ dy, const bf16* __restrict__ y, long n, bf16* __restrict__ dz) {
-    const long e = (long)blockIdx.x * 256 + threadIdx.x;
+__global__ void k_relu_bwd(const float* __restrict__ dy, const bf16* __restrict__ y, int n, bf16* __restrict__ dz) {
+    const int e = blockIdx.x * 256 + threadIdx.x;
     if (e >= n / 4) return;
     const float4 d = *reinterpret_cast<const float4*>(dy + 4 * e);
     const float4 a = ld_bf4(y + 4 * e);
@@ -648,15 +756,26 @@ namespace {
 
 inline dim3 g1(long n) { return dim3((unsigned)((n + 255) / 256)); }
 
-// voxel splits of the weight pass: enough blocks to fill the chip, at least
-// 8 K steps per wave
-int bwdw_splits(int cin, long nvox) {
-    const int units = 3 * (cin / 16);
-    const long cap = std::max(1L, nvox / 16 / 32);
-    return (int)std::min<long>(cap, std::max(1, ceil_div(1024, units)));
+// voxel splits of the weight pass: enough blocks to fill the chip. At sides
+// 8 and 16 a split is a range of 16-voxel K steps, at least 8 per wave; at
+// side 32 it is a range of (sample, z, x segment) columns, a multiple of 4
+// so that the 4 waves of a block get the same number.
+int bwdw_target(int cin) { return std::max(1, ceil_div(1024, 3 * (cin / 16))); }
+long bwdw_col_chunk(int cin, long ncol) {
+    const long t = bwdw_target(cin);
+    return 4 * std::max(1L, (ncol + 4 * t - 1) / (4 * t));
 }
-size_t wpart_floats(int cin, int cout, long nvox) {
-    return (size_t)bwdw_splits(cin, nvox) * (27 * (size_t)cin + 1) * cout;
+int bwdw_splits(int cin, long nvox, int D) {
+    const int target = bwdw_target(cin);
+    if (D == 32) {
+        const long ncol = nvox / D / 16, chunk = bwdw_col_chunk(cin, ncol);
+        return (int)((ncol + chunk - 1) / chunk);
+    }
+    const long cap = std::max(1L, nvox / 16 / 32);
+    return (int)std::min<long>(cap, target);
+}
+size_t wpart_floats(int cin, int cout, long nvox, int D) {
+    return (size_t)bwdw_splits(cin, nvox, D) * (27 * (size_t)cin + 1) * cout;
 }
 
 template <int CIN, int COUT, int D, int TY, int NTB>
@@ -685,7 +804,7 @@ int conv(int cin, int cout, bool relu, bool outf32, const bf16* in, const bf16* 
     return PETGEM_INVALID_ARG;
 }
 
-int to_quads(int c, const bf16* in, long nvox, bf16* out, hipStream_t s) {
+int to_quads(int c, const bf16* in, int nvox, bf16* out, hipStream_t s) {
 #define PG_TQ(C)                                                                                    \
     if (c == C) {                                                                                   \
         hipLaunchKernelGGL((k_to_quads<C>), g1(nvox / 4 * (C / 4)), dim3(256), 0, s, in, nvox, out); \
@@ -700,13 +819,21 @@ int to_quads(int c, const bf16* in, long nvox, bf16* out, hipStream_t s) {
 int conv_bwdw(int cin, int cout, const bf16* inQ, const bf16* dzQ, float* part, int nvox, int D, int nsplit,
               hipStream_t s) {
     const int nb = 3 * (cin / 16) * nsplit;
+    const int ncol = nvox / D / 16, chunk = (int)bwdw_col_chunk(cin, ncol);
 #define PG_BW(A, B, SIDE)                                                                                     \
     if (cin == A && cout == B && D == SIDE) {                                                                 \
         hipLaunchKernelGGL((k_conv_bwdw<A, B, SIDE>), dim3(nb), dim3(256), 0, s, inQ, dzQ, part, nvox, nsplit); \
         return PETGEM_OK;                                                                                     \
     }
-    PG_BW(16, 16, 32) PG_BW(16, 32, 16) PG_BW(32, 64, 8) PG_BW(64, 64, 8) PG_BW(96, 32, 16) PG_BW(48, 16, 32)
+#define PG_BWC(A, B, SIDE)                                                                                         \
+    if (cin == A && cout == B && D == SIDE) {                                                                      \
+        hipLaunchKernelGGL((k_conv_bwdw_col<A, B, SIDE>), dim3(nb), dim3(256), 0, s, inQ, dzQ, part, ncol, nsplit, \
+                           chunk);                                                                                 \
+        return PETGEM_OK;                                                                                          \
+    }
+    PG_BWC(16, 16, 32) PG_BW(16, 32, 16) PG_BW(32, 64, 8) PG_BW(64, 64, 8) PG_BW(96, 32, 16) PG_BWC(48, 16, 32)
 #undef PG_BW
+#undef PG_BWC
     set_error("unsupported convolution shape");
     return PETGEM_INVALID_ARG;
 }
@@ -772,7 +899,7 @@ int layer_grads(petgem_net* n, int li, const bf16* in, const bf16* dz, int nvox,
     const NetLayer& l = n->L[li];
     PG_TRY(to_quads(l.cin, in, nvox, n->tin, s));
     PG_TRY(to_quads(l.cout, dz, nvox, n->tdz, s));
-    const int ns = bwdw_splits(l.cin, nvox);
+    const int ns = bwdw_splits(l.cin, nvox, D);
     PG_TRY(conv_bwdw(l.cin, l.cout, n->tin, n->tdz, n->wpart, nvox, D, ns, s));
     const int nw = (27 * l.cin + 1) * l.cout;
     hipLaunchKernelGGL(k_sum_splits, dim3(ceil_div(nw, 64)), dim3(1024), 0, s, n->wpart, ns, nw, n->Gr + l.w_off);
@@ -789,7 +916,7 @@ int backward(petgem_net* n, int B, hipStream_t s) {
     // c7 (linear): dz = dY
     PG_TRY(layer_grads(n, 6, n->A6, dz, v32, 32, s));
     PG_TRY(conv(16, 16, false, true, dz, L[6].wtb, nullptr, g0, v32, 32, s));                  // dA6
-    hipLaunchKernelGGL(k_relu_bwd, g1((long)v32 * 4), dim3(256), 0, s, g0, n->A6, (long)v32 * 16, dz);
+    hipLaunchKernelGGL(k_relu_bwd, g1((long)v32 * 4), dim3(256), 0, s, g0, n->A6, v32 * 16, dz);
     // c6
     PG_TRY(layer_grads(n, 5, n->Q1, dz, v32, 32, s));
     PG_TRY(conv(16, 48, false, true, dz, L[5].wtb, nullptr, g0, v32, 32, s));                  // dQ1 [v32][48]
@@ -803,7 +930,7 @@ int backward(petgem_net* n, int B, hipStream_t s) {
     // c4
     PG_TRY(layer_grads(n, 3, n->A3, dz, v8, 8, s));
     PG_TRY(conv(64, 64, false, true, dz, L[3].wtb, nullptr, g2, v8, 8, s));                    // dA3
-    hipLaunchKernelGGL(k_relu_bwd, g1((long)v8 * 16), dim3(256), 0, s, g2, n->A3, (long)v8 * 64, dz);
+    hipLaunchKernelGGL(k_relu_bwd, g1((long)v8 * 16), dim3(256), 0, s, g2, n->A3, v8 * 64, dz);
     // c3
     PG_TRY(layer_grads(n, 2, n->P2, dz, v8, 8, s));
     float* dP2 = g2;   // [v8][32]
@@ -951,11 +1078,10 @@ int petgem_net_create(int32_t batch_max, uint64_t seed, petgem_net** out) {
         (rc = dalloc(&n->scal, (size_t)batch_max)) || (rc = dalloc(&n->vsrc, (size_t)batch_max)) ||
         (rc = dalloc(&n->bn, (size_t)batch_max)))
         return fail(rc);
-    size_t wp = 0;
-    for (auto& l : n->L) {
-        const long nv = (long)batch_max * (l.side * l.side * l.side);
-        wp = std::max(wp, wpart_floats(l.cin, l.cout, nv));
-    }
+    size_t wp = 0;   // the largest split count over every batch size up to batch_max
+    for (auto& l : n->L)
+        for (int bb = 1; bb <= batch_max; ++bb)
+            wp = std::max(wp, wpart_floats(l.cin, l.cout, (long)bb * l.side * l.side * l.side, l.side));
     if ((rc = dalloc(&n->wpart, wp)) || (rc = dalloc(&n->tin, v32 * 48)) || (rc = dalloc(&n->tdz, v32 * 16)) || (rc = dalloc(&n->lpart, (size_t)ceil_div((int64_t)v32, 256))))
         return fail(rc);
     if (hipHostMalloc(reinterpret_cast<void**>(&n->lpart_h), sizeof(double) * ceil_div((int64_t)v32, 256)) != hipSuccess)
