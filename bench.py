@@ -128,6 +128,8 @@ def kernel_name(form, shape):
     if form == "plain":
         return f"k_spmv<{shape}, false> complex128 CSR (A D^-1)"
     kind, a, b = shape // 10000, (shape // 100) % 100, shape % 100
+    if kind == 3:
+        return f"k_spmm_sp<{a}, {b}> complex64 pipelined sliced ELLPACK (K, M_sigma)"
     if kind == 2:
         return f"k_spmm_s<{a}, {b}> complex64 sliced ELLPACK (K, M_sigma)"
     if kind == 1:

@@ -117,8 +117,11 @@ typedef struct {
                                lanes (a lanes per row, b columns per lane),
                                1 = CSR nonzero lanes (a lanes per row, b
                                columns), 2 = sliced ELLPACK (a columns, b
-                               slice columns in flight); GMRES: the lanes per
-                               row of the complex128 CSR SpMV                   */
+                               slice columns in flight), 3 = sliced ELLPACK
+                               with the next b slice columns' indices and
+                               values loaded during the current b gathers;
+                               GMRES: the lanes per row of the complex128
+                               CSR SpMV                                         */
     double  b_norm;         /* |b|_2 of the source's right-hand side            */
 } petgem_stats;
 

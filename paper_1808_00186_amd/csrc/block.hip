@@ -540,6 +540,104 @@ k_spmm_s(Op op, const ColState* __restrict__ st, const float2* __restrict__ X, f
     }
 }
 
+// Software-pipelined sliced-ELLPACK variant: the same layout and epilogue
+// as k_spmm_s, but the indices and values of the next U slice columns are
+// loaded before the gathers of the current U, so their latency overlaps.
+template <int CM, int U>
+__global__ void __launch_bounds__(256)
+k_spmm_sp(Op op, const ColState* __restrict__ st, const float2* __restrict__ X, float2* __restrict__ Y,
+         double2* __restrict__ partial) {
+    __shared__ double2 red[4][CM];
+    const int tile = tile_of(op, xcd_block(blockIdx.x, gridDim.x));
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int sl = tile * 4 + wave;
+    const int i = sl * 64 + lane;
+    const int C = op.C;
+    const int seg = op.tile_seg ? op.tile_seg[tile] : 0;
+    double2 pacc[CM];
+    float wmu[CM];
+    bool live[CM], any = false;
+#pragma unroll
+    for (int u = 0; u < CM; ++u) {
+        pacc[u] = make_double2(0.0, 0.0);
+        live[u] = u < C && col_live(st, seg * C + u, 1);
+        any = any || live[u];
+        wmu[u] = u < C ? (float)op.wmu[seg * C + u] : 0.f;
+    }
+    if (any) {   // the same for the whole block (one segment)
+        float2 ak[CM], am[CM];
+#pragma unroll
+        for (int u = 0; u < CM; ++u) { ak[u] = f2(0.f, 0.f); am[u] = f2(0.f, 0.f); }
+        const int base = op.sp[sl], wd = op.sw[sl];
+        // slice columns k .. k+U-1 (past the width: zero values, own row)
+        int32_t cj[U];
+        float kv[U], mv[U];
+        auto fetch = [&](int k, int32_t* c, float* kk, float* mm) {
+#pragma unroll
+            for (int q = 0; q < U; ++q) {
+                if (k + q < wd) {
+                    const int e = base + (k + q) * 64 + lane;
+                    c[q] = op.scol[e];
+                    kk[q] = op.sK[e];
+                    mm[q] = op.sM[e];
+                } else {
+                    c[q] = i < op.nrow_valid ? i : 0;
+                    kk[q] = 0.f;
+                    mm[q] = 0.f;
+                }
+            }
+        };
+        fetch(0, cj, kv, mv);
+        for (int k = 0; k < wd; k += U) {
+            float2 xv[U][CM];
+#pragma unroll
+            for (int q = 0; q < U; ++q) {
+                const float2* xr = X + (size_t)cj[q] * C;
+#pragma unroll
+                for (int u = 0; u < CM; ++u) xv[q][u] = live[u] ? xr[u] : f2(0.f, 0.f);
+            }
+            int32_t cn[U];
+            float kn[U], mn[U];
+            if (k + U < wd) fetch(k + U, cn, kn, mn);
+#pragma unroll
+            for (int q = 0; q < U; ++q)
+#pragma unroll
+                for (int u = 0; u < CM; ++u) {
+                    ak[u].x += kv[q] * xv[q][u].x; ak[u].y += kv[q] * xv[q][u].y;
+                    am[u].x += mv[q] * xv[q][u].x; am[u].y += mv[q] * xv[q][u].y;
+                }
+            if (k + U < wd) {
+#pragma unroll
+                for (int q = 0; q < U; ++q) { cj[q] = cn[q]; kv[q] = kn[q]; mv[q] = mn[q]; }
+            }
+        }
+        if (i < op.nrow_valid) {
+#pragma unroll
+            for (int u = 0; u < CM; ++u) {
+                if (!live[u]) continue;
+                float2 y;
+                y.x = ak[u].x + wmu[u] * am[u].y;   // K x - i wmu M x
+                y.y = ak[u].y - wmu[u] * am[u].x;
+                const size_t o = (size_t)i * C + u;
+                const float2 xo = X[o];
+                pacc[u].x += (double)xo.x * (double)y.x - (double)xo.y * (double)y.y;
+                pacc[u].y += (double)xo.x * (double)y.y + (double)xo.y * (double)y.x;
+                Y[o] = y;
+            }
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < CM; ++u) {
+        const double sx = wave_sum(pacc[u].x), sy = wave_sum(pacc[u].y);
+        if (lane == 0) red[wave][u] = make_double2(sx, sy);
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < C && (int)threadIdx.x < CM) {
+        const int u = threadIdx.x;
+        partial[(size_t)tile * C + u] = cadd(cadd(red[0][u], red[1][u]), cadd(red[2][u], red[3][u]));
+    }
+}
+
 // Fixed-shape sums over the row slots of a CP-lane row layout (thread t holds
 // column t % CP of slot t / CP); the results for column c end in la[c], lb[c].
 // Below 64 lanes per row the slots inside a wave are folded by shuffles.
@@ -599,11 +697,30 @@ __device__ __forceinline__ float2 jacobi_z(float2 r, double kd, double md, doubl
               (float)(((double)r.y * dr - (double)r.x * di) * inv));
 }
 
-// r = (r64 / |r64|) in complex64, x = 0, z = D^-1 r, p = z; partials r^T z, |r|^2.
+__device__ __forceinline__ float2 cmulf(float2 a, float2 b) {
+    return f2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// D^-1 = 1 / (Kd - i wmu Md) in complex64 for a single-column solve (one
+// frequency): the vector kernels then read 8 bytes per row instead of Kd, Md.
+__global__ void k_dinv(Op op, float2* __restrict__ dinv) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= op.ntiles * kTR) return;
+    float2 v = f2(0.f, 0.f);
+    if (i < op.nrow_valid) {
+        const double dr = op.Kd[i], di = -op.wmu[0] * op.Md[i];
+        const double inv = 1.0 / (dr * dr + di * di);
+        v = f2((float)(dr * inv), (float)(-di * inv));
+    }
+    dinv[i] = v;
+}
+
+// r = (r64 / |r64|) in complex64, x = 0, z = D^-1 r, p = z; partials r^T z,
+// |r|^2. dinv (or NULL): the precomputed D^-1 of a single-column solve.
 __global__ void __launch_bounds__(256)
 k_inner_init(Op op, int CP, const double2* __restrict__ R64, const ColState* __restrict__ st,
-             float2* __restrict__ Xi, float2* __restrict__ R, float2* __restrict__ Z, float2* __restrict__ P,
-             double2* __restrict__ p0, double2* __restrict__ p1) {
+             const float2* __restrict__ dinv, float2* __restrict__ Xi, float2* __restrict__ R,
+             float2* __restrict__ Z, float2* __restrict__ P, double2* __restrict__ p0, double2* __restrict__ p1) {
     __shared__ double2 ra[256], rb[256];
     const int tile = blockIdx.x, C = op.C;
     const int c = threadIdx.x % CP, slot = threadIdx.x / CP, RPB = 256 / CP;
@@ -620,7 +737,7 @@ k_inner_init(Op op, int CP, const double2* __restrict__ R64, const ColState* __r
             if (S.outer && i < op.nrow_valid) {
                 const double2 rr = R64[o];
                 r = f2((float)(rr.x * inv), (float)(rr.y * inv));
-                z = jacobi_z(r, op.Kd[i], op.Md[i], wmu);
+                z = dinv ? cmulf(r, dinv[i]) : jacobi_z(r, op.Kd[i], op.Md[i], wmu);
             }
             Xi[o] = f2(0.f, 0.f);
             R[o] = r;
@@ -738,14 +855,15 @@ __device__ __forceinline__ void cols_sum2(const double2* __restrict__ p0, const 
     cp_sum2(a, b, CP, la, lb);
 }
 
-// alpha from the nps SpMM partials of p^T q (state slot s1 -> s0), then as
-// k_update over tpb tiles: x += alpha p; r -= alpha q; z = D^-1 r; partials
-// r^T z, |r|^2 (one slot per block).
+// alpha from the nps SpMM partials of p^T q (state slot s1 -> s0), then over
+// tpb tiles: r -= alpha q; z = D^-1 r; partials r^T z, |r|^2 (one slot per
+// block). x += alpha p waits for k_pupdate_p, which reads p anyway. dinv (or
+// NULL): the precomputed D^-1 of a single-column solve.
 __global__ void __launch_bounds__(256)
 k_update_p(Op op, int CP, int tpb, const ColState* __restrict__ s1, ColState* __restrict__ s0,
-           const double2* __restrict__ ps, int nps, float2* __restrict__ Xi, float2* __restrict__ R,
-           float2* __restrict__ Z, const float2* __restrict__ P, const float2* __restrict__ Q,
-           double2* __restrict__ p0, double2* __restrict__ p1) {
+           const double2* __restrict__ ps, int nps, float2* __restrict__ R, float2* __restrict__ Z,
+           const float2* __restrict__ Q, const float2* __restrict__ dinv, double2* __restrict__ p0,
+           double2* __restrict__ p1) {
     __shared__ double2 ra[256], rb[256];
     const int C = op.C;
     const int c = threadIdx.x % CP, slot = threadIdx.x / CP, RPB = 256 / CP;
@@ -753,15 +871,16 @@ k_update_p(Op op, int CP, int tpb, const ColState* __restrict__ s1, ColState* __
     const int cc = min(c, C - 1);   // lanes past the last column load column C-1 and store nothing
     // The first four rows' vectors and the two scalars the update needs are
     // loaded ahead of the partial sums (none of them depends on alpha).
-    float2 p[4], q[4], x[4], r[4];
+    float2 q[4], r[4], dv[4];
     double kd[4], md[4];
     auto load4 = [&](int ib) {
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int i = max(min(ib + u * RPB, i1 - 1), 0);   // in range; the duplicates are not stored
             const size_t o = (size_t)i * C + cc;
-            p[u] = P[o]; q[u] = Q[o]; x[u] = Xi[o]; r[u] = R[o];
-            kd[u] = op.Kd[i]; md[u] = op.Md[i];
+            q[u] = Q[o]; r[u] = R[o];
+            if (dinv) dv[u] = dinv[i];
+            else { kd[u] = op.Kd[i]; md[u] = op.Md[i]; }
         }
     };
     load4(i0 + slot);
@@ -792,12 +911,9 @@ k_update_p(Op op, int CP, int tpb, const ColState* __restrict__ s1, ColState* __
                 const int i = ib + u * RPB;
                 if (i >= i1) break;
                 const size_t o = (size_t)i * C + c;
-                x[u].x += ax * p[u].x - ay * p[u].y;
-                x[u].y += ax * p[u].y + ay * p[u].x;
                 r[u].x -= ax * q[u].x - ay * q[u].y;
                 r[u].y -= ax * q[u].y + ay * q[u].x;
-                const float2 z = jacobi_z(r[u], kd[u], md[u], wmu);
-                Xi[o] = x[u];
+                const float2 z = dinv ? cmulf(r[u], dv[u]) : jacobi_z(r[u], kd[u], md[u], wmu);
                 R[o] = r[u];
                 Z[o] = z;
                 a.x += (double)r[u].x * z.x - (double)r[u].y * z.y;
@@ -814,33 +930,38 @@ k_update_p(Op op, int CP, int tpb, const ColState* __restrict__ s1, ColState* __
 }
 
 // convergence test and beta from the npu partials of r^T z and |r|^2 (state
-// slot s0 -> s1), then p = z + beta p over tpb tiles for the columns still active.
+// slot s0 -> s1); then, over tpb tiles, for the columns whose alpha was
+// applied to r: x += alpha p, and for those still active: p = z + beta p.
 __global__ void __launch_bounds__(256)
 k_pupdate_p(Op op, int CP, int tpb, const ColState* __restrict__ s0, ColState* __restrict__ s1,
             const double2* __restrict__ pg, const double2* __restrict__ pr, int npu, const float2* __restrict__ Z,
-            float2* __restrict__ P) {
+            float2* __restrict__ P, float2* __restrict__ Xi) {
     __shared__ double2 ra[256], rb[256];
     const int C = op.C;
     const int c = threadIdx.x % CP, slot = threadIdx.x / CP, RPB = 256 / CP;
     const int i0 = blockIdx.x * tpb * kTR, i1 = min(i0 + tpb * kTR, op.nrow_valid);
     const int cc = min(c, C - 1);   // lanes past the last column load column C-1 and store nothing
-    // the first four rows of z and p are loaded ahead of the partial sums
-    float2 z[4], p[4];
+    // the first four rows of z, p and x are loaded ahead of the partial sums
+    float2 z[4], p[4], x[4];
     auto load4 = [&](int ib) {
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const size_t o = (size_t)max(min(ib + u * RPB, i1 - 1), 0) * C + cc;   // duplicates are not stored
             z[u] = Z[o];
             p[u] = P[o];
+            x[u] = Xi[o];
         }
     };
     load4(i0 + slot);
     cols_sum2(pg, pr, npu, C, CP, ra, rb);
     if (c >= C) return;
     ColState S = s0[c];
+    const bool stepped = S.active;   // this iteration's alpha was applied to r
     if (S.active) step_beta(S, ra[c], rb[c].x);
     if (blockIdx.x == 0 && slot == 0) s1[c] = S;
-    if (!S.active) return;
+    if (!stepped) return;
+    const bool more = S.active;
+    const float ax = (float)S.alpha.x, ay = (float)S.alpha.y;
     const float bx = (float)S.beta.x, by = (float)S.beta.y;
     for (int ib = i0 + slot; ib < i1; ib += 4 * RPB) {
         if (ib != i0 + slot) load4(ib);
@@ -848,7 +969,9 @@ k_pupdate_p(Op op, int CP, int tpb, const ColState* __restrict__ s0, ColState* _
         for (int u = 0; u < 4; ++u) {
             const int i = ib + u * RPB;
             if (i >= i1) break;
-            P[(size_t)i * C + c] = f2(z[u].x + bx * p[u].x - by * p[u].y, z[u].y + bx * p[u].y + by * p[u].x);
+            const size_t o = (size_t)i * C + c;
+            Xi[o] = f2(x[u].x + ax * p[u].x - ay * p[u].y, x[u].y + ax * p[u].y + ay * p[u].x);
+            if (more) P[o] = f2(z[u].x + bx * p[u].x - by * p[u].y, z[u].y + bx * p[u].y + by * p[u].x);
         }
     }
 }
@@ -1103,10 +1226,14 @@ struct BlockWork {
     int cap_C = 0, cap_nsc = 0, cap_tiles = 0;
     double2 *X64 = nullptr, *R64 = nullptr, *B64 = nullptr;
     float2 *Xi = nullptr, *R = nullptr, *Z = nullptr, *P = nullptr, *Q = nullptr;
+    float2* Dinv = nullptr;    // complex64 D^-1 of a single-column solve
+    size_t dinv_rows = 0;
     double2 *p0 = nullptr, *p1 = nullptr, *p2 = nullptr;
     ColState* st = nullptr;
     ColState* st2 = nullptr;   // second state slot of the in-consumer reductions
     ColState* st_h = nullptr;
+    ColState* st_h2 = nullptr;             // second host snapshot of the state (overlapped checks)
+    hipEvent_t snap_ev[2] = {nullptr, nullptr};
     int* tmap = nullptr;       // launched tiles of a compacted uneven batch
     int* flags = nullptr;      // [nsc] per-column flags (rejected initial guesses)
     double* wmu = nullptr;
@@ -1133,12 +1260,20 @@ struct BlockWork {
         if (graph_stream) (void)hipStreamDestroy(graph_stream);
         graph_stream = nullptr;
         dfree(X64); dfree(R64); dfree(B64); dfree(Xi); dfree(R); dfree(Z); dfree(P); dfree(Q);
+        dfree(Dinv);
+        dinv_rows = 0;
         dfree(p0); dfree(p1); dfree(p2); dfree(st); dfree(st2); dfree(tmap); dfree(flags); dfree(wmu);
         dfree(seg_tile); dfree(tile_seg);
         dfree(rp); dfree(col); dfree(K64); dfree(M64); dfree(Kd); dfree(Md); dfree(K32); dfree(M32);
         cat_sell.release();
         if (st_h) (void)hipHostFree(st_h);
         st_h = nullptr;
+        if (st_h2) (void)hipHostFree(st_h2);
+        st_h2 = nullptr;
+        for (auto& e : snap_ev) {
+            if (e) (void)hipEventDestroy(e);
+            e = nullptr;
+        }
         cap_rows = 0; cap_C = cap_nsc = cap_tiles = 0;
         cat_rows = cat_nnz = 0;
     }
@@ -1240,6 +1375,17 @@ bool spmm_dispatch_(const SpmmChoice& ch, Op op, const ColState* st, const SpmmA
         }
         return false;
     }
+    if (ch.kind == 3) {
+        if constexpr (sizeof(T) == 4 && EPI == 1) {
+            if (!op.sp) return false;
+#define PG_SP(CM, U) if (ch.a == CM && ch.b == U) { \
+            launch_timed(k_spmm_sp<CM, U>, dim3(op.nlaunch), s, g.e0, g.e1, op, st, (const float2*)g.X, \
+                         (float2*)g.Y, g.part); return true; }
+            PG_SP(1, 4) PG_SP(1, 8) PG_SP(2, 4)
+#undef PG_SP
+        }
+        return false;
+    }
     if (ch.kind == 1) {
 #define PG_N(G, CM) if (ch.a == G && ch.b == CM) { spmm_thunk<T, G, CM, EPI, false>(op, st, g, s); return true; }
         PG_N(4, 1) PG_N(8, 1) PG_N(16, 1) PG_N(4, 2) PG_N(8, 2) PG_N(16, 2) PG_N(4, 4) PG_N(8, 4) PG_N(16, 4)
@@ -1270,6 +1416,8 @@ std::vector<SpmmChoice> candidates(int C, bool sell) {
         if (sell) {
             v.push_back({2, cm, 4});
             if (cm < 4) v.push_back({2, cm, 8});
+            if (cm == 1) v.push_back({3, 1, 8});
+            if (cm <= 2) v.push_back({3, cm, 4});
         }
     }
     if (C >= 4) {
@@ -1302,6 +1450,8 @@ int ensure_work(BlockWork*& w, size_t rows, int C, int nsc, int ntiles) {
     dfree(w->p0); dfree(w->p1); dfree(w->p2); dfree(w->st); dfree(w->st2); dfree(w->tmap); dfree(w->flags); dfree(w->wmu); dfree(w->seg_tile); dfree(w->tile_seg);
     if (w->st_h) (void)hipHostFree(w->st_h);
     w->st_h = nullptr;
+    if (w->st_h2) (void)hipHostFree(w->st_h2);
+    w->st_h2 = nullptr;
     const size_t e = rows * (size_t)C;
     PG_TRY(dalloc(&w->X64, e));
     PG_TRY(dalloc(&w->R64, e));
@@ -1322,6 +1472,9 @@ int ensure_work(BlockWork*& w, size_t rows, int C, int nsc, int ntiles) {
     PG_TRY(dalloc(&w->seg_tile, (size_t)nsc + 1));
     PG_TRY(dalloc(&w->tile_seg, (size_t)ntiles));
     PG_HIP(hipHostMalloc(reinterpret_cast<void**>(&w->st_h), sizeof(ColState) * (size_t)nsc));
+    PG_HIP(hipHostMalloc(reinterpret_cast<void**>(&w->st_h2), sizeof(ColState) * (size_t)nsc));
+    for (auto& e : w->snap_ev)
+        if (!e) PG_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     w->cap_rows = rows;
     w->cap_C = C;
     w->cap_nsc = nsc;
@@ -1359,12 +1512,13 @@ int tune_spmm(BlockWork* w, const Op& op, int64_t nnz, hipStream_t s, SpmmTuned&
         PG_HIP(hipEventElapsedTime(&ms, e0, e1));
         c.ms = ms / 3.f;
         if (verbose) {
-            static const char* kinds[3] = {"column lanes", "nonzero lanes", "sliced ELLPACK"};
+            static const char* kinds[4] = {"column lanes", "nonzero lanes", "sliced ELLPACK",
+                                           "pipelined sliced ELLPACK"};
             fprintf(stderr, "[petgem] SpMM tuning: %s %d x %d: %.1f us\n", kinds[c.kind], c.a, c.b, 1e3 * c.ms);
             fflush(stderr);
         }
         if (c.ms < best.best.ms) best.best = c;
-        if (c.kind != 2 && c.ms < best.csr.ms) best.csr = c;
+        if (c.kind < 2 && c.ms < best.csr.ms) best.csr = c;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -1394,7 +1548,7 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
         for (const SpmmChoice& c : candidates(op.C, op.sp != nullptr))
             if (10000 * c.kind + 100 * c.a + c.b == o.spmm_shape) {
                 tu.best = c;
-                if (c.kind != 2) tu.csr = c;
+                if (c.kind < 2) tu.csr = c;
                 found = true;
             }
         if (!found) {
@@ -1408,6 +1562,20 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
     // the reductions run inside the vector kernels for one mesh whose
     // partials are few enough for every block to sum
     const bool in_consumer = op.nseg == 1 && (int64_t)op.ntiles * ppS * C <= kConsumerMax;
+    // one column of one system: D^-1 once per solve in complex64
+    const float2* dinv = nullptr;
+    if (in_consumer && C == 1) {
+        const size_t rows = (size_t)op.ntiles * kTR;
+        if (w->dinv_rows < rows) {
+            dfree(w->Dinv);
+            w->dinv_rows = 0;
+            PG_TRY(dalloc(&w->Dinv, rows));
+            w->dinv_rows = rows;
+        }
+        hipLaunchKernelGGL(k_dinv, dim3(ceil_div(rows, 256)), dim3(256), 0, s, op, w->Dinv);
+        PG_HIP(hipGetLastError());
+        dinv = w->Dinv;
+    }
     const int nbu = ceil_div(op.ntiles, kConsumerTiles);   // blocks of the two vector kernels
     hipLaunchKernelGGL(k_init_state, dim3(ceil_div(nsc, 64)), dim3(64), 0, s, w->st, nsc, o.rtol,
                        o.inner_rtol);
@@ -1512,9 +1680,9 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
         spmm_dispatch<float, 1>(ch, opi, w->st, ev_pair(SpmmArgs{w->P, nullptr, w->Q, w->p0}), s);
         if (in_consumer) {
             hipLaunchKernelGGL(k_update_p, dim3(nbu), dim3(256), 0, s, op, CP, kConsumerTiles, w->st, w->st2,
-                               w->p0, op.ntiles * ppS, w->Xi, w->R, w->Z, w->P, w->Q, w->p1, w->p2);
+                               w->p0, op.ntiles * ppS, w->R, w->Z, w->Q, dinv, w->p1, w->p2);
             hipLaunchKernelGGL(k_pupdate_p, dim3(nbu), dim3(256), 0, s, op, CP, kConsumerTiles, w->st2, w->st,
-                               w->p1, w->p2, nbu, w->Z, w->P);
+                               w->p1, w->p2, nbu, w->Z, w->P, w->Xi);
         } else {
             hipLaunchKernelGGL(k_reduce, dim3(nsc), dim3(1024), 0, s, op, w->p0, ppS, nullptr, 1, w->st,
                                (int)RED_ALPHA, 0);
@@ -1538,7 +1706,7 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
             sig.insert(sig.end(), c, c + nb);
         };
         put(&opi, sizeof(opi));
-        const void* ptrs[10] = {w->Xi, w->R, w->Z, w->P, w->Q, w->p0, w->p1, w->p2, w->st, w->st2};
+        const void* ptrs[11] = {w->Xi, w->R, w->Z, w->P, w->Q, w->p0, w->p1, w->p2, w->st, w->st2, dinv};
         put(ptrs, sizeof(ptrs));
         int chv[5] = {ch.kind, ch.a, ch.b, (int)in_consumer, opi.tmap ? tgen : 0};
         put(chv, sizeof(chv));
@@ -1598,7 +1766,7 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
             break;
         }
         // inner complex64 COCG on A d = r64 / |r64|
-        hipLaunchKernelGGL(k_inner_init, dim3(op.ntiles), dim3(256), 0, s, op, CP, w->R64, w->st, w->Xi,
+        hipLaunchKernelGGL(k_inner_init, dim3(op.ntiles), dim3(256), 0, s, op, CP, w->R64, w->st, dinv, w->Xi,
                            w->R, w->Z, w->P, w->p1, w->p2);
         hipLaunchKernelGGL(k_reduce, dim3(nsc), dim3(1024), 0, s, op, w->p1, 1, w->p2, 1, w->st,
                            (int)RED_INIT, 0);
@@ -1609,21 +1777,45 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
         int inner = 0, groups = 1, next_print = 512;
         double prev_gap = -1.0;
         uncompact();
-        while (true) {
+        // A single system keeps one more batch of iteration groups queued while
+        // the host reads the state after the previous batch, so the GPU does
+        // not idle during the check; a batch queued after convergence finds
+        // every column inactive and changes nothing. An uneven batch checks
+        // synchronously: a check may rebuild its tile list.
+        const bool overlap = use_graph && !(seg_tile_h && op.nseg > 1);
+        ColState* snap[2] = {w->st_h, w->st_h2};
+        int cur = 0;
+        auto launch_batch = [&](int n, int slot) -> int {
             PG_TRY(ensure_graph());
-            for (int g = 0; g < groups; ++g) {
+            for (int g = 0; g < n; ++g) {
                 if (use_graph) {
                     PG_HIP(hipGraphLaunch(w->graph, s));
                 } else {
                     group();
                 }
             }
-            inner += kCheck * groups;
-            PG_TRY(read_state());
+            inner += kCheck * n;
+            PG_HIP(hipMemcpyAsync(snap[slot], w->st, sizeof(ColState) * nsc, hipMemcpyDeviceToHost, s));
+            PG_HIP(hipEventRecord(w->snap_ev[slot], s));
+            return PETGEM_OK;
+        };
+        PG_TRY(launch_batch(groups, cur));
+        int queued = groups;   // groups of the batch that snap[cur] follows
+        double need = -1.0;    // half the predicted groups to convergence (-1: unknown)
+        while (true) {
+            int ahead = 0;
+            if (overlap) {
+                if (need < 0.0) ahead = 1;
+                else if (need > queued) ahead = (int)std::min<double>(kMaxGroups, std::max(1.0, need - queued));
+                ahead = std::min(ahead, std::max(0, (o.max_iter - total_inner - inner) / kCheck));
+                if (ahead > 0) PG_TRY(launch_batch(ahead, cur ^ 1));
+            }
+            PG_HIP(hipEventSynchronize(w->snap_ev[cur]));
+            const ColState* sv = snap[cur];
             int act = 0;
             double gap = 0.0;   // worst log(|r|^2 / tol^2) over the active columns
             for (int k = 0; k < nsc; ++k) {
-                const ColState& S = w->st_h[k];
+                const ColState& S = sv[k];
                 if (!S.active) continue;
                 ++act;
                 if (S.rn2 > 0.0 && S.inner_tol2 > 0.0) gap = std::max(gap, std::log(S.rn2 / S.inner_tol2));
@@ -1631,22 +1823,26 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
             if (o.verbose && inner >= next_print) {
                 double worst = 0.0;
                 for (int k = 0; k < nsc; ++k)
-                    if (w->st_h[k].active) worst = std::max(worst, w->st_h[k].rn2);
+                    if (sv[k].active) worst = std::max(worst, sv[k].rn2);
                 fprintf(stderr, "[petgem]   inner %d: %d active, worst inner residual %.3e, %.0f ms\n", inner, act,
                         std::sqrt(worst), t_all.ms());
                 fflush(stderr);
                 next_print += 512;
             }
             if (act == 0 || total_inner + inner >= o.max_iter) break;
-            PG_TRY(compact());
-            const int ran = groups;
-            groups = 1;
-            if (prev_gap > 0.0 && gap < prev_gap && std::isfinite(gap)) {
-                const double per_group = (prev_gap - gap) / ran;
-                groups = (int)std::min<double>(kMaxGroups, std::max(1.0, 0.5 * gap / per_group));
-            }
-            groups = std::max(1, std::min(groups, (o.max_iter - total_inner - inner) / kCheck));
+            need = -1.0;
+            if (prev_gap > 0.0 && gap < prev_gap && std::isfinite(gap)) need = 0.5 * gap * queued / (prev_gap - gap);
             prev_gap = gap;
+            if (ahead > 0) {   // the next state is already on its way
+                cur ^= 1;
+                queued = ahead;
+                continue;
+            }
+            PG_TRY(compact());
+            groups = need < 0.0 ? 1 : (int)std::min<double>(kMaxGroups, std::max(1.0, need));
+            groups = std::max(1, std::min(groups, (o.max_iter - total_inner - inner) / kCheck));
+            PG_TRY(launch_batch(groups, cur));
+            queued = groups;
         }
         total_inner += inner;
         hipLaunchKernelGGL(k_ir_update, dim3(op.ntiles), dim3(256), 0, s, op, CP, w->st, w->Xi, w->X64);

@@ -120,7 +120,7 @@ def test_cocg_cfg2_single_source_matches_stored_oracle(pg):
 # 10000 kind + 100 a + b (kind 0 CSR column lanes, 1 CSR nonzero lanes,
 # 2 sliced ELLPACK)
 SHAPES = {
-    1: [10401, 10801, 11601, 20104, 20108],
+    1: [10401, 10801, 11601, 20104, 20108, 30104, 30108],
     3: [10404, 10804, 11604, 20404],
     33: [1603, 1604, 3202, 6401],
 }
