@@ -58,6 +58,8 @@ HBM_PEAK_GBS = 8000.0
 # bytes copied, WRITE_SIZE 1.0); profiles/spmm_cfg2_traffic.md holds the
 # figures and commands. A kernel changed since then reads null.
 MEASURED_TRAFFIC = {
+    "k_spmm_sp<1, 4> complex64 pipelined sliced ELLPACK (K, M_sigma)": (48342.8 * 2.0 + 3219.3) * 1024,
+    "k_spmm_s<1, 4> complex64 sliced ELLPACK (K, M_sigma)": (47676.3 * 2.0 + 3219.2) * 1024,
     "k_spmm_s<1, 8> complex64 sliced ELLPACK (K, M_sigma)": (49890.8 * 2.0 + 3367.3) * 1024,
 }
 RTOL = 1e-9
@@ -160,7 +162,8 @@ def bench_cfg2(args, petgem, synth, torch):
     ref = np.load(GOLDEN_CFG2)["E"] if os.path.exists(GOLDEN_CFG2) else None
     forms = {
         "plain": dict(rtol=RTOL),
-        "mixed": dict(rtol=RTOL, method=petgem.COCG, precision=petgem.MIXED, inner_rtol=args.inner_rtol),
+        "mixed": dict(rtol=RTOL, method=petgem.COCG, precision=petgem.MIXED, inner_rtol=args.inner_rtol,
+                      spmm_shape=args.spmm_shape),
     }
     res = {}
     for name, kw in forms.items():
@@ -481,6 +484,9 @@ def main():
     ap.add_argument("--plain-subset", type=int, default=3, choices=[3, 9],
                     help="cfg3: sources solved by the plain path for the comparison")
     ap.add_argument("--max-iter", type=int, default=20000)
+    ap.add_argument("--spmm-shape", type=int, default=0,
+                    help="cfg2: force the mixed form's SpMM shape (its spmv_shape code; 0 = autotune), "
+                         "so that counter runs measure a chosen kernel")
     ap.add_argument("--verbose", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true",
