@@ -176,6 +176,24 @@ def test_cfg1_solution_bitwise_reproducible(torch_cuda, pg):
     assert np.array_equal(x1, x2) and np.array_equal(x1, x3)
 
 
+def test_mixed_solution_bitwise_reproducible(torch_cuda, pg):
+    """Mixed COCG: graph replay with the overlapped host checks and the
+    synchronous loop without graphs run the same iterations (convergence is
+    decided on the device), so the solutions agree bitwise."""
+    m = synth.config1()
+    _case(m)
+    S = pg.System.from_model(m)
+    kw = dict(method=pg.COCG, precision=pg.MIXED)
+    sol1, st1, _ = S.solve(m.sources, pg.default_opts(**kw))
+    x1 = sol1.x().cpu().numpy()
+    sol2, st2, _ = S.solve(m.sources, pg.default_opts(**kw), solution=sol1)
+    x2 = sol2.x().cpu().numpy()
+    sol3, st3, _ = S.solve(m.sources, pg.default_opts(use_graph=0, **kw))
+    x3 = sol3.x().cpu().numpy()
+    assert st1[0]["iters"] == st2[0]["iters"] == st3[0]["iters"]
+    assert np.array_equal(x1, x2) and np.array_equal(x1, x3)
+
+
 def test_initial_guess_and_fallback(torch_cuda, pg):
     torch = torch_cuda
     m = synth.config1()

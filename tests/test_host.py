@@ -102,3 +102,14 @@ def test_error_paths():
     with pytest.raises(petgem.PetgemError) as e:
         petgem.mesh_pattern(xyz, extra)
     assert e.value.code == petgem.MESH_TOPOLOGY
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU: --gpus above 1 exits with a message before
+    touching a device."""
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=300)
+    assert r.returncode != 0
+    assert "one GPU" in (r.stdout + r.stderr)
