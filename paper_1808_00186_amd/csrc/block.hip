@@ -22,7 +22,9 @@
 // the x / r / z update (partials of r^T z and |r|^2), a reduction, the p
 // update. For one mesh with few partials the two reductions move into the
 // prologues of the update kernels (see "reductions in the consumers"), so an
-// iteration is three kernels. Not used, after trial: the single-reduction
+// iteration is three kernels; there the first updates r and z, the second x
+// and p (both read p's row anyway), and a single column reads a precomputed
+// complex64 D^-1. Not used, after trial: the single-reduction
 // rearrangement of Chronopoulos and Gear, which carries A p by a recurrence,
 // loses convergence in complex64 on the harder marine models; folding the p
 // update into the SpMM (gathering z and p together) costs more than the pass
@@ -30,8 +32,9 @@
 // a device-wide cache write-back per block, which costs more than a reduction
 // kernel.
 // The SpMM shapes: CSR with nonzero lanes or column lanes, or a sliced
-// ELLPACK copy of the operator (one row per lane) for up to four columns;
-// the autotuner picks per operator and column count.
+// ELLPACK copy of the operator (one row per lane) for up to four columns,
+// also in a software-pipelined form; the autotuner picks per operator and
+// column count.
 // The dots are accumulated in double precision from complex64 data, per tile,
 // and reduced per (segment, column) in a fixed order (bitwise reproducible).
 // Refinement: r64 = b - A x64 in double precision, the inner solve runs on
