@@ -1230,6 +1230,7 @@ struct BlockWork {
     double2 *X64 = nullptr, *R64 = nullptr, *B64 = nullptr;
     float2 *Xi = nullptr, *R = nullptr, *Z = nullptr, *P = nullptr, *Q = nullptr;
     float2* Dinv = nullptr;    // complex64 D^-1 of a single-column solve
+    int p0_slots = 0;          // SpMM partial slots per tile that p0 holds
     size_t dinv_rows = 0;
     double2 *p0 = nullptr, *p1 = nullptr, *p2 = nullptr;
     ColState* st = nullptr;
@@ -1464,7 +1465,10 @@ int ensure_work(BlockWork*& w, size_t rows, int C, int nsc, int ntiles) {
     PG_TRY(dalloc(&w->Z, e));
     PG_TRY(dalloc(&w->P, e));
     PG_TRY(dalloc(&w->Q, e));
-    PG_TRY(dalloc(&w->p0, (size_t)ntiles * C * (C <= 4 ? 16 : 1)));   // nonzero-lane SpMM: G slots per tile
+    // SpMM partial slots per tile: up to 16 for the nonzero-lane shapes (few
+    // columns), one otherwise
+    w->p0_slots = C <= 4 ? 16 : 1;
+    PG_TRY(dalloc(&w->p0, (size_t)ntiles * C * w->p0_slots));
     PG_TRY(dalloc(&w->p1, (size_t)ntiles * C));
     PG_TRY(dalloc(&w->p2, (size_t)ntiles * C));
 
@@ -1505,6 +1509,7 @@ int tune_spmm(BlockWork* w, const Op& op, int64_t nnz, hipStream_t s, SpmmTuned&
     SpmmTuned best;
     best.best.ms = best.csr.ms = 1e30f;
     for (auto& c : cands) {
+        if (spmm_slots(c) > w->p0_slots) continue;   // more partial slots than p0 holds
         const SpmmArgs g{w->P, nullptr, w->Q, w->p0};
         spmm_dispatch<float, 1>(c, op, w->st, g, s);   // warm-up
         PG_HIP(hipEventRecord(e0, s));
@@ -1562,6 +1567,12 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
     }
     const SpmmChoice ch = tu.best, ch64 = tu.csr;
     const int ppS = spmm_slots(ch), pp64 = spmm_slots(ch64);
+    if (ppS > w->p0_slots || pp64 > w->p0_slots) {
+        set_error("SpMM shape " + std::to_string(10000 * ch.kind + 100 * ch.a + ch.b) + " needs " +
+                  std::to_string(ppS) + " partial slots per tile; the work space holds " +
+                  std::to_string(w->p0_slots));
+        return PETGEM_INVALID_ARG;
+    }
     // the reductions run inside the vector kernels for one mesh whose
     // partials are few enough for every block to sum
     const bool in_consumer = op.nseg == 1 && (int64_t)op.ntiles * ppS * C <= kConsumerMax;
