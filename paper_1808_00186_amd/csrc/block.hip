@@ -81,6 +81,7 @@ struct ColState {
     int breakdown;
     int iters;         // inner iterations (all refinement steps)
     int kin;           // inner iterations of the current refinement step
+    int stepped;       // this iteration's alpha was applied to r (set at the beta step)
 };
 
 // Operator view shared by the kernels.
@@ -161,9 +162,11 @@ __device__ void apply_red(ColState& S, int mode, int first, double2 a, double2 b
         S.beta = make_double2(0.0, 0.0);
         S.active = S.outer && cfinite(a) && !czero(a);
         S.breakdown = 0;
+        S.stepped = 0;
     } else if (mode == RED_ALPHA) {    // a = p^T q
         step_alpha(S, a);
     } else if (mode == RED_BETA) {     // a = r^T z (new), b.x = |r|^2
+        S.stepped = 1;
         step_beta(S, a, b.x);
     } else if (mode == RED_X0) {       // a = w^H b, b.x = |w|^2 for w = A x0
         // a zero right-hand side (its residual never formed) has x = 0; a guess
@@ -197,7 +200,10 @@ k_reduce(Op op, const double2* __restrict__ p0, int pp0, const double2* __restri
     const int sc = blockIdx.x;
     const int s = sc / op.C, c = sc % op.C;
     ColState& S = st[sc];
-    if (red_skips(S, mode, first)) return;
+    if (red_skips(S, mode, first)) {
+        if (mode == RED_BETA && threadIdx.x == 0) S.stepped = 0;   // inactive: no alpha was applied
+        return;
+    }
     const int t0 = op.seg_tile[s], t1 = op.seg_tile[s + 1];
     double2 a = make_double2(0.0, 0.0), b = make_double2(0.0, 0.0);
     {
@@ -704,14 +710,16 @@ __device__ __forceinline__ float2 cmulf(float2 a, float2 b) {
     return f2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
-// D^-1 = 1 / (Kd - i wmu Md) in complex64 for a single-column solve (one
-// frequency): the vector kernels then read 8 bytes per row instead of Kd, Md.
+// D^-1 = 1 / (Kd - i wmu Md) in complex64 for single-column solves (one
+// frequency per mesh; a row takes its segment's): the vector kernels then read
+// 8 bytes per row instead of Kd, Md.
 __global__ void k_dinv(Op op, float2* __restrict__ dinv) {
     const int i = blockIdx.x * 256 + threadIdx.x;
     if (i >= op.ntiles * kTR) return;
     float2 v = f2(0.f, 0.f);
     if (i < op.nrow_valid) {
-        const double dr = op.Kd[i], di = -op.wmu[0] * op.Md[i];
+        const int seg = op.tile_seg ? op.tile_seg[i / kTR] : 0;
+        const double dr = op.Kd[i], di = -op.wmu[seg] * op.Md[i];
         const double inv = 1.0 / (dr * dr + di * di);
         v = f2((float)(dr * inv), (float)(-di * inv));
     }
@@ -719,7 +727,7 @@ __global__ void k_dinv(Op op, float2* __restrict__ dinv) {
 }
 
 // r = (r64 / |r64|) in complex64, x = 0, z = D^-1 r, p = z; partials r^T z,
-// |r|^2. dinv (or NULL): the precomputed D^-1 of a single-column solve.
+// |r|^2. dinv (or NULL): the precomputed D^-1 of single-column solves.
 __global__ void __launch_bounds__(256)
 k_inner_init(Op op, int CP, const double2* __restrict__ R64, const ColState* __restrict__ st,
              const float2* __restrict__ dinv, float2* __restrict__ Xi, float2* __restrict__ R,
@@ -758,11 +766,13 @@ k_inner_init(Op op, int CP, const double2* __restrict__ R64, const ColState* __r
     }
 }
 
-// x += alpha p; r -= alpha q; z = D^-1 r; partials r^T z and |r|^2.
+// r -= alpha q; z = D^-1 r for the active columns; partials of r^T z and
+// |r|^2. x += alpha p waits for k_pupdate, which reads p anyway. dinv (or
+// NULL): the precomputed D^-1 of single-column solves.
 __global__ void __launch_bounds__(256)
-k_update(Op op, int CP, const ColState* __restrict__ st, float2* __restrict__ Xi, float2* __restrict__ R,
-         float2* __restrict__ Z, const float2* __restrict__ P, const float2* __restrict__ Q,
-         double2* __restrict__ p0, double2* __restrict__ p1) {
+k_update(Op op, int CP, const ColState* __restrict__ st, float2* __restrict__ R, float2* __restrict__ Z,
+         const float2* __restrict__ Q, const float2* __restrict__ dinv, double2* __restrict__ p0,
+         double2* __restrict__ p1) {
     __shared__ double2 ra[256], rb[256];
     const int tile = tile_of(op, blockIdx.x), C = op.C;
     const int c = threadIdx.x % CP, slot = threadIdx.x / CP, RPB = 256 / CP;
@@ -777,14 +787,11 @@ k_update(Op op, int CP, const ColState* __restrict__ st, float2* __restrict__ Xi
                 const int i = tile * kTR + r0 + slot;
                 if (i >= op.nrow_valid) break;
                 const size_t o = (size_t)i * C + c;
-                const float2 p = P[o], q = Q[o];
-                float2 x = Xi[o], r = R[o];
-                x.x += ax * p.x - ay * p.y;
-                x.y += ax * p.y + ay * p.x;
+                const float2 q = Q[o];
+                float2 r = R[o];
                 r.x -= ax * q.x - ay * q.y;
                 r.y -= ax * q.y + ay * q.x;
-                const float2 z = jacobi_z(r, op.Kd[i], op.Md[i], wmu);
-                Xi[o] = x;
+                const float2 z = dinv ? cmulf(r, dinv[i]) : jacobi_z(r, op.Kd[i], op.Md[i], wmu);
                 R[o] = r;
                 Z[o] = z;
                 a.x += (double)r.x * z.x - (double)r.y * z.y;
@@ -800,22 +807,27 @@ k_update(Op op, int CP, const ColState* __restrict__ st, float2* __restrict__ Xi
     }
 }
 
-// p = z + beta p for the columns still active.
+// x += alpha p for the columns whose alpha was applied to r this iteration,
+// then p = z + beta p for those still active.
 __global__ void __launch_bounds__(256)
-k_pupdate(Op op, int CP, const ColState* __restrict__ st, const float2* __restrict__ Z, float2* __restrict__ P) {
+k_pupdate(Op op, int CP, const ColState* __restrict__ st, const float2* __restrict__ Z, float2* __restrict__ P,
+          float2* __restrict__ Xi) {
     const int tile = tile_of(op, blockIdx.x), C = op.C;
     const int c = threadIdx.x % CP, slot = threadIdx.x / CP, RPB = 256 / CP;
     if (c >= C) return;
     const int seg = op.tile_seg ? op.tile_seg[tile] : 0;
     const ColState& S = st[seg * C + c];
-    if (!S.active) return;
+    if (!S.stepped) return;
+    const bool more = S.active;
+    const float ax = (float)S.alpha.x, ay = (float)S.alpha.y;
     const float bx = (float)S.beta.x, by = (float)S.beta.y;
     for (int r0 = 0; r0 < kTR; r0 += RPB) {
         const int i = tile * kTR + r0 + slot;
         if (i >= op.nrow_valid) break;
         const size_t o = (size_t)i * C + c;
-        const float2 z = Z[o], p = P[o];
-        P[o] = f2(z.x + bx * p.x - by * p.y, z.y + bx * p.y + by * p.x);
+        const float2 z = Z[o], p = P[o], x = Xi[o];
+        Xi[o] = f2(x.x + ax * p.x - ay * p.y, x.y + ax * p.y + ay * p.x);
+        if (more) P[o] = f2(z.x + bx * p.x - by * p.y, z.y + bx * p.y + by * p.x);
     }
 }
 
@@ -1576,7 +1588,9 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
     // the reductions run inside the vector kernels for one mesh whose
     // partials are few enough for every block to sum
     const bool in_consumer = op.nseg == 1 && (int64_t)op.ntiles * ppS * C <= kConsumerMax;
-    // one column of one system: D^-1 once per solve in complex64
+    // one column of one system: D^-1 once per solve in complex64 (an uneven
+    // batch keeps the double-precision diagonal: its hardest models need a few
+    // percent more iterations with the rounded D^-1)
     const float2* dinv = nullptr;
     if (in_consumer && C == 1) {
         const size_t rows = (size_t)op.ntiles * kTR;
@@ -1700,11 +1714,11 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
         } else {
             hipLaunchKernelGGL(k_reduce, dim3(nsc), dim3(1024), 0, s, op, w->p0, ppS, nullptr, 1, w->st,
                                (int)RED_ALPHA, 0);
-            hipLaunchKernelGGL(k_update, dim3(opi.nlaunch), dim3(256), 0, s, opi, CP, w->st, w->Xi, w->R, w->Z,
-                               w->P, w->Q, w->p1, w->p2);
+            hipLaunchKernelGGL(k_update, dim3(opi.nlaunch), dim3(256), 0, s, opi, CP, w->st, w->R, w->Z, w->Q,
+                               dinv, w->p1, w->p2);
             hipLaunchKernelGGL(k_reduce, dim3(nsc), dim3(1024), 0, s, op, w->p1, 1, w->p2, 1, w->st,
                                (int)RED_BETA, 0);
-            hipLaunchKernelGGL(k_pupdate, dim3(opi.nlaunch), dim3(256), 0, s, opi, CP, w->st, w->Z, w->P);
+            hipLaunchKernelGGL(k_pupdate, dim3(opi.nlaunch), dim3(256), 0, s, opi, CP, w->st, w->Z, w->P, w->Xi);
         }
     };
     auto group = [&]() {
