@@ -71,10 +71,25 @@ k_gather(int64_t nnz, const int32_t* __restrict__ cptr, const int32_t* __restric
     int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= nnz) return;
     double sk = 0.0, sm = 0.0;
-    for (int32_t c = cptr[k]; c < cptr[k + 1]; ++c) {
-        int32_t idx = cidx[c];
-        sk += Kst[idx];
-        sm += Mst[idx];
+    const int32_t c1 = cptr[k + 1];
+    // four contribution indices, then their values, in flight at a time; the
+    // sums keep the list order
+    for (int32_t c = cptr[k]; c < c1; c += 4) {
+        int32_t idx[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) idx[q] = c + q < c1 ? cidx[c + q] : -1;
+        double kv[4], mv[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            kv[q] = idx[q] >= 0 ? Kst[idx[q]] : 0.0;
+            mv[q] = idx[q] >= 0 ? Mst[idx[q]] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (idx[q] >= 0) {
+                sk += kv[q];
+                sm += mv[q];
+            }
     }
     K[k] = sk;
     Ms[k] = sm;

@@ -90,10 +90,22 @@ k_rhs_gather(int n, int T, const int32_t* __restrict__ iptr, const int32_t* __re
     int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= n) return;
     double2 acc = make_double2(0.0, 0.0);
-    for (int32_t k = iptr[r]; k < iptr[r + 1]; ++k) {
-        int32_t s = islot[k];
-        int32_t t = s / 6, i = s - 6 * t;
-        acc = cadd(acc, Rst[(size_t)i * T + t]);
+    const int32_t k1 = iptr[r + 1];
+    // four incidences, then their entries, in flight at a time; the sum keeps
+    // the list order
+    for (int32_t k = iptr[r]; k < k1; k += 4) {
+        int32_t sl[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) sl[q] = k + q < k1 ? islot[k + q] : -1;
+        double2 v[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int32_t t = sl[q] / 6, i = sl[q] - 6 * t;
+            v[q] = sl[q] >= 0 ? Rst[(size_t)i * T + t] : make_double2(0.0, 0.0);
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (sl[q] >= 0) acc = cadd(acc, v[q]);
     }
     b[(size_t)r * stride] = acc;
 }
