@@ -60,6 +60,8 @@ constexpr int kCheck = 8;       // inner iterations between host checks (one gra
 constexpr int64_t kConsumerMax = 8192;   // partials a vector kernel's block may sum itself
 constexpr int kConsumerTiles = 4;        // tiles per block of the in-consumer vector kernels
 constexpr int kMaxGroups = 8;            // iteration groups between two host checks
+constexpr int kGraphSizes = 4;           // captured graphs hold 1, 2, 4 or 8 groups
+static_assert(kMaxGroups == 1 << (kGraphSizes - 1), "a batch of groups is a sum of graph sizes");
 
 __device__ __forceinline__ float2 f2(float x, float y) { return make_float2(x, y); }
 
@@ -153,6 +155,20 @@ __device__ __forceinline__ void step_beta(ColState& S, double2 rz, double r2) {
     }
 }
 
+// The true residual norm rn of the current iterate is known: the outer
+// convergence test and the next refinement step's inner tolerance.
+__device__ __forceinline__ void res_step(ColState& S, double rn, int first) {
+    S.rnorm64 = rn;
+    if (first) S.bnorm = rn;
+    S.scale = rn;
+    S.outer = S.outer && !(rn <= S.tol_abs) && isfinite(rn);
+    // no need to solve the correction more accurately than the target asks:
+    // a factor 0.3 below rtol |b| / |r64| leaves a safety margin
+    const double need = rn > 0.0 ? 0.3 * S.tol_abs / rn : 1.0;
+    const double it = fmax(S.inner_rtol, fmin(need, 0.5));
+    S.inner_tol2 = it * it;
+}
+
 // The scalar step of one (segment, column) once its sums a, b are known.
 __device__ void apply_red(ColState& S, int mode, int first, double2 a, double2 b) {
     if (mode == RED_INIT) {            // a = r^T z, b.x = |r|^2 of the normalised start
@@ -174,16 +190,7 @@ __device__ void apply_red(ColState& S, int mode, int first, double2 a, double2 b
         S.alpha = (S.bnorm > 0.0 && b.x > 0.0 && isfinite(b.x) && cfinite(a)) ? cscale(a, 1.0 / b.x)
                                                                              : make_double2(0.0, 0.0);
     } else {                           // RED_RES: a.x = |b - A x|^2
-        const double rn = sqrt(a.x);
-        S.rnorm64 = rn;
-        if (first) S.bnorm = rn;
-        S.scale = rn;
-        S.outer = S.outer && !(rn <= S.tol_abs) && isfinite(rn);
-        // no need to solve the correction more accurately than the target asks:
-        // a factor 0.3 below rtol |b| / |r64| leaves a safety margin
-        const double need = rn > 0.0 ? 0.3 * S.tol_abs / rn : 1.0;
-        const double it = fmax(S.inner_rtol, fmin(need, 0.5));
-        S.inner_tol2 = it * it;
+        res_step(S, sqrt(a.x), first);
     }
 }
 
@@ -374,6 +381,8 @@ k_spmm_n(Op op, const ColState* __restrict__ st, const typename V2<T>::t* __rest
         live[u] = u < C && col_live(st, seg * C + u, EPI);
         any = any || live[u];
     }
+    // every column of this segment stopped: nothing reads this tile's partials
+    if (!any) return;
     {
         const int i = tile * kTR + pass * RPB + slot;
         if (any && i < op.nrow_valid) {   // the whole G-lane group shares i and seg
@@ -480,6 +489,8 @@ k_spmm_s(Op op, const ColState* __restrict__ st, const float2* __restrict__ X, f
         any = any || live[u];
         wmu[u] = u < C ? (float)op.wmu[seg * C + u] : 0.f;
     }
+    // every column of this segment stopped: nothing reads this tile's partials
+    if (!any) return;
     if (any) {   // the same for the whole block (one segment)
         float2 ak[CM], am[CM];
 #pragma unroll
@@ -573,6 +584,8 @@ k_spmm_sp(Op op, const ColState* __restrict__ st, const float2* __restrict__ X, 
         any = any || live[u];
         wmu[u] = u < C ? (float)op.wmu[seg * C + u] : 0.f;
     }
+    // every column of this segment stopped: nothing reads this tile's partials
+    if (!any) return;
     if (any) {   // the same for the whole block (one segment)
         float2 ak[CM], am[CM];
 #pragma unroll
@@ -1148,11 +1161,16 @@ __global__ void k_set_live(ColState* st, int nsc) {
     st[k].rho = make_double2(1.0, 0.0);
 }
 
-__global__ void k_set_tol(ColState* st, int nsc, double rtol) {
+// tol_abs = rtol |b|; zero_x: the iterate is zero, so its residual is b
+// itself and the residual step takes |b| without a product
+__global__ void k_set_tol(ColState* st, int nsc, double rtol, int zero_x) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= nsc) return;
-    st[k].tol_abs = rtol * st[k].bnorm;
-    st[k].outer = st[k].bnorm > 0.0 && isfinite(st[k].bnorm);
+    ColState S = st[k];
+    S.tol_abs = rtol * S.bnorm;
+    S.outer = S.bnorm > 0.0 && isfinite(S.bnorm);
+    if (zero_x && S.outer) res_step(S, S.bnorm, 0);
+    st[k] = S;
 }
 
 // Builders of the concatenated (block-diagonal) operator of several meshes.
@@ -1262,13 +1280,16 @@ struct BlockWork {
     Sell cat_sell;
     size_t cat_rows = 0, cat_nnz = 0;
     std::map<std::tuple<int, int64_t, int>, SpmmTuned> tuned;   // (n, nnz, C) -> choices
-    hipGraphExec_t graph = nullptr;
+    // graphs of 1, 2, 4 and 8 iteration groups (captured when first needed)
+    hipGraphExec_t graphs[kGraphSizes] = {};
     hipStream_t graph_stream = nullptr;
-    std::vector<char> graph_sig;   // bytes of every argument baked into the graph
+    std::vector<char> graph_sig;   // bytes of every argument baked into the graphs
     ~BlockWork() { release(); }
     void release_graph() {
-        if (graph) (void)hipGraphExecDestroy(graph);
-        graph = nullptr;
+        for (auto& g : graphs) {
+            if (g) (void)hipGraphExecDestroy(g);
+            g = nullptr;
+        }
         graph_sig.clear();
     }
     void release() {
@@ -1515,6 +1536,13 @@ int tune_spmm(BlockWork* w, const Op& op, int64_t nnz, hipStream_t s, SpmmTuned&
     auto it = w->tuned.find(key);
     if (it != w->tuned.end()) { out = it->second; return PETGEM_OK; }
     auto cands = candidates(op.C, op.sp != nullptr);
+    // P (complex64, rows x C) gets finite values and every column is live
+    // for the timing launches (the solve initialises both afterwards)
+    const int nsc = op.nseg * op.C;
+    hipLaunchKernelGGL(k_fill_f2, dim3(ceil_div((size_t)op.n * op.C, 256)), dim3(256), 0, s,
+                       (size_t)op.n * op.C, w->P);
+    hipLaunchKernelGGL(k_set_live, dim3(ceil_div(nsc, 64)), dim3(64), 0, s, w->st, nsc);
+    static const char* kinds[4] = {"column lanes", "nonzero lanes", "sliced ELLPACK", "pipelined sliced ELLPACK"};
     hipEvent_t e0, e1;
     PG_HIP(hipEventCreate(&e0));
     PG_HIP(hipEventCreate(&e1));
@@ -1532,13 +1560,35 @@ int tune_spmm(BlockWork* w, const Op& op, int64_t nnz, hipStream_t s, SpmmTuned&
         PG_HIP(hipEventElapsedTime(&ms, e0, e1));
         c.ms = ms / 3.f;
         if (verbose) {
-            static const char* kinds[4] = {"column lanes", "nonzero lanes", "sliced ELLPACK",
-                                           "pipelined sliced ELLPACK"};
             fprintf(stderr, "[petgem] SpMM tuning: %s %d x %d: %.1f us\n", kinds[c.kind], c.a, c.b, 1e3 * c.ms);
             fflush(stderr);
         }
         if (c.ms < best.best.ms) best.best = c;
         if (c.kind < 2 && c.ms < best.csr.ms) best.csr = c;
+    }
+    // The double-precision residual of a few columns times the CSR shapes in
+    // double (it reads X64 and B64 as they are and writes R64, all of which
+    // the solve rewrites before use); more columns keep the complex64 order.
+    if (op.C <= 4) {
+        best.csr.ms = 1e30f;
+        for (SpmmChoice c : cands) {
+            if (c.kind >= 2 || spmm_slots(c) > w->p0_slots) continue;
+            const SpmmArgs g{w->X64, w->B64, w->R64, w->p0};
+            spmm_dispatch<double, 2>(c, op, w->st, g, s);   // warm-up
+            PG_HIP(hipEventRecord(e0, s));
+            for (int r = 0; r < 3; ++r) spmm_dispatch<double, 2>(c, op, w->st, g, s);
+            PG_HIP(hipEventRecord(e1, s));
+            PG_HIP(hipEventSynchronize(e1));
+            float ms = 0.f;
+            PG_HIP(hipEventElapsedTime(&ms, e0, e1));
+            c.ms = ms / 3.f;
+            if (verbose) {
+                fprintf(stderr, "[petgem] SpMM tuning: double residual, %s %d x %d: %.1f us\n", kinds[c.kind], c.a,
+                        c.b, 1e3 * c.ms);
+                fflush(stderr);
+            }
+            if (c.ms < best.csr.ms) best.csr = c;
+        }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -1557,11 +1607,6 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
     const int C = op.C, nsc = op.nseg * C, CP = cp_of(C);
     Timer t_all;
     SpmmTuned tu;
-    // P (complex64, rows x C) gets finite values and every column is live
-    // for the tuning launches
-    hipLaunchKernelGGL(k_fill_f2, dim3(ceil_div((size_t)op.n * C, 256)), dim3(256), 0, s,
-                       (size_t)op.n * C, w->P);
-    hipLaunchKernelGGL(k_set_live, dim3(ceil_div(nsc, 64)), dim3(64), 0, s, w->st, nsc);
     PG_TRY(tune_spmm(w, op, nnz, s, tu, o.verbose != 0));
     if (o.spmm_shape != 0) {   // a caller-chosen shape instead of the tuned one
         bool found = false;
@@ -1639,7 +1684,7 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
         return PETGEM_OK;
     };
     PG_TRY(bnorms());
-    hipLaunchKernelGGL(k_set_tol, dim3(ceil_div(nsc, 64)), dim3(64), 0, s, w->st, nsc, o.rtol);
+    hipLaunchKernelGGL(k_set_tol, dim3(ceil_div(nsc, 64)), dim3(64), 0, s, w->st, nsc, o.rtol, (int)!have_x0);
     if (have_x0) {
         // scale every guess by the alpha minimising |b - alpha A x0|
         PG_TRY(residual(0));
@@ -1649,7 +1694,9 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
         hipLaunchKernelGGL(k_scale_cols, dim3(op.ntiles), dim3(256), 0, s, op, CP, w->st, w->X64);
         PG_HIP(hipGetLastError());
     }
-    PG_TRY(residual(0));
+    // with x = 0 the residual is b (k_set_tol took its norm) and the first
+    // refinement step starts from B64 itself
+    if (have_x0) PG_TRY(residual(0));
     PG_TRY(read_state());
     std::vector<int> fallback(nsc, 0);
     if (have_x0) {
@@ -1665,7 +1712,7 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
             hipLaunchKernelGGL(k_init_state, dim3(ceil_div(nsc, 64)), dim3(64), 0, s, w->st, nsc,
                                o.rtol, o.inner_rtol);
             PG_TRY(bnorms());
-            hipLaunchKernelGGL(k_set_tol, dim3(ceil_div(nsc, 64)), dim3(64), 0, s, w->st, nsc, o.rtol);
+            hipLaunchKernelGGL(k_set_tol, dim3(ceil_div(nsc, 64)), dim3(64), 0, s, w->st, nsc, o.rtol, 0);
             PG_TRY(residual(0));
             PG_TRY(read_state());
         }
@@ -1725,8 +1772,9 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
         for (int k = 0; k < kCheck; ++k) iteration();
     };
     const bool use_graph = o.use_graph && !prof;
-    // (re)capture the group graph whenever an argument baked into it changed
-    auto ensure_graph = [&]() -> int {
+    // (re)capture the graph of 2^lg groups; every graph is dropped whenever an
+    // argument baked into them changed
+    auto ensure_graph = [&](int lg) -> int {
         if (!use_graph) return PETGEM_OK;
         std::vector<char> sig;
         auto put = [&](const void* p, size_t nb) {
@@ -1738,21 +1786,21 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
         put(ptrs, sizeof(ptrs));
         int chv[5] = {ch.kind, ch.a, ch.b, (int)in_consumer, opi.tmap ? tgen : 0};
         put(chv, sizeof(chv));
-        if (w->graph != nullptr && w->graph_sig == sig) return PETGEM_OK;
-        w->release_graph();
+        if (w->graph_sig != sig) w->release_graph();
+        if (w->graphs[lg] != nullptr) return PETGEM_OK;
         if (!w->graph_stream) PG_HIP(hipStreamCreateWithFlags(&w->graph_stream, hipStreamNonBlocking));
         hipGraph_t g;
         hipStream_t caller = s;
         s = w->graph_stream;
         PG_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-        group();
+        for (int k = 0; k < (1 << lg); ++k) group();
         hipError_t ce = hipStreamEndCapture(s, &g);
         s = caller;
         if (ce != hipSuccess) {
             set_error(std::string("graph capture: ") + hipGetErrorString(ce));
             return PETGEM_HIP_ERROR;
         }
-        hipError_t ie = hipGraphInstantiate(&w->graph, g, nullptr, nullptr, 0);
+        hipError_t ie = hipGraphInstantiate(&w->graphs[lg], g, nullptr, nullptr, 0);
         (void)hipGraphDestroy(g);
         if (ie != hipSuccess) {
             set_error(std::string("graph instantiate: ") + hipGetErrorString(ie));
@@ -1794,7 +1842,8 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
             break;
         }
         // inner complex64 COCG on A d = r64 / |r64|
-        hipLaunchKernelGGL(k_inner_init, dim3(op.ntiles), dim3(256), 0, s, op, CP, w->R64, w->st, dinv, w->Xi,
+        const double2* r64 = steps == 0 && !have_x0 ? w->B64 : w->R64;
+        hipLaunchKernelGGL(k_inner_init, dim3(op.ntiles), dim3(256), 0, s, op, CP, r64, w->st, dinv, w->Xi,
                            w->R, w->Z, w->P, w->p1, w->p2);
         hipLaunchKernelGGL(k_reduce, dim3(nsc), dim3(1024), 0, s, op, w->p1, 1, w->p2, 1, w->st,
                            (int)RED_INIT, 0);
@@ -1813,14 +1862,22 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
         const bool overlap = use_graph && !(seg_tile_h && op.nseg > 1);
         ColState* snap[2] = {w->st_h, w->st_h2};
         int cur = 0;
+        // A single system launches n groups as few graphs (of 1, 2, 4 and 8
+        // groups): the kernels inside one graph follow each other without the
+        // gap that separates two graph launches. An uneven batch recaptures
+        // its graph after each rebuild of its tile list, so it keeps to the
+        // one-group graph, whose capture is cheapest.
+        const int lg_max = overlap ? kGraphSizes - 1 : 0;
         auto launch_batch = [&](int n, int slot) -> int {
-            PG_TRY(ensure_graph());
-            for (int g = 0; g < n; ++g) {
-                if (use_graph) {
-                    PG_HIP(hipGraphLaunch(w->graph, s));
-                } else {
-                    group();
-                }
+            if (use_graph) {
+                for (int lg = lg_max, left = n; lg >= 0; --lg)
+                    while (left >= (1 << lg)) {
+                        PG_TRY(ensure_graph(lg));
+                        PG_HIP(hipGraphLaunch(w->graphs[lg], s));
+                        left -= 1 << lg;
+                    }
+            } else {
+                for (int g = 0; g < n; ++g) group();
             }
             inner += kCheck * n;
             PG_HIP(hipMemcpyAsync(snap[slot], w->st, sizeof(ColState) * nsc, hipMemcpyDeviceToHost, s));
