@@ -58,6 +58,8 @@ HBM_PEAK_GBS = 8000.0
 # bytes copied, WRITE_SIZE 1.0); profiles/spmm_cfg2_traffic.md holds the
 # figures and commands. A kernel changed since then reads null.
 MEASURED_TRAFFIC = {
+    "k_spmm_spb<4, 4> complex64 pipelined sliced ELLPACK with beta partials (K, M_sigma)":
+        (48593.5 * 2.0 + 3112.2) * 1024,
     "k_spmm_sp<1, 4> complex64 pipelined sliced ELLPACK (K, M_sigma)": (48342.8 * 2.0 + 3219.3) * 1024,
     "k_spmm_s<1, 4> complex64 sliced ELLPACK (K, M_sigma)": (47676.3 * 2.0 + 3219.2) * 1024,
     "k_spmm_s<1, 8> complex64 sliced ELLPACK (K, M_sigma)": (49890.8 * 2.0 + 3367.3) * 1024,
@@ -77,11 +79,12 @@ def spmv_bytes_fp64(n: int, nnz: int) -> int:
     return 20 * nnz + 36 * n
 
 
-def spmm_bytes_fp32(n: int, nnz: int, cols: int) -> int:
+def spmm_bytes_fp32(n: int, nnz: int, cols: int, shape: int = 0) -> int:
     """Algorithmic bytes of one complex64 SpMM of the COCG over real K and
     M_sigma: K, M 4 + 4 and column 4 per nonzero; row pointer 4 per row;
-    x read 8, y written 8 per row and column."""
-    return 12 * nnz + n * (4 + 16 * cols)
+    x read 8, y written 8 per row and column. The single-column product of
+    the fused step (shape kind 4) also reads r and D^-1, 8 + 8 per row."""
+    return 12 * nnz + n * (4 + 16 * cols) + (16 * n if shape // 10000 == 4 else 0)
 
 
 def rx_error(E, ref):
@@ -130,6 +133,8 @@ def kernel_name(form, shape):
     if form == "plain":
         return f"k_spmv<{shape}, false> complex128 CSR (A D^-1)"
     kind, a, b = shape // 10000, (shape // 100) % 100, shape % 100
+    if kind == 4:
+        return f"k_spmm_spb<{b}, 4> complex64 pipelined sliced ELLPACK with beta partials (K, M_sigma)"
     if kind == 3:
         return f"k_spmm_sp<{a}, {b}> complex64 pipelined sliced ELLPACK (K, M_sigma)"
     if kind == 2:
@@ -192,7 +197,8 @@ def bench_cfg2(args, petgem, synth, torch):
             pst = [o[0] for o in pouts]
             n_launch = sum(s["spmv_launches"] for s in pst)
             avg_ms = sum(s["spmv_ms"] for s in pst) / n_launch if n_launch else float("nan")
-        nbytes = spmv_bytes_fp64(S.n_dof, S.nnz) if name == "plain" else spmm_bytes_fp32(S.n_dof, S.nnz, 1)
+        nbytes = (spmv_bytes_fp64(S.n_dof, S.nnz) if name == "plain"
+                  else spmm_bytes_fp32(S.n_dof, S.nnz, 1, st[-1]["spmv_shape"]))
         res[name] = {
             "solves_per_s": args.steps / dt, "ms_per_step": dt / args.steps * 1e3,
             "iters": st[-1]["iters"], "ir_steps": st[-1]["ir_steps"],

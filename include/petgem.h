@@ -119,9 +119,12 @@ typedef struct {
                                columns), 2 = sliced ELLPACK (a columns, b
                                slice columns in flight), 3 = sliced ELLPACK
                                with the next b slice columns' indices and
-                               values loaded during the current b gathers;
-                               GMRES: the lanes per row of the complex128
-                               CSR SpMV                                         */
+                               values loaded during the current b gathers,
+                               4 = shape 3 for one column of one mesh, run as
+                               the fused step (the product also sums
+                               q^T D^-1 r and q^T D^-1 q, and one vector
+                               kernel applies alpha and beta); GMRES: the
+                               lanes per row of the complex128 CSR SpMV         */
     double  b_norm;         /* |b|_2 of the source's right-hand side            */
 } petgem_stats;
 

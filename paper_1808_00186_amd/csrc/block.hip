@@ -57,6 +57,7 @@ namespace {
 
 constexpr int kTR = 256;        // rows per tile
 constexpr int kCheck = 8;       // inner iterations between host checks (one graph)
+static_assert(kCheck % 2 == 0, "the fused step's state slots alternate within a group");
 constexpr int64_t kConsumerMax = 8192;   // partials a vector kernel's block may sum itself
 constexpr int kConsumerTiles = 4;        // tiles per block of the in-consumer vector kernels
 constexpr int kMaxGroups = 8;            // iteration groups between two host checks
@@ -660,6 +661,104 @@ k_spmm_sp(Op op, const ColState* __restrict__ st, const float2* __restrict__ X, 
     }
 }
 
+__device__ __forceinline__ float2 cmulf(float2 a, float2 b) {
+    return f2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// Single-column form of k_spmm_sp for the fused COCG step: besides y = A x
+// and p^T q it forms q^T D^-1 r and q^T D^-1 q from each row's r and D^-1
+// (three partials per block, in that order). They give the next
+// rho = (r - alpha q)^T D^-1 (r - alpha q) before r itself is updated. A
+// block of W waves takes W consecutive 64-row slices (8 and 16 waves per
+// block, i.e. fewer partials for the step to sum, measured no faster than 4).
+template <int U, int W>
+__global__ void __launch_bounds__(64 * W)
+k_spmm_spb(Op op, const ColState* __restrict__ st, const float2* __restrict__ X, float2* __restrict__ Y,
+           const float2* __restrict__ R, const float2* __restrict__ dinv, double2* __restrict__ partial) {
+    __shared__ double2 red[W][3];
+    const int blk = xcd_block(blockIdx.x, gridDim.x);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int sl = blk * W + wave;
+    const bool slice = sl < op.ntiles * 4;   // the last block may reach past the last slice
+    const int i = sl * 64 + lane;
+    if (!st[0].active) return;   // stopped: nothing reads the partials
+    const float wmu = (float)op.wmu[0];
+    const bool row = slice && i < op.nrow_valid;
+    // this row's r and D^-1 do not depend on the product: loaded first
+    const float2 rv = row ? R[i] : f2(0.f, 0.f);
+    const float2 dv = row ? dinv[i] : f2(0.f, 0.f);
+    float2 ak = f2(0.f, 0.f), am = f2(0.f, 0.f);
+    const int base = slice ? op.sp[sl] : 0, wd = slice ? op.sw[sl] : 0;
+    int32_t cj[U];
+    float kv[U], mv[U];
+    auto fetch = [&](int k, int32_t* c, float* kk, float* mm) {
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+            if (k + q < wd) {
+                const int e = base + (k + q) * 64 + lane;
+                c[q] = op.scol[e];
+                kk[q] = op.sK[e];
+                mm[q] = op.sM[e];
+            } else {
+                c[q] = row ? i : 0;
+                kk[q] = 0.f;
+                mm[q] = 0.f;
+            }
+        }
+    };
+    fetch(0, cj, kv, mv);
+    for (int k = 0; k < wd; k += U) {
+        float2 xv[U];
+#pragma unroll
+        for (int q = 0; q < U; ++q) xv[q] = X[cj[q]];
+        int32_t cn[U];
+        float kn[U], mn[U];
+        if (k + U < wd) fetch(k + U, cn, kn, mn);
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+            ak.x += kv[q] * xv[q].x; ak.y += kv[q] * xv[q].y;
+            am.x += mv[q] * xv[q].x; am.y += mv[q] * xv[q].y;
+        }
+        if (k + U < wd) {
+#pragma unroll
+            for (int q = 0; q < U; ++q) { cj[q] = cn[q]; kv[q] = kn[q]; mv[q] = mn[q]; }
+        }
+    }
+    double2 pq = make_double2(0.0, 0.0), qzr = pq, qzq = pq;
+    if (row) {
+        float2 y;
+        y.x = ak.x + wmu * am.y;   // K x - i wmu M x
+        y.y = ak.y - wmu * am.x;
+        const float2 xo = X[i];
+        const float2 zr = cmulf(rv, dv), zq = cmulf(y, dv);
+        pq.x = (double)xo.x * y.x - (double)xo.y * y.y;
+        pq.y = (double)xo.x * y.y + (double)xo.y * y.x;
+        qzr.x = (double)y.x * zr.x - (double)y.y * zr.y;
+        qzr.y = (double)y.x * zr.y + (double)y.y * zr.x;
+        qzq.x = (double)y.x * zq.x - (double)y.y * zq.y;
+        qzq.y = (double)y.x * zq.y + (double)y.y * zq.x;
+        Y[i] = y;
+    }
+    const double s0 = wave_sum(pq.x), s1 = wave_sum(pq.y), s2 = wave_sum(qzr.x), s3 = wave_sum(qzr.y),
+                 s4 = wave_sum(qzq.x), s5 = wave_sum(qzq.y);
+    if (lane == 0) {
+        red[wave][0] = make_double2(s0, s1);
+        red[wave][1] = make_double2(s2, s3);
+        red[wave][2] = make_double2(s4, s5);
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        const int u = threadIdx.x;
+        double2 t = red[0][u];
+#pragma unroll
+        for (int k = 1; k < W; ++k) t = cadd(t, red[k][u]);
+        partial[(size_t)blk * 3 + u] = t;
+    }
+}
+
+// waves per block of the fused step's product
+constexpr int kSpbWaves = 4;
+
 // Fixed-shape sums over the row slots of a CP-lane row layout (thread t holds
 // column t % CP of slot t / CP); the results for column c end in la[c], lb[c].
 // Below 64 lanes per row the slots inside a wave are folded by shuffles.
@@ -717,10 +816,6 @@ __device__ __forceinline__ float2 jacobi_z(float2 r, double kd, double md, doubl
     const double inv = 1.0 / (dr * dr + di * di);
     return f2((float)(((double)r.x * dr + (double)r.y * di) * inv),
               (float)(((double)r.y * dr - (double)r.x * di) * inv));
-}
-
-__device__ __forceinline__ float2 cmulf(float2 a, float2 b) {
-    return f2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
 // D^-1 = 1 / (Kd - i wmu Md) in complex64 for single-column solves (one
@@ -1001,6 +1096,169 @@ k_pupdate_p(Op op, int CP, int tpb, const ColState* __restrict__ s0, ColState* _
             Xi[o] = f2(x[u].x + ax * p[u].x - ay * p[u].y, x[u].y + ax * p[u].y + ay * p[u].x);
             if (more) P[o] = f2(z[u].x + bx * p[u].x - by * p[u].y, z[u].y + bx * p[u].y + by * p[u].x);
         }
+    }
+}
+
+// ------------------------------------------- fused single-column step
+// One mesh, one column, D^-1 precomputed: after the product q = A p a single
+// vector kernel takes the whole COCG step. The next rho is known before r is
+// updated, by expanding
+//   (r - alpha q)^T D^-1 (r - alpha q) = rho - 2 alpha q^T D^-1 r + alpha^2 q^T D^-1 q
+// with the product's partials, so beta is known too: r -= alpha q,
+// z = D^-1 r, x += alpha p and p = z + beta p go in one pass over the rows
+// (64 B per row instead of 80 B in two kernels). The exact r^T z and |r|^2
+// of the new r are summed at the next step, which tests convergence on them
+// and takes that r^T z for its alpha, so the expansion only ever sets beta.
+// The iteration is two kernels: the product and this step.
+//
+// The step (state slot sin -> sout): every block sums the product's nps
+// partial triples and the previous step's npg partial pairs in a fixed order;
+// one thread then takes the scalar step (block 0 stores the state) and
+// hands alpha and beta to the block; then, over tpb tiles, the row updates,
+// with the partials of the new r^T z and |r|^2 (one slot per block) into go,
+// ro, which must not be pg, pr: other blocks may still be reading those.
+// kin == 0 (just started): rho and |r|^2 are the state's own; otherwise the
+// convergence test runs first on the previous step's sums. (With the scalar
+// step taken by every thread on its own copy of the state, the kernel took
+// 19 us instead of 11.)
+__global__ void __launch_bounds__(256)
+k_step1(Op op, int tpb, const ColState* __restrict__ sin, ColState* __restrict__ sout,
+        const double2* __restrict__ ps, int nps, const double2* __restrict__ pg, const double2* __restrict__ pr,
+        int npg, float2* __restrict__ R, const float2* __restrict__ Q,
+        const float2* __restrict__ dinv, float2* __restrict__ P, float2* __restrict__ Xi, double2* __restrict__ go,
+        double2* __restrict__ ro) {
+    __shared__ double2 ra[256], rb[256];
+    __shared__ double2 scal[3];
+    __shared__ double2 tot[5];
+    const int i0 = blockIdx.x * tpb * kTR, i1 = min(i0 + tpb * kTR, op.nrow_valid);
+    // the first four rows of every vector are loaded ahead of the sums
+    float2 q[4], r[4], dv[4], x[4], p[4];
+    auto load4 = [&](int ib) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int i = max(min(ib + u * 256, i1 - 1), 0);   // in range; the duplicates are not stored
+            q[u] = Q[i]; r[u] = R[i]; dv[u] = dinv[i]; x[u] = Xi[i]; p[u] = P[i];
+        }
+    };
+    load4(i0 + threadIdx.x);
+    // fixed-order sums of the product's partials (three per tile) and of the
+    // previous step's (two per block): strided per thread, then the waves
+    {
+        double2 v[5];
+#pragma unroll
+        for (int j = 0; j < 5; ++j) v[j] = make_double2(0.0, 0.0);
+        for (int e0 = threadIdx.x; e0 < nps; e0 += 4 * 256) {
+            double2 a[4][3];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int e = e0 + u * 256;
+#pragma unroll
+                for (int j = 0; j < 3; ++j) a[u][j] = e < nps ? ps[(size_t)e * 3 + j] : make_double2(0.0, 0.0);
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int j = 0; j < 3; ++j) v[j] = cadd(v[j], a[u][j]);
+        }
+        for (int e0 = threadIdx.x; e0 < npg; e0 += 4 * 256) {
+            double2 a[4][2];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int e = e0 + u * 256;
+                a[u][0] = e < npg ? pg[e] : make_double2(0.0, 0.0);
+                a[u][1] = e < npg ? pr[e] : make_double2(0.0, 0.0);
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                v[3] = cadd(v[3], a[u][0]);
+                v[4] = cadd(v[4], a[u][1]);
+            }
+        }
+        const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+        for (int j = 0; j < 5; ++j) {
+            const double sx = wave_sum(v[j].x), sy = wave_sum(v[j].y);
+            if (lane == 0) ra[wave * 5 + j] = make_double2(sx, sy);
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < 5) {
+        const int j = threadIdx.x;
+        tot[j] = cadd(cadd(ra[j], ra[5 + j]), cadd(ra[10 + j], ra[15 + j]));
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        ColState S = sin[0];
+        if (S.active && S.kin > 0) {   // the r left by the previous step
+            const double2 rz = tot[3];
+            const double r2 = tot[4].x;
+            S.rn2 = r2;
+            if (!isfinite(r2) || !cfinite(rz)) {
+                S.active = 0;
+                S.breakdown = 1;
+            } else if (r2 <= S.inner_tol2) {
+                S.active = 0;
+            } else if (czero(rz)) {
+                S.active = 0;
+                S.breakdown = 1;
+            } else {
+                S.rho = rz;
+            }
+        }
+        if (S.active) {
+            const double2 pq = tot[0];
+            if (!cfinite(pq) || czero(pq)) {
+                S.active = 0;
+                S.breakdown = 1;
+            } else {
+                const double2 al = cdiv(S.rho, pq);
+                // rho - 2 alpha q^T D^-1 r + alpha^2 q^T D^-1 q
+                const double2 next =
+                    cadd(cadd(S.rho, cscale(cmul(al, tot[1]), -2.0)), cmul(cmul(al, al), tot[2]));
+                const double2 be = cdiv(next, S.rho);
+                if (!cfinite(be)) {
+                    S.active = 0;
+                    S.breakdown = 1;
+                } else {
+                    S.alpha = al;
+                    S.beta = be;
+                    S.iters += 1;
+                    S.kin += 1;
+                }
+            }
+        }
+        if (blockIdx.x == 0) sout[0] = S;
+        scal[0] = S.alpha;
+        scal[1] = S.beta;
+        scal[2] = make_double2(S.active ? 1.0 : 0.0, 0.0);
+    }
+    __syncthreads();
+    if (scal[2].x == 0.0) return;   // the same in every thread
+    const double2 alpha = scal[0], beta = scal[1];
+    const float ax = (float)alpha.x, ay = (float)alpha.y, bx = (float)beta.x, by = (float)beta.y;
+    double2 a = make_double2(0.0, 0.0), b = make_double2(0.0, 0.0);
+    for (int ib = i0 + (int)threadIdx.x; ib < i1; ib += 4 * 256) {
+        if (ib != i0 + (int)threadIdx.x) load4(ib);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int i = ib + u * 256;
+            if (i >= i1) break;
+            float2 rr = r[u];
+            rr.x -= ax * q[u].x - ay * q[u].y;
+            rr.y -= ax * q[u].y + ay * q[u].x;
+            const float2 z = cmulf(rr, dv[u]);
+            R[i] = rr;
+            Xi[i] = f2(x[u].x + ax * p[u].x - ay * p[u].y, x[u].y + ax * p[u].y + ay * p[u].x);
+            P[i] = f2(z.x + bx * p[u].x - by * p[u].y, z.y + bx * p[u].y + by * p[u].x);
+            a.x += (double)rr.x * z.x - (double)rr.y * z.y;
+            a.y += (double)rr.x * z.y + (double)rr.y * z.x;
+            b.x += (double)rr.x * rr.x + (double)rr.y * rr.y;
+        }
+    }
+    cp_sum2(a, b, 1, ra, rb);
+    if (threadIdx.x == 0) {
+        go[blockIdx.x] = ra[0];
+        ro[blockIdx.x] = rb[0];
     }
 }
 
@@ -1388,6 +1646,14 @@ void launch_timed(K kernel, dim3 grid, hipStream_t s, hipEvent_t e0, hipEvent_t 
         hipLaunchKernelGGL(kernel, grid, dim3(256), 0, s, args...);
 }
 
+template <typename K, typename... Args>
+void launch_timed_b(K kernel, dim3 grid, dim3 block, hipStream_t s, hipEvent_t e0, hipEvent_t e1, Args... args) {
+    if (e0)
+        hipExtLaunchKernelGGL(kernel, grid, block, 0, s, e0, e1, 0, args...);
+    else
+        hipLaunchKernelGGL(kernel, grid, block, 0, s, args...);
+}
+
 template <typename T, int A, int B, int EPI, bool COLS>
 void spmm_thunk(Op op, const ColState* st, const SpmmArgs& g, hipStream_t s) {
     using T2 = typename V2<T>::t;
@@ -1502,8 +1768,11 @@ int ensure_work(BlockWork*& w, size_t rows, int C, int nsc, int ntiles) {
     // columns), one otherwise
     w->p0_slots = C <= 4 ? 16 : 1;
     PG_TRY(dalloc(&w->p0, (size_t)ntiles * C * w->p0_slots));
-    PG_TRY(dalloc(&w->p1, (size_t)ntiles * C));
-    PG_TRY(dalloc(&w->p2, (size_t)ntiles * C));
+    // p1, p2: per-tile or per-block partials; the fused single-column step
+    // keeps two halves of ceil(ntiles / kConsumerTiles) blocks each
+    const size_t np12 = std::max((size_t)ntiles * C, 2 * (size_t)ceil_div(ntiles, kConsumerTiles));
+    PG_TRY(dalloc(&w->p1, np12));
+    PG_TRY(dalloc(&w->p2, np12));
 
     PG_TRY(dalloc(&w->st, (size_t)nsc));
     PG_TRY(dalloc(&w->st2, (size_t)nsc));
@@ -1650,6 +1919,10 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
         dinv = w->Dinv;
     }
     const int nbu = ceil_div(op.ntiles, kConsumerTiles);   // blocks of the two vector kernels
+    // One column with D^-1 and the pipelined sliced-ELLPACK product: the fused
+    // step (the product with its two extra partials, then one vector kernel).
+    const bool fused = dinv != nullptr && ch.kind == 3 && ch.a == 1 && (ch.b == 4 || ch.b == 8);
+    const int nspb = ceil_div((int64_t)op.ntiles * 4, kSpbWaves);   // blocks (and partials) of its product
     hipLaunchKernelGGL(k_init_state, dim3(ceil_div(nsc, 64)), dim3(64), 0, s, w->st, nsc, o.rtol,
                        o.inner_rtol);
     const bool prof = o.profile != 0;
@@ -1751,7 +2024,32 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
         opi.tmap = nullptr;
         opi.nlaunch = op.ntiles;
     };
-    auto iteration = [&]() {
+    // iteration k of a group: the fused step alternates its two state slots
+    // with the parity of k (a group has an even count, so every group starts
+    // and ends with the state in st)
+    auto iteration = [&](int k) {
+        if (fused) {
+            const bool odd = (k & 1) != 0;
+            ColState* sa = odd ? w->st2 : w->st;   // read by the product and the step
+            ColState* sb = odd ? w->st : w->st2;   // written by the step
+            const SpmmArgs g = ev_pair(SpmmArgs{w->P, nullptr, w->Q, w->p0});
+            if (ch.b == 4)
+                launch_timed_b(k_spmm_spb<4, kSpbWaves>, dim3(nspb), dim3(64 * kSpbWaves), s, g.e0, g.e1, opi,
+                               (const ColState*)sa, (const float2*)w->P, w->Q, (const float2*)w->R, dinv, w->p0);
+            else
+                launch_timed_b(k_spmm_spb<8, kSpbWaves>, dim3(nspb), dim3(64 * kSpbWaves), s, g.e0, g.e1, opi,
+                               (const ColState*)sa, (const float2*)w->P, w->Q, (const float2*)w->R, dinv, w->p0);
+            // the step reads the previous step's partials from one half of p1,
+            // p2 and writes its own to the other (its blocks run concurrently)
+            const double2* gin = odd ? w->p1 + nbu : w->p1;
+            const double2* rin = odd ? w->p2 + nbu : w->p2;
+            double2* gout = odd ? w->p1 : w->p1 + nbu;
+            double2* rout = odd ? w->p2 : w->p2 + nbu;
+            hipLaunchKernelGGL(k_step1, dim3(nbu), dim3(256), 0, s, op, kConsumerTiles, (const ColState*)sa, sb,
+                               (const double2*)w->p0, nspb, gin, rin, nbu, w->R, (const float2*)w->Q, dinv,
+                               w->P, w->Xi, gout, rout);
+            return;
+        }
         spmm_dispatch<float, 1>(ch, opi, w->st, ev_pair(SpmmArgs{w->P, nullptr, w->Q, w->p0}), s);
         if (in_consumer) {
             hipLaunchKernelGGL(k_update_p, dim3(nbu), dim3(256), 0, s, op, CP, kConsumerTiles, w->st, w->st2,
@@ -1769,7 +2067,7 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
         }
     };
     auto group = [&]() {
-        for (int k = 0; k < kCheck; ++k) iteration();
+        for (int k = 0; k < kCheck; ++k) iteration(k);
     };
     const bool use_graph = o.use_graph && !prof;
     // (re)capture the graph of 2^lg groups; every graph is dropped whenever an
@@ -1784,7 +2082,7 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
         put(&opi, sizeof(opi));
         const void* ptrs[11] = {w->Xi, w->R, w->Z, w->P, w->Q, w->p0, w->p1, w->p2, w->st, w->st2, dinv};
         put(ptrs, sizeof(ptrs));
-        int chv[5] = {ch.kind, ch.a, ch.b, (int)in_consumer, opi.tmap ? tgen : 0};
+        int chv[6] = {ch.kind, ch.a, ch.b, (int)in_consumer, opi.tmap ? tgen : 0, (int)fused};
         put(chv, sizeof(chv));
         if (w->graph_sig != sig) w->release_graph();
         if (w->graphs[lg] != nullptr) return PETGEM_OK;
@@ -1972,7 +2270,7 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
         st->t_solve_ms = t_solve;
         st->spmv_ms = spmv_ms;
         st->spmv_launches = spmv_n;
-        st->spmv_shape = 10000 * ch.kind + 100 * ch.a + ch.b;
+        st->spmv_shape = 10000 * (fused ? 4 : ch.kind) + 100 * ch.a + ch.b;
         st->status = S.outer ? (std::isfinite(S.rnorm64) ? PETGEM_NOT_CONVERGED : PETGEM_NONFINITE) : PETGEM_OK;
         if (st->status != PETGEM_OK && status == PETGEM_OK) status = st->status;
     }

@@ -176,14 +176,16 @@ def test_cfg1_solution_bitwise_reproducible(torch_cuda, pg):
     assert np.array_equal(x1, x2) and np.array_equal(x1, x3)
 
 
-def test_mixed_solution_bitwise_reproducible(torch_cuda, pg):
+@pytest.mark.parametrize("shape", [0, 20104, 30104])
+def test_mixed_solution_bitwise_reproducible(torch_cuda, pg, shape):
     """Mixed COCG: graph replay with the overlapped host checks and the
     synchronous loop without graphs run the same iterations (convergence is
-    decided on the device), so the solutions agree bitwise."""
+    decided on the device), so the solutions agree bitwise. Shape 0 is the
+    tuned one, 20104 the two-vector-kernel step, 30104 the fused step."""
     m = synth.config1()
     _case(m)
     S = pg.System.from_model(m)
-    kw = dict(method=pg.COCG, precision=pg.MIXED)
+    kw = dict(method=pg.COCG, precision=pg.MIXED, spmm_shape=shape)
     sol1, st1, _ = S.solve(m.sources, pg.default_opts(**kw))
     x1 = sol1.x().cpu().numpy()
     sol2, st2, _ = S.solve(m.sources, pg.default_opts(**kw), solution=sol1)
@@ -192,6 +194,9 @@ def test_mixed_solution_bitwise_reproducible(torch_cuda, pg):
     x3 = sol3.x().cpu().numpy()
     assert st1[0]["iters"] == st2[0]["iters"] == st3[0]["iters"]
     assert np.array_equal(x1, x2) and np.array_equal(x1, x3)
+    if shape:
+        assert st1[0]["spmv_shape"] == (40104 if shape == 30104 else shape)
+    assert st1[0]["rel_residual"] <= 1e-8
 
 
 def test_initial_guess_and_fallback(torch_cuda, pg):
