@@ -60,6 +60,7 @@ constexpr int kCheck = 8;       // inner iterations between host checks (one gra
 static_assert(kCheck % 2 == 0, "the fused step's state slots alternate within a group");
 constexpr int64_t kConsumerMax = 8192;   // partials a vector kernel's block may sum itself
 constexpr int kConsumerTiles = 4;        // tiles per block of the in-consumer vector kernels
+constexpr int kStepTiles = 8;   // tiles per block of the fused single-column step (2, 4, 16: 12, 2.5, 3.5 % slower)
 constexpr int kMaxGroups = 8;            // iteration groups between two host checks
 constexpr int kGraphSizes = 4;           // captured graphs hold 1, 2, 4 or 8 groups
 static_assert(kMaxGroups == 1 << (kGraphSizes - 1), "a batch of groups is a sum of graph sizes");
@@ -1077,15 +1078,27 @@ k_pupdate_p(Op op, int CP, int tpb, const ColState* __restrict__ s0, ColState* _
     };
     load4(i0 + slot);
     cols_sum2(pg, pr, npu, C, CP, ra, rb);
+    // one thread per column takes the beta step and hands the scalars to the
+    // block through LDS
+    __shared__ double2 sab[256][2];
+    __shared__ int sflag[256];
+    if (slot == 0 && c < C) {
+        ColState S = s0[c];
+        const bool stepped = S.active;   // this iteration's alpha was applied to r
+        if (S.active) step_beta(S, ra[c], rb[c].x);
+        if (blockIdx.x == 0) s1[c] = S;
+        sab[c][0] = S.alpha;
+        sab[c][1] = S.beta;
+        sflag[c] = (stepped ? 1 : 0) | (S.active ? 2 : 0);
+    }
+    __syncthreads();
     if (c >= C) return;
-    ColState S = s0[c];
-    const bool stepped = S.active;   // this iteration's alpha was applied to r
-    if (S.active) step_beta(S, ra[c], rb[c].x);
-    if (blockIdx.x == 0 && slot == 0) s1[c] = S;
-    if (!stepped) return;
-    const bool more = S.active;
-    const float ax = (float)S.alpha.x, ay = (float)S.alpha.y;
-    const float bx = (float)S.beta.x, by = (float)S.beta.y;
+    const int flag = sflag[c];
+    if (!(flag & 1)) return;
+    const bool more = (flag & 2) != 0;
+    const double2 al = sab[c][0], be = sab[c][1];
+    const float ax = (float)al.x, ay = (float)al.y;
+    const float bx = (float)be.x, by = (float)be.y;
     for (int ib = i0 + slot; ib < i1; ib += 4 * RPB) {
         if (ib != i0 + slot) load4(ib);
 #pragma unroll
@@ -1769,8 +1782,8 @@ int ensure_work(BlockWork*& w, size_t rows, int C, int nsc, int ntiles) {
     w->p0_slots = C <= 4 ? 16 : 1;
     PG_TRY(dalloc(&w->p0, (size_t)ntiles * C * w->p0_slots));
     // p1, p2: per-tile or per-block partials; the fused single-column step
-    // keeps two halves of ceil(ntiles / kConsumerTiles) blocks each
-    const size_t np12 = std::max((size_t)ntiles * C, 2 * (size_t)ceil_div(ntiles, kConsumerTiles));
+    // keeps two halves of ceil(ntiles / kStepTiles) blocks each
+    const size_t np12 = std::max((size_t)ntiles * C, 2 * (size_t)ceil_div(ntiles, kStepTiles));
     PG_TRY(dalloc(&w->p1, np12));
     PG_TRY(dalloc(&w->p2, np12));
 
@@ -1923,6 +1936,7 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
     // step (the product with its two extra partials, then one vector kernel).
     const bool fused = dinv != nullptr && ch.kind == 3 && ch.a == 1 && (ch.b == 4 || ch.b == 8);
     const int nspb = ceil_div((int64_t)op.ntiles * 4, kSpbWaves);   // blocks (and partials) of its product
+    const int nst = ceil_div(op.ntiles, kStepTiles);                // blocks of the step
     hipLaunchKernelGGL(k_init_state, dim3(ceil_div(nsc, 64)), dim3(64), 0, s, w->st, nsc, o.rtol,
                        o.inner_rtol);
     const bool prof = o.profile != 0;
@@ -2041,12 +2055,12 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
                                (const ColState*)sa, (const float2*)w->P, w->Q, (const float2*)w->R, dinv, w->p0);
             // the step reads the previous step's partials from one half of p1,
             // p2 and writes its own to the other (its blocks run concurrently)
-            const double2* gin = odd ? w->p1 + nbu : w->p1;
-            const double2* rin = odd ? w->p2 + nbu : w->p2;
-            double2* gout = odd ? w->p1 : w->p1 + nbu;
-            double2* rout = odd ? w->p2 : w->p2 + nbu;
-            hipLaunchKernelGGL(k_step1, dim3(nbu), dim3(256), 0, s, op, kConsumerTiles, (const ColState*)sa, sb,
-                               (const double2*)w->p0, nspb, gin, rin, nbu, w->R, (const float2*)w->Q, dinv,
+            const double2* gin = odd ? w->p1 + nst : w->p1;
+            const double2* rin = odd ? w->p2 + nst : w->p2;
+            double2* gout = odd ? w->p1 : w->p1 + nst;
+            double2* rout = odd ? w->p2 : w->p2 + nst;
+            hipLaunchKernelGGL(k_step1, dim3(nst), dim3(256), 0, s, op, kStepTiles, (const ColState*)sa, sb,
+                               (const double2*)w->p0, nspb, gin, rin, nst, w->R, (const float2*)w->Q, dinv,
                                w->P, w->Xi, gout, rout);
             return;
         }
