@@ -106,9 +106,11 @@ struct Op {
     const double* wmu;     // [nseg][C] w mu0
     int nrow_valid;        // rows with a matrix row (rp[i] defined for i < nrow_valid)
     // sliced-ELLPACK copy of the complex64 operator (null when absent); its
-    // 64-row slices tile the kTR-row tiles exactly
+    // 64-row slices tile the kTR-row tiles exactly, with the rows of a tile
+    // reordered by length (srow: the matrix row of each slice lane)
     const int32_t* sp;
     const int32_t* sw;
+    const int32_t* srow;
     const int32_t* scol;
     const float* sK;
     const float* sM;
@@ -478,7 +480,7 @@ k_spmm_s(Op op, const ColState* __restrict__ st, const float2* __restrict__ X, f
     const int tile = tile_of(op, xcd_block(blockIdx.x, gridDim.x));
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int sl = tile * 4 + wave;
-    const int i = sl * 64 + lane;
+    const int i = op.srow[sl * 64 + lane];
     const int C = op.C;
     const int seg = op.tile_seg ? op.tile_seg[tile] : 0;
     double2 pacc[CM];
@@ -573,7 +575,7 @@ k_spmm_sp(Op op, const ColState* __restrict__ st, const float2* __restrict__ X, 
     const int tile = tile_of(op, xcd_block(blockIdx.x, gridDim.x));
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int sl = tile * 4 + wave;
-    const int i = sl * 64 + lane;
+    const int i = op.srow[sl * 64 + lane];
     const int C = op.C;
     const int seg = op.tile_seg ? op.tile_seg[tile] : 0;
     double2 pacc[CM];
@@ -681,7 +683,7 @@ k_spmm_spb(Op op, const ColState* __restrict__ st, const float2* __restrict__ X,
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int sl = blk * W + wave;
     const bool slice = sl < op.ntiles * 4;   // the last block may reach past the last slice
-    const int i = sl * 64 + lane;
+    const int i = slice ? op.srow[sl * 64 + lane] : op.n;
     if (!st[0].active) return;   // stopped: nothing reads the partials
     const float wmu = (float)op.wmu[0];
     const bool row = slice && i < op.nrow_valid;
@@ -1471,15 +1473,30 @@ __global__ void k_fill_d(int n, double v, double* __restrict__ a) {
     if (i < n) a[i] = v;
 }
 
-// Sliced-ELLPACK builders: the width (longest row) of every 64-row slice,
-// then the column-major fill of every slice (padding: zero values pointing at
-// the row itself, or at row 0 past the last matrix row).
-__global__ void k_sell_width(int nsl, int nrow_valid, const int32_t* __restrict__ rp, int32_t* __restrict__ w) {
+// Sliced-ELLPACK builders: the order of the rows inside each 256-row tile
+// (by length, longest first, ties by index; rows past the last matrix row
+// last), the width (longest row) of every 64-row slice, then the
+// column-major fill of every slice (padding: zero values pointing at the row
+// itself, or at row 0 for a lane past the last matrix row).
+__global__ void __launch_bounds__(256)
+k_sell_rows(int nrow_valid, const int32_t* __restrict__ rp, int32_t* __restrict__ row) {
+    __shared__ int len[256];
+    const int t = threadIdx.x, i = blockIdx.x * 256 + t;
+    const int mine = i < nrow_valid ? rp[i + 1] - rp[i] : -1;
+    len[t] = mine;
+    __syncthreads();
+    int rank = 0;
+    for (int j = 0; j < 256; ++j) rank += (len[j] > mine) || (len[j] == mine && j < t);
+    row[blockIdx.x * 256 + rank] = i;
+}
+
+__global__ void k_sell_width(int nsl, int nrow_valid, const int32_t* __restrict__ rp, const int32_t* __restrict__ row,
+                             int32_t* __restrict__ w) {
     const int sl = blockIdx.x * blockDim.x + threadIdx.x;
     if (sl >= nsl) return;
     int m = 0;
     for (int l = 0; l < 64; ++l) {
-        const int i = sl * 64 + l;
+        const int i = row[sl * 64 + l];
         if (i < nrow_valid) m = max(m, rp[i + 1] - rp[i]);
     }
     w[sl] = m;
@@ -1487,12 +1504,12 @@ __global__ void k_sell_width(int nsl, int nrow_valid, const int32_t* __restrict_
 
 __global__ void k_sell_fill(int nsl, int nrow_valid, const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
                             const float* __restrict__ K, const float* __restrict__ M, const int32_t* __restrict__ ptr,
-                            const int32_t* __restrict__ w, int32_t* __restrict__ scol, float* __restrict__ sK,
-                            float* __restrict__ sM, int values_only) {
+                            const int32_t* __restrict__ w, const int32_t* __restrict__ row, int32_t* __restrict__ scol,
+                            float* __restrict__ sK, float* __restrict__ sM, int values_only) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     const int sl = t >> 6, l = t & 63;
     if (sl >= nsl) return;
-    const int i = sl * 64 + l;
+    const int i = row[sl * 64 + l];
     const int b = i < nrow_valid ? rp[i] : 0;
     const int len = i < nrow_valid ? rp[i + 1] - b : 0;
     const int wd = w[sl];
@@ -1593,17 +1610,23 @@ void release_block_work(BlockWork*& w) {
 }
 
 // (Re)build the sliced-ELLPACK copy of a complex64 operator of nrows rows
-// (a multiple of 64; rows from nrow_valid on are empty). The pattern is kept
-// when `pattern` is false and the slice count is unchanged; the values are
-// always refreshed.
+// (a multiple of the 256-row tile; rows from nrow_valid on are empty). The
+// pattern is kept when `pattern` is false and the slice count is unchanged;
+// the values are always refreshed.
 int build_sell(Sell& S, int nrows, int nrow_valid, const int32_t* rp, const int32_t* col, const float* K,
                const float* M, bool pattern, hipStream_t s) {
+    if (nrows % kTR != 0 || nrow_valid > nrows) {
+        set_error("sliced ELLPACK: the rows must fill whole tiles");
+        return PETGEM_INVALID_ARG;
+    }
     const int nsl = nrows / 64;
     if (pattern || S.nsl != nsl || !S.ptr) {
         S.release();
         PG_TRY(dalloc(&S.ptr, (size_t)nsl + 1));
         PG_TRY(dalloc(&S.w, (size_t)nsl));
-        hipLaunchKernelGGL(k_sell_width, dim3(ceil_div(nsl, 256)), dim3(256), 0, s, nsl, nrow_valid, rp, S.w);
+        PG_TRY(dalloc(&S.row, (size_t)nrows));
+        hipLaunchKernelGGL(k_sell_rows, dim3(nrows / kTR), dim3(256), 0, s, nrow_valid, rp, S.row);
+        hipLaunchKernelGGL(k_sell_width, dim3(ceil_div(nsl, 256)), dim3(256), 0, s, nsl, nrow_valid, rp, S.row, S.w);
         std::vector<int32_t> w(nsl), ptr(nsl + 1);
         PG_HIP(hipMemcpyAsync(w.data(), S.w, sizeof(int32_t) * nsl, hipMemcpyDeviceToHost, s));
         PG_HIP(hipStreamSynchronize(s));
@@ -1624,12 +1647,12 @@ int build_sell(Sell& S, int nrows, int nrow_valid, const int32_t* rp, const int3
         S.nsl = nsl;
         S.elems = tot;
         hipLaunchKernelGGL(k_sell_fill, dim3(ceil_div((size_t)nsl * 64, 256)), dim3(256), 0, s, nsl, nrow_valid, rp,
-                           col, K, M, S.ptr, S.w, S.col, S.K, S.M, 0);
+                           col, K, M, S.ptr, S.w, S.row, S.col, S.K, S.M, 0);
         // the host vectors above must outlive the copy
         PG_HIP(hipStreamSynchronize(s));
     } else {
         hipLaunchKernelGGL(k_sell_fill, dim3(ceil_div((size_t)nsl * 64, 256)), dim3(256), 0, s, nsl, nrow_valid, rp,
-                           col, K, M, S.ptr, S.w, S.col, S.K, S.M, 1);
+                           col, K, M, S.ptr, S.w, S.row, S.col, S.K, S.M, 1);
     }
     PG_HIP(hipGetLastError());
     S.values = true;
@@ -2344,6 +2367,7 @@ int block_solve(petgem_system* sys, const petgem_source* src, int32_t n_src, con
         if (!S.ptr || !S.values) PG_TRY(build_sell(S, (int)rows, n, sys->row_ptr, sys->col, sys->K32, sys->Ms32, false, s));
         op.sp = S.ptr;
         op.sw = S.w;
+        op.srow = S.row;
         op.scol = S.col;
         op.sK = S.K;
         op.sM = S.M;
@@ -2463,6 +2487,7 @@ int batch_solve(petgem_system* const* systems, const petgem_source* src, int32_t
     PG_TRY(build_sell(w->cat_sell, (int)rows, (int)rows, w->rp, w->col, w->K32, w->M32, true, s));
     op.sp = w->cat_sell.ptr;
     op.sw = w->cat_sell.w;
+    op.srow = w->cat_sell.row;
     op.scol = w->cat_sell.col;
     op.sK = w->cat_sell.K;
     op.sM = w->cat_sell.M;
