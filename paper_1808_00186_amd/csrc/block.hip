@@ -60,9 +60,10 @@ constexpr int kCheck = 8;       // inner iterations between host checks (one gra
 static_assert(kCheck % 2 == 0, "the fused step's state slots alternate within a group");
 constexpr int64_t kConsumerMax = 8192;   // partials a vector kernel's block may sum itself
 constexpr int kConsumerTiles = 4;        // tiles per block of the in-consumer vector kernels
+constexpr int kSnapRing = 32;            // host snapshot slots of the fused step (a power of two)
 constexpr int kStepTiles = 8;   // tiles per block of the fused single-column step (2, 4, 16: 12, 2.5, 3.5 % slower)
-constexpr int kMaxGroups = 8;            // iteration groups between two host checks
-constexpr int kGraphSizes = 4;           // captured graphs hold 1, 2, 4 or 8 groups
+constexpr int kMaxGroups = 4;            // iteration groups between two host checks (8: 1 % slower on cfg2)
+constexpr int kGraphSizes = 3;           // captured graphs hold 1, 2 or 4 groups
 static_assert(kMaxGroups == 1 << (kGraphSizes - 1), "a batch of groups is a sum of graph sizes");
 
 __device__ __forceinline__ float2 f2(float x, float y) { return make_float2(x, y); }
@@ -1136,12 +1137,16 @@ k_pupdate_p(Op op, int CP, int tpb, const ColState* __restrict__ s0, ColState* _
 // convergence test runs first on the previous step's sums. (With the scalar
 // step taken by every thread on its own copy of the state, the kernel took
 // 19 us instead of 11.)
+// snap (or null): a ring of kSnapRing host-memory slots; block 0 also copies
+// the new state into slot *gcount and advances the count (the last step of
+// every iteration group does, so the host reads the state of a group without
+// a copy of its own on the stream).
 __global__ void __launch_bounds__(256)
 k_step1(Op op, int tpb, const ColState* __restrict__ sin, ColState* __restrict__ sout,
         const double2* __restrict__ ps, int nps, const double2* __restrict__ pg, const double2* __restrict__ pr,
         int npg, float2* __restrict__ R, const float2* __restrict__ Q,
         const float2* __restrict__ dinv, float2* __restrict__ P, float2* __restrict__ Xi, double2* __restrict__ go,
-        double2* __restrict__ ro) {
+        double2* __restrict__ ro, ColState* __restrict__ snap, int* __restrict__ gcount) {
     __shared__ double2 ra[256], rb[256];
     __shared__ double2 scal[3];
     __shared__ double2 tot[5];
@@ -1242,7 +1247,14 @@ k_step1(Op op, int tpb, const ColState* __restrict__ sin, ColState* __restrict__
                 }
             }
         }
-        if (blockIdx.x == 0) sout[0] = S;
+        if (blockIdx.x == 0) {
+            sout[0] = S;
+            if (snap) {
+                const int g = *gcount;
+                snap[g & (kSnapRing - 1)] = S;
+                *gcount = g + 1;
+            }
+        }
         scal[0] = S.alpha;
         scal[1] = S.beta;
         scal[2] = make_double2(S.active ? 1.0 : 0.0, 0.0);
@@ -1555,6 +1567,8 @@ struct BlockWork {
     ColState* st2 = nullptr;   // second state slot of the in-consumer reductions
     ColState* st_h = nullptr;
     ColState* st_h2 = nullptr;             // second host snapshot of the state (overlapped checks)
+    ColState* snap_ring = nullptr;         // [kSnapRing] host slots the fused step writes
+    int* gcount = nullptr;                 // groups completed by the fused step (device)
     hipEvent_t snap_ev[2] = {nullptr, nullptr};
     int* tmap = nullptr;       // launched tiles of a compacted uneven batch
     int* flags = nullptr;      // [nsc] per-column flags (rejected initial guesses)
@@ -1568,7 +1582,7 @@ struct BlockWork {
     Sell cat_sell;
     size_t cat_rows = 0, cat_nnz = 0;
     std::map<std::tuple<int, int64_t, int>, SpmmTuned> tuned;   // (n, nnz, C) -> choices
-    // graphs of 1, 2, 4 and 8 iteration groups (captured when first needed)
+    // graphs of 1, 2 and 4 iteration groups (captured when first needed)
     hipGraphExec_t graphs[kGraphSizes] = {};
     hipStream_t graph_stream = nullptr;
     std::vector<char> graph_sig;   // bytes of every argument baked into the graphs
@@ -1595,6 +1609,9 @@ struct BlockWork {
         st_h = nullptr;
         if (st_h2) (void)hipHostFree(st_h2);
         st_h2 = nullptr;
+        if (snap_ring) (void)hipHostFree(snap_ring);
+        snap_ring = nullptr;
+        dfree(gcount);
         for (auto& e : snap_ev) {
             if (e) (void)hipEventDestroy(e);
             e = nullptr;
@@ -1960,6 +1977,13 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
     const bool fused = dinv != nullptr && ch.kind == 3 && ch.a == 1 && (ch.b == 4 || ch.b == 8);
     const int nspb = ceil_div((int64_t)op.ntiles * 4, kSpbWaves);   // blocks (and partials) of its product
     const int nst = ceil_div(op.ntiles, kStepTiles);                // blocks of the step
+    int64_t groups_done = 0;   // groups launched since the fused step's group count was cleared
+    if (fused) {
+        if (!w->snap_ring)
+            PG_HIP(hipHostMalloc(reinterpret_cast<void**>(&w->snap_ring), sizeof(ColState) * kSnapRing));
+        if (!w->gcount) PG_TRY(dalloc(&w->gcount, 1));
+        hipLaunchKernelGGL(k_fill_rp, dim3(1), dim3(256), 0, s, 1, 0, w->gcount);
+    }
     hipLaunchKernelGGL(k_init_state, dim3(ceil_div(nsc, 64)), dim3(64), 0, s, w->st, nsc, o.rtol,
                        o.inner_rtol);
     const bool prof = o.profile != 0;
@@ -2084,7 +2108,7 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
             double2* rout = odd ? w->p2 : w->p2 + nst;
             hipLaunchKernelGGL(k_step1, dim3(nst), dim3(256), 0, s, op, kStepTiles, (const ColState*)sa, sb,
                                (const double2*)w->p0, nspb, gin, rin, nst, w->R, (const float2*)w->Q, dinv,
-                               w->P, w->Xi, gout, rout);
+                               w->P, w->Xi, gout, rout, k == kCheck - 1 ? w->snap_ring : nullptr, w->gcount);
             return;
         }
         spmm_dispatch<float, 1>(ch, opi, w->st, ev_pair(SpmmArgs{w->P, nullptr, w->Q, w->p0}), s);
@@ -2117,7 +2141,8 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
             sig.insert(sig.end(), c, c + nb);
         };
         put(&opi, sizeof(opi));
-        const void* ptrs[11] = {w->Xi, w->R, w->Z, w->P, w->Q, w->p0, w->p1, w->p2, w->st, w->st2, dinv};
+        const void* ptrs[13] = {w->Xi, w->R, w->Z, w->P, w->Q, w->p0, w->p1, w->p2, w->st, w->st2, dinv,
+                                w->snap_ring, w->gcount};
         put(ptrs, sizeof(ptrs));
         int chv[6] = {ch.kind, ch.a, ch.b, (int)in_consumer, opi.tmap ? tgen : 0, (int)fused};
         put(chv, sizeof(chv));
@@ -2197,7 +2222,12 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
         const bool overlap = use_graph && !(seg_tile_h && op.nseg > 1);
         ColState* snap[2] = {w->st_h, w->st_h2};
         int cur = 0;
-        // A single system launches n groups as few graphs (of 1, 2, 4 and 8
+        // the fused step writes the state of every group's end into the host
+        // ring itself; a batch's state is then in the slot of its last group
+        // (the at most kMaxGroups groups queued behind it cannot reach that
+        // slot again)
+        static_assert(kSnapRing > 2 * kMaxGroups, "a queued batch must not overwrite the slot being read");
+        // A single system launches n groups as few graphs (of 1, 2 and 4
         // groups): the kernels inside one graph follow each other without the
         // gap that separates two graph launches. An uneven batch recaptures
         // its graph after each rebuild of its tile list, so it keeps to the
@@ -2215,7 +2245,13 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
                 for (int g = 0; g < n; ++g) group();
             }
             inner += kCheck * n;
-            PG_HIP(hipMemcpyAsync(snap[slot], w->st, sizeof(ColState) * nsc, hipMemcpyDeviceToHost, s));
+            if (fused) {
+                groups_done += n;
+                snap[slot] = w->snap_ring + ((groups_done - 1) & (kSnapRing - 1));
+            } else {
+                snap[slot] = slot ? w->st_h2 : w->st_h;
+                PG_HIP(hipMemcpyAsync(snap[slot], w->st, sizeof(ColState) * nsc, hipMemcpyDeviceToHost, s));
+            }
             PG_HIP(hipEventRecord(w->snap_ev[slot], s));
             return PETGEM_OK;
         };
