@@ -62,9 +62,7 @@ constexpr int64_t kConsumerMax = 8192;   // partials a vector kernel's block may
 constexpr int kConsumerTiles = 4;        // tiles per block of the in-consumer vector kernels
 constexpr int kSnapRing = 32;            // host snapshot slots of the fused step (a power of two)
 constexpr int kStepTiles = 8;   // tiles per block of the fused single-column step (2, 4, 16: 12, 2.5, 3.5 % slower)
-constexpr int kMaxGroups = 4;            // iteration groups between two host checks (8: 1 % slower on cfg2)
-constexpr int kGraphSizes = 3;           // captured graphs hold 1, 2 or 4 groups
-static_assert(kMaxGroups == 1 << (kGraphSizes - 1), "a batch of groups is a sum of graph sizes");
+constexpr int kMaxGroups = 6;            // iteration groups between two host checks (4, 8: 0.5, 1.5 % slower on cfg2)
 
 __device__ __forceinline__ float2 f2(float x, float y) { return make_float2(x, y); }
 
@@ -1582,8 +1580,8 @@ struct BlockWork {
     Sell cat_sell;
     size_t cat_rows = 0, cat_nnz = 0;
     std::map<std::tuple<int, int64_t, int>, SpmmTuned> tuned;   // (n, nnz, C) -> choices
-    // graphs of 1, 2 and 4 iteration groups (captured when first needed)
-    hipGraphExec_t graphs[kGraphSizes] = {};
+    // graphs[k]: k + 1 iteration groups (captured when first needed)
+    hipGraphExec_t graphs[kMaxGroups] = {};
     hipStream_t graph_stream = nullptr;
     std::vector<char> graph_sig;   // bytes of every argument baked into the graphs
     ~BlockWork() { release(); }
@@ -2131,9 +2129,9 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
         for (int k = 0; k < kCheck; ++k) iteration(k);
     };
     const bool use_graph = o.use_graph && !prof;
-    // (re)capture the graph of 2^lg groups; every graph is dropped whenever an
+    // (re)capture the graph of ng groups; every graph is dropped whenever an
     // argument baked into them changed
-    auto ensure_graph = [&](int lg) -> int {
+    auto ensure_graph = [&](int ng) -> int {
         if (!use_graph) return PETGEM_OK;
         std::vector<char> sig;
         auto put = [&](const void* p, size_t nb) {
@@ -2147,20 +2145,20 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
         int chv[6] = {ch.kind, ch.a, ch.b, (int)in_consumer, opi.tmap ? tgen : 0, (int)fused};
         put(chv, sizeof(chv));
         if (w->graph_sig != sig) w->release_graph();
-        if (w->graphs[lg] != nullptr) return PETGEM_OK;
+        if (w->graphs[ng - 1] != nullptr) return PETGEM_OK;
         if (!w->graph_stream) PG_HIP(hipStreamCreateWithFlags(&w->graph_stream, hipStreamNonBlocking));
         hipGraph_t g;
         hipStream_t caller = s;
         s = w->graph_stream;
         PG_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-        for (int k = 0; k < (1 << lg); ++k) group();
+        for (int k = 0; k < ng; ++k) group();
         hipError_t ce = hipStreamEndCapture(s, &g);
         s = caller;
         if (ce != hipSuccess) {
             set_error(std::string("graph capture: ") + hipGetErrorString(ce));
             return PETGEM_HIP_ERROR;
         }
-        hipError_t ie = hipGraphInstantiate(&w->graphs[lg], g, nullptr, nullptr, 0);
+        hipError_t ie = hipGraphInstantiate(&w->graphs[ng - 1], g, nullptr, nullptr, 0);
         (void)hipGraphDestroy(g);
         if (ie != hipSuccess) {
             set_error(std::string("graph instantiate: ") + hipGetErrorString(ie));
@@ -2227,20 +2225,20 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
         // (the at most kMaxGroups groups queued behind it cannot reach that
         // slot again)
         static_assert(kSnapRing > 2 * kMaxGroups, "a queued batch must not overwrite the slot being read");
-        // A single system launches n groups as few graphs (of 1, 2 and 4
-        // groups): the kernels inside one graph follow each other without the
+        // A single system launches a batch of n groups as one graph of n
+        // groups: the kernels inside one graph follow each other without the
         // gap that separates two graph launches. An uneven batch recaptures
         // its graph after each rebuild of its tile list, so it keeps to the
         // one-group graph, whose capture is cheapest.
-        const int lg_max = overlap ? kGraphSizes - 1 : 0;
+        const int ng_max = overlap ? kMaxGroups : 1;
         auto launch_batch = [&](int n, int slot) -> int {
             if (use_graph) {
-                for (int lg = lg_max, left = n; lg >= 0; --lg)
-                    while (left >= (1 << lg)) {
-                        PG_TRY(ensure_graph(lg));
-                        PG_HIP(hipGraphLaunch(w->graphs[lg], s));
-                        left -= 1 << lg;
-                    }
+                for (int left = n; left > 0;) {
+                    const int ng = std::min(left, ng_max);
+                    PG_TRY(ensure_graph(ng));
+                    PG_HIP(hipGraphLaunch(w->graphs[ng - 1], s));
+                    left -= ng;
+                }
             } else {
                 for (int g = 0; g < n; ++g) group();
             }
