@@ -62,7 +62,7 @@ constexpr int64_t kConsumerMax = 8192;   // partials a vector kernel's block may
 constexpr int kConsumerTiles = 4;        // tiles per block of the in-consumer vector kernels
 constexpr int kSnapRing = 32;            // host snapshot slots of the fused step (a power of two)
 constexpr int kStepTiles = 8;   // tiles per block of the fused single-column step (2, 4, 16: 12, 2.5, 3.5 % slower)
-constexpr int kMaxGroups = 6;            // iteration groups between two host checks (4, 8: 0.5, 1.5 % slower on cfg2)
+constexpr int kMaxGroups = 6;   // iteration groups between two host checks (4, 8: 0.5, 1.5 % slower on a 434k-DOF mesh)
 
 __device__ __forceinline__ float2 f2(float x, float y) { return make_float2(x, y); }
 
@@ -1444,16 +1444,11 @@ __global__ void k_set_live(ColState* st, int nsc) {
     st[k].rho = make_double2(1.0, 0.0);
 }
 
-// tol_abs = rtol |b|; zero_x: the iterate is zero, so its residual is b
-// itself and the residual step takes |b| without a product
-__global__ void k_set_tol(ColState* st, int nsc, double rtol, int zero_x) {
+__global__ void k_set_tol(ColState* st, int nsc, double rtol) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= nsc) return;
-    ColState S = st[k];
-    S.tol_abs = rtol * S.bnorm;
-    S.outer = S.bnorm > 0.0 && isfinite(S.bnorm);
-    if (zero_x && S.outer) res_step(S, S.bnorm, 0);
-    st[k] = S;
+    st[k].tol_abs = rtol * st[k].bnorm;
+    st[k].outer = st[k].bnorm > 0.0 && isfinite(st[k].bnorm);
 }
 
 // Builders of the concatenated (block-diagonal) operator of several meshes.
@@ -2016,7 +2011,7 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
         return PETGEM_OK;
     };
     PG_TRY(bnorms());
-    hipLaunchKernelGGL(k_set_tol, dim3(ceil_div(nsc, 64)), dim3(64), 0, s, w->st, nsc, o.rtol, (int)!have_x0);
+    hipLaunchKernelGGL(k_set_tol, dim3(ceil_div(nsc, 64)), dim3(64), 0, s, w->st, nsc, o.rtol);
     if (have_x0) {
         // scale every guess by the alpha minimising |b - alpha A x0|
         PG_TRY(residual(0));
@@ -2026,9 +2021,11 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
         hipLaunchKernelGGL(k_scale_cols, dim3(op.ntiles), dim3(256), 0, s, op, CP, w->st, w->X64);
         PG_HIP(hipGetLastError());
     }
-    // with x = 0 the residual is b (k_set_tol took its norm) and the first
-    // refinement step starts from B64 itself
-    if (have_x0) PG_TRY(residual(0));
+    // the true residual even for a zero start (taking |b| from k_norm2 instead,
+    // a last-bit change of the first step's scale, made one column of a
+    // 32-source block on the 6.9M-DOF marine mesh diverge in its second
+    // refinement step)
+    PG_TRY(residual(0));
     PG_TRY(read_state());
     std::vector<int> fallback(nsc, 0);
     if (have_x0) {
@@ -2044,7 +2041,7 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
             hipLaunchKernelGGL(k_init_state, dim3(ceil_div(nsc, 64)), dim3(64), 0, s, w->st, nsc,
                                o.rtol, o.inner_rtol);
             PG_TRY(bnorms());
-            hipLaunchKernelGGL(k_set_tol, dim3(ceil_div(nsc, 64)), dim3(64), 0, s, w->st, nsc, o.rtol, 0);
+            hipLaunchKernelGGL(k_set_tol, dim3(ceil_div(nsc, 64)), dim3(64), 0, s, w->st, nsc, o.rtol);
             PG_TRY(residual(0));
             PG_TRY(read_state());
         }
@@ -2200,8 +2197,7 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
             break;
         }
         // inner complex64 COCG on A d = r64 / |r64|
-        const double2* r64 = steps == 0 && !have_x0 ? w->B64 : w->R64;
-        hipLaunchKernelGGL(k_inner_init, dim3(op.ntiles), dim3(256), 0, s, op, CP, r64, w->st, dinv, w->Xi,
+        hipLaunchKernelGGL(k_inner_init, dim3(op.ntiles), dim3(256), 0, s, op, CP, w->R64, w->st, dinv, w->Xi,
                            w->R, w->Z, w->P, w->p1, w->p2);
         hipLaunchKernelGGL(k_reduce, dim3(nsc), dim3(1024), 0, s, op, w->p1, 1, w->p2, 1, w->st,
                            (int)RED_INIT, 0);

@@ -58,7 +58,7 @@ inline void dfree(T*& p) {
 // to the slice's longest with zero values that point at the row itself.
 // Inside every 256-row tile the rows are ordered by length (longest first,
 // then by index) before they are cut into slices, so that a slice holds rows
-// of like length: on the cfg2 mesh this takes the padding from 18.6 % of the
+// of like length: on a 434k-DOF marine mesh this takes the padding from 18.6 % of the
 // nonzeros to 6.7 %. row[] maps each slice lane back to its matrix row.
 struct Sell {
     int nsl = 0;
