@@ -1128,7 +1128,7 @@ k_pupdate_p(Op op, int CP, int tpb, const ColState* __restrict__ s0, ColState* _
 // The step (state slot sin -> sout): every block sums the product's nps
 // partial triples and the previous step's npg partial pairs in a fixed order;
 // one thread then takes the scalar step (block 0 stores the state) and
-// hands alpha and beta to the block; then, over tpb tiles, the row updates,
+// hands alpha and beta to the block; then, over NR tiles, the row updates,
 // with the partials of the new r^T z and |r|^2 (one slot per block) into go,
 // ro, which must not be pg, pr: other blocks may still be reading those.
 // kin == 0 (just started): rho and |r|^2 are the state's own; otherwise the
@@ -1139,8 +1139,9 @@ k_pupdate_p(Op op, int CP, int tpb, const ColState* __restrict__ s0, ColState* _
 // the new state into slot *gcount and advances the count (the last step of
 // every iteration group does, so the host reads the state of a group without
 // a copy of its own on the stream).
+template <int NR>
 __global__ void __launch_bounds__(256)
-k_step1(Op op, int tpb, const ColState* __restrict__ sin, ColState* __restrict__ sout,
+k_step1(Op op, const ColState* __restrict__ sin, ColState* __restrict__ sout,
         const double2* __restrict__ ps, int nps, const double2* __restrict__ pg, const double2* __restrict__ pr,
         int npg, float2* __restrict__ R, const float2* __restrict__ Q,
         const float2* __restrict__ dinv, float2* __restrict__ P, float2* __restrict__ Xi, double2* __restrict__ go,
@@ -1148,17 +1149,15 @@ k_step1(Op op, int tpb, const ColState* __restrict__ sin, ColState* __restrict__
     __shared__ double2 ra[256], rb[256];
     __shared__ double2 scal[3];
     __shared__ double2 tot[5];
-    const int i0 = blockIdx.x * tpb * kTR, i1 = min(i0 + tpb * kTR, op.nrow_valid);
-    // the first four rows of every vector are loaded ahead of the sums
-    float2 q[4], r[4], dv[4], x[4], p[4];
-    auto load4 = [&](int ib) {
+    // NR tiles per block, one row of each per thread: all NR rows of every
+    // vector are loaded ahead of the sums
+    const int i0 = blockIdx.x * NR * kTR + (int)threadIdx.x, i1 = op.nrow_valid;
+    float2 q[NR], r[NR], dv[NR], x[NR], p[NR];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int i = max(min(ib + u * 256, i1 - 1), 0);   // in range; the duplicates are not stored
-            q[u] = Q[i]; r[u] = R[i]; dv[u] = dinv[i]; x[u] = Xi[i]; p[u] = P[i];
-        }
-    };
-    load4(i0 + threadIdx.x);
+    for (int u = 0; u < NR; ++u) {
+        const int i = max(min(i0 + u * 256, i1 - 1), 0);   // in range; the duplicates are not stored
+        q[u] = Q[i]; r[u] = R[i]; dv[u] = dinv[i]; x[u] = Xi[i]; p[u] = P[i];
+    }
     // fixed-order sums of the product's partials (three per tile) and of the
     // previous step's (two per block): strided per thread, then the waves
     {
@@ -1262,11 +1261,10 @@ k_step1(Op op, int tpb, const ColState* __restrict__ sin, ColState* __restrict__
     const double2 alpha = scal[0], beta = scal[1];
     const float ax = (float)alpha.x, ay = (float)alpha.y, bx = (float)beta.x, by = (float)beta.y;
     double2 a = make_double2(0.0, 0.0), b = make_double2(0.0, 0.0);
-    for (int ib = i0 + (int)threadIdx.x; ib < i1; ib += 4 * 256) {
-        if (ib != i0 + (int)threadIdx.x) load4(ib);
+    {
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int i = ib + u * 256;
+        for (int u = 0; u < NR; ++u) {
+            const int i = i0 + u * 256;
             if (i >= i1) break;
             float2 rr = r[u];
             rr.x -= ax * q[u].x - ay * q[u].y;
@@ -2101,7 +2099,7 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
             const double2* rin = odd ? w->p2 + nst : w->p2;
             double2* gout = odd ? w->p1 : w->p1 + nst;
             double2* rout = odd ? w->p2 : w->p2 + nst;
-            hipLaunchKernelGGL(k_step1, dim3(nst), dim3(256), 0, s, op, kStepTiles, (const ColState*)sa, sb,
+            hipLaunchKernelGGL(k_step1<kStepTiles>, dim3(nst), dim3(256), 0, s, op, (const ColState*)sa, sb,
                                (const double2*)w->p0, nspb, gin, rin, nst, w->R, (const float2*)w->Q, dinv,
                                w->P, w->Xi, gout, rout, k == kCheck - 1 ? w->snap_ring : nullptr, w->gcount);
             return;
