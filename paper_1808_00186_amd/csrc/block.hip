@@ -73,6 +73,7 @@ template <> struct V2<double> { using t = double2; };
 struct ColState {
     double2 rho, alpha, beta;
     double rn2;        // inner |r|^2 (relative to the normalised start)
+    double rn2_best;   // least inner |r|^2 of the current refinement step
     double scale;      // |r64| of the current refinement step
     double bnorm;      // |b|
     double rnorm64;    // true residual norm
@@ -85,7 +86,30 @@ struct ColState {
     int iters;         // inner iterations (all refinement steps)
     int kin;           // inner iterations of the current refinement step
     int stepped;       // this iteration's alpha was applied to r (set at the beta step)
+    int k_best;        // inner iteration of rn2_best
+    int stalled;       // inner steps ended by the stagnation guard (all refinement steps)
 };
+
+// Stagnation guard of the inner COCG, which has no minimisation property: a
+// column whose inner |r|^2 has not improved on its best of this refinement
+// step for twice the iterations the best took plus kStallIters stops its
+// inner solve; the refinement step applies its correction and the next step
+// restarts from the true residual. Without it one column of a 32-source block
+// on the 6.9M-DOF marine mesh, after a last-bit change of its starting scale,
+// wandered at inner |r| ~ 1 for 18,000 iterations instead of converging.
+// (A guard that also stopped a column on a 1000-fold rise of |r|, with 500
+// instead of 3000 iterations, fired on ordinary spikes of converging columns:
+// their corrections raised the true residual 50-fold and the block needed
+// 4-6 refinement steps instead of 3.)
+constexpr int kStallIters = 3000;
+__device__ __forceinline__ bool stalled_now(ColState& S, double r2) {
+    if (r2 < S.rn2_best) {
+        S.rn2_best = r2;
+        S.k_best = S.kin;
+        return false;
+    }
+    return S.kin - S.k_best > 2 * S.k_best + kStallIters;
+}
 
 // Operator view shared by the kernels.
 struct Op {
@@ -149,6 +173,9 @@ __device__ __forceinline__ void step_beta(ColState& S, double2 rz, double r2) {
         S.breakdown = 1;
     } else if (r2 <= S.inner_tol2) {
         S.active = 0;
+    } else if (stalled_now(S, r2)) {
+        S.active = 0;
+        S.stalled += 1;
     } else if (czero(S.rho)) {
         S.active = 0;
         S.breakdown = 1;
@@ -177,6 +204,8 @@ __device__ void apply_red(ColState& S, int mode, int first, double2 a, double2 b
     if (mode == RED_INIT) {            // a = r^T z, b.x = |r|^2 of the normalised start
         S.rho = a;
         S.rn2 = b.x;
+        S.rn2_best = b.x;
+        S.k_best = 0;
         S.kin = 0;
         S.beta = make_double2(0.0, 0.0);
         S.active = S.outer && cfinite(a) && !czero(a);
@@ -1215,6 +1244,9 @@ k_step1(Op op, const ColState* __restrict__ sin, ColState* __restrict__ sout,
                 S.breakdown = 1;
             } else if (r2 <= S.inner_tol2) {
                 S.active = 0;
+            } else if (stalled_now(S, r2)) {
+                S.active = 0;
+                S.stalled += 1;
             } else if (czero(rz)) {
                 S.active = 0;
                 S.breakdown = 1;
@@ -1418,6 +1450,7 @@ __global__ void k_init_state(ColState* st, int nsc, double rtol, double inner_rt
     ColState S;
     S.rho = S.alpha = S.beta = make_double2(0.0, 0.0);
     S.rn2 = 0.0;
+    S.rn2_best = 0.0;
     S.scale = 0.0;
     S.bnorm = 0.0;
     S.rnorm64 = 0.0;
@@ -1428,6 +1461,10 @@ __global__ void k_init_state(ColState* st, int nsc, double rtol, double inner_rt
     S.outer = 1;
     S.breakdown = 0;
     S.iters = 0;
+    S.kin = 0;
+    S.stepped = 0;
+    S.k_best = 0;
+    S.stalled = 0;
     st[k] = S;
 }
 
@@ -2299,13 +2336,15 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
         ++steps;
         if (o.verbose) {
             double worst = 0.0;
-            int left = 0;
+            int left = 0, stalls = 0;
             for (int k = 0; k < nsc; ++k) {
                 if (w->st_h[k].bnorm > 0) worst = std::max(worst, w->st_h[k].rnorm64 / w->st_h[k].bnorm);
                 left += w->st_h[k].outer;
+                stalls += w->st_h[k].stalled;
             }
             fprintf(stderr, "[petgem] COCG refinement step %d: %d inner iterations, worst true residual "
-                            "%.3e, %d of %d columns left, %.0f ms\n", steps, inner, worst, left, nsc, t_all.ms());
+                            "%.3e, %d of %d columns left, %d inner solves stopped by the stagnation guard, "
+                            "%.0f ms\n", steps, inner, worst, left, nsc, stalls, t_all.ms());
             fflush(stderr);
         }
     }
