@@ -24,7 +24,12 @@
 // prologues of the update kernels (see "reductions in the consumers"), so an
 // iteration is three kernels; there the first updates r and z, the second x
 // and p (both read p's row anyway), and a single column reads a precomputed
-// complex64 D^-1. Not used, after trial: the single-reduction
+// complex64 D^-1. One column of one mesh on the pipelined sliced ELLPACK
+// takes the fused step instead (see "fused single-column step"): the product
+// also sums q^T D^-1 r and q^T D^-1 q, beta follows from the expanded next
+// rho, and one vector kernel updates r, x and p: two kernels per iteration.
+// A stagnation guard ends the inner solve of a column that stops improving.
+// Not used, after trial: the single-reduction
 // rearrangement of Chronopoulos and Gear, which carries A p by a recurrence,
 // loses convergence in complex64 on the harder marine models; folding the p
 // update into the SpMM (gathering z and p together) costs more than the pass
@@ -32,9 +37,12 @@
 // a device-wide cache write-back per block, which costs more than a reduction
 // kernel.
 // The SpMM shapes: CSR with nonzero lanes or column lanes, or a sliced
-// ELLPACK copy of the operator (one row per lane) for up to four columns,
-// also in a software-pipelined form; the autotuner picks per operator and
-// column count.
+// ELLPACK copy of the operator (one row per lane, the rows of each tile
+// ordered by length) for up to four columns, also in a software-pipelined
+// form; the autotuner picks per operator and column count.
+// Host loop: runs of 8-iteration groups as captured graphs (one graph per
+// run length), the host reading the column states between runs while the
+// next run is already queued.
 // The dots are accumulated in double precision from complex64 data, per tile,
 // and reduced per (segment, column) in a fixed order (bitwise reproducible).
 // Refinement: r64 = b - A x64 in double precision, the inner solve runs on
