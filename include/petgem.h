@@ -120,11 +120,13 @@ typedef struct {
                                slice columns in flight), 3 = sliced ELLPACK
                                with the next b slice columns' indices and
                                values loaded during the current b gathers,
-                               4 = shape 3 for one column of one mesh, run as
-                               the fused step (the product also sums
-                               q^T D^-1 r and q^T D^-1 q, and one vector
-                               kernel applies alpha and beta); GMRES: the
-                               lanes per row of the complex128 CSR SpMV         */
+                               4 = the fused step, which one column of one
+                               mesh runs whatever shape is tuned (or when
+                               shape 3 is chosen): a shape-3 product that
+                               also sums q^T D^-1 r and q^T D^-1 q, then one
+                               vector kernel applying alpha and beta;
+                               GMRES: the lanes per row of the complex128
+                               CSR SpMV                                         */
     double  b_norm;         /* |b|_2 of the source's right-hand side            */
 } petgem_stats;
 

@@ -2008,9 +2008,15 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
         dinv = w->Dinv;
     }
     const int nbu = ceil_div(op.ntiles, kConsumerTiles);   // blocks of the two vector kernels
-    // One column with D^-1 and the pipelined sliced-ELLPACK product: the fused
-    // step (the product with its two extra partials, then one vector kernel).
-    const bool fused = dinv != nullptr && ch.kind == 3 && ch.a == 1 && (ch.b == 4 || ch.b == 8);
+    // One column with D^-1 and a sliced-ELLPACK copy takes the fused step
+    // (the product with its two extra partials, then one vector kernel),
+    // whichever product shape the tuner timed fastest on its own: the step
+    // saves more than the shapes differ (its own product is the pipelined
+    // one with 4 slice columns in flight; 8 measured 2 % slower). A
+    // caller-chosen shape is honoured as given: shape 3 runs fused, others not.
+    const bool fused = dinv != nullptr && op.sp != nullptr &&
+                       (o.spmm_shape == 0 || (ch.kind == 3 && ch.a == 1 && (ch.b == 4 || ch.b == 8)));
+    const int fused_u = o.spmm_shape == 0 ? 4 : ch.b;   // slice columns in flight in the fused product
     const int nspb = ceil_div((int64_t)op.ntiles * 4, kSpbWaves);   // blocks (and partials) of its product
     const int nst = ceil_div(op.ntiles, kStepTiles);                // blocks of the step
     int64_t groups_done = 0;   // groups launched since the fused step's group count was cleared
@@ -2132,7 +2138,7 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
             ColState* sa = odd ? w->st2 : w->st;   // read by the product and the step
             ColState* sb = odd ? w->st : w->st2;   // written by the step
             const SpmmArgs g = ev_pair(SpmmArgs{w->P, nullptr, w->Q, w->p0});
-            if (ch.b == 4)
+            if (fused_u == 4)
                 launch_timed_b(k_spmm_spb<4, kSpbWaves>, dim3(nspb), dim3(64 * kSpbWaves), s, g.e0, g.e1, opi,
                                (const ColState*)sa, (const float2*)w->P, w->Q, (const float2*)w->R, dinv, w->p0);
             else
@@ -2182,7 +2188,7 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
         const void* ptrs[13] = {w->Xi, w->R, w->Z, w->P, w->Q, w->p0, w->p1, w->p2, w->st, w->st2, dinv,
                                 w->snap_ring, w->gcount};
         put(ptrs, sizeof(ptrs));
-        int chv[6] = {ch.kind, ch.a, ch.b, (int)in_consumer, opi.tmap ? tgen : 0, (int)fused};
+        int chv[7] = {ch.kind, ch.a, ch.b, (int)in_consumer, opi.tmap ? tgen : 0, (int)fused, fused_u};
         put(chv, sizeof(chv));
         if (w->graph_sig != sig) w->release_graph();
         if (w->graphs[ng - 1] != nullptr) return PETGEM_OK;
@@ -2382,7 +2388,7 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
         st->t_solve_ms = t_solve;
         st->spmv_ms = spmv_ms;
         st->spmv_launches = spmv_n;
-        st->spmv_shape = 10000 * (fused ? 4 : ch.kind) + 100 * ch.a + ch.b;
+        st->spmv_shape = fused ? 40100 + fused_u : 10000 * ch.kind + 100 * ch.a + ch.b;
         st->status = S.outer ? (std::isfinite(S.rnorm64) ? PETGEM_NOT_CONVERGED : PETGEM_NONFINITE) : PETGEM_OK;
         if (st->status != PETGEM_OK && status == PETGEM_OK) status = st->status;
     }
