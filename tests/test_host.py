@@ -113,3 +113,21 @@ def test_bench_refuses_more_than_one_gpu():
                        text=True, timeout=300)
     assert r.returncode != 0
     assert "one GPU" in (r.stdout + r.stderr)
+
+
+def test_bench_names_and_prices_the_fused_product():
+    """The roofline entry of bench.py: shape 40104 (the fused step's product)
+    is named after its kernel, charged 16 B per row more than the plain
+    sliced-ELLPACK product (r and D^-1), and has a measured traffic figure."""
+    import importlib.util
+    spec = importlib.util.spec_from_file_location("bench_mod", os.path.join(ROOT, "bench.py"))
+    bench = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(bench)
+    n, nnz = 433720, 6950152
+    assert bench.spmm_bytes_fp32(n, nnz, 1, 40104) == 12 * nnz + 36 * n == 99015744
+    assert bench.spmm_bytes_fp32(n, nnz, 1, 30104) == 12 * nnz + 20 * n
+    name = bench.kernel_name("mixed", 40104)
+    assert name.startswith("k_spmm_spb<4, 4>")
+    assert name in bench.MEASURED_TRAFFIC
+    assert bench.kernel_name("mixed", 30104).startswith("k_spmm_sp<1, 4>")
+    assert bench.kernel_name("plain", 8).startswith("k_spmv<8, false>")
