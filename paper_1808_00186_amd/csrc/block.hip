@@ -1452,7 +1452,7 @@ __global__ void k_cols_in(int nr, int C, size_t r0, const double2* __restrict__ 
     dst[(r0 + i) * C + c] = src[c * lds + i];
 }
 
-__global__ void k_init_state(ColState* st, int nsc, double rtol, double inner_rtol) {
+__global__ void k_init_state(ColState* st, int nsc, double inner_rtol) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= nsc) return;
     ColState S;
@@ -2026,7 +2026,7 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
         if (!w->gcount) PG_TRY(dalloc(&w->gcount, 1));
         hipLaunchKernelGGL(k_fill_rp, dim3(1), dim3(256), 0, s, 1, 0, w->gcount);
     }
-    hipLaunchKernelGGL(k_init_state, dim3(ceil_div(nsc, 64)), dim3(64), 0, s, w->st, nsc, o.rtol,
+    hipLaunchKernelGGL(k_init_state, dim3(ceil_div(nsc, 64)), dim3(64), 0, s, w->st, nsc,
                        o.inner_rtol);
     const bool prof = o.profile != 0;
     std::vector<hipEvent_t> evs;
@@ -2088,7 +2088,7 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
             PG_HIP(hipMemcpyAsync(w->flags, fallback.data(), sizeof(int) * nsc, hipMemcpyHostToDevice, s));
             hipLaunchKernelGGL(k_zero_cols, dim3(op.ntiles), dim3(256), 0, s, op, CP, w->flags, w->X64);
             hipLaunchKernelGGL(k_init_state, dim3(ceil_div(nsc, 64)), dim3(64), 0, s, w->st, nsc,
-                               o.rtol, o.inner_rtol);
+                               o.inner_rtol);
             PG_TRY(bnorms());
             hipLaunchKernelGGL(k_set_tol, dim3(ceil_div(nsc, 64)), dim3(64), 0, s, w->st, nsc, o.rtol);
             PG_TRY(residual(0));

@@ -45,7 +45,6 @@ __device__ __forceinline__ bf16 f2bf(float f) {
     u += 0x7fffu + ((u >> 16) & 1u);                                        // round to nearest even
     return (bf16)(u >> 16);
 }
-__device__ __forceinline__ float bf2f(bf16 h) { return __uint_as_float((uint32_t)h << 16); }
 
 // ---------------------------------------------------------------- conv
 // out[v][co] = sum_tap sum_ci in[v + off(tap)][ci] W[tap][ci][co] (+ bias, relu)
