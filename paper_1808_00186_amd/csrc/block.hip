@@ -706,7 +706,8 @@ __device__ __forceinline__ float2 cmulf(float2 a, float2 b) {
 
 // Single-column form of k_spmm_sp for the fused COCG step: besides y = A x
 // and p^T q it forms q^T D^-1 r and q^T D^-1 q from each row's r and D^-1
-// (three partials per block, in that order). They give the next
+// (three partials per block, in that order, each in its own plane of
+// gridDim.x values so that the step reads each plane coalesced). They give the next
 // rho = (r - alpha q)^T D^-1 (r - alpha q) before r itself is updated. A
 // block of W waves takes W consecutive 64-row slices (8 and 16 waves per
 // block, i.e. fewer partials for the step to sum, measured no faster than 4).
@@ -791,7 +792,7 @@ k_spmm_spb(Op op, const ColState* __restrict__ st, const float2* __restrict__ X,
         double2 t = red[0][u];
 #pragma unroll
         for (int k = 1; k < W; ++k) t = cadd(t, red[k][u]);
-        partial[(size_t)blk * 3 + u] = t;
+        partial[(size_t)u * gridDim.x + blk] = t;   // three planes of one partial per block
     }
 }
 
@@ -1163,7 +1164,8 @@ k_pupdate_p(Op op, int CP, int tpb, const ColState* __restrict__ s0, ColState* _
 // The iteration is two kernels: the product and this step.
 //
 // The step (state slot sin -> sout): every block sums the product's nps
-// partial triples and the previous step's npg partial pairs in a fixed order;
+// partial triples (three planes of nps) and the previous step's npg partial
+// pairs in a fixed order, with all of a thread's loads in flight at once;
 // one thread then takes the scalar step (block 0 stores the state) and
 // hands alpha and beta to the block; then, over NR tiles, the row updates,
 // with the partials of the new r^T z and |r|^2 (one slot per block) into go,
@@ -1186,6 +1188,12 @@ k_step1(Op op, const ColState* __restrict__ sin, ColState* __restrict__ sout,
     __shared__ double2 ra[256], rb[256];
     __shared__ double2 scal[3];
     __shared__ double2 tot[5];
+    __shared__ ColState s_in;
+    static_assert(sizeof(ColState) % 8 == 0 && sizeof(ColState) / 8 <= 256, "state copied as doubles");
+    // the state (written by the previous step's block 0) is copied to LDS
+    // first, so its load overlaps the partial sums instead of following them
+    if (threadIdx.x < sizeof(ColState) / 8)
+        reinterpret_cast<double*>(&s_in)[threadIdx.x] = reinterpret_cast<const double*>(sin)[threadIdx.x];
     // NR tiles per block, one row of each per thread: all NR rows of every
     // vector are loaded ahead of the sums
     const int i0 = blockIdx.x * NR * kTR + (int)threadIdx.x, i1 = op.nrow_valid;
@@ -1201,16 +1209,18 @@ k_step1(Op op, const ColState* __restrict__ sin, ColState* __restrict__ sout,
         double2 v[5];
 #pragma unroll
         for (int j = 0; j < 5; ++j) v[j] = make_double2(0.0, 0.0);
-        for (int e0 = threadIdx.x; e0 < nps; e0 += 4 * 256) {
-            double2 a[4][3];
+        // eight slots of each source per thread in flight (one round up to
+        // 2,048 product tiles), then the additions in slot order
+        for (int e0 = threadIdx.x; e0 < nps; e0 += 8 * 256) {
+            double2 a[8][3];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
+            for (int u = 0; u < 8; ++u) {
                 const int e = e0 + u * 256;
 #pragma unroll
-                for (int j = 0; j < 3; ++j) a[u][j] = e < nps ? ps[(size_t)e * 3 + j] : make_double2(0.0, 0.0);
+                for (int j = 0; j < 3; ++j) a[u][j] = e < nps ? ps[(size_t)j * nps + e] : make_double2(0.0, 0.0);
             }
 #pragma unroll
-            for (int u = 0; u < 4; ++u)
+            for (int u = 0; u < 8; ++u)
 #pragma unroll
                 for (int j = 0; j < 3; ++j) v[j] = cadd(v[j], a[u][j]);
         }
@@ -1242,7 +1252,7 @@ k_step1(Op op, const ColState* __restrict__ sin, ColState* __restrict__ sout,
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        ColState S = sin[0];
+        ColState S = s_in;
         if (S.active && S.kin > 0) {   // the r left by the previous step
             const double2 rz = tot[3];
             const double r2 = tot[4].x;
