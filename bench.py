@@ -83,8 +83,10 @@ def spmm_bytes_fp32(n: int, nnz: int, cols: int, shape: int = 0) -> int:
     """Algorithmic bytes of one complex64 SpMM of the COCG over real K and
     M_sigma: K, M 4 + 4 and column 4 per nonzero; row pointer 4 per row;
     x read 8, y written 8 per row and column. The single-column product of
-    the fused step (shape kind 4) also reads r and D^-1, 8 + 8 per row."""
-    return 12 * nnz + n * (4 + 16 * cols) + (16 * n if shape // 10000 == 4 else 0)
+    the fused step (shape kind 4) also reads r and D^-1, 8 + 8 per row; the
+    per-mesh one (kind 5) r and the two double diagonals, 8 + 16 per row."""
+    extra = {4: 16, 5: 24}.get(shape // 10000, 0)
+    return 12 * nnz + n * (4 + 16 * cols + extra)
 
 
 def rx_error(E, ref):
@@ -133,6 +135,8 @@ def kernel_name(form, shape):
     if form == "plain":
         return f"k_spmv<{shape}, false> complex128 CSR (A D^-1)"
     kind, a, b = shape // 10000, (shape // 100) % 100, shape % 100
+    if kind == 5:
+        return f"k_spmm_spbs<{b}> complex64 pipelined sliced ELLPACK with beta partials, per mesh (K, M_sigma)"
     if kind == 4:
         return f"k_spmm_spb<{b}, 4> complex64 pipelined sliced ELLPACK with beta partials (K, M_sigma)"
     if kind == 3:

@@ -125,6 +125,10 @@ typedef struct {
                                shape 3 is chosen): a shape-3 product that
                                also sums q^T D^-1 r and q^T D^-1 q, then one
                                vector kernel applying alpha and beta;
+                               5 = the fused step with one reduction block
+                               per mesh, which one column per mesh of an
+                               uneven batch (or of a mesh with too many
+                               tiles for kind 4) runs for a tuned shape;
                                GMRES: the lanes per row of the complex128
                                CSR SpMV                                         */
     double  b_norm;         /* |b|_2 of the source's right-hand side            */

@@ -1151,6 +1151,54 @@ k_pupdate_p(Op op, int CP, int tpb, const ColState* __restrict__ s0, ColState* _
     }
 }
 
+// The scalar step of the fused step for one column, from the five sums t:
+// the product's p^T q, q^T D^-1 r, q^T D^-1 q and the previous step's r^T z,
+// |r|^2. kin == 0 (just started): rho and |r|^2 are the state's own;
+// otherwise the convergence test (with the stagnation guard) runs first.
+__device__ void fused_scalars(ColState& S, const double2* t) {
+    if (S.active && S.kin > 0) {   // the r left by the previous step
+        const double2 rz = t[3];
+        const double r2 = t[4].x;
+        S.rn2 = r2;
+        if (!isfinite(r2) || !cfinite(rz)) {
+            S.active = 0;
+            S.breakdown = 1;
+        } else if (r2 <= S.inner_tol2) {
+            S.active = 0;
+        } else if (stalled_now(S, r2)) {
+            S.active = 0;
+            S.stalled += 1;
+        } else if (czero(rz)) {
+            S.active = 0;
+            S.breakdown = 1;
+        } else {
+            S.rho = rz;
+        }
+    }
+    if (S.active) {
+        const double2 pq = t[0];
+        if (!cfinite(pq) || czero(pq)) {
+            S.active = 0;
+            S.breakdown = 1;
+        } else {
+            const double2 al = cdiv(S.rho, pq);
+            // rho - 2 alpha q^T D^-1 r + alpha^2 q^T D^-1 q
+            const double2 next =
+                cadd(cadd(S.rho, cscale(cmul(al, t[1]), -2.0)), cmul(cmul(al, al), t[2]));
+            const double2 be = cdiv(next, S.rho);
+            if (!cfinite(be)) {
+                S.active = 0;
+                S.breakdown = 1;
+            } else {
+                S.alpha = al;
+                S.beta = be;
+                S.iters += 1;
+                S.kin += 1;
+            }
+        }
+    }
+}
+
 // ------------------------------------------- fused single-column step
 // One mesh, one column, D^-1 precomputed: after the product q = A p a single
 // vector kernel takes the whole COCG step. The next rho is known before r is
@@ -1253,47 +1301,7 @@ k_step1(Op op, const ColState* __restrict__ sin, ColState* __restrict__ sout,
     __syncthreads();
     if (threadIdx.x == 0) {
         ColState S = s_in;
-        if (S.active && S.kin > 0) {   // the r left by the previous step
-            const double2 rz = tot[3];
-            const double r2 = tot[4].x;
-            S.rn2 = r2;
-            if (!isfinite(r2) || !cfinite(rz)) {
-                S.active = 0;
-                S.breakdown = 1;
-            } else if (r2 <= S.inner_tol2) {
-                S.active = 0;
-            } else if (stalled_now(S, r2)) {
-                S.active = 0;
-                S.stalled += 1;
-            } else if (czero(rz)) {
-                S.active = 0;
-                S.breakdown = 1;
-            } else {
-                S.rho = rz;
-            }
-        }
-        if (S.active) {
-            const double2 pq = tot[0];
-            if (!cfinite(pq) || czero(pq)) {
-                S.active = 0;
-                S.breakdown = 1;
-            } else {
-                const double2 al = cdiv(S.rho, pq);
-                // rho - 2 alpha q^T D^-1 r + alpha^2 q^T D^-1 q
-                const double2 next =
-                    cadd(cadd(S.rho, cscale(cmul(al, tot[1]), -2.0)), cmul(cmul(al, al), tot[2]));
-                const double2 be = cdiv(next, S.rho);
-                if (!cfinite(be)) {
-                    S.active = 0;
-                    S.breakdown = 1;
-                } else {
-                    S.alpha = al;
-                    S.beta = be;
-                    S.iters += 1;
-                    S.kin += 1;
-                }
-            }
-        }
+        fused_scalars(S, tot);
         if (blockIdx.x == 0) {
             sout[0] = S;
             if (snap) {
@@ -1332,6 +1340,179 @@ k_step1(Op op, const ColState* __restrict__ sin, ColState* __restrict__ sout,
     if (threadIdx.x == 0) {
         go[blockIdx.x] = ra[0];
         ro[blockIdx.x] = rb[0];
+    }
+}
+
+// ------------------------------------------- fused step, several meshes
+// The fused step for one column per mesh when the meshes' partials are too
+// many for every block to sum (an uneven batch, or one large mesh): the
+// product (one 256-row tile per block, D^-1 from the double-precision
+// diagonal), one block per mesh forming its scalars, then the row update.
+// Three kernels per iteration instead of five. Partials are per tile: the
+// product's three in planes of ntiles, the step's two in p1, p2.
+template <int U>
+__global__ void __launch_bounds__(256)
+k_spmm_spbs(Op op, const ColState* __restrict__ st, const float2* __restrict__ X, float2* __restrict__ Y,
+            const float2* __restrict__ R, double2* __restrict__ partial) {
+    __shared__ double2 red[4][3];
+    const int tile = tile_of(op, xcd_block(blockIdx.x, gridDim.x));
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int sl = tile * 4 + wave;
+    const int seg = op.tile_seg ? op.tile_seg[tile] : 0;
+    if (!st[seg].active) return;   // stopped: nothing reads the partials
+    const double wmu_d = op.wmu[seg];
+    const float wmu = (float)wmu_d;
+    const int i = op.srow[sl * 64 + lane];
+    const bool row = i < op.nrow_valid;
+    // this row's r and diagonal do not depend on the product: loaded first
+    const float2 rv = row ? R[i] : f2(0.f, 0.f);
+    const double kd = row ? op.Kd[i] : 1.0, md = row ? op.Md[i] : 0.0;
+    float2 ak = f2(0.f, 0.f), am = f2(0.f, 0.f);
+    const int base = op.sp[sl], wd = op.sw[sl];
+    int32_t cj[U];
+    float kv[U], mv[U];
+    auto fetch = [&](int k, int32_t* c, float* kk, float* mm) {
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+            if (k + q < wd) {
+                const int e = base + (k + q) * 64 + lane;
+                c[q] = op.scol[e];
+                kk[q] = op.sK[e];
+                mm[q] = op.sM[e];
+            } else {
+                c[q] = row ? i : 0;
+                kk[q] = 0.f;
+                mm[q] = 0.f;
+            }
+        }
+    };
+    fetch(0, cj, kv, mv);
+    for (int k = 0; k < wd; k += U) {
+        float2 xv[U];
+#pragma unroll
+        for (int q = 0; q < U; ++q) xv[q] = X[cj[q]];
+        int32_t cn[U];
+        float kn[U], mn[U];
+        if (k + U < wd) fetch(k + U, cn, kn, mn);
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+            ak.x += kv[q] * xv[q].x; ak.y += kv[q] * xv[q].y;
+            am.x += mv[q] * xv[q].x; am.y += mv[q] * xv[q].y;
+        }
+        if (k + U < wd) {
+#pragma unroll
+            for (int q = 0; q < U; ++q) { cj[q] = cn[q]; kv[q] = kn[q]; mv[q] = mn[q]; }
+        }
+    }
+    double2 pq = make_double2(0.0, 0.0), qzr = pq, qzq = pq;
+    if (row) {
+        float2 y;
+        y.x = ak.x + wmu * am.y;   // K x - i wmu M x
+        y.y = ak.y - wmu * am.x;
+        const float2 xo = X[i];
+        const float2 zr = jacobi_z(rv, kd, md, wmu_d), zq = jacobi_z(y, kd, md, wmu_d);
+        pq.x = (double)xo.x * y.x - (double)xo.y * y.y;
+        pq.y = (double)xo.x * y.y + (double)xo.y * y.x;
+        qzr.x = (double)y.x * zr.x - (double)y.y * zr.y;
+        qzr.y = (double)y.x * zr.y + (double)y.y * zr.x;
+        qzq.x = (double)y.x * zq.x - (double)y.y * zq.y;
+        qzq.y = (double)y.x * zq.y + (double)y.y * zq.x;
+        Y[i] = y;
+    }
+    const double s0 = wave_sum(pq.x), s1 = wave_sum(pq.y), s2 = wave_sum(qzr.x), s3 = wave_sum(qzr.y),
+                 s4 = wave_sum(qzq.x), s5 = wave_sum(qzq.y);
+    if (lane == 0) {
+        red[wave][0] = make_double2(s0, s1);
+        red[wave][1] = make_double2(s2, s3);
+        red[wave][2] = make_double2(s4, s5);
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        const int u = threadIdx.x;
+        partial[(size_t)u * op.ntiles + tile] = cadd(cadd(red[0][u], red[1][u]), cadd(red[2][u], red[3][u]));
+    }
+}
+
+// One block per mesh: fixed-order sums over the mesh's tiles of the
+// product's three partials and the previous step's two, then the scalar step.
+__global__ void __launch_bounds__(1024)
+k_red_seg(Op op, ColState* __restrict__ st, const double2* __restrict__ ps, const double2* __restrict__ pg,
+          const double2* __restrict__ pr) {
+    __shared__ double2 red[16][5];
+    const int seg = blockIdx.x;
+    if (!st[seg].active) return;   // the same in every thread
+    const int t0 = op.seg_tile[seg], t1 = op.seg_tile[seg + 1];
+    double2 v[5];
+#pragma unroll
+    for (int j = 0; j < 5; ++j) v[j] = make_double2(0.0, 0.0);
+    for (int e0 = t0 + (int)threadIdx.x; e0 < t1; e0 += 4 * 1024) {
+        double2 a[4][5];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int e = e0 + u * 1024;
+            const bool ok = e < t1;
+#pragma unroll
+            for (int j = 0; j < 3; ++j) a[u][j] = ok ? ps[(size_t)j * op.ntiles + e] : make_double2(0.0, 0.0);
+            a[u][3] = ok ? pg[e] : make_double2(0.0, 0.0);
+            a[u][4] = ok ? pr[e] : make_double2(0.0, 0.0);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int j = 0; j < 5; ++j) v[j] = cadd(v[j], a[u][j]);
+    }
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+    for (int j = 0; j < 5; ++j) {
+        const double sx = wave_sum(v[j].x), sy = wave_sum(v[j].y);
+        if (lane == 0) red[wave][j] = make_double2(sx, sy);
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    double2 t[5];
+#pragma unroll
+    for (int j = 0; j < 5; ++j) {
+        t[j] = red[0][j];
+        for (int k = 1; k < 16; ++k) t[j] = cadd(t[j], red[k][j]);
+    }
+    ColState S = st[seg];
+    fused_scalars(S, t);
+    st[seg] = S;
+}
+
+// The row update of the fused step over one tile per block (the mesh's
+// scalars from the state), with the tile's partials of the new r^T z and
+// |r|^2 into go, ro.
+__global__ void __launch_bounds__(256)
+k_step_seg(Op op, const ColState* __restrict__ st, float2* __restrict__ R, const float2* __restrict__ Q,
+           float2* __restrict__ P, float2* __restrict__ Xi, double2* __restrict__ go, double2* __restrict__ ro) {
+    __shared__ double2 ra[256], rb[256];
+    const int tile = tile_of(op, blockIdx.x);
+    const int seg = op.tile_seg ? op.tile_seg[tile] : 0;
+    const int i = tile * kTR + (int)threadIdx.x;
+    const int ic = min(i, op.nrow_valid - 1);   // in range; the duplicate is not stored
+    const float2 q = Q[ic], r = R[ic], x = Xi[ic], p = P[ic];
+    const double kd = op.Kd[ic], md = op.Md[ic];
+    const int active = st[seg].active;
+    const double2 alpha = st[seg].alpha, beta = st[seg].beta;
+    double2 a = make_double2(0.0, 0.0), b = make_double2(0.0, 0.0);
+    if (active && i < op.nrow_valid) {
+        const float ax = (float)alpha.x, ay = (float)alpha.y, bx = (float)beta.x, by = (float)beta.y;
+        float2 rr = r;
+        rr.x -= ax * q.x - ay * q.y;
+        rr.y -= ax * q.y + ay * q.x;
+        const float2 z = jacobi_z(rr, kd, md, op.wmu[seg]);
+        R[i] = rr;
+        Xi[i] = f2(x.x + ax * p.x - ay * p.y, x.y + ax * p.y + ay * p.x);
+        P[i] = f2(z.x + bx * p.x - by * p.y, z.y + bx * p.y + by * p.x);
+        a.x = (double)rr.x * z.x - (double)rr.y * z.y;
+        a.y = (double)rr.x * z.y + (double)rr.y * z.x;
+        b.x = (double)rr.x * rr.x + (double)rr.y * rr.y;
+    }
+    cp_sum2(a, b, 1, ra, rb);
+    if (threadIdx.x == 0) {
+        go[tile] = ra[0];
+        ro[tile] = rb[0];
     }
 }
 
@@ -2027,6 +2208,10 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
     const bool fused = dinv != nullptr && op.sp != nullptr &&
                        (o.spmm_shape == 0 || (ch.kind == 3 && ch.a == 1 && (ch.b == 4 || ch.b == 8)));
     const int fused_u = o.spmm_shape == 0 ? 4 : ch.b;   // slice columns in flight in the fused product
+    // one column per mesh otherwise (an uneven batch, or one mesh too large for
+    // every block to sum its partials): the fused step with a reduction block
+    // per mesh, for a tuned shape
+    const bool fused_seg = !fused && C == 1 && op.sp != nullptr && o.spmm_shape == 0;
     const int nspb = ceil_div((int64_t)op.ntiles * 4, kSpbWaves);   // blocks (and partials) of its product
     const int nst = ceil_div(op.ntiles, kStepTiles);                // blocks of the step
     int64_t groups_done = 0;   // groups launched since the fused step's group count was cleared
@@ -2165,6 +2350,16 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
                                w->P, w->Xi, gout, rout, k == kCheck - 1 ? w->snap_ring : nullptr, w->gcount);
             return;
         }
+        if (fused_seg) {
+            const SpmmArgs g = ev_pair(SpmmArgs{w->P, nullptr, w->Q, w->p0});
+            launch_timed(k_spmm_spbs<4>, dim3(opi.nlaunch), s, g.e0, g.e1, opi, (const ColState*)w->st,
+                         (const float2*)w->P, w->Q, (const float2*)w->R, w->p0);
+            hipLaunchKernelGGL(k_red_seg, dim3(op.nseg), dim3(1024), 0, s, op, w->st, (const double2*)w->p0,
+                               (const double2*)w->p1, (const double2*)w->p2);
+            hipLaunchKernelGGL(k_step_seg, dim3(opi.nlaunch), dim3(256), 0, s, opi, (const ColState*)w->st, w->R,
+                               (const float2*)w->Q, w->P, w->Xi, w->p1, w->p2);
+            return;
+        }
         spmm_dispatch<float, 1>(ch, opi, w->st, ev_pair(SpmmArgs{w->P, nullptr, w->Q, w->p0}), s);
         if (in_consumer) {
             hipLaunchKernelGGL(k_update_p, dim3(nbu), dim3(256), 0, s, op, CP, kConsumerTiles, w->st, w->st2,
@@ -2198,7 +2393,7 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
         const void* ptrs[13] = {w->Xi, w->R, w->Z, w->P, w->Q, w->p0, w->p1, w->p2, w->st, w->st2, dinv,
                                 w->snap_ring, w->gcount};
         put(ptrs, sizeof(ptrs));
-        int chv[7] = {ch.kind, ch.a, ch.b, (int)in_consumer, opi.tmap ? tgen : 0, (int)fused, fused_u};
+        int chv[8] = {ch.kind, ch.a, ch.b, (int)in_consumer, opi.tmap ? tgen : 0, (int)fused, fused_u, (int)fused_seg};
         put(chv, sizeof(chv));
         if (w->graph_sig != sig) w->release_graph();
         if (w->graphs[ng - 1] != nullptr) return PETGEM_OK;
@@ -2398,7 +2593,7 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
         st->t_solve_ms = t_solve;
         st->spmv_ms = spmv_ms;
         st->spmv_launches = spmv_n;
-        st->spmv_shape = fused ? 40100 + fused_u : 10000 * ch.kind + 100 * ch.a + ch.b;
+        st->spmv_shape = fused ? 40100 + fused_u : fused_seg ? 50104 : 10000 * ch.kind + 100 * ch.a + ch.b;
         st->status = S.outer ? (std::isfinite(S.rnorm64) ? PETGEM_NOT_CONVERGED : PETGEM_NONFINITE) : PETGEM_OK;
         if (st->status != PETGEM_OK && status == PETGEM_OK) status = st->status;
     }
