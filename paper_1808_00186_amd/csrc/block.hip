@@ -2212,6 +2212,8 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
     // every block to sum its partials): the fused step with a reduction block
     // per mesh, for a tuned shape
     const bool fused_seg = !fused && C == 1 && op.sp != nullptr && o.spmm_shape == 0;
+    // its product keeps the slice columns in flight of the tuned sliced-ELLPACK shape
+    const int seg_u = ch.kind >= 2 && ch.a == 1 && ch.b == 8 ? 8 : 4;
     const int nspb = ceil_div((int64_t)op.ntiles * 4, kSpbWaves);   // blocks (and partials) of its product
     const int nst = ceil_div(op.ntiles, kStepTiles);                // blocks of the step
     int64_t groups_done = 0;   // groups launched since the fused step's group count was cleared
@@ -2352,8 +2354,12 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
         }
         if (fused_seg) {
             const SpmmArgs g = ev_pair(SpmmArgs{w->P, nullptr, w->Q, w->p0});
-            launch_timed(k_spmm_spbs<4>, dim3(opi.nlaunch), s, g.e0, g.e1, opi, (const ColState*)w->st,
-                         (const float2*)w->P, w->Q, (const float2*)w->R, w->p0);
+            if (seg_u == 8)
+                launch_timed(k_spmm_spbs<8>, dim3(opi.nlaunch), s, g.e0, g.e1, opi, (const ColState*)w->st,
+                             (const float2*)w->P, w->Q, (const float2*)w->R, w->p0);
+            else
+                launch_timed(k_spmm_spbs<4>, dim3(opi.nlaunch), s, g.e0, g.e1, opi, (const ColState*)w->st,
+                             (const float2*)w->P, w->Q, (const float2*)w->R, w->p0);
             hipLaunchKernelGGL(k_red_seg, dim3(op.nseg), dim3(1024), 0, s, op, w->st, (const double2*)w->p0,
                                (const double2*)w->p1, (const double2*)w->p2);
             hipLaunchKernelGGL(k_step_seg, dim3(opi.nlaunch), dim3(256), 0, s, opi, (const ColState*)w->st, w->R,
@@ -2393,7 +2399,8 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
         const void* ptrs[13] = {w->Xi, w->R, w->Z, w->P, w->Q, w->p0, w->p1, w->p2, w->st, w->st2, dinv,
                                 w->snap_ring, w->gcount};
         put(ptrs, sizeof(ptrs));
-        int chv[8] = {ch.kind, ch.a, ch.b, (int)in_consumer, opi.tmap ? tgen : 0, (int)fused, fused_u, (int)fused_seg};
+        int chv[9] = {ch.kind, ch.a, ch.b, (int)in_consumer, opi.tmap ? tgen : 0, (int)fused, fused_u, (int)fused_seg,
+                      seg_u};
         put(chv, sizeof(chv));
         if (w->graph_sig != sig) w->release_graph();
         if (w->graphs[ng - 1] != nullptr) return PETGEM_OK;
@@ -2593,7 +2600,7 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
         st->t_solve_ms = t_solve;
         st->spmv_ms = spmv_ms;
         st->spmv_launches = spmv_n;
-        st->spmv_shape = fused ? 40100 + fused_u : fused_seg ? 50104 : 10000 * ch.kind + 100 * ch.a + ch.b;
+        st->spmv_shape = fused ? 40100 + fused_u : fused_seg ? 50100 + seg_u : 10000 * ch.kind + 100 * ch.a + ch.b;
         st->status = S.outer ? (std::isfinite(S.rnorm64) ? PETGEM_NOT_CONVERGED : PETGEM_NONFINITE) : PETGEM_OK;
         if (st->status != PETGEM_OK && status == PETGEM_OK) status = st->status;
     }
