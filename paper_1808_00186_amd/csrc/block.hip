@@ -1155,7 +1155,7 @@ k_pupdate_p(Op op, int CP, int tpb, const ColState* __restrict__ s0, ColState* _
 // the product's p^T q, q^T D^-1 r, q^T D^-1 q and the previous step's r^T z,
 // |r|^2. kin == 0 (just started): rho and |r|^2 are the state's own;
 // otherwise the convergence test (with the stagnation guard) runs first.
-__device__ void fused_scalars(ColState& S, const double2* t) {
+__device__ __forceinline__ void fused_scalars(ColState& S, const double2* t) {
     if (S.active && S.kin > 0) {   // the r left by the previous step
         const double2 rz = t[3];
         const double r2 = t[4].x;
@@ -1439,12 +1439,18 @@ __global__ void __launch_bounds__(1024)
 k_red_seg(Op op, ColState* __restrict__ st, const double2* __restrict__ ps, const double2* __restrict__ pg,
           const double2* __restrict__ pr) {
     __shared__ double2 red[16][5];
+    __shared__ double2 tot[5];
+    __shared__ ColState s_in;
     const int seg = blockIdx.x;
     if (!st[seg].active) return;   // the same in every thread
+    // the state is copied to LDS first, so its load overlaps the sums
+    if (threadIdx.x < sizeof(ColState) / 8)
+        reinterpret_cast<double*>(&s_in)[threadIdx.x] = reinterpret_cast<const double*>(st + seg)[threadIdx.x];
     const int t0 = op.seg_tile[seg], t1 = op.seg_tile[seg + 1];
     double2 v[5];
 #pragma unroll
     for (int j = 0; j < 5; ++j) v[j] = make_double2(0.0, 0.0);
+    // four tiles per thread in flight
     for (int e0 = t0 + (int)threadIdx.x; e0 < t1; e0 += 4 * 1024) {
         double2 a[4][5];
 #pragma unroll
@@ -1468,15 +1474,16 @@ k_red_seg(Op op, ColState* __restrict__ st, const double2* __restrict__ ps, cons
         if (lane == 0) red[wave][j] = make_double2(sx, sy);
     }
     __syncthreads();
-    if (threadIdx.x != 0) return;
-    double2 t[5];
-#pragma unroll
-    for (int j = 0; j < 5; ++j) {
-        t[j] = red[0][j];
-        for (int k = 1; k < 16; ++k) t[j] = cadd(t[j], red[k][j]);
+    if (threadIdx.x < 5) {   // one sum per thread, the waves in order
+        const int j = threadIdx.x;
+        double2 a = red[0][j];
+        for (int k = 1; k < 16; ++k) a = cadd(a, red[k][j]);
+        tot[j] = a;
     }
-    ColState S = st[seg];
-    fused_scalars(S, t);
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    ColState S = s_in;
+    fused_scalars(S, tot);
     st[seg] = S;
 }
 
