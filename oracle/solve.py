@@ -13,21 +13,52 @@ the 1e-8 of the GPU solve so that the oracle's own error stays far below the
 """
 from __future__ import annotations
 
+import os
+from concurrent.futures import ThreadPoolExecutor
+
 import numpy as np
 import scipy.linalg as sla
+from scipy.linalg import blas
 import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
 from . import fem
 
 
+class RowBlockMatvec:
+    """y = A x by row blocks on a thread pool (SciPy's CSR product releases
+    the interpreter lock). Each row's sum is the same as in A @ x, so the
+    result is bitwise that of the one-thread product; only the wall time
+    changes."""
+
+    def __init__(self, A: sp.csr_matrix, threads: int | None = None):
+        self.threads = threads or int(os.environ.get("ORACLE_THREADS", len(os.sched_getaffinity(0))))
+        n = A.shape[0]
+        self.A = A
+        if self.threads <= 1 or A.nnz < 1_000_000:
+            self.blocks = None
+            return
+        cuts = np.linspace(0, n, self.threads + 1).astype(np.int64)
+        self.blocks = [A[cuts[i]:cuts[i + 1]] for i in range(self.threads)]
+        self.pool = ThreadPoolExecutor(self.threads)
+
+    def __matmul__(self, x):
+        if self.blocks is None:
+            return self.A @ x
+        return np.concatenate(list(self.pool.map(lambda B: B @ x, self.blocks)))
+
+
 def gmres(A: sp.csr_matrix, b: np.ndarray, rtol: float = 1e-12, restart: int = 60,
-          max_iter: int = 200000, x0=None):
+          max_iter: int = 200000, x0=None, progress: int = 0):
     """Restarted GMRES on A D^{-1} y = b, x = D^{-1} y with D = diag(A).
     Stops when the true residual |b - A x| / |b| <= rtol (checked at every
-    restart). Returns (x, iterations, true relative residual)."""
+    restart). Returns (x, iterations, true relative residual).
+    Gram-Schmidt is the modified one; its updates are in-place BLAS axpy
+    (w <- w - h v), and the products run by row blocks on threads
+    (`RowBlockMatvec`): neither changes what is computed."""
     n = len(b)
     dinv = 1.0 / A.diagonal()
+    A = RowBlockMatvec(A)
     x = np.zeros(n, dtype=np.complex128) if x0 is None else np.array(x0, dtype=np.complex128)
     bn = np.linalg.norm(b)
     if bn == 0.0:
@@ -36,6 +67,8 @@ def gmres(A: sp.csr_matrix, b: np.ndarray, rtol: float = 1e-12, restart: int = 6
     while True:
         r = b - A @ x
         rn = np.linalg.norm(r)
+        if progress:
+            print(f"oracle gmres: {it} iterations, true relative residual {rn / bn:.3e}", flush=True)
         if rn <= rtol * bn or it >= max_iter:
             return x, it, rn / bn
         V = np.zeros((restart + 1, n), dtype=np.complex128)
@@ -50,7 +83,7 @@ def gmres(A: sp.csr_matrix, b: np.ndarray, rtol: float = 1e-12, restart: int = 6
             w = A @ (dinv * V[j])
             for i in range(j + 1):
                 H[i, j] = np.vdot(V[i], w)
-                w = w - H[i, j] * V[i]
+                w = blas.zaxpy(V[i], w, a=-H[i, j])
             H[j + 1, j] = np.linalg.norm(w)
             if H[j + 1, j] != 0.0:
                 V[j + 1] = w / H[j + 1, j]
@@ -74,7 +107,7 @@ def gmres(A: sp.csr_matrix, b: np.ndarray, rtol: float = 1e-12, restart: int = 6
         x = x + dinv * (V[:m].T @ y)
 
 
-def solve_system(A: sp.csr_matrix, b: np.ndarray, rtol: float = 1e-12):
+def solve_system(A: sp.csr_matrix, b: np.ndarray, rtol: float = 1e-12, progress: int = 0):
     """Dense LU up to 6000 unknowns, sparse LU up to 60000, GMRES above.
     Returns (x, true relative residual, method)."""
     n = A.shape[0]
@@ -86,13 +119,13 @@ def solve_system(A: sp.csr_matrix, b: np.ndarray, rtol: float = 1e-12):
         x = spla.spsolve(A.tocsc(), b)
         method = "splu"
     else:
-        x, _, _ = gmres(A, b, rtol=rtol)
+        x, _, _ = gmres(A, b, rtol=rtol, progress=progress)
         method = "gmres"
     res = np.linalg.norm(b - A @ x) / bn if bn > 0 else 0.0
     return x, res, method
 
 
-def forward(model, src_index: int = 0, sys_=None, rtol: float = 1e-12):
+def forward(model, src_index: int = 0, sys_=None, rtol: float = 1e-12, progress: int = 0):
     """End-to-end oracle response of one source: assemble, right-hand side,
     solve, total field at the receivers. Returns a dict."""
     xyz, tets = model.xyz, model.tets
@@ -102,7 +135,7 @@ def forward(model, src_index: int = 0, sys_=None, rtol: float = 1e-12):
     A = fem.system_matrix(sys_, s.freq)
     b = fem.rhs(xyz, tets, model.sigma, model.sigma_bg, sys_.topo, s.pos, s.dir,
                 s.freq, s.moment)
-    x, res, method = solve_system(A, b, rtol)
+    x, res, method = solve_system(A, b, rtol, progress)
     E = fem.receivers_total(xyz, tets, sys_.topo, x, model.receivers, s.pos, s.dir,
                             s.freq, model.sigma_bg, s.moment)
     Es = fem.interpolate(xyz, tets, sys_.topo, x, model.receivers)

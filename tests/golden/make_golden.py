@@ -3,11 +3,21 @@
 Calls only the CPU oracle (``oracle/``) and the seeded input generator; no
 value comes from the GPU library. Run from the repository root:
 
-    python tests/golden/make_golden.py cfg2
+    python tests/golden/make_golden.py cfg2 cfg3 cfg4
 
 cfg2 -- the marine layered model (n = 40, 433,720 unknowns): receiver total and
 secondary fields of its single source, solved by the oracle's Jacobi GMRES to
 a true relative residual of 1e-12, plus the residual reached.
+
+cfg3 -- the same model at n = 100 (6,910,300 unknowns): a stated subset of its
+96 sources (dipole positions x = -3100 + 200 i), each solved by the oracle's
+Jacobi GMRES(60) to 1e-12; one file per source, ``cfg3_f<freq>_i<i>.npz``.
+The centre dipole (i = 16) at 1.25 Hz comes first, then the end dipole at
+1.25 Hz and the centre dipole at the two lower frequencies.
+
+cfg4 -- the largest (seed 4018, 1,361,886 elements) and the slowest to
+converge (seed 4047, 1,296,000 elements at 0.61 Hz) of the 48 uneven-batch
+models, to 1e-12; ``cfg4_<seed>.npz``.
 """
 import os
 import sys
@@ -22,16 +32,49 @@ from oracle import fem, solve  # noqa: E402
 from paper_1808_00186_amd import synth  # noqa: E402
 
 HERE = os.path.dirname(os.path.abspath(__file__))
+CFG3_PICKS = ((1.25, 16), (1.25, 0), (0.5, 16), (0.25, 16))
+CFG4_SEEDS = (4018, 4047)
+
+
+def _save(name, m, r, src_index, t0, **extra):
+    np.savez_compressed(os.path.join(HERE, name), E=r["E"], Es=r["Es"], residual=r["residual"],
+                        receivers=m.receivers, n_dof=r["sys"].topo.n_dof, nnz=r["sys"].K.nnz,
+                        src_index=src_index, **extra)
+    print(f"{name}: {r['method']} residual {r['residual']:.3e} in {time.time() - t0:.1f} s", flush=True)
 
 
 def cfg2():
     t0 = time.time()
     m = synth.config2()
     r = solve.forward(m, rtol=1e-12)
-    np.savez_compressed(os.path.join(HERE, "cfg2_receivers.npz"), E=r["E"], Es=r["Es"],
-                        residual=r["residual"], receivers=m.receivers,
-                        n_dof=r["sys"].topo.n_dof, nnz=r["sys"].K.nnz)
-    print(f"cfg2: {r['method']} residual {r['residual']:.3e} in {time.time() - t0:.1f} s")
+    _save("cfg2_receivers.npz", m, r, 0, t0)
+
+
+def cfg3(picks=CFG3_PICKS):
+    t0 = time.time()
+    m = synth.config3()
+    s = fem.assemble(m.xyz, m.tets, m.sigma)
+    print(f"cfg3 oracle assembly: {s.topo.n_dof} unknowns, {s.K.nnz} nonzeros, {time.time() - t0:.1f} s",
+          flush=True)
+    for f, i in picks:
+        name = f"cfg3_f{f:g}_i{i}.npz"
+        if os.path.exists(os.path.join(HERE, name)):
+            continue
+        k = synth.CFG3_FREQS.index(f) * 32 + i
+        t1 = time.time()
+        r = solve.forward(m, k, sys_=s, rtol=1e-12, progress=1)
+        _save(name, m, r, k, t1, freq=f, pos=np.array(m.sources[k].pos))
+
+
+def cfg4(seeds=CFG4_SEEDS):
+    for seed in seeds:
+        name = f"cfg4_{seed}.npz"
+        if os.path.exists(os.path.join(HERE, name)):
+            continue
+        t0 = time.time()
+        m = synth.config4_model(seed)
+        r = solve.forward(m, rtol=1e-12, progress=1)
+        _save(name, m, r, 0, t0, seed=seed, n_tets=len(m.tets))
 
 
 if __name__ == "__main__":
