@@ -187,9 +187,12 @@ def system_matrix(sys_: System, freq: float) -> sp.csr_matrix:
 
 
 def rhs(xyz, tets, sigma, sigma_bg, topo: Topology, src_pos, src_dir, freq,
-        moment=1.0) -> np.ndarray:
+        moment=1.0, field=None) -> np.ndarray:
     """b_i = i omega mu0 sum_e dsigma_e sum_q w_q N_i(x_q) . E_p(x_q) over the
-    elements with dsigma_e != 0 (Section 3, eq. 9; Appendix A for E_p)."""
+    elements with dsigma_e != 0 (Section 3, eq. 9; Appendix A for E_p).
+    ``field`` (points [..][3] -> complex [..][3]) replaces E_p when given
+    (a test hook: a field in the edge-element space has a closed-form
+    right-hand side)."""
     sigma = np.asarray(sigma, dtype=np.float64)
     dsig = sigma - sigma_bg
     sel = np.flatnonzero(dsig != 0.0)
@@ -202,7 +205,10 @@ def rhs(xyz, tets, sigma, sigma_bg, topo: Topology, src_pos, src_dir, freq,
     sign = topo.elem_sign[sel]
     lam = np.broadcast_to(QUAD4, (len(sel), 4, 4))
     xq = np.einsum("tqv,tvk->tqk", lam, X)
-    Ep = dipole_field(xq, src_pos, src_dir, freq, sigma_bg, moment)       # [T][4][3]
+    if field is None:
+        Ep = dipole_field(xq, src_pos, src_dir, freq, sigma_bg, moment)   # [T][4][3]
+    else:
+        Ep = np.asarray(field(xq), dtype=np.complex128)
     N = basis_at(g, sign, ell, lam)                                        # [T][4][6][3]
     Re = (vol / 4.0)[:, None] * np.einsum("tqik,tqk->ti", N, Ep)           # [T][6]
     omega = 2.0 * np.pi * freq

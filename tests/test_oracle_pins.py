@@ -323,7 +323,42 @@ def _born_secondary(xyz, tets, mask, dsig, src, p, f, sigma_bg, probes):
     return out
 
 
-@pytest.mark.slow
+@pytest.mark.parametrize("seed", [3, 8])
+def test_rhs_of_an_edge_element_field_is_its_mass_product(seed):
+    """Eq. 9 with E_p replaced by a field u = a + b x x of the lowest-order
+    edge-element space: N_i . u is a polynomial of degree 2, which the 4-point
+    rule integrates exactly, and u = sum_j u_j N_j with u_j its tangential
+    component at the midpoint of edge j, so the right-hand side must be
+    i w mu0 (sum_e dsigma_e M^e) u over the interior rows, to round-off. The
+    mass matrices come from the closed form of eq. B.14 (not from the
+    quadrature), so a wrong weight, a dropped dsigma, a wrong local sign or a
+    transposed basis evaluation in the quadrature path fails this."""
+    rng = np.random.default_rng(seed)
+    xyz, tets = synth.kuhn_mesh(4, -1000.0, 1000.0, seed)
+    topo = fem.topology(xyz, tets)
+    sig = rng.uniform(0.2, 3.0, len(tets))
+    sig[rng.random(len(tets)) < 0.4] = 1.3          # elements with dsigma = 0 are skipped
+    sb, f = 1.3, 0.7
+    a = rng.standard_normal(3) + 1j * rng.standard_normal(3)
+    bb = (rng.standard_normal(3) + 1j * rng.standard_normal(3)) / 500.0
+
+    def u(pts):
+        return a + np.cross(np.broadcast_to(bb, pts.shape), pts)
+
+    b = fem.rhs(xyz, tets, sig, sb, topo, (0.0, 0.0, 5000.0), np.array([1.0, 0.0, 0.0]), f, field=u)
+    lo, hi = xyz[topo.edge_nodes[:, 0]], xyz[topo.edge_nodes[:, 1]]
+    t = (hi - lo) / np.linalg.norm(hi - lo, axis=1)[:, None]
+    ue = np.sum(u(0.5 * (lo + hi)) * t, axis=1)                 # every edge, boundary included
+    Md = fem.assemble(xyz, tets, sig - sb, topo, full=True).Ms   # sum_e dsigma_e M^e
+    want_all = 1j * 2 * np.pi * f * primary.MU0 * (Md @ ue)
+    interior = np.flatnonzero(topo.dof_of_edge >= 0)
+    want = np.zeros(topo.n_dof, dtype=complex)
+    want[topo.dof_of_edge[interior]] = want_all[interior]
+    assert np.abs(b - want).max() <= 1e-12 * np.abs(want).max()
+    # a 1 % error in the quadrature weights is far outside that bound
+    assert np.abs(1.01 * b - want).max() > 1e-4 * np.abs(want).max()
+
+
 def test_secondary_field_matches_born_limit_and_converges():
     """Whole chain (eqs. 6, 9, 8 and Appendix A) against an independent
     reference: for a weak anomaly (dsigma/sigma = -1e-4) the exact secondary
