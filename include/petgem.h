@@ -98,7 +98,13 @@ typedef struct {
     int32_t spmm_shape;     /* COCG: 0 = autotune the complex64 SpMM shape;
                                otherwise that shape, encoded as the
                                spmv_shape statistic (PETGEM_INVALID_ARG if it
-                               is not a candidate for this column count)       */
+                               is not a candidate for this column count, see
+                               petgem_spmm_candidates); 40104 / 40108 force
+                               the fused single-column step and 50104 / 50108
+                               the fused step with one reduction block per
+                               mesh, with 4 or 8 slice columns in flight (one
+                               column per mesh only; 4010x also needs at most
+                               8192 tiles of 256 rows)                         */
 } petgem_opts;
 
 typedef struct {
@@ -248,6 +254,12 @@ int petgem_locate(const petgem_mesh* mesh, const double* pts, int32_t n_pts, dou
 int petgem_tuning(const petgem_system* sys, int32_t* spmv_group, float* spmv_ms);
 /* Seconds spent in the host preprocessing of the last petgem_assemble. */
 double petgem_setup_seconds(const petgem_system* sys);
+/* Host-only: the complex64 SpMM shapes the autotuner times for n_cols
+ * columns (sliced != 0: with the sliced-ELLPACK copy, which one mesh has for
+ * up to four columns), as petgem_opts.spmm_shape codes. Writes at most cap
+ * codes to shapes (host int32, may be NULL when cap is 0) and returns how
+ * many there are, or PETGEM_INVALID_ARG. */
+int32_t petgem_spmm_candidates(int32_t n_cols, int32_t sliced, int32_t* shapes, int32_t cap);
 
 /* ---- learned initial guess (not in the paper) -------------------------------
  * A small 3D U-Net on a 32^3 voxel grid covering the mesh's bounding box

@@ -2164,7 +2164,17 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
     Timer t_all;
     SpmmTuned tu;
     PG_TRY(tune_spmm(w, op, nnz, s, tu, o.verbose != 0));
-    if (o.spmm_shape != 0) {   // a caller-chosen shape instead of the tuned one
+    // a caller-chosen fused step (kind 4: one column of one mesh, kind 5: one
+    // column per mesh with a reduction block per mesh), with 4 or 8 slice
+    // columns in flight; the other kernels keep the tuned shapes
+    const int force_kind = o.spmm_shape / 10000;
+    const bool force_fused = (force_kind == 4 || force_kind == 5) && o.spmm_shape % 10000 / 100 == 1 &&
+                             (o.spmm_shape % 100 == 4 || o.spmm_shape % 100 == 8);
+    if (force_fused && (C != 1 || op.sp == nullptr)) {
+        set_error("spmm_shape " + std::to_string(o.spmm_shape) + " (a fused step) needs one column per mesh");
+        return PETGEM_INVALID_ARG;
+    }
+    if (o.spmm_shape != 0 && !force_fused) {   // a caller-chosen shape instead of the tuned one
         bool found = false;
         for (const SpmmChoice& c : candidates(op.C, op.sp != nullptr))
             if (10000 * c.kind + 100 * c.a + c.b == o.spmm_shape) {
@@ -2189,11 +2199,33 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
     // the reductions run inside the vector kernels for one mesh whose
     // partials are few enough for every block to sum
     const bool in_consumer = op.nseg == 1 && (int64_t)op.ntiles * ppS * C <= kConsumerMax;
+    const int nspb = ceil_div((int64_t)op.ntiles * 4, kSpbWaves);   // blocks (and partials) of the fused product
+    const int nst = ceil_div(op.ntiles, kStepTiles);                // blocks of the fused step
+    // One column of one mesh with a sliced-ELLPACK copy takes the fused step
+    // (the product with its two extra partials, then one vector kernel) when
+    // every step block can sum the product's partials, whichever product
+    // shape the tuner timed fastest on its own: the step saves more than the
+    // shapes differ (its own product is the pipelined one with 4 slice
+    // columns in flight; 8 measured 2 % slower). The gate depends on the
+    // fused kernels' own partial counts only, never on the tuned shape, so
+    // the kernel path does not follow the tuner's timing noise. A
+    // caller-chosen shape is honoured as given: shape 3 (or 4) runs fused,
+    // the others not.
+    const bool fused_fits = op.nseg == 1 && C == 1 && op.sp != nullptr && nspb <= kConsumerMax;
+    const bool fused = fused_fits && force_kind != 5 &&
+                       (o.spmm_shape == 0 || force_kind == 4 ||
+                        (ch.kind == 3 && ch.a == 1 && (ch.b == 4 || ch.b == 8)));
+    const int fused_u = o.spmm_shape == 0 ? 4 : force_fused ? o.spmm_shape % 100 : ch.b;
+    if (force_kind == 4 && !fused) {
+        set_error("spmm_shape " + std::to_string(o.spmm_shape) + " (the fused single-column step) needs one mesh "
+                  "of at most " + std::to_string(kConsumerMax) + " tiles");
+        return PETGEM_INVALID_ARG;
+    }
     // one column of one system: D^-1 once per solve in complex64 (an uneven
     // batch keeps the double-precision diagonal: its hardest models need a few
     // percent more iterations with the rounded D^-1)
     const float2* dinv = nullptr;
-    if (in_consumer && C == 1) {
+    if ((in_consumer && C == 1) || fused) {
         const size_t rows = (size_t)op.ntiles * kTR;
         if (w->dinv_rows < rows) {
             dfree(w->Dinv);
@@ -2206,23 +2238,12 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
         dinv = w->Dinv;
     }
     const int nbu = ceil_div(op.ntiles, kConsumerTiles);   // blocks of the two vector kernels
-    // One column with D^-1 and a sliced-ELLPACK copy takes the fused step
-    // (the product with its two extra partials, then one vector kernel),
-    // whichever product shape the tuner timed fastest on its own: the step
-    // saves more than the shapes differ (its own product is the pipelined
-    // one with 4 slice columns in flight; 8 measured 2 % slower). A
-    // caller-chosen shape is honoured as given: shape 3 runs fused, others not.
-    const bool fused = dinv != nullptr && op.sp != nullptr &&
-                       (o.spmm_shape == 0 || (ch.kind == 3 && ch.a == 1 && (ch.b == 4 || ch.b == 8)));
-    const int fused_u = o.spmm_shape == 0 ? 4 : ch.b;   // slice columns in flight in the fused product
     // one column per mesh otherwise (an uneven batch, or one mesh too large for
     // every block to sum its partials): the fused step with a reduction block
-    // per mesh, for a tuned shape
-    const bool fused_seg = !fused && C == 1 && op.sp != nullptr && o.spmm_shape == 0;
+    // per mesh, for a tuned shape or when chosen (shape 5)
+    const bool fused_seg = !fused && C == 1 && op.sp != nullptr && (o.spmm_shape == 0 || force_kind == 5);
     // its product keeps the slice columns in flight of the tuned sliced-ELLPACK shape
-    const int seg_u = ch.kind >= 2 && ch.a == 1 && ch.b == 8 ? 8 : 4;
-    const int nspb = ceil_div((int64_t)op.ntiles * 4, kSpbWaves);   // blocks (and partials) of its product
-    const int nst = ceil_div(op.ntiles, kStepTiles);                // blocks of the step
+    const int seg_u = force_kind == 5 ? o.spmm_shape % 100 : ch.kind >= 2 && ch.a == 1 && ch.b == 8 ? 8 : 4;
     int64_t groups_done = 0;   // groups launched since the fused step's group count was cleared
     if (fused) {
         if (!w->snap_ring)
@@ -2630,6 +2651,16 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
 }
 
 }  // namespace
+
+int spmm_candidate_codes(int C, bool sliced, int32_t* out, int cap) {
+    const auto v = candidates(C, sliced);
+    int n = 0;
+    for (const SpmmChoice& c : v) {
+        if (out && n < cap) out[n] = 10000 * c.kind + 100 * c.a + c.b;
+        ++n;
+    }
+    return n;
+}
 
 int block_solve(petgem_system* sys, const petgem_source* src, int32_t n_src, const petgem_opts& o,
                 const double2* x0, double2* x_out, hipStream_t s, petgem_stats* st) {

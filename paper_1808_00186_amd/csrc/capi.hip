@@ -397,6 +397,14 @@ int petgem_tuning(const petgem_system* sys, int32_t* spmv_group, float* spmv_ms)
 
 double petgem_setup_seconds(const petgem_system* sys) { return sys ? sys->setup_seconds : -1.0; }
 
+int32_t petgem_spmm_candidates(int32_t n_cols, int32_t sliced, int32_t* shapes, int32_t cap) {
+    if (n_cols < 1 || cap < 0 || (cap > 0 && !shapes)) {
+        set_error("petgem_spmm_candidates: n_cols >= 1 and a shapes array of cap entries");
+        return PETGEM_INVALID_ARG;
+    }
+    return spmm_candidate_codes(n_cols, sliced != 0, shapes, cap);
+}
+
 int petgem_get_dof_edges(const petgem_system* sys, int32_t* edges) {
     PG_TRY(check_sys(sys));
     if (!edges) { set_error("null output"); return PETGEM_INVALID_ARG; }

@@ -215,6 +215,9 @@ int batch_solve(petgem_system* const* systems, const petgem_source* src, int32_t
                 const petgem_opts& o, const void* const* x0, petgem_solution** sols, hipStream_t s,
                 petgem_stats* st);
 int ensure_fp32(petgem_system* sys, hipStream_t s);
+// complex64 SpMM shapes the autotuner times for C columns (codes as the
+// spmv_shape statistic); returns the count, writes at most cap codes
+int spmm_candidate_codes(int C, bool sliced, int32_t* out, int cap);
 
 // Grid helpers
 inline int ceil_div(int64_t a, int64_t b) { return int((a + b - 1) / b); }

@@ -87,6 +87,7 @@ _SIGS = {
                                  C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_void_p]),
     "petgem_spmv": (C.c_int, [C.c_void_p, C.c_double, C.c_void_p, C.c_void_p, C.c_void_p]),
     "petgem_setup_seconds": (C.c_double, [C.c_void_p]),
+    "petgem_spmm_candidates": (C.c_int32, [C.c_int32, C.c_int32, C.POINTER(C.c_int32), C.c_int32]),
     "petgem_tuning": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_float)]),
     "petgem_mesh_pattern": (C.c_int, [C.POINTER(Mesh), C.POINTER(C.c_int32), C.POINTER(C.c_int64),
                                       C.POINTER(C.c_int32), C.POINTER(C.c_int32),
@@ -422,6 +423,22 @@ def mesh_pattern(xyz, tets):
     P = lambda a: a.ctypes.data_as(C.POINTER(C.c_int32))
     _check(lib().petgem_mesh_pattern(C.byref(m), C.byref(n), C.byref(nnz), P(de), P(rp), P(col)))
     return de, rp, col
+
+
+def spmm_candidates(n_cols: int, sliced: bool) -> List[int]:
+    """The complex64 SpMM shapes the autotuner times for n_cols columns
+    (``spmm_shape`` codes); host only."""
+    L = lib()
+    n = _check_count(L.petgem_spmm_candidates(n_cols, int(sliced), None, 0))
+    out = (C.c_int32 * max(n, 1))()
+    _check_count(L.petgem_spmm_candidates(n_cols, int(sliced), out, n))
+    return list(out[:n])
+
+
+def _check_count(n: int) -> int:
+    if n < 0:
+        raise PetgemError(n, lib().petgem_last_error().decode())
+    return n
 
 
 def locate(xyz, tets, pts, tol=1e-12):

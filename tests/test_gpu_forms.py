@@ -113,38 +113,60 @@ def test_cocg_cfg2_single_source_matches_stored_oracle(pg):
     print(f"cfg2 COCG mixed iters {st[0]['iters']} ir {st[0]['ir_steps']} res "
           f"{st[0]['rel_residual']:.2e} rx err {err:.2e} solve {st[0]['t_solve_ms']:.1f} ms", flush=True)
     assert rc == pg.OK and st[0]["rel_residual"] <= 1e-9
+    # 1,695 tiles: the fused single-column step, whatever shape the tuner timed fastest
+    assert st[0]["spmv_shape"] in (40104, 40108), st[0]["spmv_shape"]
     assert err <= 1e-6
 
 
-# every complex64 SpMM shape the autotuner can pick, per column count:
-# 10000 kind + 100 a + b (kind 0 CSR column lanes, 1 CSR nonzero lanes,
-# 2 sliced ELLPACK, 3 pipelined sliced ELLPACK; one column of one mesh runs
-# kind 3 as the fused step and reports kind 4)
-SHAPES = {
-    1: [10401, 10801, 11601, 20104, 20108, 30104, 30108],
-    3: [10404, 10804, 11604, 20404],
-    33: [1603, 1604, 3202, 6401],
-}
+# every complex64 SpMM shape the autotuner can pick, per column count, as the
+# library lists them (petgem_spmm_candidates): 10000 kind + 100 a + b (kind 0
+# CSR column lanes, 1 CSR nonzero lanes, 2 sliced ELLPACK, 3 pipelined sliced
+# ELLPACK; one column of one mesh runs kind 3 as the fused step and reports
+# kind 4), plus, for one column, the two fused steps forced with 4 and 8 slice
+# columns in flight. 32 columns at one frequency is the block shape of the
+# 6.9M-unknown survey; 33 columns over three frequencies leaves a ragged lane.
+SHAPE_COLS = (1, 2, 3, 4, 32, 33)
 
 
-@pytest.mark.parametrize("C", sorted(SHAPES))
+def _shapes(pg, C):
+    v = pg.spmm_candidates(C, C <= 4)
+    if C == 1:
+        v += [40104, 40108, 50104, 50108]
+    return v
+
+
+def _shape_sources(C):
+    if C == 33:
+        return _survey_sources(11, (0.25, 1.0, 3.0))
+    if C == 32:
+        return _survey_sources(32, (1.25,))
+    return _survey_sources(C, (1.5,))
+
+
+@pytest.mark.parametrize("C", SHAPE_COLS)
 def test_every_spmm_shape_matches_oracle(pg, C):
     m = synth.config1()
-    srcs = _survey_sources(C, (1.5,)) if C < 33 else _survey_sources(11, (0.25, 1.0, 3.0))
+    srcs = _shape_sources(C)
     ref = _oracle_fields(m, srcs)
     S = pg.System.from_model(m)
-    for shape in SHAPES[C]:
+    shapes = _shapes(pg, C)
+    assert shapes, C
+    for shape in shapes:
         print(f"[case] cfg1 C={C} shape {shape}", flush=True)
         o = pg.default_opts(method=pg.COCG, precision=pg.MIXED, rtol=1e-8, spmm_shape=shape)
         sol, st, rc = S.solve(srcs, o)
         want = shape + 10000 if C == 1 and shape // 10000 == 3 else shape
-        assert rc == pg.OK and all(s_["spmv_shape"] == want for s_ in st)
+        assert rc == pg.OK and all(s_["spmv_shape"] == want for s_ in st), (shape, st[0]["spmv_shape"])
         E = sol.receivers(m.receivers).cpu().numpy()
         err = max(fem.receiver_error(E[k], ref[k]) for k in range(len(srcs)))
         print(f"  shape {shape}: iters {st[0]['iters']} err {err:.1e}", flush=True)
+        assert all(s_["rel_residual"] <= 1e-8 for s_ in st)
         assert err <= 1e-6
     with pytest.raises(pg.PetgemError):
         S.solve(srcs, pg.default_opts(method=pg.COCG, precision=pg.MIXED, spmm_shape=99999))
+    if C > 1:   # the fused steps take one column only
+        with pytest.raises(pg.PetgemError):
+            S.solve(srcs, pg.default_opts(method=pg.COCG, precision=pg.MIXED, spmm_shape=40104))
 
 
 def _small_marine(seed, n, f):
@@ -167,6 +189,8 @@ def test_solve_many_uneven_batch_matches_oracle(pg):
     o = pg.default_opts(method=pg.COCG, precision=pg.MIXED, rtol=1e-9)
     sols, st, rc = pg.solve_many(systems, [mm.sources[0] for mm in models], o)
     assert rc == pg.OK
+    # one column per mesh takes the fused step with a reduction block per mesh
+    assert all(s_["spmv_shape"] in (50104, 50108) for s_ in st), [s_["spmv_shape"] for s_ in st]
     for k, mm in enumerate(models):
         E = sols[k].receivers(mm.receivers).cpu().numpy()[0]
         ref = solve.forward(mm)["E"]
@@ -210,6 +234,7 @@ def test_uneven_batch_of_smallest_cfg4_models_matches_oracle(pg):
     o = pg.default_opts(method=pg.COCG, precision=pg.MIXED, rtol=1e-12)
     sols, st, rc = pg.solve_many(systems, [m.sources[0] for m in small], o)
     assert rc == pg.OK
+    assert all(s_["spmv_shape"] in (50104, 50108) for s_ in st), [s_["spmv_shape"] for s_ in st]
     for k, m in enumerate(small):
         E = sols[k].receivers(m.receivers).cpu().numpy()[0]
         err = fem.receiver_error(E, solve.forward(m)["E"])

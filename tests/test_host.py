@@ -131,3 +131,24 @@ def test_bench_names_and_prices_the_fused_product():
     assert name in bench.MEASURED_TRAFFIC
     assert bench.kernel_name("mixed", 30104).startswith("k_spmm_sp<1, 4>")
     assert bench.kernel_name("plain", 8).startswith("k_spmv<8, false>")
+
+
+def test_spmm_candidates_listed_by_the_library():
+    """The autotuner's shape lists (host only): sliced ELLPACK only with the
+    sliced copy and up to four columns, column lanes from four columns on,
+    every list non-empty, and a column lane layout always covers the block."""
+    for C in (1, 2, 3, 4, 5, 8, 16, 32, 33, 96, 300):
+        for sliced in (False, True):
+            v = petgem.spmm_candidates(C, sliced)
+            assert v, (C, sliced)
+            for code in v:
+                kind, a, b = code // 10000, code // 100 % 100, code % 100
+                assert kind in (0, 1, 2, 3)
+                if kind >= 2:
+                    assert sliced and C <= 4
+                if kind == 0:
+                    assert C >= 4 and (a * b >= C or (a, b) == (64, 4))
+                if kind == 1:
+                    assert C <= 4
+    with pytest.raises(petgem.PetgemError):
+        petgem.spmm_candidates(0, False)
