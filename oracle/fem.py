@@ -35,7 +35,7 @@ from dataclasses import dataclass
 import numpy as np
 import scipy.sparse as sp
 
-from .primary import MU0, dipole_field
+from .primary import MU0, dipole_field, dipole_magnetic_field
 
 LOCAL_EDGES = np.array([(0, 1), (0, 2), (0, 3), (1, 2), (3, 1), (2, 3)], dtype=np.int64)
 FACES = np.array([(1, 2, 3), (0, 2, 3), (0, 1, 3), (0, 1, 2)], dtype=np.int64)
@@ -261,6 +261,32 @@ def receivers_total(xyz, tets, topo, e_dof, points, src_pos, src_dir, freq,
     """Total field E = E_p + E_s at the receivers (Section 2, eq. 4)."""
     return (dipole_field(points, src_pos, src_dir, freq, sigma_bg, moment)
             + interpolate(xyz, tets, topo, e_dof, points))
+
+
+def curl_at(xyz, tets, topo: Topology, e_dof: np.ndarray, points) -> np.ndarray:
+    """curl E = sum_i e_i curl N_i in the element containing each point, with
+    curl N_i = 2 s_i l_i grad lambda_a x grad lambda_b (constant per element;
+    Appendix B); boundary edges carry zero. Returns complex128 [R][3]."""
+    elem, _ = locate(xyz, tets, points)
+    if np.any(elem < 0):
+        raise ValueError("receiver outside the mesh")
+    vol, g, X = geometry(xyz, np.asarray(tets)[elem])
+    ell = edge_lengths(X)
+    sign = topo.elem_sign[elem]
+    ea, eb = LOCAL_EDGES[:, 0], LOCAL_EDGES[:, 1]
+    curl = 2.0 * (sign * ell)[:, :, None] * np.cross(g[:, ea], g[:, eb])     # [R][6][3]
+    dof = topo.dof_of_edge[topo.elem_edge[elem]]
+    vals = np.where(dof >= 0, np.asarray(e_dof)[np.maximum(dof, 0)], 0.0)
+    return np.einsum("rik,ri->rk", curl, vals)
+
+
+def receivers_total_h(xyz, tets, topo, e_dof, points, src_pos, src_dir, freq,
+                      sigma_bg, moment=1.0) -> np.ndarray:
+    """Total magnetic field H = H_p + curl E_s / (i omega mu0) at the receivers
+    (Faraday's law, Section 2, eq. 1, e^{-i omega t})."""
+    omega = 2.0 * np.pi * freq
+    return (dipole_magnetic_field(points, src_pos, src_dir, freq, sigma_bg, moment)
+            + curl_at(xyz, tets, topo, e_dof, points) / (1j * omega * MU0))
 
 
 def receiver_error(E_test: np.ndarray, E_ref: np.ndarray) -> float:

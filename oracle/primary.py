@@ -19,6 +19,10 @@ appendix are the cases p = x, y, z of this formula with k replaced by -k
 (complex conjugate convention). It equals (1/sigma)(k^2 + grad grad) G p with
 G = e^{ikr} / (4 pi r), the solution of the first-order system of Section 2
 (eqs. 1-2) for a point current source.
+
+The magnetic field follows from Faraday's law of Section 2 (eq. 1 with the
+e^{-i omega t} sign), H = curl E / (i omega mu0): the gradient part of E has
+no curl and k^2 = i omega mu0 sigma, so H_p = I dS grad G x p.
 """
 from __future__ import annotations
 
@@ -73,3 +77,17 @@ def dipole_field_appendix_rows(x: np.ndarray, src_pos, axis: int, freq: float,
             q = q + (kr * kr - 1j * kr - 1.0)
         out[..., j] = pref * q
     return out
+
+
+def dipole_magnetic_field(x: np.ndarray, src_pos, src_dir, freq: float, sigma: float,
+                          moment: float = 1.0) -> np.ndarray:
+    """Primary magnetic field H_p = curl E_p / (i omega mu0) = I dS grad G x p
+    (complex128 [..., 3], A/m) at points x [..., 3]:
+    grad G = (ikr - 1) e^{ikr} / (4 pi r^3) d, d = x - x_s."""
+    x = np.asarray(x, dtype=np.float64)
+    p = np.asarray(src_dir, dtype=np.float64)
+    d = x - np.asarray(src_pos, dtype=np.float64)
+    r = np.sqrt(np.sum(d * d, axis=-1))
+    kr = wavenumber(freq, sigma) * r
+    amp = moment * (1j * kr - 1.0) * np.exp(1j * kr) / (4.0 * np.pi * r ** 3)
+    return amp[..., None] * np.cross(d, np.broadcast_to(p, d.shape))

@@ -305,6 +305,49 @@ def test_skin_depth_worked_values():
     assert np.isclose(k, (1 + 1j) / primary.skin_depth(1.3, 0.8), rtol=1e-14)
 
 
+def test_primary_magnetic_field_is_curl_of_electric_field():
+    """H_p of the oracle (closed form) against curl E_p / (i w mu0) by central
+    differences of the electric field, for three directions and moments."""
+    rng = np.random.default_rng(4)
+    for p in (np.eye(3)[0], np.eye(3)[1], np.array([0.3, -0.5, 0.81]) / np.linalg.norm([0.3, -0.5, 0.81])):
+        src, f, sig, mom = rng.uniform(-50, 50, 3), 0.8, 1.7, 2.5
+        pts = src + rng.uniform(-900, 900, (12, 3))
+        pts = pts[np.linalg.norm(pts - src, axis=1) > 100.0]   # central differences lose accuracy at kr << 1
+        H = primary.dipole_magnetic_field(pts, src, p, f, sig, mom)
+        curl = np.zeros_like(H)
+        for i, pt in enumerate(pts):
+            hstep = 1e-5 * np.linalg.norm(pt - src)
+            J = np.zeros((3, 3), dtype=complex)    # J[a, b] = dE_a / dx_b
+            for bdir in range(3):
+                e = np.eye(3)[bdir] * hstep
+                J[:, bdir] = (primary.dipole_field((pt + e)[None], src, p, f, sig, mom)[0]
+                              - primary.dipole_field((pt - e)[None], src, p, f, sig, mom)[0]) / (2 * hstep)
+            curl[i] = [J[2, 1] - J[1, 2], J[0, 2] - J[2, 0], J[1, 0] - J[0, 1]]
+        want = curl / (1j * 2 * np.pi * f * primary.MU0)
+        err = np.linalg.norm(H - want, axis=1) / np.linalg.norm(want, axis=1)
+        assert err.max() < 1e-6, err.max()
+
+
+def test_curl_of_edge_element_field_is_exact():
+    """For u = a + b x x in the edge-element space, interpolated by its
+    tangential midpoint components, the per-element curl is 2 b exactly."""
+    rng = np.random.default_rng(6)
+    xyz, tets = synth.kuhn_mesh(4, -1000.0, 1000.0, 6)
+    topo = fem.topology(xyz, tets)
+    a = rng.standard_normal(3) + 1j * rng.standard_normal(3)
+    bb = (rng.standard_normal(3) + 1j * rng.standard_normal(3)) / 300.0
+    lo, hi = xyz[topo.edge_nodes[:, 0]], xyz[topo.edge_nodes[:, 1]]
+    t = (hi - lo) / np.linalg.norm(hi - lo, axis=1)[:, None]
+    mid = 0.5 * (lo + hi)
+    ue = np.sum((a + np.cross(np.broadcast_to(bb, mid.shape), mid)) * t, axis=1)
+    interior = np.flatnonzero(topo.dof_of_edge >= 0)
+    x = np.zeros(topo.n_dof, dtype=complex)
+    x[topo.dof_of_edge[interior]] = ue[interior]
+    pts = rng.uniform(-240, 240, (15, 3))       # inside elements with no boundary edge
+    c = fem.curl_at(xyz, tets, topo, x, pts)
+    assert np.abs(c - 2 * bb).max() <= 1e-12 * np.abs(bb).max()
+
+
 # ------------------------------------------------------- whole solve (V6, V7, V8, V9)
 
 def _born_secondary(xyz, tets, mask, dsig, src, p, f, sigma_bg, probes):
