@@ -217,6 +217,19 @@ int petgem_solve_many(petgem_system* const* systems, const petgem_source* src,
 int petgem_receivers(const petgem_solution* sol, const double* rx, int32_t n_rx,
                      void* E_dev, void* Es_dev, void* stream);
 
+/* Magnetic field at the receivers (not in the paper, which reports E only):
+ * H = curl E / (i w mu0) from Faraday's law of Section 2 (eq. 1, e^{-i w t}),
+ * i.e. H_p + curl(sum_i e_i N_i) / (i w mu0) in the receiver's element (the
+ * curl of a lowest-order edge field is constant per element; boundary DOFs
+ * are zero), H_p = moment (ikr - 1) e^{ikr} / (4 pi r^3) (d x dir) the
+ * analytic field of the dipole of Appendix A (d = x - pos). Receivers are
+ * located as in petgem_receivers (the same cache).
+ *   H_dev   device complex128 [n_src][n_rx][3] total magnetic field, A/m.
+ *   Hs_dev  optional device complex128 [n_src][n_rx][3] secondary part.
+ * Errors: RECEIVER_OUTSIDE, INVALID_ARG, HIP_ERROR. */
+int petgem_receivers_h(const petgem_solution* sol, const double* rx, int32_t n_rx,
+                       void* H_dev, void* Hs_dev, void* stream);
+
 /* ---- accessors --------------------------------------------------------- */
 int32_t petgem_num_dofs(const petgem_system* sys);
 int64_t petgem_nnz(const petgem_system* sys);

@@ -394,6 +394,121 @@ k_spmm_c(Op op, const ColState* __restrict__ st, const typename V2<T>::t* __rest
     for (int c = threadIdx.x; c < C && c < LPR * CPL; c += 256) partial[(size_t)tile * C + c] = red[0][c];
 }
 
+// Column-lane variant with the row's nonzeros spread over its lanes ("kind
+// 6"): the LPR lanes of a row load NB consecutive (column, K, M) entries with
+// coalesced accesses (lane l takes entries l, l + LPR, ...), then every lane
+// takes the whole chunk's indices and values from its neighbours by shuffles
+// within the row's lane group and issues all NB gathers of its CPL columns
+// before the first accumulation. A row of up to NB nonzeros costs one
+// dependent round trip (the entries, then the gathers) instead of one per four
+// nonzeros; the sums keep the row's nonzero order. Rows of a wave with
+// different lengths take different trip counts; a row's lane group is always
+// active or inactive as a whole, so the shuffles read active lanes only.
+template <typename T, int LPR, int CPL, int NB, int EPI>
+__global__ void __launch_bounds__(256)
+k_spmm_g(Op op, const ColState* __restrict__ st, const typename V2<T>::t* __restrict__ X,
+         const typename V2<T>::t* __restrict__ B, typename V2<T>::t* __restrict__ Y,
+         double2* __restrict__ partial) {
+    using T2 = typename V2<T>::t;
+    static_assert(LPR <= kWave && (LPR & (LPR - 1)) == 0, "a row's lanes are a power-of-two group of one wave");
+    constexpr int NH = (NB + LPR - 1) / LPR;   // entry loads per lane and trip
+    const T* __restrict__ Kv = nullptr;
+    const T* __restrict__ Mv = nullptr;
+    if constexpr (sizeof(T) == 4) { Kv = op.K32; Mv = op.M32; } else { Kv = op.K64; Mv = op.M64; }
+    constexpr int RPB = 256 / LPR;
+    __shared__ double2 red[RPB][LPR * CPL];
+    const int tile = tile_of(op, xcd_block(blockIdx.x, gridDim.x));
+    const int slot = threadIdx.x / LPR, l = threadIdx.x % LPR;
+    const int C = op.C;
+    const int seg = op.tile_seg ? op.tile_seg[tile] : 0;
+    T wmu[CPL];
+    bool live[CPL];
+#pragma unroll
+    for (int u = 0; u < CPL; ++u) {
+        const int c = l * CPL + u;
+        live[u] = c < C && col_live(st, seg * C + c, EPI);
+        wmu[u] = c < C ? (T)op.wmu[seg * C + c] : (T)0;
+    }
+    double2 pacc[CPL];
+#pragma unroll
+    for (int u = 0; u < CPL; ++u) pacc[u] = make_double2(0.0, 0.0);
+    for (int r0 = 0; r0 < kTR; r0 += RPB) {
+        const int i = tile * kTR + r0 + slot;
+        const bool okrow = i < op.nrow_valid;
+        int32_t kb = okrow ? op.rp[i] : 0;
+        const int32_t ke = okrow ? op.rp[i + 1] : 0;
+        T2 ak[CPL], am[CPL];
+#pragma unroll
+        for (int u = 0; u < CPL; ++u) { ak[u].x = ak[u].y = (T)0; am[u].x = am[u].y = (T)0; }
+        for (; kb < ke; kb += NB) {
+            int32_t cj[NH];
+            T kv[NH], mv[NH];
+#pragma unroll
+            for (int h = 0; h < NH; ++h) {
+                const int32_t k = kb + h * LPR + l;
+                const bool ok = h * LPR + l < NB && k < ke;
+                cj[h] = ok ? op.col[k] : 0;
+                kv[h] = ok ? Kv[k] : (T)0;
+                mv[h] = ok ? Mv[k] : (T)0;
+            }
+            T2 xv[NB][CPL];
+#pragma unroll
+            for (int q = 0; q < NB; ++q) {
+                const int c = __shfl(cj[q / LPR], q % LPR, LPR);
+                const bool ok = kb + q < ke;
+                const T2* xr = X + (size_t)c * C + l * CPL;
+#pragma unroll
+                for (int u = 0; u < CPL; ++u) {
+                    if (ok && live[u]) xv[q][u] = xr[u];
+                    else { xv[q][u].x = (T)0; xv[q][u].y = (T)0; }
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < NB; ++q) {
+                const T kq = __shfl(kv[q / LPR], q % LPR, LPR);
+                const T mq = __shfl(mv[q / LPR], q % LPR, LPR);
+#pragma unroll
+                for (int u = 0; u < CPL; ++u) {
+                    ak[u].x += kq * xv[q][u].x; ak[u].y += kq * xv[q][u].y;
+                    am[u].x += mq * xv[q][u].x; am[u].y += mq * xv[q][u].y;
+                }
+            }
+        }
+        if (!okrow) continue;
+#pragma unroll
+        for (int u = 0; u < CPL; ++u) {
+            const int c = l * CPL + u;
+            if (!live[u]) continue;
+            T2 y;
+            y.x = ak[u].x + wmu[u] * am[u].y;   // K x - i wmu M x
+            y.y = ak[u].y - wmu[u] * am[u].x;
+            const size_t o = (size_t)i * C + c;
+            if constexpr (EPI == 2) {
+                const T2 bb = B[o];
+                y.x = bb.x - y.x;
+                y.y = bb.y - y.y;
+                pacc[u].x += (double)y.x * (double)y.x + (double)y.y * (double)y.y;
+            } else {
+                const T2 xo = X[o];
+                pacc[u].x += (double)xo.x * (double)y.x - (double)xo.y * (double)y.y;
+                pacc[u].y += (double)xo.x * (double)y.y + (double)xo.y * (double)y.x;
+            }
+            Y[o] = y;
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < CPL; ++u) red[slot][l * CPL + u] = pacc[u];
+    for (int w = RPB >> 1; w > 0; w >>= 1) {
+        __syncthreads();
+        if (slot < w)
+#pragma unroll
+            for (int u = 0; u < CPL; ++u)
+                red[slot][l * CPL + u] = cadd(red[slot][l * CPL + u], red[slot + w][l * CPL + u]);
+    }
+    __syncthreads();
+    for (int c = threadIdx.x; c < C && c < LPR * CPL; c += 256) partial[(size_t)tile * C + c] = red[0][c];
+}
+
 // Nonzero-lane variant for few columns: G lanes share the nonzeros of a row,
 // each lane accumulates all (<= CM) columns, then a shuffle reduction.
 template <typename T, int G, int CM, int EPI>
@@ -1941,6 +2056,23 @@ void launch_timed_b(K kernel, dim3 grid, dim3 block, hipStream_t s, hipEvent_t e
         hipLaunchKernelGGL(kernel, grid, block, 0, s, args...);
 }
 
+// nonzeros per trip of k_spmm_g: 20 (every row of the Kuhn meshes in one
+// trip), fewer where the gathered values of a trip would need more than
+// about 160 registers per lane
+template <typename T, int CPL>
+constexpr int spmm_g_nb() {
+    constexpr int per = CPL * 2 * (int)sizeof(T) / 4;   // registers per gathered nonzero
+    constexpr int nb = 160 / per;
+    return nb > 20 ? 20 : (nb < 4 ? 4 : nb);
+}
+
+template <typename T, int A, int B, int EPI>
+void spmm_thunk_g(Op op, const ColState* st, const SpmmArgs& g, hipStream_t s) {
+    using T2 = typename V2<T>::t;
+    launch_timed(k_spmm_g<T, A, B, spmm_g_nb<T, B>(), EPI>, dim3(op.nlaunch), s, g.e0, g.e1, op, st,
+                 (const T2*)g.X, (const T2*)g.B, (T2*)g.Y, g.part);
+}
+
 template <typename T, int A, int B, int EPI, bool COLS>
 void spmm_thunk(Op op, const ColState* st, const SpmmArgs& g, hipStream_t s) {
     using T2 = typename V2<T>::t;
@@ -1976,6 +2108,13 @@ bool spmm_dispatch_(const SpmmChoice& ch, Op op, const ColState* st, const SpmmA
         }
         return false;
     }
+    if (ch.kind == 6) {
+#define PG_G(L, P) if (ch.a == L && ch.b == P) { spmm_thunk_g<T, L, P, EPI>(op, st, g, s); return true; }
+        PG_G(8, 1) PG_G(8, 2) PG_G(8, 4) PG_G(16, 1) PG_G(16, 2) PG_G(16, 3) PG_G(16, 4) PG_G(32, 1) PG_G(32, 2)
+        PG_G(64, 1)
+#undef PG_G
+        return false;
+    }
     if (ch.kind == 1) {
 #define PG_N(G, CM) if (ch.a == G && ch.b == CM) { spmm_thunk<T, G, CM, EPI, false>(op, st, g, s); return true; }
         PG_N(4, 1) PG_N(8, 1) PG_N(16, 1) PG_N(4, 2) PG_N(8, 2) PG_N(16, 2) PG_N(4, 4) PG_N(8, 4) PG_N(16, 4)
@@ -1996,6 +2135,8 @@ void spmm_dispatch(const SpmmChoice& ch, Op op, const ColState* st, const SpmmAr
 
 // partial slots per tile of an SpMM shape
 int spmm_slots(const SpmmChoice& ch) { return ch.kind == 1 ? ch.a : 1; }
+// shapes on the CSR arrays, which also serve the double-precision residual
+bool csr_kind(const SpmmChoice& ch) { return ch.kind == 0 || ch.kind == 1 || ch.kind == 6; }
 
 
 std::vector<SpmmChoice> candidates(int C, bool sell) {
@@ -2019,6 +2160,14 @@ std::vector<SpmmChoice> candidates(int C, bool sell) {
                 v.push_back({0, l, p});
             }
         if (v.empty() || (C > 256)) v.push_back({0, 64, 4});
+        // the same lane shapes with the row's entries spread over its lanes
+        // (kind 6), up to 64 columns and 32 columns per lane group
+        for (int l : {8, 16, 32, 64})
+            for (int p : {1, 2, 3, 4}) {
+                const bool inst = (l == 8 && p != 3) || (l == 16) || (l == 32 && p <= 2) || (l == 64 && p == 1);
+                if (!inst || l * p < C || (l * p >= 2 * C && l > 8) || C > 64) continue;
+                v.push_back({6, l, p});
+            }
     }
     return v;
 }
@@ -2098,7 +2247,8 @@ int tune_spmm(BlockWork* w, const Op& op, int64_t nnz, hipStream_t s, SpmmTuned&
     hipLaunchKernelGGL(k_fill_f2, dim3(ceil_div((size_t)op.n * op.C, 256)), dim3(256), 0, s,
                        (size_t)op.n * op.C, w->P);
     hipLaunchKernelGGL(k_set_live, dim3(ceil_div(nsc, 64)), dim3(64), 0, s, w->st, nsc);
-    static const char* kinds[4] = {"column lanes", "nonzero lanes", "sliced ELLPACK", "pipelined sliced ELLPACK"};
+    static const char* kinds[7] = {"column lanes", "nonzero lanes", "sliced ELLPACK", "pipelined sliced ELLPACK",
+                                   "fused", "fused per mesh", "column lanes, entries over the lanes"};
     hipEvent_t e0, e1;
     PG_HIP(hipEventCreate(&e0));
     PG_HIP(hipEventCreate(&e1));
@@ -2120,7 +2270,7 @@ int tune_spmm(BlockWork* w, const Op& op, int64_t nnz, hipStream_t s, SpmmTuned&
             fflush(stderr);
         }
         if (c.ms < best.best.ms) best.best = c;
-        if (c.kind < 2 && c.ms < best.csr.ms) best.csr = c;
+        if (csr_kind(c) && c.ms < best.csr.ms) best.csr = c;
     }
     // The double-precision residual of a few columns times the CSR shapes in
     // double (it reads X64 and B64 as they are and writes R64, all of which
@@ -2128,7 +2278,7 @@ int tune_spmm(BlockWork* w, const Op& op, int64_t nnz, hipStream_t s, SpmmTuned&
     if (op.C <= 4) {
         best.csr.ms = 1e30f;
         for (SpmmChoice c : cands) {
-            if (c.kind >= 2 || spmm_slots(c) > w->p0_slots) continue;
+            if (!csr_kind(c) || spmm_slots(c) > w->p0_slots) continue;
             const SpmmArgs g{w->X64, w->B64, w->R64, w->p0};
             spmm_dispatch<double, 2>(c, op, w->st, g, s);   // warm-up
             PG_HIP(hipEventRecord(e0, s));
@@ -2179,7 +2329,7 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
         for (const SpmmChoice& c : candidates(op.C, op.sp != nullptr))
             if (10000 * c.kind + 100 * c.a + c.b == o.spmm_shape) {
                 tu.best = c;
-                if (c.kind < 2) tu.csr = c;
+                if (csr_kind(c)) tu.csr = c;
                 found = true;
             }
         if (!found) {
@@ -2243,7 +2393,8 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
     // per mesh, for a tuned shape or when chosen (shape 5)
     const bool fused_seg = !fused && C == 1 && op.sp != nullptr && (o.spmm_shape == 0 || force_kind == 5);
     // its product keeps the slice columns in flight of the tuned sliced-ELLPACK shape
-    const int seg_u = force_kind == 5 ? o.spmm_shape % 100 : ch.kind >= 2 && ch.a == 1 && ch.b == 8 ? 8 : 4;
+    const int seg_u = force_kind == 5 ? o.spmm_shape % 100
+                      : (ch.kind == 2 || ch.kind == 3) && ch.a == 1 && ch.b == 8 ? 8 : 4;
     int64_t groups_done = 0;   // groups launched since the fused step's group count was cleared
     if (fused) {
         if (!w->snap_ring)

@@ -68,6 +68,27 @@ __device__ __forceinline__ void dipole_E(const double x[3], const double src[3],
     E[2] = make_double2(Ad.x * d2 + Bp.x * p[2], Ad.y * d2 + Bp.y * p[2]);
 }
 
+// Primary magnetic field of the same dipole, H = curl E / (i w mu0)
+// (Faraday's law with e^{-iwt}): the gradient part of E has no curl and
+// k^2 = i w mu0 sigma, so H = mom grad G x p with G = e^{ikr} / (4 pi r),
+//   H = mom (ikr - 1) e^{ikr} / (4 pi r^3) (d x p),
+// and ikr - 1 = -(1 + kappa r) + i kappa r. hpref = mom / (4 pi).
+__device__ __forceinline__ void dipole_H(const double x[3], const double src[3],
+                                         const double p[3], double kappa, double hpref,
+                                         double2 H[3]) {
+    double d0 = x[0] - src[0], d1 = x[1] - src[1], d2 = x[2] - src[2];
+    double r2 = d0 * d0 + d1 * d1 + d2 * d2;
+    double r = sqrt(r2);
+    double kr = kappa * r;
+    double s, c;
+    sincos(kr, &s, &c);
+    double a = hpref * exp(-kr) / (r2 * r);
+    const double2 f = cmul(make_double2(a * c, a * s), make_double2(-(1.0 + kr), kr));
+    const double dxp[3] = {d1 * p[2] - d2 * p[1], d2 * p[0] - d0 * p[2], d0 * p[1] - d1 * p[0]};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) H[k] = make_double2(f.x * dxp[k], f.y * dxp[k]);
+}
+
 // Barycentric gradients, volume, edge sign*length of a tetrahedron.
 // J = [x1-x0, x2-x0, x3-x0]; grad lambda_{1,2,3} = rows of J^{-1}
 // = (b x c, c x a, a x b)/det; grad lambda_0 = -sum.

@@ -77,6 +77,8 @@ _SIGS = {
                                     C.POINTER(C.c_void_p), C.POINTER(Stats)]),
     "petgem_receivers": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.c_int32, C.c_void_p,
                                    C.c_void_p, C.c_void_p]),
+    "petgem_receivers_h": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.c_int32, C.c_void_p,
+                                     C.c_void_p, C.c_void_p]),
     "petgem_num_dofs": (C.c_int32, [C.c_void_p]),
     "petgem_nnz": (C.c_int64, [C.c_void_p]),
     "petgem_solution_nsrc": (C.c_int32, [C.c_void_p]),
@@ -196,6 +198,17 @@ class Solution:
         _check(lib().petgem_receivers(self.handle, rx.ctypes.data_as(C.POINTER(C.c_double)),
                                       len(rx), _ptr(E), _ptr(Es), _stream(stream)))
         return (E, Es) if secondary else E
+
+    def receivers_h(self, rx: np.ndarray, secondary: bool = False, stream=None):
+        """Total magnetic field H = curl E / (i w mu0) (and optionally its
+        secondary part) at receivers: complex128 CUDA tensors [n_src][n_rx][3]."""
+        import torch
+        rx = np.ascontiguousarray(rx, dtype=np.float64)
+        H = torch.empty((self.n_src, len(rx), 3), dtype=torch.complex128, device="cuda")
+        Hs = torch.empty_like(H) if secondary else None
+        _check(lib().petgem_receivers_h(self.handle, rx.ctypes.data_as(C.POINTER(C.c_double)),
+                                        len(rx), _ptr(H), _ptr(Hs), _stream(stream)))
+        return (H, Hs) if secondary else H
 
     def free(self):
         if self.handle:

@@ -135,19 +135,23 @@ def test_bench_names_and_prices_the_fused_product():
 
 def test_spmm_candidates_listed_by_the_library():
     """The autotuner's shape lists (host only): sliced ELLPACK only with the
-    sliced copy and up to four columns, column lanes from four columns on,
-    every list non-empty, and a column lane layout always covers the block."""
+    sliced copy and up to four columns, column lanes (also with the row's
+    entries spread over the lanes, kind 6, up to 64 columns) from four columns
+    on, every list non-empty, and a column lane layout always covers the
+    block."""
     for C in (1, 2, 3, 4, 5, 8, 16, 32, 33, 96, 300):
         for sliced in (False, True):
             v = petgem.spmm_candidates(C, sliced)
             assert v, (C, sliced)
             for code in v:
                 kind, a, b = code // 10000, code // 100 % 100, code % 100
-                assert kind in (0, 1, 2, 3)
-                if kind >= 2:
+                assert kind in (0, 1, 2, 3, 6)
+                if kind in (2, 3):
                     assert sliced and C <= 4
                 if kind == 0:
                     assert C >= 4 and (a * b >= C or (a, b) == (64, 4))
+                if kind == 6:
+                    assert 4 <= C <= 64 and a * b >= C
                 if kind == 1:
                     assert C <= 4
     with pytest.raises(petgem.PetgemError):
