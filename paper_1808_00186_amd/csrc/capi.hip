@@ -91,6 +91,35 @@ void release_system(petgem_system* sys) {
     sys->rxc.release();
 }
 
+// Locates the receivers on the host (cached while the same coordinates are
+// passed again) and uploads their elements and DOFs.
+int prepare_receivers(const petgem_solution* sol, const double* rx, int32_t n_rx) {
+    petgem_system* sys = sol->sys;
+    ReceiverCache& c = sys->rxc;
+    if (c.n_rx != n_rx || std::memcmp(c.rx.data(), rx, sizeof(double) * 3 * (size_t)n_rx) != 0) {
+        c.release();
+        std::vector<int32_t> tet(n_rx);
+        locate_points(sys->n_tets, sys->xyz_h.data(), sys->tets_h.data(), rx, n_rx, 1e-12, tet.data());
+        std::vector<int32_t> dof(6 * (size_t)n_rx);
+        for (int32_t r = 0; r < n_rx; ++r) {
+            if (tet[r] < 0) {
+                set_error("receiver " + std::to_string(r) + " lies outside the mesh");
+                return PETGEM_RECEIVER_OUTSIDE;
+            }
+            for (int i = 0; i < 6; ++i) dof[6 * r + i] = sys->elem_dof_h[6 * (size_t)tet[r] + i];
+        }
+        PG_TRY(dalloc(&c.tet, (size_t)n_rx));
+        PG_TRY(dalloc(&c.dof, 6 * (size_t)n_rx));
+        PG_TRY(dalloc(&c.xyz, 3 * (size_t)n_rx));
+        PG_HIP(hipMemcpy(c.tet, tet.data(), sizeof(int32_t) * n_rx, hipMemcpyHostToDevice));
+        PG_HIP(hipMemcpy(c.dof, dof.data(), sizeof(int32_t) * 6 * n_rx, hipMemcpyHostToDevice));
+        PG_HIP(hipMemcpy(c.xyz, rx, sizeof(double) * 3 * n_rx, hipMemcpyHostToDevice));
+        c.rx.assign(rx, rx + 3 * (size_t)n_rx);
+        c.n_rx = n_rx;
+    }
+    return PETGEM_OK;
+}
+
 }  // namespace
 
 void set_error(const std::string& msg) { g_err = msg; }
@@ -315,37 +344,27 @@ int petgem_solve_many(petgem_system* const* systems, const petgem_source* src, i
     return batch_solve(systems, src, n_sys, o, x0_dev, sols, static_cast<hipStream_t>(stream), stats);
 }
 
+
 int petgem_receivers(const petgem_solution* sol, const double* rx, int32_t n_rx, void* E_dev,
                      void* Es_dev, void* stream) {
     if (!sol || !sol->sys || !rx || n_rx <= 0 || !E_dev) {
         set_error("solution, receivers and output are required");
         return PETGEM_INVALID_ARG;
     }
-    petgem_system* sys = sol->sys;
-    ReceiverCache& c = sys->rxc;
-    if (c.n_rx != n_rx || std::memcmp(c.rx.data(), rx, sizeof(double) * 3 * (size_t)n_rx) != 0) {
-        c.release();
-        std::vector<int32_t> tet(n_rx);
-        locate_points(sys->n_tets, sys->xyz_h.data(), sys->tets_h.data(), rx, n_rx, 1e-12, tet.data());
-        std::vector<int32_t> dof(6 * (size_t)n_rx);
-        for (int32_t r = 0; r < n_rx; ++r) {
-            if (tet[r] < 0) {
-                set_error("receiver " + std::to_string(r) + " lies outside the mesh");
-                return PETGEM_RECEIVER_OUTSIDE;
-            }
-            for (int i = 0; i < 6; ++i) dof[6 * r + i] = sys->elem_dof_h[6 * (size_t)tet[r] + i];
-        }
-        PG_TRY(dalloc(&c.tet, (size_t)n_rx));
-        PG_TRY(dalloc(&c.dof, 6 * (size_t)n_rx));
-        PG_TRY(dalloc(&c.xyz, 3 * (size_t)n_rx));
-        PG_HIP(hipMemcpy(c.tet, tet.data(), sizeof(int32_t) * n_rx, hipMemcpyHostToDevice));
-        PG_HIP(hipMemcpy(c.dof, dof.data(), sizeof(int32_t) * 6 * n_rx, hipMemcpyHostToDevice));
-        PG_HIP(hipMemcpy(c.xyz, rx, sizeof(double) * 3 * n_rx, hipMemcpyHostToDevice));
-        c.rx.assign(rx, rx + 3 * (size_t)n_rx);
-        c.n_rx = n_rx;
-    }
+    PG_TRY(prepare_receivers(sol, rx, n_rx));
     return launch_receivers(sol, n_rx, static_cast<double2*>(E_dev), static_cast<double2*>(Es_dev),
                             static_cast<hipStream_t>(stream));
+}
+
+int petgem_receivers_h(const petgem_solution* sol, const double* rx, int32_t n_rx, void* H_dev,
+                       void* Hs_dev, void* stream) {
+    if (!sol || !sol->sys || !rx || n_rx <= 0 || !H_dev) {
+        set_error("solution, receivers and output are required");
+        return PETGEM_INVALID_ARG;
+    }
+    PG_TRY(prepare_receivers(sol, rx, n_rx));
+    return launch_receivers(sol, n_rx, static_cast<double2*>(H_dev), static_cast<double2*>(Hs_dev),
+                            static_cast<hipStream_t>(stream), true);
 }
 
 int32_t petgem_num_dofs(const petgem_system* sys) { return sys ? sys->n_dof : -1; }

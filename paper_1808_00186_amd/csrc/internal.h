@@ -205,7 +205,7 @@ int launch_spmv_ahat(petgem_system* sys, const double2* x, double2* y, hipStream
 int tune_spmv(petgem_system* sys, hipStream_t s);
 int launch_spmv_unscaled(petgem_system* sys, const double2* x, double2* y, hipStream_t s);
 int launch_receivers(const petgem_solution* sol, int32_t n_rx, double2* E, double2* Es,
-                     hipStream_t s);
+                     hipStream_t s, bool magnetic = false);
 int gmres_solve(petgem_system* sys, const petgem_source& src, const petgem_opts& o,
                 const double2* x0, double2* x_out, hipStream_t s, petgem_stats* st);
 int block_solve(petgem_system* sys, const petgem_source* src, int32_t n_src,

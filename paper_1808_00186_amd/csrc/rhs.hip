@@ -8,6 +8,10 @@
 //   increasing element order (deterministic, no atomics).
 // k_receivers: one thread per receiver evaluates the 6 basis functions of its
 //   element at the receiver and adds the primary field.
+// k_receivers_h: the magnetic field H = curl E / (i w mu0) (Faraday's law of
+//   Section 2 with e^{-iwt}): the curl of the secondary field is constant in
+//   an element, sum_i e_i 2 s_i l_i grad lambda_a x grad lambda_b, and the
+//   primary part is the dipole's analytic H.
 #include "device.h"
 #include "internal.h"
 
@@ -23,6 +27,8 @@ struct SrcParams {
     double dir[3];
     double kappa;   // sqrt(w mu0 sigma_bg / 2)
     double pref;    // moment / (4 pi sigma_bg)
+    double hpref;   // moment / (4 pi)
+    double inv_wmu; // 1 / (w mu0)
 };
 
 SrcParams make_src(const petgem_source& s, double sigma_bg) {
@@ -31,6 +37,8 @@ SrcParams make_src(const petgem_source& s, double sigma_bg) {
     const double w = 2.0 * kPi * s.freq_hz;
     p.kappa = sqrt(w * kMu0 * sigma_bg * 0.5);
     p.pref = s.moment / (4.0 * kPi * sigma_bg);
+    p.hpref = s.moment / (4.0 * kPi);
+    p.inv_wmu = 1.0 / (w * kMu0);
     return p;
 }
 
@@ -149,6 +157,41 @@ __global__ void k_receivers(int n_rx, const double* __restrict__ rxyz, const int
     }
 }
 
+__global__ void k_receivers_h(int n_rx, const double* __restrict__ rxyz, const int32_t* __restrict__ rtet,
+                              const int32_t* __restrict__ rdof, const double* __restrict__ xyz,
+                              const int4* __restrict__ tets, const double2* __restrict__ x,
+                              SrcParams sp, double2* __restrict__ H, double2* __restrict__ Hs) {
+    int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n_rx) return;
+    TetGeom G;
+    tet_geometry(xyz, tets[rtet[r]], G);
+    double2 cs[3] = {make_double2(0, 0), make_double2(0, 0), make_double2(0, 0)};
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+        int d = rdof[6 * r + i];
+        if (d < 0) continue;
+        const double2 v = x[d];
+        const int a = kE0[i], b = kE1[i];
+        // curl N_i = 2 s_i l_i grad lambda_a x grad lambda_b
+        const double c0 = 2.0 * G.sl[i] * (G.g[a][1] * G.g[b][2] - G.g[a][2] * G.g[b][1]);
+        const double c1 = 2.0 * G.sl[i] * (G.g[a][2] * G.g[b][0] - G.g[a][0] * G.g[b][2]);
+        const double c2 = 2.0 * G.sl[i] * (G.g[a][0] * G.g[b][1] - G.g[a][1] * G.g[b][0]);
+        cs[0].x += c0 * v.x; cs[0].y += c0 * v.y;
+        cs[1].x += c1 * v.x; cs[1].y += c1 * v.y;
+        cs[2].x += c2 * v.x; cs[2].y += c2 * v.y;
+    }
+    const double p[3] = {rxyz[3 * r], rxyz[3 * r + 1], rxyz[3 * r + 2]};
+    double2 hp[3];
+    dipole_H(p, sp.pos, sp.dir, sp.kappa, sp.hpref, hp);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        // curl E_s / (i w mu0) = -i curl E_s / (w mu0): (x, y) -> (y, -x) / (w mu0)
+        const double2 hs = make_double2(cs[k].y * sp.inv_wmu, -cs[k].x * sp.inv_wmu);
+        H[3 * r + k] = cadd(hp[k], hs);
+        if (Hs) Hs[3 * r + k] = hs;
+    }
+}
+
 }  // namespace
 
 int launch_rhs(petgem_system* sys, const petgem_source& src, double2* b, int b_stride,
@@ -168,10 +211,19 @@ int launch_rhs(petgem_system* sys, const petgem_source& src, double2* b, int b_s
 }
 
 int launch_receivers(const petgem_solution* sol, int32_t n_rx, double2* E, double2* Es,
-                     hipStream_t s) {
+                     hipStream_t s, bool magnetic) {
     const petgem_system* sys = sol->sys;
     for (int32_t k = 0; k < sol->n_src; ++k) {
         SrcParams sp = make_src(sol->src[k], sol->sigma_bg);
+        if (magnetic) {
+            hipLaunchKernelGGL(k_receivers_h, dim3(ceil_div(n_rx, 64)), dim3(64), 0, s, n_rx,
+                               sys->rxc.xyz, sys->rxc.tet, sys->rxc.dof, sys->xyz,
+                               reinterpret_cast<const int4*>(sys->tets),
+                               sol->x + (size_t)k * sys->n_dof, sp, E + (size_t)k * n_rx * 3,
+                               Es ? Es + (size_t)k * n_rx * 3 : nullptr);
+            PG_HIP(hipGetLastError());
+            continue;
+        }
         hipLaunchKernelGGL(k_receivers, dim3(ceil_div(n_rx, 64)), dim3(64), 0, s, n_rx,
                            sys->rxc.xyz, sys->rxc.tet, sys->rxc.dof, sys->xyz,
                            reinterpret_cast<const int4*>(sys->tets),
