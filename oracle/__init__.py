@@ -15,6 +15,8 @@ in complex128 / float64, citing the passage it follows:
                    right-hand side (eq. 9), receiver interpolation (eq. 8).
 * ``primary``   -- whole-space dipole primary field (Appendix A, repaired).
 * ``solve``     -- direct and GMRES solves of the assembled system.
+* ``precond``   -- the multicolour SSOR preconditioner and a preconditioned
+                   COCG (the SOR family of Section 5.3).
 * ``network``   -- FP64 reference of the learned initial-guess network
                    (not in the paper; its parity is "unpinned" by the paper and
                    pinned by central finite differences instead).
