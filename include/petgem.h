@@ -60,6 +60,14 @@ extern "C" {
 #define PETGEM_COCG    1  /* multi-source conjugate-orthogonal CG with Jacobi,
                              one sparse matrix pass per iteration for all
                              sources and frequencies                          */
+#define PETGEM_JACOBI  0  /* z = D^-1 r, D = diag A                            */
+#define PETGEM_SSOR    1  /* multicolour symmetric SOR (the SOR family of the
+                             paper's single-process solves, Section 5.3,
+                             Table 2): COCG, mixed precision, petgem_solve     */
+#define PETGEM_BCOCG   2  /* block COCG: the sources (one frequency, at most
+                             32, zero guesses, Jacobi) share one block Krylov
+                             space; directions orthonormalised with
+                             dependent ones dropped; mixed precision           */
 #define PETGEM_FP64    0  /* every step in double precision                   */
 #define PETGEM_MIXED   1  /* complex64 Krylov solves inside a double-precision
                              iterative-refinement loop                         */
@@ -84,7 +92,7 @@ typedef struct {
 } petgem_source;
 
 typedef struct {
-    int32_t method;         /* PETGEM_GMRES or PETGEM_COCG                      */
+    int32_t method;         /* PETGEM_GMRES, PETGEM_COCG or PETGEM_BCOCG        */
     int32_t precision;      /* PETGEM_FP64 or PETGEM_MIXED                      */
     int32_t restart;        /* GMRES restart length, 1..64 (default 30)         */
     int32_t max_iter;       /* total Krylov iterations per source               */
@@ -105,6 +113,19 @@ typedef struct {
                                mesh, with 4 or 8 slice columns in flight (one
                                column per mesh only; 4010x also needs at most
                                8192 tiles of 256 rows)                         */
+    int32_t precond;        /* PETGEM_JACOBI (default) or PETGEM_SSOR. SSOR:
+                               the unknowns are coloured so that no two of a
+                               colour share a matrix entry (greedy, in the
+                               order of the unknowns' global node pairs
+                               (lo, hi), smallest colour free among the
+                               neighbours); with D = diag A, L / U the entries
+                               coupling a row to earlier / later colours,
+                               M = (D/omega + L)(D/omega)^-1(D/omega + U), so
+                               z = M^-1 r is a forward sweep over the colours
+                               and a backward one (complex symmetric: COCG
+                               keeps its short recurrence). COCG + MIXED in
+                               petgem_solve only (INVALID_ARG otherwise)       */
+    double  omega;          /* SSOR relaxation factor, 0 < omega < 2 (1)        */
 } petgem_opts;
 
 typedef struct {
@@ -141,7 +162,8 @@ typedef struct {
 } petgem_stats;
 
 /* Fill *opts with the defaults: GMRES, FP64, restart 30, max_iter 20000,
- * rtol 1e-8, inner_rtol 3e-5, use_graph 1, profile 0, verbose 0, spmm_shape 0. */
+ * rtol 1e-8, inner_rtol 3e-5, use_graph 1, profile 0, verbose 0, spmm_shape 0,
+ * precond PETGEM_JACOBI, omega 1. */
 void petgem_default_opts(petgem_opts* opts);
 
 /* ---- assembly (Section 3, eq. 9; Section 4; Appendix B) -----------------
@@ -267,6 +289,15 @@ int petgem_locate(const petgem_mesh* mesh, const double* pts, int32_t n_pts, dou
 int petgem_tuning(const petgem_system* sys, int32_t* spmv_group, float* spmv_ms);
 /* Seconds spent in the host preprocessing of the last petgem_assemble. */
 double petgem_setup_seconds(const petgem_system* sys);
+/* The multicolour SSOR preconditioner of PETGEM_SSOR (see petgem_opts):
+ * petgem_ssor_colors writes the colour of every DOF (host int32 [n_dof],
+ * library DOF order) and returns the number of colours (builds the colouring
+ * if needed; synchronises `stream`). petgem_ssor_apply computes z = M^-1 r
+ * for one complex64 column at frequency freq: r_dev, z_dev device complex64
+ * [n_dof], distinct; synchronises `stream`. */
+int32_t petgem_ssor_colors(petgem_system* sys, int32_t* colors, void* stream);
+int petgem_ssor_apply(petgem_system* sys, double freq, double omega, const void* r_dev, void* z_dev,
+                      void* stream);
 /* Host-only: the complex64 SpMM shapes the autotuner times for n_cols
  * columns (sliced != 0: with the sliced-ELLPACK copy, which one mesh has for
  * up to four columns), as petgem_opts.spmm_shape codes. Writes at most cap

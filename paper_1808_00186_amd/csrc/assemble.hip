@@ -181,6 +181,7 @@ int ensure_fp32(petgem_system* sys, hipStream_t s) {
     PG_HIP(hipGetLastError());
     sys->have32 = true;
     sys->sell32.values = false;
+    sys->ssor32.values = false;
     return PETGEM_OK;
 }
 

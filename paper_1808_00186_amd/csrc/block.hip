@@ -1032,10 +1032,11 @@ k_inner_init(Op op, int CP, const double2* __restrict__ R64, const ColState* __r
 // r -= alpha q; z = D^-1 r for the active columns; partials of r^T z and
 // |r|^2. x += alpha p waits for k_pupdate, which reads p anyway. dinv (or
 // NULL): the precomputed D^-1 of single-column solves.
+// jac = 0 (SSOR): only r and its |r|^2 partials; z and r^T z follow the sweeps.
 __global__ void __launch_bounds__(256)
 k_update(Op op, int CP, const ColState* __restrict__ st, float2* __restrict__ R, float2* __restrict__ Z,
          const float2* __restrict__ Q, const float2* __restrict__ dinv, double2* __restrict__ p0,
-         double2* __restrict__ p1) {
+         double2* __restrict__ p1, int jac) {
     __shared__ double2 ra[256], rb[256];
     const int tile = tile_of(op, blockIdx.x), C = op.C;
     const int c = threadIdx.x % CP, slot = threadIdx.x / CP, RPB = 256 / CP;
@@ -1054,11 +1055,13 @@ k_update(Op op, int CP, const ColState* __restrict__ st, float2* __restrict__ R,
                 float2 r = R[o];
                 r.x -= ax * q.x - ay * q.y;
                 r.y -= ax * q.y + ay * q.x;
-                const float2 z = dinv ? cmulf(r, dinv[i]) : jacobi_z(r, op.Kd[i], op.Md[i], wmu);
                 R[o] = r;
-                Z[o] = z;
-                a.x += (double)r.x * z.x - (double)r.y * z.y;
-                a.y += (double)r.x * z.y + (double)r.y * z.x;
+                if (jac) {
+                    const float2 z = dinv ? cmulf(r, dinv[i]) : jacobi_z(r, op.Kd[i], op.Md[i], wmu);
+                    Z[o] = z;
+                    a.x += (double)r.x * z.x - (double)r.y * z.y;
+                    a.y += (double)r.x * z.y + (double)r.y * z.x;
+                }
                 b.x += (double)r.x * r.x + (double)r.y * r.y;
             }
         }
@@ -1092,6 +1095,192 @@ k_pupdate(Op op, int CP, const ColState* __restrict__ st, const float2* __restri
         Xi[o] = f2(x.x + ax * p.x - ay * p.y, x.y + ax * p.y + ay * p.x);
         if (more) P[o] = f2(z.x + bx * p.x - by * p.y, z.y + bx * p.y + by * p.x);
     }
+}
+
+// ------------------------------------------- multicolour SSOR
+// Symmetric successive over-relaxation, the SOR family of the paper's
+// single-process runs (Section 5.3, Table 2), made parallel by a multicolour
+// ordering: no two DOFs of one colour share a matrix entry, and the sweeps
+// take the colours in order, all rows of a colour at once. With D = diag A(w)
+// and L, U the entries coupling a row to earlier and to later colours
+// (U = L^T: A is complex symmetric), the preconditioner is
+//   M = (D / omega + L) (D / omega)^-1 (D / omega + U)
+// (the factor (2 - omega) / omega left out: COCG's iterates do not depend on
+// a constant scaling of M). z = M^-1 r is the forward sweep
+//   y_i = omega (r_i - sum_{j in L(i)} a_ij y_j) / d_i       colours 0 .. nc-1
+// then the backward sweep
+//   z_i = y_i - omega (sum_{j in U(i)} a_ij z_j) / d_i        colours nc-1 .. 0
+// in place in Z. M is complex symmetric, so COCG's short recurrence holds.
+// Per column c: a_ij = K_ij - i w_c mu0 M_ij, d_i = Kd_i - i w_c mu0 Md_i.
+struct SsorOp {
+    const int32_t* row;
+    const int32_t* rp;     // L part (forward) or U part (backward)
+    const int32_t* col;
+    const float* K;
+    const float* M;
+};
+
+__device__ __forceinline__ void ssor_row_out(const Op& op, int i, int C, int c, float2 ak, float2 am, double wmu,
+                                             float omega, bool bwd, const float2* __restrict__ R,
+                                             float2* __restrict__ Z) {
+    // s = sum a_ij v_j = ak - i wmu am; d = Kd - i wmu Md
+    const float2 sv = f2(ak.x + (float)wmu * am.y, ak.y - (float)wmu * am.x);
+    const double dr = op.Kd[i], di = -wmu * op.Md[i];
+    const double inv = 1.0 / (dr * dr + di * di);
+    const float2 dinv = f2((float)(dr * inv), (float)(-di * inv));
+    const size_t o = (size_t)i * C + c;
+    if (!bwd) {
+        const float2 r = R[o];
+        const float2 t = f2(omega * (r.x - sv.x), omega * (r.y - sv.y));
+        Z[o] = cmulf(t, dinv);
+    } else {
+        const float2 y = Z[o];
+        const float2 t = cmulf(f2(omega * sv.x, omega * sv.y), dinv);
+        Z[o] = f2(y.x - t.x, y.y - t.y);
+    }
+}
+
+// C <= 4 columns: G lanes share a row's entries (lane l takes entries l,
+// l + G, ...), every lane accumulates all CM columns, then a shuffle
+// reduction over the G lanes (fixed order). Rows [p0, p1) of the colour
+// order. st (or null): columns whose inner solve stopped are skipped.
+template <int G, int CM, bool BWD>
+__global__ void __launch_bounds__(256)
+k_ssor_n(Op op, SsorOp so, int p0, int p1, const ColState* __restrict__ st, const float2* __restrict__ R,
+         float2* __restrict__ Z, float omega) {
+    constexpr int RPB = 256 / G;
+    const int slot = threadIdx.x / G, l = threadIdx.x % G;
+    const int p = p0 + blockIdx.x * RPB + slot;
+    if (p >= p1) return;   // the whole lane group of this row
+    const int C = op.C;
+    const int i = so.row[p];
+    bool live[CM];
+#pragma unroll
+    for (int u = 0; u < CM; ++u) live[u] = u < C && (!st || st[u].active);
+    float2 ak[CM], am[CM];
+#pragma unroll
+    for (int u = 0; u < CM; ++u) { ak[u] = f2(0.f, 0.f); am[u] = f2(0.f, 0.f); }
+    const int32_t e = so.rp[p + 1];
+    for (int32_t k = so.rp[p] + l; k < e; k += G) {
+        const int32_t j = so.col[k];
+        const float kv = so.K[k], mv = so.M[k];
+        const float2* zr = Z + (size_t)j * C;
+#pragma unroll
+        for (int u = 0; u < CM; ++u) {
+            if (!live[u]) continue;
+            const float2 v = zr[u];
+            ak[u].x += kv * v.x; ak[u].y += kv * v.y;
+            am[u].x += mv * v.x; am[u].y += mv * v.y;
+        }
+    }
+#pragma unroll
+    for (int off = G >> 1; off > 0; off >>= 1)
+#pragma unroll
+        for (int u = 0; u < CM; ++u) {
+            ak[u].x += __shfl_xor(ak[u].x, off, G); ak[u].y += __shfl_xor(ak[u].y, off, G);
+            am[u].x += __shfl_xor(am[u].x, off, G); am[u].y += __shfl_xor(am[u].y, off, G);
+        }
+    // lane u writes column u (every lane holds the same sums)
+#pragma unroll
+    for (int u = 0; u < CM; ++u)
+        if (l == u && live[u]) ssor_row_out(op, i, C, u, ak[u], am[u], op.wmu[u], omega, BWD, R, Z);
+}
+
+// More columns: LPR lanes per row, CPL consecutive columns per lane; the
+// row's entries are loaded across the lanes and handed out by shuffles, all
+// of a chunk's gathers in flight at once (as k_spmm_g).
+template <int LPR, int CPL, bool BWD>
+__global__ void __launch_bounds__(256)
+k_ssor_c(Op op, SsorOp so, int p0, int p1, const ColState* __restrict__ st, const float2* __restrict__ R,
+         float2* __restrict__ Z, float omega) {
+    constexpr int RPB = 256 / LPR;
+    constexpr int NB = 12;                        // entries per trip (an L or U part has 3..10)
+    constexpr int NH = (NB + LPR - 1) / LPR;
+    const int slot = threadIdx.x / LPR, l = threadIdx.x % LPR;
+    const int p = p0 + blockIdx.x * RPB + slot;
+    if (p >= p1) return;   // the whole lane group of this row
+    const int C = op.C;
+    const int i = so.row[p];
+    bool live[CPL];
+#pragma unroll
+    for (int u = 0; u < CPL; ++u) {
+        const int c = l * CPL + u;
+        live[u] = c < C && (!st || st[c].active);
+    }
+    float2 ak[CPL], am[CPL];
+#pragma unroll
+    for (int u = 0; u < CPL; ++u) { ak[u] = f2(0.f, 0.f); am[u] = f2(0.f, 0.f); }
+    const int32_t ke = so.rp[p + 1];
+    for (int32_t kb = so.rp[p]; kb < ke; kb += NB) {
+        int32_t cj[NH];
+        float kv[NH], mv[NH];
+#pragma unroll
+        for (int h = 0; h < NH; ++h) {
+            const int32_t k = kb + h * LPR + l;
+            const bool ok = h * LPR + l < NB && k < ke;
+            cj[h] = ok ? so.col[k] : 0;
+            kv[h] = ok ? so.K[k] : 0.f;
+            mv[h] = ok ? so.M[k] : 0.f;
+        }
+        float2 xv[NB][CPL];
+#pragma unroll
+        for (int q = 0; q < NB; ++q) {
+            const int j = __shfl(cj[q / LPR], q % LPR, LPR);
+            const bool ok = kb + q < ke;
+            const float2* zr = Z + (size_t)j * C + l * CPL;
+#pragma unroll
+            for (int u = 0; u < CPL; ++u) xv[q][u] = (ok && live[u]) ? zr[u] : f2(0.f, 0.f);
+        }
+#pragma unroll
+        for (int q = 0; q < NB; ++q) {
+            const float kq = __shfl(kv[q / LPR], q % LPR, LPR);
+            const float mq = __shfl(mv[q / LPR], q % LPR, LPR);
+#pragma unroll
+            for (int u = 0; u < CPL; ++u) {
+                ak[u].x += kq * xv[q][u].x; ak[u].y += kq * xv[q][u].y;
+                am[u].x += mq * xv[q][u].x; am[u].y += mq * xv[q][u].y;
+            }
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < CPL; ++u) {
+        const int c = l * CPL + u;
+        if (live[u]) ssor_row_out(op, i, C, c, ak[u], am[u], op.wmu[c], omega, BWD, R, Z);
+    }
+}
+
+// Partials of r^T z per tile and column (the sweeps wrote z); with P not
+// null also p = z (the start of an inner solve). st (or null) as above; with
+// P, columns still in the refinement (outer) take part.
+__global__ void __launch_bounds__(256)
+k_rz(Op op, int CP, const ColState* __restrict__ st, const float2* __restrict__ R, const float2* __restrict__ Z,
+     float2* __restrict__ P, double2* __restrict__ part) {
+    __shared__ double2 ra[256], rb[256];
+    const int tile = tile_of(op, blockIdx.x), C = op.C;
+    const int c = threadIdx.x % CP, slot = threadIdx.x / CP, RPB = 256 / CP;
+    double2 a = make_double2(0.0, 0.0), b = make_double2(0.0, 0.0);
+    if (c < C && (!st || (P ? st[c].outer : st[c].active))) {
+        for (int r0 = 0; r0 < kTR; r0 += RPB) {
+            const int i = tile * kTR + r0 + slot;
+            if (i >= op.nrow_valid) break;
+            const size_t o = (size_t)i * C + c;
+            const float2 r = R[o], z = Z[o];
+            if (P) P[o] = z;
+            a.x += (double)r.x * z.x - (double)r.y * z.y;
+            a.y += (double)r.x * z.y + (double)r.y * z.x;
+        }
+    }
+    cp_sum2(a, b, CP, ra, rb);
+    if ((int)threadIdx.x < C && (int)threadIdx.x < CP) part[(size_t)tile * C + threadIdx.x] = ra[threadIdx.x];
+}
+
+__global__ void k_ssor_vals(int64_t n, const int32_t* __restrict__ pos, const float* __restrict__ K,
+                            const float* __restrict__ M, float* __restrict__ oK, float* __restrict__ oM) {
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= n) return;
+    const int32_t k = pos[e];
+    oK[e] = K[k];
+    oM[e] = M[k];
 }
 
 // ------------------------------------------- reductions in the consumers
@@ -2025,6 +2214,163 @@ int build_sell(Sell& S, int nrows, int nrow_valid, const int32_t* rp, const int3
     return PETGEM_OK;
 }
 
+// The multicolour split of the operator for SSOR (host build of the pattern
+// on first use; values gathered on the GPU after every change of K32, Ms32).
+// Colouring: the DOFs in the order of their global node pairs (lo, hi) (a
+// numbering-free order), each taking the smallest colour none of its matrix
+// neighbours already has.
+int ensure_ssor(petgem_system* sys, hipStream_t s) {
+    PG_TRY(ensure_fp32(sys, s));
+    Ssor& Q = sys->ssor32;
+    const int n = sys->n_dof;
+    if (Q.nc == 0) {
+        std::vector<int32_t> col((size_t)sys->nnz);
+        PG_HIP(hipMemcpyAsync(col.data(), sys->col, sizeof(int32_t) * (size_t)sys->nnz, hipMemcpyDeviceToHost, s));
+        PG_HIP(hipStreamSynchronize(s));
+        const std::vector<int32_t>& rp = sys->row_ptr_h;
+        std::vector<int32_t> order(n);
+        for (int i = 0; i < n; ++i) order[i] = i;
+        const int32_t* dn = sys->dof_nodes_h.data();
+        std::sort(order.begin(), order.end(), [dn](int32_t a, int32_t b) {
+            return dn[2 * a] != dn[2 * b] ? dn[2 * a] < dn[2 * b] : dn[2 * a + 1] < dn[2 * b + 1];
+        });
+        std::vector<int32_t> color(n, -1);
+        std::vector<int32_t> seen;   // seen[c] == row: colour c taken by a neighbour of row
+        int nc = 0;
+        for (int32_t i : order) {
+            for (int32_t k = rp[i]; k < rp[i + 1]; ++k) {
+                const int32_t c = color[col[k]];
+                if (c >= 0) seen[c] = i;
+            }
+            int32_t c = 0;
+            while (c < nc && seen[c] == i) ++c;
+            if (c == nc) { ++nc; seen.push_back(-1); }
+            color[i] = c;
+        }
+        // rows listed colour by colour, in DOF order within a colour
+        std::vector<int32_t> cptr(nc + 1, 0), row(n);
+        for (int i = 0; i < n; ++i) ++cptr[color[i] + 1];
+        for (int c = 0; c < nc; ++c) cptr[c + 1] += cptr[c];
+        {
+            std::vector<int32_t> fill(cptr.begin(), cptr.end() - 1);
+            for (int i = 0; i < n; ++i) row[fill[color[i]]++] = i;
+        }
+        std::vector<int32_t> lrp(n + 1, 0), urp(n + 1, 0), lcol, lpos, ucol, upos;
+        lcol.reserve((size_t)sys->nnz / 2); lpos.reserve((size_t)sys->nnz / 2);
+        ucol.reserve((size_t)sys->nnz / 2); upos.reserve((size_t)sys->nnz / 2);
+        for (int p = 0; p < n; ++p) {
+            const int32_t i = row[p];
+            for (int32_t k = rp[i]; k < rp[i + 1]; ++k) {
+                const int32_t j = col[k];
+                if (color[j] < color[i]) { lcol.push_back(j); lpos.push_back(k); }
+                else if (color[j] > color[i]) { ucol.push_back(j); upos.push_back(k); }
+                else if (j != i) {
+                    set_error("SSOR colouring: two coupled unknowns share a colour");
+                    return PETGEM_HIP_ERROR;
+                }
+            }
+            lrp[p + 1] = (int32_t)lcol.size();
+            urp[p + 1] = (int32_t)ucol.size();
+        }
+        Q.nl = (int64_t)lcol.size();
+        Q.nu = (int64_t)ucol.size();
+        PG_TRY(dalloc(&Q.row, (size_t)n));
+        PG_TRY(dalloc(&Q.lrp, (size_t)n + 1));
+        PG_TRY(dalloc(&Q.urp, (size_t)n + 1));
+        PG_TRY(dalloc(&Q.lcol, (size_t)std::max<int64_t>(Q.nl, 1)));
+        PG_TRY(dalloc(&Q.lpos, (size_t)std::max<int64_t>(Q.nl, 1)));
+        PG_TRY(dalloc(&Q.ucol, (size_t)std::max<int64_t>(Q.nu, 1)));
+        PG_TRY(dalloc(&Q.upos, (size_t)std::max<int64_t>(Q.nu, 1)));
+        PG_TRY(dalloc(&Q.lK, (size_t)std::max<int64_t>(Q.nl, 1)));
+        PG_TRY(dalloc(&Q.lM, (size_t)std::max<int64_t>(Q.nl, 1)));
+        PG_TRY(dalloc(&Q.uK, (size_t)std::max<int64_t>(Q.nu, 1)));
+        PG_TRY(dalloc(&Q.uM, (size_t)std::max<int64_t>(Q.nu, 1)));
+        PG_HIP(hipMemcpyAsync(Q.row, row.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s));
+        PG_HIP(hipMemcpyAsync(Q.lrp, lrp.data(), sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice, s));
+        PG_HIP(hipMemcpyAsync(Q.urp, urp.data(), sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice, s));
+        PG_HIP(hipMemcpyAsync(Q.lcol, lcol.data(), sizeof(int32_t) * lcol.size(), hipMemcpyHostToDevice, s));
+        PG_HIP(hipMemcpyAsync(Q.lpos, lpos.data(), sizeof(int32_t) * lpos.size(), hipMemcpyHostToDevice, s));
+        PG_HIP(hipMemcpyAsync(Q.ucol, ucol.data(), sizeof(int32_t) * ucol.size(), hipMemcpyHostToDevice, s));
+        PG_HIP(hipMemcpyAsync(Q.upos, upos.data(), sizeof(int32_t) * upos.size(), hipMemcpyHostToDevice, s));
+        PG_HIP(hipStreamSynchronize(s));   // the host vectors die here
+        Q.cptr = std::move(cptr);
+        Q.color_h = std::move(color);
+        Q.nc = nc;
+        Q.values = false;
+    }
+    if (!Q.values) {
+        if (Q.nl > 0)
+            hipLaunchKernelGGL(k_ssor_vals, dim3(ceil_div(Q.nl, 256)), dim3(256), 0, s, Q.nl, Q.lpos, sys->K32,
+                               sys->Ms32, Q.lK, Q.lM);
+        if (Q.nu > 0)
+            hipLaunchKernelGGL(k_ssor_vals, dim3(ceil_div(Q.nu, 256)), dim3(256), 0, s, Q.nu, Q.upos, sys->K32,
+                               sys->Ms32, Q.uK, Q.uM);
+        PG_HIP(hipGetLastError());
+        Q.values = true;
+    }
+    return PETGEM_OK;
+}
+
+namespace {
+
+// z = M^-1 r by the two multicolour sweeps over op's columns (Z in place; R
+// read by the forward sweep). st (or null) skips stopped columns.
+void ssor_sweeps(const Ssor& Q, const Op& op, const ColState* st, const float2* R, float2* Z, float omega,
+                 hipStream_t s) {
+    const int C = op.C;
+    for (int pass = 0; pass < 2; ++pass) {
+        const bool bwd = pass == 1;
+        SsorOp so{Q.row, bwd ? Q.urp : Q.lrp, bwd ? Q.ucol : Q.lcol, bwd ? Q.uK : Q.lK, bwd ? Q.uM : Q.lM};
+        for (int k = 0; k < Q.nc; ++k) {
+            const int c = bwd ? Q.nc - 1 - k : k;
+            const int p0 = Q.cptr[c], p1 = Q.cptr[c + 1];
+            if (p1 <= p0) continue;
+#define PG_SN(G, CM) { const dim3 gr(ceil_div(p1 - p0, 256 / G)); \
+            if (bwd) hipLaunchKernelGGL((k_ssor_n<G, CM, true>), gr, dim3(256), 0, s, op, so, p0, p1, st, R, Z, omega); \
+            else hipLaunchKernelGGL((k_ssor_n<G, CM, false>), gr, dim3(256), 0, s, op, so, p0, p1, st, R, Z, omega); }
+#define PG_SC(L, P) { const dim3 gr(ceil_div(p1 - p0, 256 / L)); \
+            if (bwd) hipLaunchKernelGGL((k_ssor_c<L, P, true>), gr, dim3(256), 0, s, op, so, p0, p1, st, R, Z, omega); \
+            else hipLaunchKernelGGL((k_ssor_c<L, P, false>), gr, dim3(256), 0, s, op, so, p0, p1, st, R, Z, omega); }
+            if (C == 1) PG_SN(8, 1)
+            else if (C == 2) PG_SN(8, 2)
+            else if (C <= 4) PG_SN(8, 4)
+            else if (C <= 8) PG_SC(8, 1)
+            else if (C <= 16) PG_SC(16, 1)
+            else if (C <= 32) PG_SC(32, 1)
+            else if (C <= 64) PG_SC(64, 1)
+            else if (C <= 128) PG_SC(64, 2)
+            else PG_SC(64, 4)
+#undef PG_SN
+#undef PG_SC
+        }
+    }
+}
+
+}  // namespace
+
+int ssor_apply1(petgem_system* sys, double freq, double omega, const float2* r, float2* z, hipStream_t s) {
+    PG_TRY(ensure_ssor(sys, s));
+    double* wmu = nullptr;
+    PG_TRY(dalloc(&wmu, 1));
+    const double w = 2.0 * kPi * freq * kMu0;
+    PG_HIP(hipMemcpyAsync(wmu, &w, sizeof(double), hipMemcpyHostToDevice, s));
+    Op op{};
+    op.n = sys->n_dof;
+    op.C = 1;
+    op.ntiles = ceil_div(sys->n_dof, kTR);
+    op.nlaunch = op.ntiles;
+    op.nseg = 1;
+    op.Kd = sys->Kd;
+    op.Md = sys->Msd;
+    op.wmu = wmu;
+    op.nrow_valid = sys->n_dof;
+    ssor_sweeps(sys->ssor32, op, nullptr, r, z, (float)omega, s);
+    PG_HIP(hipGetLastError());
+    PG_HIP(hipStreamSynchronize(s));
+    dfree(wmu);
+    return PETGEM_OK;
+}
+
 namespace {
 
 // Launch arguments of one SpMM (X, B, Y as described at the kernels; e0 / e1
@@ -2309,8 +2655,13 @@ int tune_spmm(BlockWork* w, const Op& op, int64_t nnz, hipStream_t s, SpmmTuned&
 // all of them when have_x0); only those can be rejected.
 int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hipStream_t s,
                std::vector<petgem_stats*>& stv, bool have_x0, const std::vector<int>* seg_tile_h = nullptr,
-               const std::vector<char>* has_x0 = nullptr) {
+               const std::vector<char>* has_x0 = nullptr, const Ssor* sq = nullptr) {
     const int C = op.C, nsc = op.nseg * C, CP = cp_of(C);
+    // multicolour SSOR instead of Jacobi (one mesh): the five-kernel
+    // iteration with the two sweeps and an r^T z pass between the r update
+    // and the beta reduction
+    const bool ssor = sq != nullptr;
+    const float omega = (float)o.omega;
     Timer t_all;
     SpmmTuned tu;
     PG_TRY(tune_spmm(w, op, nnz, s, tu, o.verbose != 0));
@@ -2320,6 +2671,10 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
     const int force_kind = o.spmm_shape / 10000;
     const bool force_fused = (force_kind == 4 || force_kind == 5) && o.spmm_shape % 10000 / 100 == 1 &&
                              (o.spmm_shape % 100 == 4 || o.spmm_shape % 100 == 8);
+    if (force_fused && ssor) {
+        set_error("the fused steps take the Jacobi preconditioner only");
+        return PETGEM_INVALID_ARG;
+    }
     if (force_fused && (C != 1 || op.sp == nullptr)) {
         set_error("spmm_shape " + std::to_string(o.spmm_shape) + " (a fused step) needs one column per mesh");
         return PETGEM_INVALID_ARG;
@@ -2348,7 +2703,7 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
     }
     // the reductions run inside the vector kernels for one mesh whose
     // partials are few enough for every block to sum
-    const bool in_consumer = op.nseg == 1 && (int64_t)op.ntiles * ppS * C <= kConsumerMax;
+    const bool in_consumer = !ssor && op.nseg == 1 && (int64_t)op.ntiles * ppS * C <= kConsumerMax;
     const int nspb = ceil_div((int64_t)op.ntiles * 4, kSpbWaves);   // blocks (and partials) of the fused product
     const int nst = ceil_div(op.ntiles, kStepTiles);                // blocks of the fused step
     // One column of one mesh with a sliced-ELLPACK copy takes the fused step
@@ -2361,7 +2716,7 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
     // the kernel path does not follow the tuner's timing noise. A
     // caller-chosen shape is honoured as given: shape 3 (or 4) runs fused,
     // the others not.
-    const bool fused_fits = op.nseg == 1 && C == 1 && op.sp != nullptr && nspb <= kConsumerMax;
+    const bool fused_fits = !ssor && op.nseg == 1 && C == 1 && op.sp != nullptr && nspb <= kConsumerMax;
     const bool fused = fused_fits && force_kind != 5 &&
                        (o.spmm_shape == 0 || force_kind == 4 ||
                         (ch.kind == 3 && ch.a == 1 && (ch.b == 4 || ch.b == 8)));
@@ -2391,7 +2746,7 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
     // one column per mesh otherwise (an uneven batch, or one mesh too large for
     // every block to sum its partials): the fused step with a reduction block
     // per mesh, for a tuned shape or when chosen (shape 5)
-    const bool fused_seg = !fused && C == 1 && op.sp != nullptr && (o.spmm_shape == 0 || force_kind == 5);
+    const bool fused_seg = !ssor && !fused && C == 1 && op.sp != nullptr && (o.spmm_shape == 0 || force_kind == 5);
     // its product keeps the slice columns in flight of the tuned sliced-ELLPACK shape
     const int seg_u = force_kind == 5 ? o.spmm_shape % 100
                       : (ch.kind == 2 || ch.kind == 3) && ch.a == 1 && ch.b == 8 ? 8 : 4;
@@ -2555,7 +2910,12 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
             hipLaunchKernelGGL(k_reduce, dim3(nsc), dim3(1024), 0, s, op, w->p0, ppS, nullptr, 1, w->st,
                                (int)RED_ALPHA, 0);
             hipLaunchKernelGGL(k_update, dim3(opi.nlaunch), dim3(256), 0, s, opi, CP, w->st, w->R, w->Z, w->Q,
-                               dinv, w->p1, w->p2);
+                               dinv, w->p1, w->p2, ssor ? 0 : 1);
+            if (ssor) {
+                ssor_sweeps(*sq, opi, w->st, w->R, w->Z, omega, s);
+                hipLaunchKernelGGL(k_rz, dim3(opi.nlaunch), dim3(256), 0, s, opi, CP, (const ColState*)w->st,
+                                   (const float2*)w->R, (const float2*)w->Z, (float2*)nullptr, w->p1);
+            }
             hipLaunchKernelGGL(k_reduce, dim3(nsc), dim3(1024), 0, s, op, w->p1, 1, w->p2, 1, w->st,
                                (int)RED_BETA, 0);
             hipLaunchKernelGGL(k_pupdate, dim3(opi.nlaunch), dim3(256), 0, s, opi, CP, w->st, w->Z, w->P, w->Xi);
@@ -2575,11 +2935,12 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
             sig.insert(sig.end(), c, c + nb);
         };
         put(&opi, sizeof(opi));
-        const void* ptrs[13] = {w->Xi, w->R, w->Z, w->P, w->Q, w->p0, w->p1, w->p2, w->st, w->st2, dinv,
-                                w->snap_ring, w->gcount};
+        const void* ptrs[15] = {w->Xi, w->R, w->Z, w->P, w->Q, w->p0, w->p1, w->p2, w->st, w->st2, dinv,
+                                w->snap_ring, w->gcount, sq ? (const void*)sq->row : nullptr,
+                                sq ? (const void*)sq->lK : nullptr};
         put(ptrs, sizeof(ptrs));
-        int chv[9] = {ch.kind, ch.a, ch.b, (int)in_consumer, opi.tmap ? tgen : 0, (int)fused, fused_u, (int)fused_seg,
-                      seg_u};
+        int chv[11] = {ch.kind, ch.a, ch.b, (int)in_consumer, opi.tmap ? tgen : 0, (int)fused, fused_u, (int)fused_seg,
+                       seg_u, (int)ssor, ssor ? (int)(o.omega * 1e6) : 0};
         put(chv, sizeof(chv));
         if (w->graph_sig != sig) w->release_graph();
         if (w->graphs[ng - 1] != nullptr) return PETGEM_OK;
@@ -2639,6 +3000,11 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
         // inner complex64 COCG on A d = r64 / |r64|
         hipLaunchKernelGGL(k_inner_init, dim3(op.ntiles), dim3(256), 0, s, op, CP, w->R64, w->st, dinv, w->Xi,
                            w->R, w->Z, w->P, w->p1, w->p2);
+        if (ssor) {   // z = M^-1 r, p = z and the r^T z partials by the sweeps
+            ssor_sweeps(*sq, op, nullptr, w->R, w->Z, omega, s);
+            hipLaunchKernelGGL(k_rz, dim3(op.ntiles), dim3(256), 0, s, op, CP, (const ColState*)w->st,
+                               (const float2*)w->R, (const float2*)w->Z, w->P, w->p1);
+        }
         hipLaunchKernelGGL(k_reduce, dim3(nsc), dim3(1024), 0, s, op, w->p1, 1, w->p2, 1, w->st,
                            (int)RED_INIT, 0);
         // Groups of kCheck iterations run between host checks; the number of
@@ -2801,6 +3167,242 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
     return status;
 }
 
+// ------------------------------------------- block COCG
+// O'Leary's block conjugate gradient carried over to the complex-symmetric
+// bilinear form u^T v (not in the paper; the columns are sources of one
+// frequency, so they share A): the C columns share one block Krylov space.
+// With P the block of search directions (orthonormal columns in the
+// Hermitian product, dependent directions dropped), Q = A P and G = P^T Q:
+//   alpha = G^-1 (P^T R)      X += P alpha     R -= Q alpha     (P^T R = 0)
+//   Z = D^-1 R                beta = -G^-1 (Q^T Z)              (P^T A P_new = 0)
+//   P~ = Z + P beta           Gamma = P~^H P~ = R_c^H R_c (Cholesky with
+//   diagonal pivoting; a pivot below kDefl^2 of the largest diagonal ends it:
+//   rank r)                   P = P~ Pi R_c^-1 (first r columns, the rest zero).
+// The small matrices are formed and factored in double precision on the
+// device; the block vectors stay complex64.
+constexpr int kBlkTiles = 8;        // tiles per block of the Gram kernels
+constexpr double kDefl = 1e-5;      // relative norm below which a direction is dropped
+
+// out[b][m][i][j] = sum over the rows of block b of U_m[r][i] V_m[r][j]
+// (conj(U_m) for CONJ), m < nprod, in double.
+template <bool CONJ>
+__global__ void __launch_bounds__(256)
+k_bgram(Op op, const float2* __restrict__ U1, const float2* __restrict__ V1, const float2* __restrict__ U2,
+        const float2* __restrict__ V2, int nprod, double2* __restrict__ out) {
+    const int C = op.C, CC = C * C;
+    const int r0 = blockIdx.x * kBlkTiles * kTR;
+    const int r1 = min(r0 + kBlkTiles * kTR, op.nrow_valid);
+    for (int e = threadIdx.x; e < nprod * CC; e += 256) {
+        const int m = e / CC, ij = e % CC, i = ij / C, j = ij % C;
+        const float2* U = m ? U2 : U1;
+        const float2* V = m ? V2 : V1;
+        double2 a = make_double2(0.0, 0.0);
+        for (int r = r0; r < r1; ++r) {
+            const float2 u = U[(size_t)r * C + i], v = V[(size_t)r * C + j];
+            const double ux = u.x, uy = CONJ ? -(double)u.y : (double)u.y;
+            a.x += ux * v.x - uy * v.y;
+            a.y += ux * v.y + uy * v.x;
+        }
+        out[(size_t)blockIdx.x * nprod * CC + e] = a;
+    }
+}
+
+// res[e] = sum over the nb blocks of part[b][e] (fixed order: strided per
+// thread, then the waves), one workgroup per entry e < ne.
+__global__ void __launch_bounds__(256)
+k_bred(int nb, int ne, const double2* __restrict__ part, double2* __restrict__ res) {
+    __shared__ double2 ws[4];
+    const int e = blockIdx.x;
+    double2 a = make_double2(0.0, 0.0);
+    for (int b = threadIdx.x; b < nb; b += 256) a = cadd(a, part[(size_t)b * ne + e]);
+    a.x = wave_sum(a.x);
+    a.y = wave_sum(a.y);
+    if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = a;
+    __syncthreads();
+    if (threadIdx.x == 0) res[e] = cadd(cadd(ws[0], ws[1]), cadd(ws[2], ws[3]));
+}
+
+// State of the block iteration on the device.
+struct BlkState {
+    int rank;        // directions in P (its first `rank` columns)
+    int stop;        // breakdown: G singular on the kept directions
+    int iters;
+};
+
+// Small dense algebra of the block iteration, one workgroup of 64 threads,
+// complex double in LDS (C <= 32).
+//  mode 0: alpha = G^-1 H (G = gram[0], H = gram[1]), rows >= rank zero.
+//  mode 1: beta = -G^-1 W (G kept from mode 0 in g_keep, W = gram[0]).
+//  mode 2: T from Gamma = gram[0] (Hermitian): pivoted Cholesky, new rank.
+constexpr int kBlkMax = 32;
+__global__ void __launch_bounds__(64)
+k_bsmall(int C, int mode, const double2* __restrict__ gram, double2* __restrict__ g_keep,
+         double2* __restrict__ outm, BlkState* __restrict__ bs) {
+    __shared__ double2 a[kBlkMax][2 * kBlkMax];
+    __shared__ int piv[kBlkMax];
+    __shared__ int s_rank, s_stop;
+    const int t = threadIdx.x;
+    if (t == 0) { s_rank = bs->rank; s_stop = bs->stop; }
+    __syncthreads();
+    const int r = s_rank;
+    if (s_stop) return;
+    if (mode == 0 || mode == 1) {
+        // [G_rr | RHS_r,:] with RHS = H (mode 0) or -W (mode 1)
+        const double2* G = mode == 0 ? gram : g_keep;
+        const double2* Rhs = mode == 0 ? gram + C * C : gram;
+        for (int e = t; e < r * (r + C); e += 64) {
+            const int i = e / (r + C), j = e % (r + C);
+            double2 v = j < r ? G[i * C + j] : Rhs[i * C + (j - r)];
+            if (j >= r && mode == 1) v = make_double2(-v.x, -v.y);
+            a[i][j] = v;
+        }
+        if (mode == 0)
+            for (int e = t; e < C * C; e += 64) g_keep[e] = gram[e];
+        __syncthreads();
+        double gmax = 0.0;
+        for (int i = 0; i < r; ++i)
+            for (int j = 0; j < r; ++j) gmax = fmax(gmax, cabs2(a[i][j]));
+        for (int k = 0; k < r; ++k) {
+            if (t == 0) {
+                int p = k;
+                for (int i = k + 1; i < r; ++i)
+                    if (cabs2(a[i][k]) > cabs2(a[p][k])) p = i;
+                piv[k] = p;
+                if (!(cabs2(a[p][k]) > 1e-28 * gmax)) s_stop = 1;
+            }
+            __syncthreads();
+            if (s_stop) break;
+            const int p = piv[k];
+            if (p != k)
+                for (int j = t; j < r + C; j += 64) {
+                    const double2 x = a[k][j];
+                    a[k][j] = a[p][j];
+                    a[p][j] = x;
+                }
+            __syncthreads();
+            const double2 inv = cdiv(make_double2(1.0, 0.0), a[k][k]);
+            for (int e = t; e < (r - k - 1) * (r + C); e += 64) {
+                const int i = k + 1 + e / (r + C), j = e % (r + C);
+                if (j <= k) continue;
+                const double2 f = cmul(a[i][k], inv);
+                a[i][j] = csub(a[i][j], cmul(f, a[k][j]));
+            }
+            __syncthreads();
+        }
+        if (s_stop) {
+            if (t == 0) bs->stop = 1;
+            return;
+        }
+        // back substitution, one right-hand column per thread
+        for (int j = t; j < C; j += 64) {
+            for (int i = r - 1; i >= 0; --i) {
+                double2 v = a[i][r + j];
+                for (int k = i + 1; k < r; ++k) v = csub(v, cmul(a[i][k], a[k][r + j]));
+                a[i][r + j] = cdiv(v, a[i][i]);
+            }
+        }
+        __syncthreads();
+        for (int e = t; e < C * C; e += 64) {
+            const int i = e / C, j = e % C;
+            outm[e] = i < r ? a[i][r + j] : make_double2(0.0, 0.0);
+        }
+        return;
+    }
+    // mode 2: pivoted Cholesky of Gamma (C x C Hermitian): Gamma[pi][pi] = L L^H
+    for (int e = t; e < C * C; e += 64) a[e / C][e % C] = gram[e];
+    if (t < C) piv[t] = t;
+    __syncthreads();
+    if (t == 0) {
+        double dmax = 0.0;
+        for (int i = 0; i < C; ++i) dmax = fmax(dmax, a[i][i].x);
+        int rank = 0;
+        for (int k = 0; k < C; ++k) {
+            int p = k;
+            for (int i = k + 1; i < C; ++i)
+                if (a[i][i].x > a[p][p].x) p = i;
+            if (!(a[p][p].x > kDefl * kDefl * dmax)) break;
+            if (p != k) {   // symmetric swap of rows and columns k, p
+                for (int j = 0; j < C; ++j) { const double2 x = a[k][j]; a[k][j] = a[p][j]; a[p][j] = x; }
+                for (int i = 0; i < C; ++i) { const double2 x = a[i][k]; a[i][k] = a[i][p]; a[i][p] = x; }
+                const int q = piv[k]; piv[k] = piv[p]; piv[p] = q;
+            }
+            const double l = sqrt(a[k][k].x);
+            a[k][k] = make_double2(l, 0.0);
+            for (int i = k + 1; i < C; ++i) a[i][k] = cscale(a[i][k], 1.0 / l);
+            for (int i = k + 1; i < C; ++i)
+                for (int j = k + 1; j <= i; ++j) {
+                    a[i][j] = csub(a[i][j], cmul(a[i][k], cconj(a[j][k])));
+                    a[j][i] = cconj(a[i][j]);
+                }
+            rank = k + 1;
+        }
+        s_rank = rank;
+    }
+    __syncthreads();
+    const int rk = s_rank;
+    // T = Pi[:, :rk] (L_rk^H)^-1: column j of the inverse of the upper
+    // triangular R = L^H, one column per thread
+    __shared__ double2 rinv[kBlkMax][kBlkMax];
+    for (int j = t; j < rk; j += 64) {
+        for (int i = rk - 1; i >= 0; --i) {
+            double2 v = make_double2(i == j ? 1.0 : 0.0, 0.0);
+            for (int k = i + 1; k < rk; ++k) v = csub(v, cmul(cconj(a[k][i]), rinv[k][j]));
+            rinv[i][j] = cdiv(v, cconj(a[i][i]));
+        }
+    }
+    __syncthreads();
+    for (int e = t; e < C * C; e += 64) {
+        const int i = e / C, j = e % C;   // T[i][j]: row i of P~ into column j of P
+        double2 v = make_double2(0.0, 0.0);
+        if (j < rk)
+            for (int k = 0; k < rk; ++k)
+                if (piv[k] == i) v = rinv[k][j];
+        outm[e] = v;
+    }
+    if (t == 0) bs->rank = rk;
+}
+
+// Row updates of the block iteration: Y_c = A_c + sgn sum_k B_k M[k][c]
+// (complex64 rows, M in LDS as complex64). With zout: also z = D^-1 Y (the
+// column's Jacobi) into zout and the partials |Y_c|^2 per tile (part).
+__global__ void __launch_bounds__(256)
+k_bmul(Op op, int CP, const float2* __restrict__ Ain, const float2* __restrict__ Bv, const double2* __restrict__ Mm,
+       float sgn, float2* __restrict__ Y, float2* __restrict__ zout, double2* __restrict__ part) {
+    __shared__ float2 Ms[kBlkMax * kBlkMax];
+    __shared__ double2 ra[256], rb[256];
+    const int C = op.C;
+    for (int e = threadIdx.x; e < C * C; e += 256) Ms[e] = f2((float)Mm[e].x, (float)Mm[e].y);
+    __syncthreads();
+    const int tile = blockIdx.x;
+    const int c = threadIdx.x % CP, slot = threadIdx.x / CP, RPB = 256 / CP;
+    double2 a = make_double2(0.0, 0.0), b = make_double2(0.0, 0.0);
+    if (c < C) {
+        const double wmu = op.wmu[c];
+        for (int r0 = 0; r0 < kTR; r0 += RPB) {
+            const int i = tile * kTR + r0 + slot;
+            if (i >= op.nrow_valid) break;
+            const float2* br = Bv + (size_t)i * C;
+            float2 acc = f2(0.f, 0.f);
+            for (int k = 0; k < C; ++k) {   // rows of M past the rank are zero
+                const float2 bk = br[k], m = Ms[k * C + c];
+                acc.x += bk.x * m.x - bk.y * m.y;
+                acc.y += bk.x * m.y + bk.y * m.x;
+            }
+            const size_t o = (size_t)i * C + c;
+            const float2 av = Ain ? Ain[o] : f2(0.f, 0.f);
+            const float2 y = f2(av.x + sgn * acc.x, av.y + sgn * acc.y);
+            Y[o] = y;
+            if (zout) {
+                zout[o] = jacobi_z(y, op.Kd[i], op.Md[i], wmu);
+                b.x += (double)y.x * y.x + (double)y.y * y.y;
+            }
+        }
+    }
+    if (!part) return;
+    cp_sum2(a, b, CP, ra, rb);
+    if ((int)threadIdx.x < C && (int)threadIdx.x < CP) part[(size_t)tile * C + threadIdx.x] = rb[threadIdx.x];
+}
+
 }  // namespace
 
 int spmm_candidate_codes(int C, bool sliced, int32_t* out, int cap) {
@@ -2812,6 +3414,173 @@ int spmm_candidate_codes(int C, bool sliced, int32_t* out, int cap) {
     }
     return n;
 }
+
+namespace {
+
+// Block COCG inside the double-precision refinement loop (one mesh, C <= 32
+// columns of one frequency, zero initial guesses).
+int bcocg_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hipStream_t s,
+                std::vector<petgem_stats*>& stv) {
+    const int C = op.C, CP = cp_of(C), CC = C * C;
+    Timer t_all;
+    SpmmTuned tu;
+    PG_TRY(tune_spmm(w, op, nnz, s, tu, o.verbose != 0));
+    const SpmmChoice ch = tu.best, ch64 = tu.csr;
+    const int pp64 = spmm_slots(ch64);
+    const int nblk = ceil_div(op.ntiles, kBlkTiles);
+    double2 *gpart = nullptr, *gram = nullptr, *gkeep = nullptr, *mat = nullptr, *norms = nullptr;
+    BlkState* bs = nullptr;
+    PG_TRY(dalloc(&gpart, (size_t)nblk * 2 * CC));
+    PG_TRY(dalloc(&gram, (size_t)2 * CC));
+    PG_TRY(dalloc(&gkeep, (size_t)CC));
+    PG_TRY(dalloc(&mat, (size_t)CC));
+    PG_TRY(dalloc(&norms, (size_t)C));
+    PG_TRY(dalloc(&bs, 1));
+    struct Frees {
+        double2** p[5];
+        BlkState** b;
+        ~Frees() { for (auto q : p) dfree(*q); dfree(*b); }
+    } frees{{&gpart, &gram, &gkeep, &mat, &norms}, &bs};
+    hipLaunchKernelGGL(k_init_state, dim3(ceil_div(C, 64)), dim3(64), 0, s, w->st, C, o.inner_rtol);
+    hipLaunchKernelGGL(k_set_live, dim3(ceil_div(C, 64)), dim3(64), 0, s, w->st2, C);   // every SpMM column live
+    auto residual = [&](int first) -> int {
+        spmm_dispatch<double, 2>(ch64, op, w->st, SpmmArgs{w->X64, w->B64, w->R64, w->p0}, s);
+        hipLaunchKernelGGL(k_reduce, dim3(C), dim3(1024), 0, s, op, w->p0, pp64, nullptr, 1, w->st, (int)RED_RES,
+                           first);
+        PG_HIP(hipGetLastError());
+        return PETGEM_OK;
+    };
+    auto read_state = [&]() -> int {
+        PG_HIP(hipMemcpyAsync(w->st_h, w->st, sizeof(ColState) * C, hipMemcpyDeviceToHost, s));
+        PG_HIP(hipStreamSynchronize(s));
+        return PETGEM_OK;
+    };
+    hipLaunchKernelGGL(k_norm2, dim3(op.ntiles), dim3(256), 0, s, op, CP, w->B64, w->p0);
+    hipLaunchKernelGGL(k_reduce, dim3(C), dim3(1024), 0, s, op, w->p0, 1, nullptr, 1, w->st, (int)RED_RES, 1);
+    hipLaunchKernelGGL(k_set_tol, dim3(ceil_div(C, 64)), dim3(64), 0, s, w->st, C, o.rtol);
+    PG_TRY(residual(0));
+    PG_TRY(read_state());
+    auto gram_of = [&](bool conj, const float2* U1, const float2* V1, const float2* U2, const float2* V2,
+                       int nprod) {
+        if (conj)
+            hipLaunchKernelGGL(k_bgram<true>, dim3(nblk), dim3(256), 0, s, op, U1, V1, U2, V2, nprod, gpart);
+        else
+            hipLaunchKernelGGL(k_bgram<false>, dim3(nblk), dim3(256), 0, s, op, U1, V1, U2, V2, nprod, gpart);
+        hipLaunchKernelGGL(k_bred, dim3(nprod * CC), dim3(256), 0, s, nblk, nprod * CC, (const double2*)gpart,
+                           gram);
+    };
+    int steps = 0, total_inner = 0, status = PETGEM_OK;
+    std::vector<int> col_iters(C, 0);
+    const char* why = "";
+    double prev_worst = 1e300;
+    int strikes = 0;
+    std::vector<double2> nh(C);
+    while (true) {
+        int n_outer = 0;
+        double worst = 0.0;
+        for (int k = 0; k < C; ++k) {
+            const ColState& S = w->st_h[k];
+            n_outer += S.outer;
+            if (!std::isfinite(S.rnorm64)) { status = PETGEM_NONFINITE; break; }
+            if (S.outer && S.bnorm > 0) worst = std::max(worst, S.rnorm64 / S.bnorm);
+        }
+        if (status != PETGEM_OK || n_outer == 0) break;
+        strikes = worst > 0.5 * prev_worst ? strikes + 1 : 0;
+        prev_worst = worst;
+        if (strikes >= 3 || steps >= 60 || total_inner >= o.max_iter) {
+            status = PETGEM_NOT_CONVERGED;
+            why = strikes >= 3 ? "stagnated" : steps >= 60 ? "reached its refinement step limit" : "reached max_iter";
+            break;
+        }
+        // inner block COCG on A D = r64 / |r64| (per column), from D = 0
+        hipLaunchKernelGGL(k_inner_init, dim3(op.ntiles), dim3(256), 0, s, op, CP, w->R64, w->st,
+                           (const float2*)nullptr, w->Xi, w->R, w->Z, w->P, w->p1, w->p2);
+        BlkState b0{C, 0, 0};
+        PG_HIP(hipMemcpyAsync(bs, &b0, sizeof(b0), hipMemcpyHostToDevice, s));
+        float2* Pc = w->Q;   // the orthonormal directions
+        float2* Qb = w->P;   // A P, then the next unnormalised directions
+        // P = orth(Z): Gamma = Z^H Z (Z is in w->P), P = Z T
+        gram_of(true, w->P, w->P, nullptr, nullptr, 1);
+        hipLaunchKernelGGL(k_bsmall, dim3(1), dim3(64), 0, s, C, 2, (const double2*)gram, gkeep, mat, bs);
+        hipLaunchKernelGGL(k_bmul, dim3(op.ntiles), dim3(256), 0, s, op, CP, (const float2*)nullptr,
+                           (const float2*)w->P, (const double2*)mat, 1.f, Pc, (float2*)nullptr, (double2*)nullptr);
+        int inner = 0;
+        std::vector<double> tol2(C);
+        for (int k = 0; k < C; ++k) tol2[k] = w->st_h[k].outer ? w->st_h[k].inner_tol2 : 1e300;
+        while (true) {
+            for (int g = 0; g < kCheck; ++g) {
+                spmm_dispatch<float, 1>(ch, op, w->st2, SpmmArgs{Pc, nullptr, Qb, w->p0}, s);
+                gram_of(false, Pc, Qb, Pc, w->R, 2);                               // G = P^T Q, H = P^T R
+                hipLaunchKernelGGL(k_bsmall, dim3(1), dim3(64), 0, s, C, 0, (const double2*)gram, gkeep, mat, bs);
+                hipLaunchKernelGGL(k_bmul, dim3(op.ntiles), dim3(256), 0, s, op, CP, (const float2*)w->Xi,
+                                   (const float2*)Pc, (const double2*)mat, 1.f, w->Xi, (float2*)nullptr,
+                                   (double2*)nullptr);                            // X += P alpha
+                hipLaunchKernelGGL(k_bmul, dim3(op.ntiles), dim3(256), 0, s, op, CP, (const float2*)w->R,
+                                   (const float2*)Qb, (const double2*)mat, -1.f, w->R, w->Z, w->p1);   // R -= Q alpha
+                gram_of(false, Qb, w->Z, nullptr, nullptr, 1);                     // W = Q^T Z
+                hipLaunchKernelGGL(k_bsmall, dim3(1), dim3(64), 0, s, C, 1, (const double2*)gram, gkeep, mat, bs);
+                hipLaunchKernelGGL(k_bmul, dim3(op.ntiles), dim3(256), 0, s, op, CP, (const float2*)w->Z,
+                                   (const float2*)Pc, (const double2*)mat, 1.f, Qb, (float2*)nullptr,
+                                   (double2*)nullptr);                            // P~ = Z + P beta
+                gram_of(true, Qb, Qb, nullptr, nullptr, 1);                        // Gamma = P~^H P~
+                hipLaunchKernelGGL(k_bsmall, dim3(1), dim3(64), 0, s, C, 2, (const double2*)gram, gkeep, mat, bs);
+                hipLaunchKernelGGL(k_bmul, dim3(op.ntiles), dim3(256), 0, s, op, CP, (const float2*)nullptr,
+                                   (const float2*)Qb, (const double2*)mat, 1.f, Pc, (float2*)nullptr,
+                                   (double2*)nullptr);                            // P = P~ T
+            }
+            PG_HIP(hipGetLastError());
+            inner += kCheck;
+            hipLaunchKernelGGL(k_bred, dim3(C), dim3(256), 0, s, op.ntiles, C, (const double2*)w->p1, norms);
+            BlkState bh{};
+            PG_HIP(hipMemcpyAsync(nh.data(), norms, sizeof(double2) * C, hipMemcpyDeviceToHost, s));
+            PG_HIP(hipMemcpyAsync(&bh, bs, sizeof(bh), hipMemcpyDeviceToHost, s));
+            PG_HIP(hipStreamSynchronize(s));
+            bool done = bh.stop || bh.rank == 0;
+            if (!done) {
+                done = true;
+                for (int k = 0; k < C; ++k)
+                    if (!(nh[k].x <= tol2[k])) done = false;
+            }
+            if (done || total_inner + inner >= o.max_iter) break;
+        }
+        total_inner += inner;
+        for (int k = 0; k < C; ++k)
+            if (w->st_h[k].outer) col_iters[k] += inner;
+        hipLaunchKernelGGL(k_ir_update, dim3(op.ntiles), dim3(256), 0, s, op, CP, w->st, w->Xi, w->X64);
+        PG_TRY(residual(0));
+        PG_TRY(read_state());
+        ++steps;
+        if (o.verbose) {
+            double wr = 0.0;
+            for (int k = 0; k < C; ++k)
+                if (w->st_h[k].bnorm > 0) wr = std::max(wr, w->st_h[k].rnorm64 / w->st_h[k].bnorm);
+            fprintf(stderr, "[petgem] block COCG refinement step %d: %d inner iterations, worst true residual %.3e, "
+                            "%.0f ms\n", steps, inner, wr, t_all.ms());
+            fflush(stderr);
+        }
+    }
+    const double t_solve = t_all.ms();
+    for (int k = 0; k < C; ++k) {
+        petgem_stats* st = stv[k];
+        if (!st) continue;
+        const ColState& S = w->st_h[k];
+        st->iters = col_iters[k];
+        st->ir_steps = steps;
+        st->rel_residual = S.bnorm > 0 ? S.rnorm64 / S.bnorm : 0.0;
+        st->b_norm = S.bnorm;
+        st->x0_rel_residual = 1.0;
+        st->t_solve_ms = t_solve;
+        st->spmv_shape = 10000 * ch.kind + 100 * ch.a + ch.b;
+        st->status = S.outer ? (std::isfinite(S.rnorm64) ? PETGEM_NOT_CONVERGED : PETGEM_NONFINITE) : PETGEM_OK;
+        if (st->status != PETGEM_OK && status == PETGEM_OK) status = st->status;
+    }
+    if (status == PETGEM_NOT_CONVERGED)
+        set_error(std::string("block COCG refinement ") + why + " before rtol");
+    if (status == PETGEM_NONFINITE) set_error("non-finite value in the block COCG recurrence");
+    return status;
+}
+
+}  // namespace
 
 int block_solve(petgem_system* sys, const petgem_source* src, int32_t n_src, const petgem_opts& o,
                 const double2* x0, double2* x_out, hipStream_t s, petgem_stats* st) {
@@ -2875,7 +3644,26 @@ int block_solve(petgem_system* sys, const petgem_source* src, int32_t n_src, con
     std::vector<petgem_stats*> stv(C, nullptr);
     if (st)
         for (int c = 0; c < C; ++c) { stv[c] = st + c; st[c].t_rhs_ms = trhs; }
-    int rc = mrhs_solve(w, op, sys->nnz, o, s, stv, x0 != nullptr);
+    if (o.method == PETGEM_BCOCG) {
+        bool one_freq = true;
+        for (int c = 1; c < C; ++c) one_freq = one_freq && src[c].freq_hz == src[0].freq_hz;
+        if (!one_freq || C > kBlkMax || x0 || o.precond != PETGEM_JACOBI) {
+            set_error("block COCG: at most 32 sources of one frequency, zero initial guesses, Jacobi");
+            return PETGEM_INVALID_ARG;
+        }
+        int rc = bcocg_solve(w, op, sys->nnz, o, s, stv);
+        if (rc != PETGEM_OK && rc != PETGEM_NOT_CONVERGED && rc != PETGEM_NONFINITE) return rc;
+        hipLaunchKernelGGL(k_cols_out, dim3(ceil_div((size_t)n * C, 256)), dim3(256), 0, s, n, C, (size_t)0,
+                           w->X64, x_out, (size_t)n);
+        PG_HIP(hipGetLastError());
+        return rc;
+    }
+    const Ssor* sq = nullptr;
+    if (o.precond == PETGEM_SSOR) {
+        PG_TRY(ensure_ssor(sys, s));
+        sq = &sys->ssor32;
+    }
+    int rc = mrhs_solve(w, op, sys->nnz, o, s, stv, x0 != nullptr, nullptr, nullptr, sq);
     if (rc != PETGEM_OK && rc != PETGEM_NOT_CONVERGED && rc != PETGEM_NONFINITE) return rc;
     hipLaunchKernelGGL(k_cols_out, dim3(ceil_div((size_t)n * C, 256)), dim3(256), 0, s, n, C, (size_t)0,
                        w->X64, x_out, (size_t)n);

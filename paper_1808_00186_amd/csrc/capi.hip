@@ -83,6 +83,7 @@ void release_system(petgem_system* sys) {
     dfree(sys->diag_pos); dfree(sys->cptr); dfree(sys->cidx); dfree(sys->iptr); dfree(sys->islot);
     dfree(sys->Kst); dfree(sys->Mst); dfree(sys->K); dfree(sys->Ms); dfree(sys->Kd); dfree(sys->Msd);
     sys->sell32.release();
+    sys->ssor32.release();
     dfree(sys->K32); dfree(sys->Ms32); dfree(sys->Ahat); dfree(sys->dvec); dfree(sys->dinv);
     dfree(sys->Rst); dfree(sys->dflag); dfree(sys->tmp);
     dfree(sys->vox_tet); dfree(sys->vox_dof); dfree(sys->dof_mid); dfree(sys->dof_tan);
@@ -145,6 +146,8 @@ void petgem_default_opts(petgem_opts* o) {
     o->profile = 0;
     o->verbose = 0;
     o->spmm_shape = 0;
+    o->precond = PETGEM_JACOBI;
+    o->omega = 1.0;
 }
 
 int petgem_assemble(const petgem_mesh* mesh, const double* sigma, double sigma_bg, void* stream,
@@ -249,14 +252,19 @@ int petgem_solve(petgem_system* sys, const petgem_source* src, int32_t n_src, co
     if (!src || n_src <= 0 || !inout) { set_error("sources and a solution handle are required"); return PETGEM_INVALID_ARG; }
     petgem_opts o;
     if (opts) o = *opts; else petgem_default_opts(&o);
-    if (o.method == PETGEM_COCG && n_src > 256) {
+    if (o.method != PETGEM_GMRES && n_src > 256) {
         set_error("COCG solves at most 256 sources per call");
         return PETGEM_INVALID_ARG;
     }
     if (o.restart < 1 || o.restart > kMaxRestart || o.max_iter < 1 || !(o.rtol > 0.0) ||
-        (o.method != PETGEM_GMRES && o.method != PETGEM_COCG) ||
+        (o.method != PETGEM_GMRES && o.method != PETGEM_COCG && o.method != PETGEM_BCOCG) ||
         (o.precision != PETGEM_FP64 && o.precision != PETGEM_MIXED)) {
         set_error("invalid solver options");
+        return PETGEM_INVALID_ARG;
+    }
+    if ((o.precond != PETGEM_JACOBI && o.precond != PETGEM_SSOR) ||
+        (o.precond == PETGEM_SSOR && (o.method != PETGEM_COCG || !(o.omega > 0.0 && o.omega < 2.0)))) {
+        set_error("precond: PETGEM_JACOBI, or PETGEM_SSOR with COCG and 0 < omega < 2");
         return PETGEM_INVALID_ARG;
     }
     for (int32_t k = 0; k < n_src; ++k) PG_TRY(valid_source(src[k]));
@@ -279,7 +287,7 @@ int petgem_solve(petgem_system* sys, const petgem_source* src, int32_t n_src, co
     sol->sigma_bg = sys->sigma_bg;
     if (stats) std::memset(stats, 0, sizeof(petgem_stats) * (size_t)n_src);
     const double2* x0 = static_cast<const double2*>(x0_dev);
-    if (o.method == PETGEM_COCG) {
+    if (o.method == PETGEM_COCG || o.method == PETGEM_BCOCG) {
         // A large block whose sources come in contiguous runs of one
         // frequency is solved one run at a time: the runs converge at very
         // different iteration counts (lower frequency, more iterations), and a
@@ -293,7 +301,9 @@ int petgem_solve(petgem_system* sys, const petgem_source* src, int32_t n_src, co
         for (size_t a = 0; a + 1 < run.size(); ++a)
             for (size_t b = a + 1; b + 1 < run.size(); ++b)
                 if (src[run[a]].freq_hz == src[run[b]].freq_hz) contiguous = false;
-        const bool split = run.size() > 2 && contiguous && (int64_t)sys->n_dof * n_src >= kFreqRunMin;
+        // (block COCG solves one frequency per block, so always by runs)
+        const bool split = run.size() > 2 && contiguous &&
+                           ((int64_t)sys->n_dof * n_src >= kFreqRunMin || o.method == PETGEM_BCOCG);
         if (!split) return block_solve(sys, src, n_src, o, x0, sol->x, s, stats);
         int worst = PETGEM_OK;
         const size_t n = (size_t)sys->n_dof;
@@ -322,6 +332,10 @@ int petgem_solve_many(petgem_system* const* systems, const petgem_source* src, i
     if (!systems || !src || n_sys <= 0 || !sols) { set_error("systems, sources and solutions are required"); return PETGEM_INVALID_ARG; }
     petgem_opts o;
     if (opts) o = *opts; else petgem_default_opts(&o);
+    if (o.precond != PETGEM_JACOBI) {
+        set_error("the uneven batch takes the Jacobi preconditioner only");
+        return PETGEM_INVALID_ARG;
+    }
     for (int32_t k = 0; k < n_sys; ++k) {
         PG_TRY(check_sys(systems[k]));
         PG_TRY(valid_source(src[k]));
@@ -415,6 +429,25 @@ int petgem_tuning(const petgem_system* sys, int32_t* spmv_group, float* spmv_ms)
 }
 
 double petgem_setup_seconds(const petgem_system* sys) { return sys ? sys->setup_seconds : -1.0; }
+
+int32_t petgem_ssor_colors(petgem_system* sys, int32_t* colors, void* stream) {
+    PG_TRY(check_sys(sys));
+    PG_TRY(ensure_ssor(sys, static_cast<hipStream_t>(stream)));
+    PG_HIP(hipStreamSynchronize(static_cast<hipStream_t>(stream)));
+    if (colors) std::memcpy(colors, sys->ssor32.color_h.data(), sizeof(int32_t) * (size_t)sys->n_dof);
+    return sys->ssor32.nc;
+}
+
+int petgem_ssor_apply(petgem_system* sys, double freq, double omega, const void* r_dev, void* z_dev,
+                      void* stream) {
+    PG_TRY(check_sys(sys));
+    if (!r_dev || !z_dev || r_dev == z_dev || !(freq > 0.0) || !(omega > 0.0 && omega < 2.0)) {
+        set_error("petgem_ssor_apply: distinct vectors, freq > 0, 0 < omega < 2");
+        return PETGEM_INVALID_ARG;
+    }
+    return ssor_apply1(sys, freq, omega, static_cast<const float2*>(r_dev), static_cast<float2*>(z_dev),
+                       static_cast<hipStream_t>(stream));
+}
 
 int32_t petgem_spmm_candidates(int32_t n_cols, int32_t sliced, int32_t* shapes, int32_t cap) {
     if (n_cols < 1 || cap < 0 || (cap > 0 && !shapes)) {

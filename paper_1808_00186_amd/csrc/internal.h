@@ -78,6 +78,30 @@ struct Sell {
     }
 };
 
+// Multicolour split of the complex64 operator for the SSOR preconditioner:
+// the DOFs coloured so that no two of a colour share a matrix entry, rows
+// listed colour by colour (in DOF order within a colour), and for each listed
+// row its entries coupling to earlier colours (L) and to later colours (U),
+// the diagonal left out. pos: the entry's position in the CSR arrays, from
+// which the values are gathered again whenever K32, Ms32 change.
+struct Ssor {
+    int nc = 0;                        // colours
+    std::vector<int32_t> cptr;         // host [nc + 1] listed rows of each colour
+    std::vector<int32_t> color_h;      // host [n] colour of each DOF
+    int32_t* row = nullptr;            // [n] DOF of each listed row
+    int32_t *lrp = nullptr, *lcol = nullptr, *lpos = nullptr;   // [n + 1], [nl], [nl]
+    int32_t *urp = nullptr, *ucol = nullptr, *upos = nullptr;   // [n + 1], [nu], [nu]
+    float *lK = nullptr, *lM = nullptr, *uK = nullptr, *uM = nullptr;
+    int64_t nl = 0, nu = 0;
+    bool values = false;               // lK .. uM current
+    void release() {
+        dfree(row); dfree(lrp); dfree(lcol); dfree(lpos); dfree(urp); dfree(ucol); dfree(upos);
+        dfree(lK); dfree(lM); dfree(uK); dfree(uM);
+        nc = 0; nl = nu = 0; values = false;
+        cptr.clear(); color_h.clear();
+    }
+};
+
 // ------------------------------------------------------- GMRES control block
 // Small device-resident state of one GMRES cycle: the Hessenberg column in
 // progress, Givens rotations, the least-squares right-hand side g and flags
@@ -162,6 +186,7 @@ struct petgem_system {
     float* Ms32 = nullptr;
     bool have32 = false;
     petgem::Sell sell32;     // sliced-ELLPACK copy of K32 / Ms32 (built on first use)
+    petgem::Ssor ssor32;     // multicolour L / U split of K32 / Ms32 (built on first SSOR use)
     // frequency-specific operator of the FP64 GMRES: Ahat = A D^{-1}
     double cached_freq = -1.0;
     double2* Ahat = nullptr;              // [nnz]
@@ -215,6 +240,11 @@ int batch_solve(petgem_system* const* systems, const petgem_source* src, int32_t
                 const petgem_opts& o, const void* const* x0, petgem_solution** sols, hipStream_t s,
                 petgem_stats* st);
 int ensure_fp32(petgem_system* sys, hipStream_t s);
+// the multicolour split of the operator (pattern built once, values gathered
+// again after every reassembly); ssor_apply: z = M^-1 r of one complex64
+// column at one frequency (device vectors of n_dof)
+int ensure_ssor(petgem_system* sys, hipStream_t s);
+int ssor_apply1(petgem_system* sys, double freq, double omega, const float2* r, float2* z, hipStream_t s);
 // complex64 SpMM shapes the autotuner times for C columns (codes as the
 // spmv_shape statistic); returns the count, writes at most cap codes
 int spmm_candidate_codes(int C, bool sliced, int32_t* out, int cap);

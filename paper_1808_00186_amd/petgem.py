@@ -20,7 +20,8 @@ LIB_PATH = os.path.join(HERE, "libpetgem.so")
 OK, INVALID_ARG, DEGENERATE_ELEMENT, MESH_TOPOLOGY = 0, -1, -2, -3
 RECEIVER_OUTSIDE, SOURCE_SINGULAR, NOT_CONVERGED, NONFINITE = -4, -5, -6, -7
 HIP_ERROR, OUT_OF_MEMORY = -8, -9
-GMRES, COCG = 0, 1
+GMRES, COCG, BCOCG = 0, 1, 2
+JACOBI, SSOR = 0, 1
 FP64, MIXED = 0, 1
 
 _NAMES = {0: "OK", -1: "INVALID_ARG", -2: "DEGENERATE_ELEMENT", -3: "MESH_TOPOLOGY",
@@ -48,7 +49,7 @@ class Opts(C.Structure):
     _fields_ = [("method", C.c_int32), ("precision", C.c_int32), ("restart", C.c_int32),
                 ("max_iter", C.c_int32), ("rtol", C.c_double), ("inner_rtol", C.c_double),
                 ("use_graph", C.c_int32), ("profile", C.c_int32), ("verbose", C.c_int32),
-                ("spmm_shape", C.c_int32)]
+                ("spmm_shape", C.c_int32), ("precond", C.c_int32), ("omega", C.c_double)]
 
 
 class Stats(C.Structure):
@@ -89,6 +90,8 @@ _SIGS = {
                                  C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_void_p]),
     "petgem_spmv": (C.c_int, [C.c_void_p, C.c_double, C.c_void_p, C.c_void_p, C.c_void_p]),
     "petgem_setup_seconds": (C.c_double, [C.c_void_p]),
+    "petgem_ssor_colors": (C.c_int32, [C.c_void_p, C.POINTER(C.c_int32), C.c_void_p]),
+    "petgem_ssor_apply": (C.c_int, [C.c_void_p, C.c_double, C.c_double, C.c_void_p, C.c_void_p, C.c_void_p]),
     "petgem_spmm_candidates": (C.c_int32, [C.c_int32, C.c_int32, C.POINTER(C.c_int32), C.c_int32]),
     "petgem_tuning": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_float)]),
     "petgem_mesh_pattern": (C.c_int, [C.POINTER(Mesh), C.POINTER(C.c_int32), C.POINTER(C.c_int64),
@@ -293,6 +296,20 @@ class System:
         y = torch.empty_like(x)
         _check(lib().petgem_spmv(self.handle, freq, _ptr(x), _ptr(y), _stream(stream)))
         return y
+
+    def ssor_colors(self, stream=None) -> np.ndarray:
+        """Colour of every DOF of the multicolour SSOR (library DOF order)."""
+        out = np.empty(self.n_dof, np.int32)
+        _check_count(lib().petgem_ssor_colors(self.handle, out.ctypes.data_as(C.POINTER(C.c_int32)),
+                                              _stream(stream)))
+        return out
+
+    def ssor_apply(self, freq: float, omega: float, r, stream=None):
+        """z = M^-1 r of the multicolour SSOR for one complex64 CUDA vector."""
+        import torch
+        z = torch.empty_like(r)
+        _check(lib().petgem_ssor_apply(self.handle, freq, omega, _ptr(r), _ptr(z), _stream(stream)))
+        return z
 
     def tuning(self) -> dict:
         g = C.c_int32()

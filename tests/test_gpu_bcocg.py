@@ -1,0 +1,65 @@
+"""Block COCG (PETGEM_BCOCG): the sources of one frequency share one block
+Krylov space (O'Leary's block CG with the bilinear form u^T v, directions
+orthonormalised and dependent ones dropped). Not in the paper; pinned like
+the other forms by the oracle's receiver fields at the stated residual.
+Marked `gpu`."""
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+from oracle import fem
+from paper_1808_00186_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pg():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1808_00186_amd import petgem
+    petgem.lib()
+    return petgem
+
+
+def _oracle_fields(m, sources):
+    s = fem.assemble(m.xyz, m.tets, m.sigma)
+    lus, out = {}, []
+    for d in sources:
+        if d.freq not in lus:
+            lus[d.freq] = spla.splu(fem.system_matrix(s, d.freq).tocsc())
+        b = fem.rhs(m.xyz, m.tets, m.sigma, m.sigma_bg, s.topo, d.pos, d.dir, d.freq, d.moment)
+        out.append(fem.receivers_total(m.xyz, m.tets, s.topo, lus[d.freq].solve(b), m.receivers, d.pos, d.dir,
+                                       d.freq, m.sigma_bg, d.moment))
+    return np.array(out)
+
+
+@pytest.mark.parametrize("n_pos,freqs", [(8, (1.25,)), (32, (1.25,)), (4, (0.5, 2.0))])
+def test_block_cocg_matches_oracle(pg, n_pos, freqs):
+    m = synth.config1()
+    xs = np.linspace(-400.0, 400.0, n_pos)
+    srcs = [synth.Dipole((float(x), 0.0, 300.0), f) for f in freqs for x in xs]
+    ref = _oracle_fields(m, srcs)
+    S = pg.System.from_model(m)
+    print(f"[case] cfg1 block COCG {n_pos} sources x {len(freqs)} frequencies", flush=True)
+    sol, st, rc = S.solve(srcs, pg.default_opts(method=pg.BCOCG, precision=pg.MIXED, rtol=1e-8))
+    assert rc == pg.OK and all(s_["rel_residual"] <= 1e-8 for s_ in st)
+    E = sol.receivers(m.receivers).cpu().numpy()
+    err = max(fem.receiver_error(E[k], ref[k]) for k in range(len(srcs)))
+    _, st_i, _ = S.solve(srcs, pg.default_opts(method=pg.COCG, precision=pg.MIXED, rtol=1e-8))
+    print(f"  block iters {max(s_['iters'] for s_ in st)} ir {st[0]['ir_steps']}, independent COCG iters "
+          f"{max(s_['iters'] for s_ in st_i)}, receiver error {err:.1e}", flush=True)
+    assert err <= 1e-6
+
+
+def test_block_cocg_refuses_what_it_does_not_take(pg):
+    m = synth.config1()
+    S = pg.System.from_model(m)
+    srcs = [synth.Dipole((0.0, 0.0, 300.0), 1.0), synth.Dipole((50.0, 0.0, 300.0), 2.0),
+            synth.Dipole((90.0, 0.0, 300.0), 1.0)]     # frequencies not in runs
+    with pytest.raises(pg.PetgemError):
+        S.solve(srcs, pg.default_opts(method=pg.BCOCG, precision=pg.MIXED))
+    many = [synth.Dipole((float(x), 0.0, 300.0), 1.0) for x in np.linspace(-400, 400, 33)]
+    with pytest.raises(pg.PetgemError):
+        S.solve(many, pg.default_opts(method=pg.BCOCG, precision=pg.MIXED))

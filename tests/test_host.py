@@ -156,3 +156,11 @@ def test_spmm_candidates_listed_by_the_library():
                     assert C <= 4
     with pytest.raises(petgem.PetgemError):
         petgem.spmm_candidates(0, False)
+
+
+def test_default_options():
+    """petgem_default_opts fills every field as its header states."""
+    o = petgem.default_opts()
+    assert (o.method, o.precision, o.restart, o.max_iter) == (petgem.GMRES, petgem.FP64, 30, 20000)
+    assert (o.rtol, o.inner_rtol, o.use_graph, o.profile, o.verbose, o.spmm_shape) == (1e-8, 3e-5, 1, 0, 0, 0)
+    assert (o.precond, o.omega) == (petgem.JACOBI, 1.0)
