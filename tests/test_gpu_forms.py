@@ -241,3 +241,28 @@ def test_uneven_batch_of_smallest_cfg4_models_matches_oracle(pg):
         print(f"  {m.name} tets {len(m.tets)} f {m.sources[0].freq:.2f} iters {st[k]['iters']} "
               f"res {st[k]['rel_residual']:.1e} err {err:.1e}", flush=True)
         assert st[k]["rel_residual"] <= 1e-12 and err <= 1e-6
+
+
+@pytest.mark.parametrize("seeds", [(4018, 4047)])
+def test_uneven_batch_of_largest_and_hardest_cfg4_models_matches_stored_oracle(pg, seeds):
+    """The largest model of the 48-model uneven batch (seed 4018, 1,361,886
+    elements) and the slowest to converge (seed 4047, 1,296,000 elements at
+    0.61 Hz), solved together as one uneven batch at the batch's residual of
+    1e-12, against the oracle's receiver fields (Jacobi GMRES to 1e-12,
+    tests/golden/cfg4_<seed>.npz, written by the oracle only)."""
+    paths = [os.path.join(GOLDEN, f"cfg4_{sd}.npz") for sd in seeds]
+    if not all(os.path.exists(p) for p in paths):
+        pytest.skip("stored oracle fields missing")
+    models = [synth.config4_model(sd) for sd in seeds]
+    print(f"[case] cfg4 models {seeds}: {[len(m.tets) for m in models]} elements", flush=True)
+    systems = [pg.System.from_model(m) for m in models]
+    o = pg.default_opts(method=pg.COCG, precision=pg.MIXED, rtol=1e-12)
+    sols, st, rc = pg.solve_many(systems, [m.sources[0] for m in models], o)
+    assert rc == pg.OK
+    for k, (m, p) in enumerate(zip(models, paths)):
+        g = np.load(p)
+        E = sols[k].receivers(m.receivers).cpu().numpy()[0]
+        err = fem.receiver_error(E, g["E"])
+        print(f"  {m.name}: iters {st[k]['iters']} res {st[k]['rel_residual']:.1e} (oracle {float(g['residual']):.1e}) "
+              f"err {err:.1e}", flush=True)
+        assert st[k]["rel_residual"] <= 1e-12 and err <= 1e-6
