@@ -1,25 +1,29 @@
 """Throughput of the edge-FEM CSEM secondary-field solve on one MI355X.
 
-Default workload (cfg2, the marine layered model): 40^3 x 6 = 384,000
-jittered tetrahedra, 433,720 unknowns, 6,950,152 nonzeros, one x-dipole at
-1 Hz, 101 receivers. One step = one pass of the whole path: device
-re-assembly of K and M_sigma, the dipole right-hand side, the solve, and the
-total field at the receivers. Inputs are resident on the GPU when the timed
-region starts; host mesh preprocessing is setup and is reported separately.
+Default workload (cfg3, the marine layered model at full size): 100^3 x 6 =
+6,000,000 jittered tetrahedra, 6,910,300 unknowns, 112,409,452 nonzeros; a
+survey of 32 x-dipole positions (x = -3100 + 200 i, z = 50 m) at 0.25, 0.5
+and 1.25 Hz (96 sources) and 101 receivers. One step = one pass of the whole
+path for one batch of 8 consecutive dipole positions at one frequency: device
+re-assembly of K and M_sigma, the 8 right-hand sides, the solve of the
+8-column block by Jacobi COCG in complex64 inside complex128 iterative
+refinement to a true relative residual of 1e-9, and the total field at the
+receivers. Timed step k takes batch k mod 12, so 12 steps cover the survey.
+Inputs are resident on the GPU when the timed region starts; host mesh
+preprocessing is setup and is reported separately. Beside it: plain FP64
+Jacobi GMRES(30) on a stated subset (the centre dipole at each frequency),
+and the cfg2 forms.
 
-Two forms of the solve are timed, both to a true relative residual of 1e-9
-(at 1e-8 the receiver error of this model is 2e-6; at 1e-9 it is below the
-1e-6 the metric asks for):
-  plain  -- Jacobi GMRES(30), complex128 throughout;
-  mixed  -- Jacobi COCG in complex64 inside complex128 iterative refinement.
-`value` is the faster form whose receiver fields meet 1e-6 against the
-stored oracle fields (tests/golden/cfg2_receivers.npz) when present.
+`value` counts only if every solve converged to its residual and the
+sources with stored oracle fields (tests/golden/cfg3_*.npz) match them within
+1e-6; otherwise it is null and the line says why. The timed steps themselves
+timestamp every sparse-matrix dispatch (HIP events on the solve's stream) for
+`roofline` (graphs are off in that mode: the kernels here take milliseconds).
 
 Other workloads (`--workload`):
-  cfg3 -- the same layered model at 100^3 x 6 = 6,000,000 tetrahedra with
-          32 dipole positions x 3 frequencies: 96 sources in one call, solved
-          as one 32-column COCG block per frequency (complex64 SpMM inside
-          complex128 refinement) vs plain GMRES on a stated subset.
+  cfg2 -- the layered model at 40^3 x 6 = 384,000 tetrahedra, one x-dipole at
+          1 Hz: plain GMRES vs mixed COCG, each timed, then a second pass of
+          the same steps with per-dispatch timestamps for the roofline.
   cfg4 -- 48 independent models of 1e4..2e6 tetrahedra, one source each, in
           one uneven batch vs plain GMRES one model at a time.
   cfg5 -- the learned initial guess: a network trained on 2000 solves of
@@ -30,13 +34,10 @@ Other workloads (`--workload`):
           16, BF16 MFMA throughput against its peak.
   copy -- a 1 GiB device copy (calibration of the rocprofv3 byte counters).
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload cfg2]
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload cfg3] [--batch 8]
 
-Prints one JSON line. `value` comes from a pass over the timed steps as the
-solver runs in use (graph-captured iterations); `roofline` reports the
-dominant sparse-matrix kernel of the reported form from a second pass over
-the same steps in which its dispatches timestamp their own start and end;
-`cpu_baseline` times the CPU oracle on a bounded sample of the same workload.
+Prints one JSON line; `cpu_baseline` times the CPU oracle on a bounded
+sample of the same workload.
 """
 from __future__ import annotations
 
@@ -143,6 +144,8 @@ def kernel_name(form, shape):
         return f"k_spmm_sp<{a}, {b}> complex64 pipelined sliced ELLPACK (K, M_sigma)"
     if kind == 2:
         return f"k_spmm_s<{a}, {b}> complex64 sliced ELLPACK (K, M_sigma)"
+    if kind == 6:
+        return f"k_spmm_g<float, {a}, {b}, 20, 1> complex64 CSR, row entries over the lanes (K, M_sigma)"
     if kind == 1:
         return f"k_spmm_n<float, {a}, {b}, 1> complex64 CSR (K, M_sigma)"
     return f"k_spmm_c<float, {a}, {b}, 1> complex64 CSR (K, M_sigma)"
@@ -161,71 +164,81 @@ def timed(fn, steps, warmup):
     return time.perf_counter() - t0, out
 
 
-def bench_cfg2(args, petgem, synth, torch):
-    dev = torch.device("cuda:0")
+def cfg2_forms(args, petgem, synth, torch, steps, warmup, profile=True):
+    """cfg2 (one source): the plain and the mixed form, each over `steps`
+    timed steps of the whole path; with `profile` a second pass has every
+    sparse-matrix dispatch timestamp its own start and end (no graphs).
+    A form counts (`ok`) only if every solve returned OK at the residual and
+    its receivers match the stored oracle fields within 1e-6."""
     model = synth.config2()
     t0 = time.perf_counter()
     S = petgem.System.from_model(model)
     setup_s = time.perf_counter() - t0
-    sigma_dev = torch.tensor(model.sigma, device=dev)
+    sigma_dev = torch.tensor(model.sigma, device="cuda")
     ref = np.load(GOLDEN_CFG2)["E"] if os.path.exists(GOLDEN_CFG2) else None
     forms = {
         "plain": dict(rtol=RTOL),
         "mixed": dict(rtol=RTOL, method=petgem.COCG, precision=petgem.MIXED, inner_rtol=args.inner_rtol,
-                      spmm_shape=args.spmm_shape),
+                      spmm_shape=args.spmm_shape if args.workload == "cfg2" else 0),
     }
     res = {}
     for name, kw in forms.items():
         sol = [None]
 
-        def run(profile):
-            opts = petgem.default_opts(profile=profile, **kw)
+        def run(prof):
+            opts = petgem.default_opts(profile=prof, **kw)
 
             def step():
                 S.reassemble(sigma_dev, model.sigma_bg)
-                sol[0], st, _ = S.solve(model.sources, opts, solution=sol[0])
+                sol[0], st, rc = S.solve(model.sources, opts, solution=sol[0], allow_not_converged=True)
                 E = sol[0].receivers(model.receivers)
-                return st[0], E
+                return st[0], E, rc
 
-            return timed(step, args.steps, args.warmup)
+            return timed(step, steps, warmup)
 
-        # the throughput pass runs the solver as deployed (graph-captured
-        # iterations); a second pass of the same steps has every sparse-matrix
-        # dispatch timestamp its own start and end (no graphs) for the roofline
         dt, outs = run(0)
         st = [o[0] for o in outs]
         E = outs[-1][1].cpu().numpy()[0]
+        converged = all(o[2] == petgem.OK and o[0]["rel_residual"] <= RTOL for o in outs)
         n_launch, avg_ms, dt_prof = 0, float("nan"), None
-        if not args.no_profile:
+        if profile:
             dt_prof, pouts = run(1)
             pst = [o[0] for o in pouts]
             n_launch = sum(s["spmv_launches"] for s in pst)
             avg_ms = sum(s["spmv_ms"] for s in pst) / n_launch if n_launch else float("nan")
         nbytes = (spmv_bytes_fp64(S.n_dof, S.nnz) if name == "plain"
                   else spmm_bytes_fp32(S.n_dof, S.nnz, 1, st[-1]["spmv_shape"]))
+        err = rx_error(E, ref) if ref is not None else None
         res[name] = {
-            "solves_per_s": args.steps / dt, "ms_per_step": dt / args.steps * 1e3,
+            "solves_per_s": steps / dt, "ms_per_step": dt / steps * 1e3,
             "iters": st[-1]["iters"], "ir_steps": st[-1]["ir_steps"],
-            "rel_residual": st[-1]["rel_residual"],
-            "rx_err_vs_oracle": rx_error(E, ref) if ref is not None else None,
+            "rel_residual": st[-1]["rel_residual"], "converged": converged,
+            "rx_err_vs_oracle": err, "ok": converged and err is not None and err <= 1e-6,
             "kernel": kernel_name(name, st[-1]["spmv_shape"]),
             "bytes_per_launch": nbytes, "avg_launch_us": avg_ms * 1e3, "launches": n_launch,
-            "profiled_pass_solves_per_s": args.steps / dt_prof if dt_prof else None,
+            "profiled_pass_solves_per_s": steps / dt_prof if dt_prof else None,
         }
-    ok = [k for k, v in res.items() if v["rx_err_vs_oracle"] is None or v["rx_err_vs_oracle"] <= 1e-6]
-    best = max(ok, key=lambda k: res[k]["solves_per_s"])
+    res["speedup_mixed_vs_plain"] = res["mixed"]["solves_per_s"] / res["plain"]["solves_per_s"]
+    res["setup_s"] = round(setup_s, 3)
+    return res, S, model
+
+
+def bench_cfg2(args, petgem, synth, torch):
+    res, S, model = cfg2_forms(args, petgem, synth, torch, args.steps, args.warmup, not args.no_profile)
+    ok = [k for k in ("plain", "mixed") if res[k]["ok"]]
+    best = max(ok, key=lambda k: res[k]["solves_per_s"]) if ok else "mixed"
     r = res[best]
     achieved = r["bytes_per_launch"] / (r["avg_launch_us"] * 1e-6) / 1e9 if r["launches"] else None
     line = {
         "metric": "receiver-field solves/s at 1e-6 rel err: plain FP64 vs batched/mixed/learned",
-        "value": r["solves_per_s"], "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+        "value": r["solves_per_s"] if ok else None, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": r["ms_per_step"], "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None,
         "dtype": "f64" if best == "plain" else "c64 inner / f64 refinement",
         "data": "synthetic",
         "config": {"workload": "cfg2 marine layered: 384000 jittered tets, 433720 DOF, 6950152 nnz, "
                                "x-dipole 1 Hz, 101 receivers, true relative residual 1e-9",
-                   "form": best, "n_dof": S.n_dof, "nnz": S.nnz, "setup_s": round(setup_s, 3),
+                   "form": best, "n_dof": S.n_dof, "nnz": S.nnz, "setup_s": res["setup_s"],
                    "tuning": S.tuning(), "parallelism": "1 GPU"},
         "forms": res,
         "speedup_vs_plain": r["solves_per_s"] / res["plain"]["solves_per_s"],
@@ -237,77 +250,179 @@ def bench_cfg2(args, petgem, synth, torch):
                      "launches": r["launches"],
                      "note": "operator (155 MB fp64 / 88 MB fp32) fits the 256 MB Infinity Cache"},
     }
+    if not ok:
+        line["invalid"] = "no form converged and matched the stored oracle fields within 1e-6"
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline_cfg2(model, 2 * res["plain"]["iters"])
     return line
 
 
+CFG3_BATCH = 8          # sources per step: a block of consecutive dipole positions at one frequency
+CFG3_GOLDEN = {(1.25, 16): "cfg3_f1.25_i16.npz", (1.25, 0): "cfg3_f1.25_i0.npz",
+               (0.5, 16): "cfg3_f0.5_i16.npz", (0.25, 16): "cfg3_f0.25_i16.npz"}
+
+
+def cpu_baseline_cfg3(model, plain_iters: float):
+    """The CPU oracle timed on a bounded sample of the cfg3 workload: a slab of
+    1/16 of its elements (the first 375,000, x in [-5000, -4375] m, all
+    depths) through the oracle's assembly, right-hand side, receiver location
+    and 30 iterations of its Jacobi GMRES(30); each part is scaled by 16 (the
+    element / nonzero ratio) and the iterations by the iteration count of a
+    full cfg3 solve (the plain GMRES(30) subset of this run), assembly
+    amortised over the 96 sources that share it. `cores` is CPU time over wall
+    time of the sample."""
+    from oracle import fem, solve as osolve
+    T = len(model.tets) // 16
+    tets = model.tets[:T]
+    used = np.unique(tets)
+    remap = np.full(len(model.xyz), -1, dtype=np.int64)
+    remap[used] = np.arange(len(used))
+    xyz, tets = model.xyz[used], remap[tets].astype(np.int32)
+    sig = model.sigma[:T]
+    src = model.sources[2 * 32 + 16]
+    rx = model.receivers[model.receivers[:, 0] < -4400.0]
+    t_cpu0, t0 = time.process_time(), time.perf_counter()
+    s = fem.assemble(xyz, tets, sig)
+    t_asm = time.perf_counter() - t0
+    t1 = time.perf_counter()
+    A = fem.system_matrix(s, src.freq)
+    b = fem.rhs(xyz, tets, sig, model.sigma_bg, s.topo, src.pos, src.dir, src.freq, src.moment)
+    t_rhs = time.perf_counter() - t1
+    t2 = time.perf_counter()
+    _, it, _ = osolve.gmres(A, b, rtol=1e-30, restart=30, max_iter=30)
+    t_it = (time.perf_counter() - t2) / max(it, 1)
+    t3 = time.perf_counter()
+    x = np.zeros(s.topo.n_dof, dtype=np.complex128)
+    fem.receivers_total(xyz, tets, s.topo, x, rx, src.pos, src.dir, src.freq, model.sigma_bg)
+    t_rx = (time.perf_counter() - t3) / max(len(rx), 1) * len(model.receivers)
+    wall = time.perf_counter() - t0
+    cores = (time.process_time() - t_cpu0) / wall
+    per_solve = 16 * (t_asm / 96 + t_rhs + plain_iters * t_it) + 16 * t_rx
+    return {
+        "value": 1.0 / per_solve, "unit": "solves/s", "cores": round(cores, 2), "kind": "oracle",
+        "sample": (f"cfg3 slab of {T} elements ({s.topo.n_dof} unknowns, {A.nnz} nonzeros): oracle assembly "
+                   f"{t_asm:.1f} s, RHS {t_rhs:.1f} s, {it} Jacobi GMRES(30) iterations {t_it * 1e3:.0f} ms each, "
+                   f"receiver location {t_rx / 16:.2f} s per 101; scaled by 16 and by {plain_iters:.0f} iterations "
+                   f"per solve (this run's plain GPU GMRES(30) subset): {per_solve:.0f} s per solve; {wall:.1f} s "
+                   f"wall on {len(os.sched_getaffinity(0))} available host cores"),
+    }
+
+
 def bench_cfg3(args, petgem, synth, torch):
+    """cfg3: 6,000,000 jittered tetrahedra (6,910,300 unknowns), 96 sources
+    (32 dipole positions x 3 frequencies). One step = one batch of B
+    consecutive dipole positions at one frequency (B = 8 by default), the whole
+    path: device re-assembly of K and M_sigma, the B right-hand sides, the
+    mixed-precision COCG solve of the B-column block, the total field at the
+    101 receivers. Timed step k takes batch k mod (96 / B), frequency-major,
+    so a run of 12 steps covers the survey once."""
     model = synth.config3()
+    B = args.batch
+    nb = len(model.sources) // B
     t0 = time.perf_counter()
     S = petgem.System.from_model(model)
     setup_s = time.perf_counter() - t0
-    print(f"cfg3 setup {setup_s:.1f} s, {S.n_dof} DOF, {S.nnz} nnz", file=sys.stderr, flush=True)
+    print(f"cfg3 setup {setup_s:.1f} s (host {S.setup_seconds:.1f} s), {S.n_dof} DOF, {S.nnz} nnz",
+          file=sys.stderr, flush=True)
     sigma_dev = torch.tensor(model.sigma, device="cuda")
-    prof = 0 if args.no_profile else 1
-    o_mix = petgem.default_opts(profile=prof, rtol=RTOL, method=petgem.COCG, precision=petgem.MIXED,
-                                inner_rtol=args.inner_rtol, max_iter=args.max_iter,
-                                verbose=int(args.verbose))
-    srcs = model.sources
-    sol = [None]
+    o_mix = petgem.default_opts(profile=0 if args.no_profile else 1, rtol=RTOL, method=petgem.COCG,
+                                precision=petgem.MIXED, inner_rtol=args.inner_rtol, max_iter=args.max_iter,
+                                verbose=int(args.verbose), spmm_shape=args.spmm_shape,
+                                precond=petgem.SSOR if args.precond == "ssor" else petgem.JACOBI,
+                                omega=args.omega)
+    sols = {}
+    fields = {}       # source index -> receiver total field of its last solve
+    bad = []
 
-    def step():
+    def step(k):
+        bi = k % nb
+        srcs = model.sources[bi * B:(bi + 1) * B]
         S.reassemble(sigma_dev, model.sigma_bg)
-        sol[0], st, _ = S.solve(srcs, o_mix, solution=sol[0], allow_not_converged=True)
-        E = sol[0].receivers(model.receivers)
-        print(f"cfg3 step: iters max {max(s['iters'] for s in st)} ir {st[0]['ir_steps']} "
-              f"solve {st[0]['t_solve_ms']:.0f} ms", file=sys.stderr, flush=True)
-        return st, E
+        sol, st, rc = S.solve(srcs, o_mix, solution=sols.get(bi), allow_not_converged=True)
+        sols[bi] = sol
+        E = sol.receivers(model.receivers)
+        if rc != petgem.OK or any(s_["rel_residual"] > RTOL for s_ in st):
+            bad.append((bi, rc, max(s_["rel_residual"] for s_ in st)))
+        print(f"cfg3 step {k}: batch {bi} ({srcs[0].freq} Hz) iters max {max(s_['iters'] for s_ in st)} "
+              f"ir {st[0]['ir_steps']} solve {st[0]['t_solve_ms']:.0f} ms", file=sys.stderr, flush=True)
+        return bi, st, E
 
-    dt, outs = timed(step, args.steps, args.warmup)
-    st = outs[-1][0]
-    n_launch = sum(o[0][0]["spmv_launches"] for o in outs)
-    avg_ms = sum(o[0][0]["spmv_ms"] for o in outs) / n_launch if n_launch else float("nan")
-    # the roofline kernel is the first block's SpMM: the sources of the first frequency
-    block = next((k for k, d in enumerate(srcs) if d.freq != srcs[0].freq), len(srcs))
-    nbytes = spmm_bytes_fp32(S.n_dof, S.nnz, block)
+    for k in range(args.warmup):
+        step(k)
+    torch.cuda.synchronize()
+    outs = []
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        outs.append(step(k))
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    for bi, st, E in outs:
+        E = E.cpu().numpy()
+        for c in range(B):
+            fields[bi * B + c] = E[c]
+    n_launch = sum(o[1][0]["spmv_launches"] for o in outs)
+    avg_ms = sum(o[1][0]["spmv_ms"] for o in outs) / n_launch if n_launch else float("nan")
+    shape = outs[-1][1][0]["spmv_shape"]
+    nbytes = spmm_bytes_fp32(S.n_dof, S.nnz, B, shape)
     achieved = nbytes / (avg_ms * 1e-3) / 1e9 if n_launch else None
-    # plain GMRES on a stated subset: the centre dipole at every frequency, or
-    # the first, centre and last with --plain-subset 9
+    kname = kernel_name("mixed", shape)
+    # accuracy: every solve converged to RTOL (gate above) and the sources with
+    # stored oracle fields match them
+    oracle_err = {}
+    for (f, i), name in CFG3_GOLDEN.items():
+        path = os.path.join(ROOT, "tests", "golden", name)
+        k = synth.CFG3_FREQS.index(f) * 32 + i
+        if os.path.exists(path) and k in fields:
+            oracle_err[f"{f} Hz, x={model.sources[k].pos[0]:.0f}"] = rx_error(fields[k], np.load(path)["E"])
+    ok = not bad and all(e <= 1e-6 for e in oracle_err.values())
+    # plain FP64 GMRES(30) on a stated subset: the centre dipole at each frequency
     picks = (16,) if args.plain_subset <= 3 else (0, 16, 31)
     sub = [f * 32 + k for f in range(3) for k in picks]
     o_plain = petgem.default_opts(rtol=RTOL, max_iter=args.max_iter, verbose=int(args.verbose))
+    S.solve([model.sources[sub[0]]], o_plain, allow_not_converged=True)   # the plain path's own autotuning
+    torch.cuda.synchronize()
     t1 = time.perf_counter()
-    psol, pst, _ = S.solve([srcs[k] for k in sub], o_plain, allow_not_converged=True)
+    psol, pst, prc = S.solve([model.sources[k] for k in sub], o_plain, allow_not_converged=True)
     Ep = psol.receivers(model.receivers)
     torch.cuda.synchronize()
     t_plain = time.perf_counter() - t1
-    Em = outs[-1][1].cpu().numpy()
     Ep = Ep.cpu().numpy()
-    agree = max(rx_error(Em[k], Ep[i]) for i, k in enumerate(sub))
+    agree = max((rx_error(fields[k], Ep[i]) for i, k in enumerate(sub) if k in fields), default=None)
     plain_rate = len(sub) / t_plain
-    value = len(srcs) * args.steps / dt
-    return {
+    plain_ok = prc == petgem.OK and all(s_["rel_residual"] <= RTOL for s_ in pst)
+    value = B * args.steps / dt
+    line = {
         "metric": "receiver-field solves/s at 1e-6 rel err: plain FP64 vs batched/mixed/learned",
-        "value": value, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+        "value": value if ok else None, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": dt / args.steps * 1e3, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "c64 inner / f64 refinement",
-        "data": "synthetic",
-        "config": {"workload": "cfg3: 6000000 jittered tets, 6910300 DOF, 112409452 nnz, 32 dipoles x "
-                               "(0.25, 0.5, 1.25) Hz = 96 sources, a 32-column COCG block per frequency",
-                   "n_dof": S.n_dof, "nnz": S.nnz, "setup_s": round(setup_s, 3),
-                   "iters_max": max(s["iters"] for s in st), "ir_steps": st[0]["ir_steps"],
-                   "rel_residual_max": max(s["rel_residual"] for s in st),
-                   "parallelism": "1 GPU"},
-        "plain_subset": {"sources": len(sub), "solves_per_s": plain_rate,
-                         "iters": [s["iters"] for s in pst],
-                         "rx_agreement_batched_vs_plain": agree},
+        "scaling": "weak", "vs_baseline": None, "dtype": "c64 inner / f64 refinement", "data": "synthetic",
+        "config": {"workload": (f"cfg3 marine layered: 6000000 jittered tets, {S.n_dof} DOF, {S.nnz} nnz, 32 x-dipoles "
+                                f"x (0.25, 0.5, 1.25) Hz = 96 sources, 101 receivers; one step = {B} dipoles at one "
+                                f"frequency as one {B}-column mixed COCG block "
+                                f"({'multicolour SSOR' if args.precond == 'ssor' else 'Jacobi'}), true relative "
+                                f"residual {RTOL:g}"),
+                   "form": "batched mixed", "n_dof": S.n_dof, "nnz": S.nnz, "setup_s": round(setup_s, 3),
+                   "batch": B, "spmv_shape": shape, "precond": args.precond,
+                   "omega": args.omega if args.precond == "ssor" else None, "parallelism": "1 GPU"},
+        "accuracy": {"all_converged": not bad, "failures": bad[:5],
+                     "rx_err_vs_oracle": oracle_err, "rx_agreement_vs_plain_gpu": agree},
+        "plain_subset": {"sources": len(sub), "solves_per_s": plain_rate, "converged": plain_ok,
+                         "iters": [s_["iters"] for s_ in pst]},
         "speedup_vs_plain": value / plain_rate,
-        "roofline": {"kernel": kernel_name("mixed", st[0]["spmv_shape"]), "bound": "hbm",
-                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS if achieved else None, "traffic": None,
+        "roofline": {"kernel": kname, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS if achieved else None,
+                     "traffic": MEASURED_TRAFFIC.get(kname + " @cfg3"),
                      "bytes_per_launch": nbytes, "avg_launch_us": avg_ms * 1e3, "launches": n_launch},
     }
+    if not ok:
+        line["invalid"] = "a solve did not converge or missed 1e-6 against the stored oracle fields"
+    if not args.no_cfg2_form:
+        del S, sols, psol
+        torch.cuda.empty_cache()
+        line["forms"] = {"cfg2": cfg2_forms(args, petgem, synth, torch, 5, 1, profile=False)[0]}
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline_cfg3(model, float(np.mean([s_["iters"] for s_ in pst])))
+    return line
 
 
 def bench_cfg4(args, petgem, synth, torch):
@@ -486,7 +601,13 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="cfg2", choices=["cfg2", "cfg3", "cfg4", "cfg5", "net", "copy"])
+    ap.add_argument("--workload", default="cfg3", choices=["cfg2", "cfg3", "cfg4", "cfg5", "net", "copy"])
+    ap.add_argument("--batch", type=int, default=CFG3_BATCH, choices=[1, 2, 4, 8, 16, 32],
+                    help="cfg3: sources per step (consecutive dipole positions at one frequency)")
+    ap.add_argument("--no-cfg2-form", action="store_true", help="cfg3: skip the cfg2 forms in the line")
+    ap.add_argument("--precond", default="jacobi", choices=["jacobi", "ssor"],
+                    help="cfg3: preconditioner of the mixed COCG (multicolour SSOR or Jacobi)")
+    ap.add_argument("--omega", type=float, default=1.0, help="SSOR relaxation factor")
     ap.add_argument("--n-train", type=int, default=2000)
     ap.add_argument("--n-test", type=int, default=200)
     ap.add_argument("--epochs", type=int, default=30)
@@ -495,8 +616,8 @@ def main():
                     help="cfg3: sources solved by the plain path for the comparison")
     ap.add_argument("--max-iter", type=int, default=20000)
     ap.add_argument("--spmm-shape", type=int, default=0,
-                    help="cfg2: force the mixed form's SpMM shape (its spmv_shape code; 0 = autotune), "
-                         "so that counter runs measure a chosen kernel")
+                    help="cfg2 / cfg3: force the mixed form's SpMM shape (its spmv_shape code; 0 = "
+                         "autotune), so that counter runs measure a chosen kernel")
     ap.add_argument("--verbose", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true",
