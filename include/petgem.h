@@ -193,6 +193,20 @@ int petgem_reassemble(petgem_system* sys, const double* sigma_dev, double sigma_
 int petgem_rhs(petgem_system* sys, const petgem_source* src, int32_t n_src,
                void* b_dev, void* stream);
 
+/* The right-hand side of petgem_rhs without any device allocation, for
+ * callers that cannot allocate (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc). Same kernels and the same result,
+ * bit for bit, as petgem_rhs; their scratch (the element staging and the
+ * singular-source flag) is a fixed 48 MiB device array of the library, one
+ * copy per GPU, held until the process ends, instead of buffers of the system.
+ * Limit: meshes of at most 524,288 elements (INVALID_ARG beyond; use
+ * petgem_rhs). The system's device must be current. Every call on one GPU
+ * shares the array, so calls that overlap on one GPU (other streams or
+ * threads) race; calls ordered on one stream do not. Synchronises `stream`
+ * to read the singular-source flag. Errors as petgem_rhs. */
+int petgem_rhs_noalloc(petgem_system* sys, const petgem_source* src, int32_t n_src,
+                       void* b_dev, void* stream);
+
 /* ---- solve ----------------------------------------------------------------
  * Solves A(f_s) x_s = b_s for every source s (each at its own frequency) to
  * the true relative residual opts->rtol.

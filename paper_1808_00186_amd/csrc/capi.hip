@@ -182,6 +182,14 @@ int petgem_assemble(const petgem_mesh* mesh, const double* sigma, double sigma_b
             return rc;
         }
         (void)hipGetDevice(&sys->device);
+        // the allocation-free entry point's scratch address on this device
+        // (looked up once per device, with it current)
+        char* scratch_base = nullptr;
+        rc = noalloc_scratch(sys->device, &scratch_base);
+        if (rc != PETGEM_OK) {
+            delete sys;
+            return rc;
+        }
         sys->n_nodes = mesh->n_nodes;
         sys->n_tets = mesh->n_tets;
         sys->n_dof = topo.n_dof;
@@ -244,6 +252,13 @@ int petgem_rhs(petgem_system* sys, const petgem_source* src, int32_t n_src, void
         return PETGEM_SOURCE_SINGULAR;
     }
     return PETGEM_OK;
+}
+
+int petgem_rhs_noalloc(petgem_system* sys, const petgem_source* src, int32_t n_src, void* b_dev, void* stream) {
+    PG_TRY(check_sys(sys));
+    if (!src || n_src <= 0 || !b_dev) { set_error("sources and output are required"); return PETGEM_INVALID_ARG; }
+    for (int32_t k = 0; k < n_src; ++k) PG_TRY(valid_source(src[k]));
+    return rhs_noalloc(sys, src, n_src, static_cast<double2*>(b_dev), static_cast<hipStream_t>(stream));
 }
 
 int petgem_solve(petgem_system* sys, const petgem_source* src, int32_t n_src, const petgem_opts* opts,

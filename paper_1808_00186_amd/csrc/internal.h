@@ -224,6 +224,12 @@ namespace petgem {
 // Launchers implemented in the .hip units; all ordered on `s`.
 int launch_assembly(petgem_system* sys, hipStream_t s);
 int launch_freq_prep(petgem_system* sys, double freq, hipStream_t s);
+// allocation-free scratch of this device (looked up once per device) and the
+// right-hand side that uses it
+int noalloc_scratch(int dev, char** out);
+int rhs_noalloc(petgem_system* sys, const petgem_source* src, int32_t n_src, double2* b, hipStream_t s);
+int launch_rhs_into(petgem_system* sys, const petgem_source& src, double2* b, int b_stride, double2* Rst,
+                    int* flag, hipStream_t s);
 int launch_rhs(petgem_system* sys, const petgem_source& src, double2* b, int b_stride,
                hipStream_t s);
 int launch_spmv_ahat(petgem_system* sys, const double2* x, double2* y, hipStream_t s);

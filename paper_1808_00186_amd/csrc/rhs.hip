@@ -194,20 +194,28 @@ __global__ void k_receivers_h(int n_rx, const double* __restrict__ rxyz, const i
 
 }  // namespace
 
-int launch_rhs(petgem_system* sys, const petgem_source& src, double2* b, int b_stride,
-               hipStream_t s) {
+// The element staging and the singular-source flag of one right-hand side,
+// written where the caller says (the system's buffers, or the scratch of the
+// allocation-free entry point).
+int launch_rhs_into(petgem_system* sys, const petgem_source& src, double2* b, int b_stride, double2* Rst,
+                    int* flag, hipStream_t s) {
     const int T = sys->n_tets;
-    if (!sys->Rst) PG_TRY(dalloc(&sys->Rst, (size_t)6 * T));
     SrcParams sp = make_src(src, sys->sigma_bg);
     const double wmu = 2.0 * kPi * src.freq_hz * kMu0;
     hipLaunchKernelGGL(k_rhs_elem, dim3(ceil_div(T, 256)), dim3(256), 0, s, T, sys->xyz,
                        reinterpret_cast<const int4*>(sys->tets), sys->sigma, sys->sigma_bg, sp, wmu,
-                       1e-9 * sys->h_mean, sys->Rst, sys->dflag);
+                       1e-9 * sys->h_mean, Rst, flag);
     PG_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_rhs_gather, dim3(ceil_div(sys->n_dof, 256)), dim3(256), 0, s, sys->n_dof,
-                       T, sys->iptr, sys->islot, sys->Rst, b, b_stride);
+                       T, sys->iptr, sys->islot, Rst, b, b_stride);
     PG_HIP(hipGetLastError());
     return PETGEM_OK;
+}
+
+int launch_rhs(petgem_system* sys, const petgem_source& src, double2* b, int b_stride,
+               hipStream_t s) {
+    if (!sys->Rst) PG_TRY(dalloc(&sys->Rst, (size_t)6 * sys->n_tets));
+    return launch_rhs_into(sys, src, b, b_stride, sys->Rst, sys->dflag, s);
 }
 
 int launch_receivers(const petgem_solution* sol, int32_t n_rx, double2* E, double2* Es,

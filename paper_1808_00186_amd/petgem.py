@@ -71,6 +71,7 @@ _SIGS = {
                                   C.POINTER(C.c_void_p)]),
     "petgem_reassemble": (C.c_int, [C.c_void_p, C.c_void_p, C.c_double, C.c_void_p]),
     "petgem_rhs": (C.c_int, [C.c_void_p, C.POINTER(Source), C.c_int32, C.c_void_p, C.c_void_p]),
+    "petgem_rhs_noalloc": (C.c_int, [C.c_void_p, C.POINTER(Source), C.c_int32, C.c_void_p, C.c_void_p]),
     "petgem_solve": (C.c_int, [C.c_void_p, C.POINTER(Source), C.c_int32, C.POINTER(Opts),
                                C.c_void_p, C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(Stats)]),
     "petgem_solve_many": (C.c_int, [C.POINTER(C.c_void_p), C.POINTER(Source), C.c_int32,
@@ -258,6 +259,17 @@ class System:
         src = make_sources(dipoles)
         b = torch.empty((len(dipoles), self.n_dof), dtype=torch.complex128, device="cuda")
         _check(lib().petgem_rhs(self.handle, src, len(dipoles), _ptr(b), _stream(stream)))
+        return b
+
+    def rhs_noalloc(self, dipoles, b=None, stream=None):
+        """petgem_rhs_noalloc: the right-hand sides without any device
+        allocation inside the library (b: an optional caller tensor
+        complex128 [n_src][n_dof])."""
+        import torch
+        src = make_sources(dipoles)
+        if b is None:
+            b = torch.empty((len(dipoles), self.n_dof), dtype=torch.complex128, device="cuda")
+        _check(lib().petgem_rhs_noalloc(self.handle, src, len(dipoles), _ptr(b), _stream(stream)))
         return b
 
     def solve(self, dipoles, opts: Optional[Opts] = None, x0=None, stream=None,
