@@ -219,6 +219,53 @@ def rhs(xyz, tets, sigma, sigma_bg, topo: Topology, src_pos, src_dir, freq,
     return b
 
 
+def background_sigma(z, layers) -> np.ndarray:
+    """sigma of the layered background at heights z: layers = (z0,
+    sigma_above, sigma_below); a point on z0 counts as above."""
+    z0, s_up, s_dn = layers
+    return np.where(np.asarray(z) >= z0, s_up, s_dn)
+
+
+def rhs_layered(xyz, tets, sigma, layers, topo: Topology, src_pos, src_dir, freq,
+                moment=1.0) -> np.ndarray:
+    """Eq. 9 with a background of two half-spaces: the primary field is the
+    layered one (``oracle.layered``) and dsigma = sigma_e - sigma_b(x_q) is
+    taken at each quadrature point:
+    b_i = i omega mu0 sum_e sum_q (V_e/4) dsigma_eq N_i(x_q) . E_p(x_q)."""
+    from .layered import layered_dipole_field
+    sigma = np.asarray(sigma, dtype=np.float64)
+    t_all = np.asarray(tets)
+    X_all = np.asarray(xyz, dtype=np.float64)[t_all]
+    xq_all = np.einsum("qv,tvk->tqk", QUAD4, X_all)                       # [T][4][3]
+    dsig = sigma[:, None] - background_sigma(xq_all[..., 2], layers)      # [T][4]
+    sel = np.flatnonzero(np.any(dsig != 0.0, axis=1))
+    b = np.zeros(topo.n_dof, dtype=np.complex128)
+    if len(sel) == 0:
+        return b
+    vol, g, X = geometry(xyz, t_all[sel])
+    ell = edge_lengths(X)
+    sign = topo.elem_sign[sel]
+    lam = np.broadcast_to(QUAD4, (len(sel), 4, 4))
+    xq = xq_all[sel]
+    Ep = layered_dipole_field(xq, src_pos, src_dir, freq, layers[1], layers[2], layers[0], moment)
+    N = basis_at(g, sign, ell, lam)                                        # [T][4][6][3]
+    Re = (vol / 4.0)[:, None] * np.einsum("tq,tqik,tqk->ti", dsig[sel], N, Ep)
+    omega = 2.0 * np.pi * freq
+    contrib = 1j * omega * MU0 * Re
+    dof = topo.dof_of_edge[topo.elem_edge[sel]]
+    keep = dof >= 0
+    np.add.at(b, dof[keep], contrib[keep])
+    return b
+
+
+def receivers_total_layered(xyz, tets, topo, e_dof, points, src_pos, src_dir, freq, layers,
+                            moment=1.0) -> np.ndarray:
+    """Total field E = E_p (layered) + E_s at the receivers (eq. 4)."""
+    from .layered import layered_dipole_field
+    return (layered_dipole_field(points, src_pos, src_dir, freq, layers[1], layers[2], layers[0], moment)
+            + interpolate(xyz, tets, topo, e_dof, points))
+
+
 def locate(xyz, tets, points, tol=1e-12):
     """Containing element and barycentric coordinates of each point: all
     lambda >= -tol, lowest element id on ties; -1 if outside the mesh."""

@@ -133,10 +133,18 @@ def forward(model, src_index: int = 0, sys_=None, rtol: float = 1e-12, progress:
         sys_ = fem.assemble(xyz, tets, model.sigma)
     s = model.sources[src_index]
     A = fem.system_matrix(sys_, s.freq)
-    b = fem.rhs(xyz, tets, model.sigma, model.sigma_bg, sys_.topo, s.pos, s.dir,
-                s.freq, s.moment)
+    layers = getattr(model, "layers", None)
+    if layers is None:
+        b = fem.rhs(xyz, tets, model.sigma, model.sigma_bg, sys_.topo, s.pos, s.dir,
+                    s.freq, s.moment)
+    else:
+        b = fem.rhs_layered(xyz, tets, model.sigma, layers, sys_.topo, s.pos, s.dir, s.freq, s.moment)
     x, res, method = solve_system(A, b, rtol, progress)
-    E = fem.receivers_total(xyz, tets, sys_.topo, x, model.receivers, s.pos, s.dir,
-                            s.freq, model.sigma_bg, s.moment)
+    if layers is None:
+        E = fem.receivers_total(xyz, tets, sys_.topo, x, model.receivers, s.pos, s.dir,
+                                s.freq, model.sigma_bg, s.moment)
+    else:
+        E = fem.receivers_total_layered(xyz, tets, sys_.topo, x, model.receivers, s.pos, s.dir, s.freq,
+                                        layers, s.moment)
     Es = fem.interpolate(xyz, tets, sys_.topo, x, model.receivers)
     return dict(x=x, b=b, A=A, E=E, Es=Es, residual=res, method=method, sys=sys_)

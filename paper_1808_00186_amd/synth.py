@@ -60,6 +60,9 @@ class Model:
     n: int = 0                 # hexahedra per side
     box: Tuple[float, float] = (0.0, 0.0)
     meta: dict = field(default_factory=dict)
+    # background of the primary field: None = the whole space sigma_bg;
+    # (z0, sigma_above, sigma_below) = two half-spaces meeting at z = z0
+    layers: Optional[Tuple[float, float, float]] = None
 
     @property
     def h(self) -> float:
@@ -67,11 +70,13 @@ class Model:
 
 
 def kuhn_mesh(n: int, lo: float, hi: float, seed: Optional[int],
-              jitter: float = 0.15) -> Tuple[np.ndarray, np.ndarray]:
+              jitter: float = 0.15, flat_z: Tuple[float, ...] = ()) -> Tuple[np.ndarray, np.ndarray]:
     """Jittered Kuhn mesh of the cube [lo, hi]^3 with n hexahedra per side.
 
     Returns (xyz float64 [(n+1)^3][3], tets int32 [6 n^3][4]).
-    ``seed=None`` gives the unjittered grid."""
+    ``seed=None`` gives the unjittered grid. Nodes of the grid planes
+    z = c for c in ``flat_z`` keep their z (jittered in x and y only), so a
+    layer interface there is matched by element faces."""
     if n < 1:
         raise ValueError("n must be >= 1")
     h = (hi - lo) / n
@@ -83,6 +88,8 @@ def kuhn_mesh(n: int, lo: float, hi: float, seed: Optional[int],
         rng = np.random.default_rng(seed)
         jit = rng.uniform(-jitter * h, jitter * h, size=xyz.shape)
         jit[(ijk == 0) | (ijk == n)] = 0.0
+        for c in flat_z:
+            jit[np.isclose(xyz[:, 2], c), 2] = 0.0
         xyz = xyz + jit
 
     def nid(i, j, k):
@@ -173,6 +180,22 @@ def config3(seed: int = 3, n: int = 100, n_pos: int = 32,
             for f in freqs for i in range(n_pos)]
     return Model("cfg3", xyz, tets, sigma, 3.3, srcs, marine_receivers_101(),
                  n, (-5000.0, 5000.0))
+
+
+def layered_marine(n: int = 8, seed: int = 21, lo: float = -1000.0, hi: float = 1000.0,
+                   reservoir=((-300.0, 300.0), (-300.0, 300.0), (-250.0, -100.0)), sigma_res: float = 0.02,
+                   src=(0.0, 0.0, 60.0), freq: float = 1.0, direction=(1.0, 0.0, 0.0)) -> Model:
+    """A marine model for the layered primary field: sea 3.3 S/m above a flat
+    sea floor at z = 0 (its nodes are not jittered in z), sediments 1 S/m
+    below, a resistive block; the primary field is that of the two
+    half-spaces, so dsigma is non-zero in the block only. Receivers on the
+    line x = -0.9 ... 0.9 (hi - lo) / 2, y = 0, z = 10 m."""
+    xyz, tets = kuhn_mesh(n, lo, hi, seed, flat_z=(0.0,))
+    sigma = marine_sigma(centroids(xyz, tets), reservoir, sigma_res)
+    L = 0.45 * (hi - lo)
+    rx = np.stack([np.linspace(-L, L, 21), np.zeros(21), np.full(21, 10.0)], 1)
+    return Model(f"layered-n{n}", xyz, tets, sigma, 3.3, [Dipole(tuple(src), freq, tuple(direction))], rx, n,
+                 (lo, hi), layers=(0.0, 3.3, 1.0))
 
 
 def config4_model(seed: int) -> Model:

@@ -556,3 +556,77 @@ def test_ssor_oracle_colouring_sweeps_and_solve():
     _, it_jac = precond.cocg(A, b, lambda v: v / A.diagonal())
     assert np.abs(x - x_direct).max() <= 1e-8 * np.abs(x_direct).max()
     assert it_ssor < 0.6 * it_jac, (it_ssor, it_jac)
+
+
+# ------------------------------------------------------- layered primary field (NEXT: two half-spaces)
+
+def test_layered_field_reduces_to_the_whole_space_field():
+    """Two half-spaces of equal conductivity: the transmitted-field formulas
+    (below the interface) and the upper ones must give the whole-space dipole
+    field of Appendix A, for x, y and z dipoles."""
+    from oracle import layered
+    src = np.array([30.0, -20.0, 50.0])
+    pts = np.array([[400.0, 300.0, 120.0], [-800.0, 100.0, -300.0], [50.0, 10.0, -1000.0],
+                    [2500.0, -1500.0, 10.0], [10.0, 5.0, -5.0]])
+    for p in np.eye(3):
+        E = layered.layered_dipole_field(pts, src, p, 0.5, 1.7, 1.7)
+        W = primary.dipole_field(pts, src, p, 0.5, 1.7)
+        assert np.abs(E - W).max() <= 1e-12 * np.abs(W).max()
+
+
+def test_layered_field_interface_pde_and_reciprocity():
+    """The layered field with 3.3 over 1 S/m: tangential E and normal current
+    sigma E_z continuous at the interface; curl curl E = k_j^2 E in each layer
+    (central differences, error falling as h^2); reciprocity of the Green
+    tensor E_a(r2; b at r1) = E_b(r1; a at r2) between two points of the
+    source layer, HED and VED terms included."""
+    from oracle import layered
+    s1, s2, f = 3.3, 1.0, 0.7
+    src = np.array([30.0, -20.0, 50.0])
+    rng = np.random.default_rng(1)
+    for p in np.eye(3):
+        xy = rng.uniform(-3000, 3000, (4, 2))
+        Eu = layered.layered_dipole_field(np.c_[xy, np.full(4, 1e-7)], src, p, f, s1, s2)
+        Ed = layered.layered_dipole_field(np.c_[xy, np.full(4, -1e-7)], src, p, f, s1, s2)
+        sc = np.abs(Eu).max(axis=1)
+        assert (np.abs(Eu[:, :2] - Ed[:, :2]).max(axis=1) / sc).max() < 1e-8
+        assert (np.abs(s1 * Eu[:, 2] - s2 * Ed[:, 2]) / (s1 * sc)).max() < 1e-8
+
+    def curlcurl_residual(p, pt, sig, h):
+        E = lambda q: layered.layered_dipole_field(q[None], src, p, f, s1, s2)[0]
+        e = np.eye(3) * h
+        E0 = E(pt)
+        lap = sum((E(pt + e[a]) - 2 * E0 + E(pt - e[a])) / h ** 2 for a in range(3))
+        gd = np.zeros(3, complex)
+        for a in range(3):
+            for b in range(3):
+                if a == b:
+                    gd[a] += (E(pt + e[a])[a] - 2 * E0[a] + E(pt - e[a])[a]) / h ** 2
+                else:
+                    gd[a] += (E(pt + e[a] + e[b])[b] - E(pt + e[a] - e[b])[b] - E(pt - e[a] + e[b])[b]
+                              + E(pt - e[a] - e[b])[b]) / (4 * h * h)
+        k2 = 1j * 2 * np.pi * f * primary.MU0 * sig
+        return np.abs(gd - lap - k2 * E0).max() / np.abs(k2 * E0).max()
+
+    for p in (np.eye(3)[0], np.eye(3)[2]):
+        for pt, sig in ((np.array([600.0, 400.0, 300.0]), s1), (np.array([-500.0, 300.0, -400.0]), s2)):
+            r4, r2 = curlcurl_residual(p, pt, sig, 4.0), curlcurl_residual(p, pt, sig, 2.0)
+            assert r2 < 1e-4 and r4 / r2 > 3.0, (r4, r2)
+    r1, r2 = np.array([100.0, 50.0, 40.0]), np.array([-700.0, 400.0, 150.0])
+    for a in range(3):
+        for b in range(3):
+            Ea = layered.layered_dipole_field(r2[None], r1, np.eye(3)[b], f, s1, s2)[0][a]
+            Eb = layered.layered_dipole_field(r1[None], r2, np.eye(3)[a], f, s1, s2)[0][b]
+            assert abs(Ea - Eb) <= 1e-10 * max(abs(Ea), abs(Eb))
+
+
+def test_layered_rhs_reduces_to_the_whole_space_rhs():
+    """With both half-spaces at sigma_bg the layered right-hand side (dsigma at
+    each quadrature point, layered E_p) equals eq. 9's whole-space one."""
+    m = synth.config1()
+    topo = fem.topology(m.xyz, m.tets)
+    src = m.sources[0]
+    b_ws = fem.rhs(m.xyz, m.tets, m.sigma, m.sigma_bg, topo, src.pos, src.dir, src.freq, src.moment)
+    b_ly = fem.rhs_layered(m.xyz, m.tets, m.sigma, (0.0, m.sigma_bg, m.sigma_bg), topo, src.pos, src.dir,
+                           src.freq, src.moment)
+    assert np.abs(b_ly - b_ws).max() <= 1e-10 * np.abs(b_ws).max()
