@@ -67,7 +67,9 @@ extern "C" {
 #define PETGEM_BCOCG   2  /* block COCG: the sources (one frequency, at most
                              32, zero guesses, Jacobi) share one block Krylov
                              space; directions orthonormalised with
-                             dependent ones dropped; mixed precision           */
+                             dependent ones dropped; double precision
+                             throughout (precision is ignored), restarted
+                             from the true residual                           */
 #define PETGEM_FP64    0  /* every step in double precision                   */
 #define PETGEM_MIXED   1  /* complex64 Krylov solves inside a double-precision
                              iterative-refinement loop                         */
@@ -185,6 +187,33 @@ int petgem_assemble(const petgem_mesh* mesh, const double* sigma, double sigma_b
  * sigma_dev: device [n_tets] double. No host work, no allocation. */
 int petgem_reassemble(petgem_system* sys, const double* sigma_dev, double sigma_bg,
                       void* stream);
+
+/* ---- background of the primary field --------------------------------------
+ * The primary field E_p solves the background problem (Section 2, eqs. 1-6).
+ * By default the background is the whole space of conductivity sigma_bg
+ * (petgem_assemble) and E_p is the dipole field of Appendix A. With
+ * layered = 1 it is two half-spaces meeting at the plane z = z0,
+ * sigma_above for z >= z0 (where every source must lie) and sigma_below
+ * beneath (a sea over the sea floor), and E_p is the dipole field of that
+ * model: the whole-space field of sigma_above plus the wave reflected at the
+ * interface above it, the transmitted wave beneath, written as Hankel
+ * transforms of the TE / TM interface coefficients and summed by Gauss-
+ * Legendre panels on the GPU (one wavefront per evaluation point). The
+ * right-hand side then takes dsigma = sigma_e - sigma_b(z) at each
+ * quadrature point, so it vanishes wherever the model equals the layers
+ * (a mesh whose faces follow the interface confines it to the anomalies).
+ * Receivers (petgem_receivers) use the same E_p; petgem_receivers_h refuses a
+ * layered background (INVALID_ARG). The setting applies to the following
+ * right-hand sides and solves of the system; a solution keeps the background
+ * it was solved with. Errors: INVALID_ARG (bad values, or later a source at
+ * or below z0). */
+typedef struct {
+    int32_t layered;        /* 0: whole space sigma_bg; 1: two half-spaces      */
+    double  z0;             /* interface height, m                              */
+    double  sigma_above;    /* S/m, z >= z0                                     */
+    double  sigma_below;    /* S/m, z < z0                                      */
+} petgem_background;
+int petgem_set_background(petgem_system* sys, const petgem_background* bg);
 
 /* ---- right-hand side (Section 3, eq. 9; Appendix A) ----------------------
  * b_i = i w mu0 sum_e (sigma_e - sigma_bg) sum_q (V_e/4) N_i(x_q) . E_p(x_q)
@@ -312,6 +341,15 @@ double petgem_setup_seconds(const petgem_system* sys);
 int32_t petgem_ssor_colors(petgem_system* sys, int32_t* colors, void* stream);
 int petgem_ssor_apply(petgem_system* sys, double freq, double omega, const void* r_dev, void* z_dev,
                       void* stream);
+/* Measurement behind the uneven batch's design (graph-replayed kernels rather
+ * than one persistent kernel): the time per round of `rounds` phase
+ * separations, mode 0 = a kernel boundary inside a captured HIP graph
+ * (rounds launches of a one-word-per-block kernel), mode 1 = a grid-wide
+ * barrier inside one cooperative kernel of as many 256-thread blocks as can be
+ * resident (*blocks receives that count). Synchronises `stream`. Errors:
+ * INVALID_ARG (rounds outside 1..100000, mode), HIP_ERROR (the runtime
+ * refused the cooperative launch). */
+int petgem_sync_probe(int32_t rounds, int32_t mode, int32_t* blocks, float* us_per_round, void* stream);
 /* Host-only: the complex64 SpMM shapes the autotuner times for n_cols
  * columns (sliced != 0: with the sliced-ELLPACK copy, which one mesh has for
  * up to four columns), as petgem_opts.spmm_shape codes. Writes at most cap

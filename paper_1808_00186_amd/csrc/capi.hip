@@ -234,6 +234,21 @@ int petgem_reassemble(petgem_system* sys, const double* sigma_dev, double sigma_
     return launch_assembly(sys, s);
 }
 
+int petgem_set_background(petgem_system* sys, const petgem_background* bg) {
+    PG_TRY(check_sys(sys));
+    if (!bg || (bg->layered != 0 && bg->layered != 1) ||
+        (bg->layered && !(bg->sigma_above > 0.0 && bg->sigma_below > 0.0 && std::isfinite(bg->sigma_above) &&
+                          std::isfinite(bg->sigma_below) && std::isfinite(bg->z0)))) {
+        set_error("background: layered 0 or 1, positive finite conductivities, finite z0");
+        return PETGEM_INVALID_ARG;
+    }
+    sys->layers.on = bg->layered;
+    sys->layers.z0 = bg->z0;
+    sys->layers.s_up = bg->sigma_above;
+    sys->layers.s_dn = bg->sigma_below;
+    return PETGEM_OK;
+}
+
 int petgem_rhs(petgem_system* sys, const petgem_source* src, int32_t n_src, void* b_dev, void* stream) {
     PG_TRY(check_sys(sys));
     if (!src || n_src <= 0 || !b_dev) { set_error("sources and output are required"); return PETGEM_INVALID_ARG; }
@@ -300,6 +315,7 @@ int petgem_solve(petgem_system* sys, const petgem_source* src, int32_t n_src, co
     }
     sol->src.assign(src, src + n_src);
     sol->sigma_bg = sys->sigma_bg;
+    sol->layers = sys->layers;
     if (stats) std::memset(stats, 0, sizeof(petgem_stats) * (size_t)n_src);
     const double2* x0 = static_cast<const double2*>(x0_dev);
     if (o.method == PETGEM_COCG || o.method == PETGEM_BCOCG) {
@@ -368,6 +384,7 @@ int petgem_solve_many(petgem_system* const* systems, const petgem_source* src, i
         }
         sol->src.assign(src + k, src + k + 1);
         sol->sigma_bg = systems[k]->sigma_bg;
+        sol->layers = systems[k]->layers;
     }
     if (stats) std::memset(stats, 0, sizeof(petgem_stats) * (size_t)n_sys);
     return batch_solve(systems, src, n_sys, o, x0_dev, sols, static_cast<hipStream_t>(stream), stats);
@@ -462,6 +479,14 @@ int petgem_ssor_apply(petgem_system* sys, double freq, double omega, const void*
     }
     return ssor_apply1(sys, freq, omega, static_cast<const float2*>(r_dev), static_cast<float2*>(z_dev),
                        static_cast<hipStream_t>(stream));
+}
+
+int petgem_sync_probe(int32_t rounds, int32_t mode, int32_t* blocks, float* us_per_round, void* stream) {
+    if (rounds < 1 || rounds > 100000 || (mode != 0 && mode != 1)) {
+        set_error("petgem_sync_probe: 1 <= rounds <= 100000, mode 0 or 1");
+        return PETGEM_INVALID_ARG;
+    }
+    return sync_probe(rounds, mode, blocks, us_per_round, static_cast<hipStream_t>(stream));
 }
 
 int32_t petgem_spmm_candidates(int32_t n_cols, int32_t sliced, int32_t* shapes, int32_t cap) {

@@ -102,6 +102,13 @@ struct Ssor {
     }
 };
 
+// Background of the primary field: the whole space sigma_bg, or two
+// half-spaces meeting at z = z0 (s_up above, holding the sources).
+struct Layers {
+    int on = 0;
+    double z0 = 0.0, s_up = 1.0, s_dn = 1.0;
+};
+
 // ------------------------------------------------------- GMRES control block
 // Small device-resident state of one GMRES cycle: the Hessenberg column in
 // progress, Givens rotations, the least-squares right-hand side g and flags
@@ -156,6 +163,7 @@ struct petgem_system {
     int64_t nnz = 0;
     double h_mean = 0.0;
     double sigma_bg = 1.0;
+    petgem::Layers layers;                // layered background (layers.on) of the primary field
     double setup_seconds = 0.0;
     // host copies kept for receivers and accessors
     std::vector<double> xyz_h;
@@ -217,6 +225,7 @@ struct petgem_solution {
     double2* x = nullptr;                 // [n_src][n_dof]
     std::vector<petgem_source> src;
     double sigma_bg = 1.0;
+    petgem::Layers layers;                // the background the solve used
 };
 
 namespace petgem {
@@ -230,6 +239,13 @@ int noalloc_scratch(int dev, char** out);
 int rhs_noalloc(petgem_system* sys, const petgem_source* src, int32_t n_src, double2* b, hipStream_t s);
 int launch_rhs_into(petgem_system* sys, const petgem_source& src, double2* b, int b_stride, double2* Rst,
                     int* flag, hipStream_t s);
+// time per round of a graph-replayed kernel boundary (mode 0) or of a grid
+// barrier in one cooperative kernel (mode 1), probe.hip
+int sync_probe(int32_t rounds, int32_t mode, int32_t* blocks_out, float* us_per_round, hipStream_t s);
+// layered background (layered.hip)
+int launch_rhs_layered(petgem_system* sys, const petgem_source& src, double2* Rst, int* flag, hipStream_t s);
+int launch_receivers_layered(const petgem_solution* sol, int k, int32_t n_rx, double2* E, double2* Es,
+                             hipStream_t s);
 int launch_rhs(petgem_system* sys, const petgem_source& src, double2* b, int b_stride,
                hipStream_t s);
 int launch_spmv_ahat(petgem_system* sys, const double2* x, double2* y, hipStream_t s);

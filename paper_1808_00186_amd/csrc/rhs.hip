@@ -202,10 +202,14 @@ int launch_rhs_into(petgem_system* sys, const petgem_source& src, double2* b, in
     const int T = sys->n_tets;
     SrcParams sp = make_src(src, sys->sigma_bg);
     const double wmu = 2.0 * kPi * src.freq_hz * kMu0;
-    hipLaunchKernelGGL(k_rhs_elem, dim3(ceil_div(T, 256)), dim3(256), 0, s, T, sys->xyz,
-                       reinterpret_cast<const int4*>(sys->tets), sys->sigma, sys->sigma_bg, sp, wmu,
-                       1e-9 * sys->h_mean, Rst, flag);
-    PG_HIP(hipGetLastError());
+    if (sys->layers.on) {
+        PG_TRY(launch_rhs_layered(sys, src, Rst, flag, s));
+    } else {
+        hipLaunchKernelGGL(k_rhs_elem, dim3(ceil_div(T, 256)), dim3(256), 0, s, T, sys->xyz,
+                           reinterpret_cast<const int4*>(sys->tets), sys->sigma, sys->sigma_bg, sp, wmu,
+                           1e-9 * sys->h_mean, Rst, flag);
+        PG_HIP(hipGetLastError());
+    }
     hipLaunchKernelGGL(k_rhs_gather, dim3(ceil_div(sys->n_dof, 256)), dim3(256), 0, s, sys->n_dof,
                        T, sys->iptr, sys->islot, Rst, b, b_stride);
     PG_HIP(hipGetLastError());
@@ -221,8 +225,17 @@ int launch_rhs(petgem_system* sys, const petgem_source& src, double2* b, int b_s
 int launch_receivers(const petgem_solution* sol, int32_t n_rx, double2* E, double2* Es,
                      hipStream_t s, bool magnetic) {
     const petgem_system* sys = sol->sys;
+    if (sol->layers.on && magnetic) {
+        set_error("the magnetic field over a layered background is not provided");
+        return PETGEM_INVALID_ARG;
+    }
     for (int32_t k = 0; k < sol->n_src; ++k) {
         SrcParams sp = make_src(sol->src[k], sol->sigma_bg);
+        if (sol->layers.on) {
+            PG_TRY(launch_receivers_layered(sol, k, n_rx, E + (size_t)k * n_rx * 3,
+                                            Es ? Es + (size_t)k * n_rx * 3 : nullptr, s));
+            continue;
+        }
         if (magnetic) {
             hipLaunchKernelGGL(k_receivers_h, dim3(ceil_div(n_rx, 64)), dim3(64), 0, s, n_rx,
                                sys->rxc.xyz, sys->rxc.tet, sys->rxc.dof, sys->xyz,

@@ -52,6 +52,11 @@ class Opts(C.Structure):
                 ("spmm_shape", C.c_int32), ("precond", C.c_int32), ("omega", C.c_double)]
 
 
+class Background(C.Structure):
+    _fields_ = [("layered", C.c_int32), ("z0", C.c_double), ("sigma_above", C.c_double),
+                ("sigma_below", C.c_double)]
+
+
 class Stats(C.Structure):
     _fields_ = [("iters", C.c_int32), ("ir_steps", C.c_int32), ("used_fallback", C.c_int32),
                 ("status", C.c_int32), ("rel_residual", C.c_double),
@@ -70,6 +75,7 @@ _SIGS = {
     "petgem_assemble": (C.c_int, [C.POINTER(Mesh), C.POINTER(C.c_double), C.c_double, C.c_void_p,
                                   C.POINTER(C.c_void_p)]),
     "petgem_reassemble": (C.c_int, [C.c_void_p, C.c_void_p, C.c_double, C.c_void_p]),
+    "petgem_set_background": (C.c_int, [C.c_void_p, C.POINTER(Background)]),
     "petgem_rhs": (C.c_int, [C.c_void_p, C.POINTER(Source), C.c_int32, C.c_void_p, C.c_void_p]),
     "petgem_rhs_noalloc": (C.c_int, [C.c_void_p, C.POINTER(Source), C.c_int32, C.c_void_p, C.c_void_p]),
     "petgem_solve": (C.c_int, [C.c_void_p, C.POINTER(Source), C.c_int32, C.POINTER(Opts),
@@ -93,6 +99,7 @@ _SIGS = {
     "petgem_setup_seconds": (C.c_double, [C.c_void_p]),
     "petgem_ssor_colors": (C.c_int32, [C.c_void_p, C.POINTER(C.c_int32), C.c_void_p]),
     "petgem_ssor_apply": (C.c_int, [C.c_void_p, C.c_double, C.c_double, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "petgem_sync_probe": (C.c_int, [C.c_int32, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_float), C.c_void_p]),
     "petgem_spmm_candidates": (C.c_int32, [C.c_int32, C.c_int32, C.POINTER(C.c_int32), C.c_int32]),
     "petgem_tuning": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_float)]),
     "petgem_mesh_pattern": (C.c_int, [C.POINTER(Mesh), C.POINTER(C.c_int32), C.POINTER(C.c_int64),
@@ -248,7 +255,17 @@ class System:
 
     @classmethod
     def from_model(cls, model, stream=None):
-        return cls(model.xyz, model.tets, model.sigma, model.sigma_bg, stream)
+        S = cls(model.xyz, model.tets, model.sigma, model.sigma_bg, stream)
+        layers = getattr(model, "layers", None)
+        if layers is not None:
+            S.set_background(layers)
+        return S
+
+    def set_background(self, layers=None):
+        """The primary field's background: None = the whole space sigma_bg,
+        or (z0, sigma_above, sigma_below) = two half-spaces."""
+        bg = Background(0, 0.0, 1.0, 1.0) if layers is None else Background(1, *map(float, layers))
+        _check(lib().petgem_set_background(self.handle, C.byref(bg)))
 
     def reassemble(self, sigma_dev, sigma_bg: float, stream=None):
         _check(lib().petgem_reassemble(self.handle, _ptr(sigma_dev), sigma_bg, _stream(stream)))
@@ -465,6 +482,15 @@ def mesh_pattern(xyz, tets):
     P = lambda a: a.ctypes.data_as(C.POINTER(C.c_int32))
     _check(lib().petgem_mesh_pattern(C.byref(m), C.byref(n), C.byref(nnz), P(de), P(rp), P(col)))
     return de, rp, col
+
+
+def sync_probe(rounds: int, mode: int, stream=None):
+    """(us per round, blocks) of a graph-replayed kernel boundary (mode 0)
+    or a grid barrier in one cooperative kernel (mode 1)."""
+    b = C.c_int32()
+    us = C.c_float()
+    _check(lib().petgem_sync_probe(rounds, mode, C.byref(b), C.byref(us), _stream(stream)))
+    return us.value, b.value
 
 
 def spmm_candidates(n_cols: int, sliced: bool) -> List[int]:
