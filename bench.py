@@ -33,6 +33,8 @@ Other workloads (`--workload`):
   net  -- the network alone: training steps and forward passes on a batch of
           16, BF16 MFMA throughput against its peak.
   copy -- a 1 GiB device copy (calibration of the rocprofv3 byte counters).
+  sync -- the cost of a kernel boundary inside a captured graph against a
+          grid barrier inside one persistent cooperative kernel.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload cfg3] [--batch 8]
 
@@ -582,6 +584,16 @@ def bench_net(args, petgem, torch):
                          "forward_ms": dt_fwd * 1e3, "flop_per_train_step": f_train, "flop_per_forward": f_fwd}}
 
 
+def sync_costs(args, petgem):
+    """Time per phase separation: a kernel boundary inside a captured graph
+    against a grid barrier inside one cooperative (persistent) kernel."""
+    out = {"metric": "phase separation cost", "unit": "us per round"}
+    for mode, name in ((0, "graph_kernel_boundary"), (1, "grid_barrier_persistent")):
+        us, blocks = petgem.sync_probe(2000, mode)
+        out[name] = {"us_per_round": us, "blocks": blocks}
+    return out
+
+
 def copy_calibration(args, torch):
     """A plain device copy of a known size (1 GiB read + 1 GiB written per
     launch): the FETCH_SIZE / WRITE_SIZE counters of this kernel give the
@@ -601,7 +613,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="cfg3", choices=["cfg2", "cfg3", "cfg4", "cfg5", "net", "copy"])
+    ap.add_argument("--workload", default="cfg3", choices=["cfg2", "cfg3", "cfg4", "cfg5", "net", "copy", "sync"])
     ap.add_argument("--batch", type=int, default=CFG3_BATCH, choices=[1, 2, 4, 8, 16, 32],
                     help="cfg3: sources per step (consecutive dipole positions at one frequency)")
     ap.add_argument("--no-cfg2-form", action="store_true", help="cfg3: skip the cfg2 forms in the line")
@@ -633,6 +645,9 @@ def main():
     torch.cuda.set_device(0)
     if args.workload == "copy":
         print(json.dumps(copy_calibration(args, torch)), flush=True)
+        return
+    if args.workload == "sync":
+        print(json.dumps(sync_costs(args, petgem)), flush=True)
         return
     if args.workload == "net":
         print(json.dumps(bench_net(args, petgem, torch)), flush=True)

@@ -266,3 +266,15 @@ def test_uneven_batch_of_largest_and_hardest_cfg4_models_matches_stored_oracle(p
         print(f"  {m.name}: iters {st[k]['iters']} res {st[k]['rel_residual']:.1e} (oracle {float(g['residual']):.1e}) "
               f"err {err:.1e}", flush=True)
         assert st[k]["rel_residual"] <= 1e-12 and err <= 1e-6
+
+
+def test_phase_separation_probe(pg):
+    """The measurement behind the uneven batch's graph-replayed kernels: both
+    probes run and report a positive time per round; the persistent form
+    fills the GPU with resident blocks."""
+    us0, b0 = pg.sync_probe(200, 0)
+    us1, b1 = pg.sync_probe(200, 1)
+    print(f"graph kernel boundary {us0:.2f} us, grid barrier {us1:.2f} us ({b1} blocks)", flush=True)
+    assert us0 > 0 and us1 > 0 and b1 >= 256
+    with pytest.raises(pg.PetgemError):
+        pg.sync_probe(0, 0)
