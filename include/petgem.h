@@ -69,7 +69,12 @@ extern "C" {
                              space; directions orthonormalised with
                              dependent ones dropped; double precision
                              throughout (precision is ignored), restarted
-                             from the true residual                           */
+                             from the true residual. The bilinear form is
+                             indefinite, so the block recurrence can lose
+                             conjugacy (many nearly dependent sources): the
+                             solve then finishes as independent mixed COCG
+                             columns from the block's iterate
+                             (stats.block_iters)                              */
 #define PETGEM_FP64    0  /* every step in double precision                   */
 #define PETGEM_MIXED   1  /* complex64 Krylov solves inside a double-precision
                              iterative-refinement loop                         */
@@ -161,6 +166,12 @@ typedef struct {
                                GMRES: the lanes per row of the complex128
                                CSR SpMV                                         */
     double  b_norm;         /* |b|_2 of the source's right-hand side            */
+    int32_t block_iters;    /* PETGEM_BCOCG: iterations of the block phase; when
+                               the block recurrence lost conjugacy (a
+                               recursive residual ten times its lowest) the
+                               rest of iters ran as independent mixed COCG
+                               columns from the block's iterate (0 otherwise) */
+    int32_t reserved;
 } petgem_stats;
 
 /* Fill *opts with the defaults: GMRES, FP64, restart 30, max_iter 20000,

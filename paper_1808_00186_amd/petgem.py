@@ -62,7 +62,8 @@ class Stats(C.Structure):
                 ("status", C.c_int32), ("rel_residual", C.c_double),
                 ("x0_rel_residual", C.c_double), ("t_rhs_ms", C.c_double),
                 ("t_solve_ms", C.c_double), ("spmv_ms", C.c_double),
-                ("spmv_launches", C.c_int32), ("spmv_shape", C.c_int32), ("b_norm", C.c_double)]
+                ("spmv_launches", C.c_int32), ("spmv_shape", C.c_int32), ("b_norm", C.c_double),
+                ("block_iters", C.c_int32), ("reserved", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -1,8 +1,11 @@
 """Block COCG (PETGEM_BCOCG): the sources of one frequency share one block
 Krylov space (O'Leary's block CG with the bilinear form u^T v, directions
-orthonormalised and dependent ones dropped). Not in the paper; pinned like
-the other forms by the oracle's receiver fields at the stated residual.
-Marked `gpu`."""
+orthonormalised and dependent ones dropped, all in double precision). The
+bilinear form is indefinite and 32 sources 26 m apart make the block
+recurrence lose conjugacy; the solve then finishes as independent mixed COCG
+from the block's iterate (stats block_iters < iters), so every case must
+still meet rtol. Not in the paper; pinned like the other forms by the
+oracle's receiver fields at the stated residual. Marked `gpu`."""
 import numpy as np
 import pytest
 import scipy.sparse.linalg as spla
@@ -43,12 +46,13 @@ def test_block_cocg_matches_oracle(pg, n_pos, freqs):
     ref = _oracle_fields(m, srcs)
     S = pg.System.from_model(m)
     print(f"[case] cfg1 block COCG {n_pos} sources x {len(freqs)} frequencies", flush=True)
-    sol, st, rc = S.solve(srcs, pg.default_opts(method=pg.BCOCG, precision=pg.MIXED, rtol=1e-8))
+    sol, st, rc = S.solve(srcs, pg.default_opts(method=pg.BCOCG, rtol=1e-8))
     assert rc == pg.OK and all(s_["rel_residual"] <= 1e-8 for s_ in st)
     E = sol.receivers(m.receivers).cpu().numpy()
     err = max(fem.receiver_error(E[k], ref[k]) for k in range(len(srcs)))
     _, st_i, _ = S.solve(srcs, pg.default_opts(method=pg.COCG, precision=pg.MIXED, rtol=1e-8))
-    print(f"  block iters {max(s_['iters'] for s_ in st)} ir {st[0]['ir_steps']}, independent COCG iters "
+    print(f"  block iters {st[0]['block_iters']} of {max(s_['iters'] for s_ in st)} ir {st[0]['ir_steps']}, "
+          f"independent COCG iters "
           f"{max(s_['iters'] for s_ in st_i)}, receiver error {err:.1e}", flush=True)
     assert err <= 1e-6
 
@@ -59,7 +63,7 @@ def test_block_cocg_refuses_what_it_does_not_take(pg):
     srcs = [synth.Dipole((0.0, 0.0, 300.0), 1.0), synth.Dipole((50.0, 0.0, 300.0), 2.0),
             synth.Dipole((90.0, 0.0, 300.0), 1.0)]     # frequencies not in runs
     with pytest.raises(pg.PetgemError):
-        S.solve(srcs, pg.default_opts(method=pg.BCOCG, precision=pg.MIXED))
+        S.solve(srcs, pg.default_opts(method=pg.BCOCG))
     many = [synth.Dipole((float(x), 0.0, 300.0), 1.0) for x in np.linspace(-400, 400, 33)]
     with pytest.raises(pg.PetgemError):
-        S.solve(many, pg.default_opts(method=pg.BCOCG, precision=pg.MIXED))
+        S.solve(many, pg.default_opts(method=pg.BCOCG))
