@@ -4,11 +4,11 @@ Default workload (cfg3, the marine layered model at full size): 100^3 x 6 =
 6,000,000 jittered tetrahedra, 6,910,300 unknowns, 112,409,452 nonzeros; a
 survey of 32 x-dipole positions (x = -3100 + 200 i, z = 50 m) at 0.25, 0.5
 and 1.25 Hz (96 sources) and 101 receivers. One step = one pass of the whole
-path for one batch of 8 consecutive dipole positions at one frequency: device
-re-assembly of K and M_sigma, the 8 right-hand sides, the solve of the
-8-column block by COCG preconditioned with multicolour SSOR (`--precond
+path for one batch of 16 consecutive dipole positions at one frequency: device
+re-assembly of K and M_sigma, the 16 right-hand sides, the solve of the
+16-column block by COCG preconditioned with multicolour SSOR (`--precond
 jacobi` for Jacobi) in complex64 inside complex128 iterative refinement to a
-true relative residual of 1e-9, and the total field at the receivers. Timed step k takes batch k mod 12, so 12 steps cover the survey.
+true relative residual of 1e-9, and the total field at the receivers. Timed step k takes batch k mod 6, so 6 steps cover the survey.
 Inputs are resident on the GPU when the timed region starts; host mesh
 preprocessing is setup and is reported separately. Beside it: plain FP64
 Jacobi GMRES(30) on a stated subset (the centre dipole at each frequency),
@@ -36,7 +36,7 @@ Other workloads (`--workload`):
   sync -- the cost of a kernel boundary inside a captured graph against a
           grid barrier inside one persistent cooperative kernel.
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload cfg3] [--batch 8]
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload cfg3] [--batch 16]
 
 Prints one JSON line; `cpu_baseline` times the CPU oracle on a bounded
 sample of the same workload.
@@ -66,9 +66,11 @@ MEASURED_TRAFFIC = {
     "k_spmm_sp<1, 4> complex64 pipelined sliced ELLPACK (K, M_sigma)": (48342.8 * 2.0 + 3219.3) * 1024,
     "k_spmm_s<1, 4> complex64 sliced ELLPACK (K, M_sigma)": (47676.3 * 2.0 + 3219.2) * 1024,
     "k_spmm_s<1, 8> complex64 sliced ELLPACK (K, M_sigma)": (49890.8 * 2.0 + 3367.3) * 1024,
-    # the 6.9M-unknown survey's 8-column product
+    # the 6.9M-unknown survey's 8- and 16-column products
     "k_spmm_g<float, 8, 1, 20, 1> complex64 CSR, row entries over the lanes (K, M_sigma) @cfg3":
         (1296681.7 * 2.0 + 435268.0) * 1024,
+    "k_spmm_g<float, 8, 2, 20, 1> complex64 CSR, row entries over the lanes (K, M_sigma) @cfg3":
+        (1779690.6 * 2.0 + 871820.1) * 1024,
 }
 RTOL = 1e-9
 # the high-frequency models of the uneven batch (f up to 2 Hz, receivers 4 km
@@ -262,7 +264,7 @@ def bench_cfg2(args, petgem, synth, torch):
     return line
 
 
-CFG3_BATCH = 8          # sources per step: a block of consecutive dipole positions at one frequency
+CFG3_BATCH = 16         # sources per step: a block of consecutive dipole positions at one frequency
 CFG3_GOLDEN = {(1.25, 16): "cfg3_f1.25_i16.npz", (1.25, 0): "cfg3_f1.25_i0.npz",
                (0.5, 16): "cfg3_f0.5_i16.npz", (0.25, 16): "cfg3_f0.25_i16.npz"}
 
@@ -316,11 +318,11 @@ def cpu_baseline_cfg3(model, plain_iters: float):
 def bench_cfg3(args, petgem, synth, torch):
     """cfg3: 6,000,000 jittered tetrahedra (6,910,300 unknowns), 96 sources
     (32 dipole positions x 3 frequencies). One step = one batch of B
-    consecutive dipole positions at one frequency (B = 8 by default), the whole
+    consecutive dipole positions at one frequency (B = 16 by default), the whole
     path: device re-assembly of K and M_sigma, the B right-hand sides, the
     mixed-precision COCG solve of the B-column block, the total field at the
     101 receivers. Timed step k takes batch k mod (96 / B), frequency-major,
-    so a run of 12 steps covers the survey once."""
+    so a run of 96 / B steps covers the survey once."""
     model = synth.config3()
     B = args.batch
     nb = len(model.sources) // B
@@ -614,7 +616,7 @@ def copy_calibration(args, torch):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=6)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="cfg3", choices=["cfg2", "cfg3", "cfg4", "cfg5", "net", "copy", "sync"])
     ap.add_argument("--batch", type=int, default=CFG3_BATCH, choices=[1, 2, 4, 8, 16, 32],

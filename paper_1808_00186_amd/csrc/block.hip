@@ -119,6 +119,20 @@ __device__ __forceinline__ bool stalled_now(ColState& S, double r2) {
     return S.kin - S.k_best > 2 * S.k_best + kStallIters;
 }
 
+// The last refinement step of a column solves its correction only as far as
+// the target needs, with a factor 0.3 to spare (res_step). A column whose
+// inner |r| hovers just above that target without a new best for a quarter
+// of the iterations its best took (at least kRelaxIters) gives the margin
+// up: it stops once |r| is within the target without the factor. (On the
+// 6.9M-unknown survey one 0.25 Hz column reached 1.04 times its target of
+// 2.2e-2 at iteration 576 of its third step, then wandered for 4,000
+// iterations until the guard above stopped it.)
+constexpr int kRelaxIters = 100;
+__device__ __forceinline__ bool relaxed_now(const ColState& S, double r2) {
+    const bool last_step = S.inner_tol2 > S.inner_rtol * S.inner_rtol;
+    return last_step && r2 <= S.inner_tol2 / (0.3 * 0.3) && S.kin - S.k_best >= max(kRelaxIters, S.k_best / 4);
+}
+
 // Operator view shared by the kernels.
 struct Op {
     int n;                 // rows including padding (multiple of kTR)
@@ -184,6 +198,8 @@ __device__ __forceinline__ void step_beta(ColState& S, double2 rz, double r2) {
     } else if (stalled_now(S, r2)) {
         S.active = 0;
         S.stalled += 1;
+    } else if (relaxed_now(S, r2)) {
+        S.active = 0;
     } else if (czero(S.rho)) {
         S.active = 0;
         S.breakdown = 1;
@@ -1472,6 +1488,8 @@ __device__ __forceinline__ void fused_scalars(ColState& S, const double2* t) {
         } else if (stalled_now(S, r2)) {
             S.active = 0;
             S.stalled += 1;
+        } else if (relaxed_now(S, r2)) {
+            S.active = 0;
         } else if (czero(rz)) {
             S.active = 0;
             S.breakdown = 1;
@@ -3078,10 +3096,12 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
             }
             if (o.verbose && inner >= next_print) {
                 double worst = 0.0;
+                int kw = -1;
                 for (int k = 0; k < nsc; ++k)
-                    if (sv[k].active) worst = std::max(worst, sv[k].rn2);
-                fprintf(stderr, "[petgem]   inner %d: %d active, worst inner residual %.3e, %.0f ms\n", inner, act,
-                        std::sqrt(worst), t_all.ms());
+                    if (sv[k].active && sv[k].rn2 >= worst) { worst = sv[k].rn2; kw = k; }
+                fprintf(stderr, "[petgem]   inner %d: %d active, worst inner residual %.3e (column %d, its best "
+                        "%.3e at %d), %.0f ms\n", inner, act, std::sqrt(worst), kw,
+                        kw >= 0 ? std::sqrt(sv[kw].rn2_best) : 0.0, kw >= 0 ? sv[kw].k_best : 0, t_all.ms());
                 fflush(stderr);
                 next_print += 512;
             }
