@@ -13,12 +13,13 @@
 //   c5 96->32 @16^3 relu | up, concat c1 | c6 48->16 @32^3 relu |
 //   c7 16->16 @32^3 (linear; channels 0..5 are the output)
 // Every convolution is 3x3x3, stride 1, zero padding 1, computed as an
-// implicit GEMM on v_mfma_f32_16x16x16_bf16: M = voxels, N = output channels,
-// K = 27 taps x input channels (each 16-wide K chunk is one tap and 16
-// channels, so every lane's 4 K values are 8 contiguous bytes). The backward
-// data pass is the same kernel with the taps mirrored and the channel roles
-// swapped; the backward weight pass is an MFMA reduction over voxels on
-// voxel-quad interleaved copies of the layer input and its output gradient.
+// implicit GEMM on v_mfma_f32_16x16x32_bf16: M = voxels, N = output channels,
+// K = 27 taps x input channels (each lane's 8 K values of a 32-wide chunk are
+// 8 channels of one tap, 16 contiguous bytes). The backward data pass is the
+// same kernel with the taps mirrored and the channel roles swapped; the
+// backward weight pass is an MFMA reduction over voxels (v_mfma_f32_16x16x16_bf16,
+// 4 voxels per lane) on voxel-quad interleaved copies of the layer input and
+// its output gradient.
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -30,6 +31,8 @@
 namespace petgem {
 
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef short s16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 using bf16 = uint16_t;
 
@@ -46,6 +49,12 @@ __device__ __forceinline__ bf16 f2bf(float f) {
     return (bf16)(u >> 16);
 }
 
+// 8 bf16 from LDS at a 16-byte aligned address (one 16-byte read), as the
+// operand type of v_mfma_f32_16x16x32_bf16
+__device__ __forceinline__ bf16x8 lds8(const bf16* p) {
+    return __builtin_bit_cast(bf16x8, *reinterpret_cast<const s16x8*>(p));
+}
+
 // ---------------------------------------------------------------- conv
 // out[v][co] = sum_tap sum_ci in[v + off(tap)][ci] W[tap][ci][co] (+ bias, relu)
 // in bf16 [B][D^3][CIN], wt bf16 [COUT][27*CIN] (K-contiguous per output
@@ -59,8 +68,8 @@ __device__ __forceinline__ bf16 f2bf(float f) {
 template <int CIN, int COUT, int D, int TY, int NTB>
 struct ConvTile {
     static constexpr int MT = TY * D / 64;           // M tiles per wave
-    static constexpr int HC = CIN + 4;               // halo voxel stride (bf16)
-    static constexpr int WK = 9 * CIN + 4;           // weight row stride (bf16)
+    static constexpr int HC = CIN + 8;               // halo voxel stride (bf16; 16-byte aligned rows)
+    static constexpr int WK = 9 * CIN + 8;           // weight row stride (bf16; 16-byte aligned rows)
     static constexpr int HALO = (TY + 2) * (D + 2) * HC;
     static constexpr int WTS = 16 * NTB * WK;
     static_assert(TY * D % 64 == 0 && D % TY == 0 && COUT % (16 * NTB) == 0 && CIN % 16 == 0, "tile shape");
@@ -84,7 +93,7 @@ k_conv(const bf16* __restrict__ in, const bf16* __restrict__ wt, const float* __
 #pragma unroll
     for (int i = 0; i < MT; ++i) {
         const int vb = (wave + 4 * i) * 16 + m;
-        aoff[i] = ((vb / D) * (D + 2) + vb % D) * HC + 4 * kq;
+        aoff[i] = ((vb / D) * (D + 2) + vb % D) * HC;
     }
     f32x4 acc[MT][NTB];
 #pragma unroll
@@ -135,23 +144,42 @@ k_conv(const bf16* __restrict__ in, const bf16* __restrict__ wt, const float* __
     __syncthreads();
     for (int pz = 0; pz < 3; ++pz) {
         if (pz < 2) fetch(pz + 1);
+        // The plane's reduction index runs over its 9 taps x CIN channels,
+        // tap-major (the order of a weight row), 32 at a time on
+        // v_mfma_f32_16x16x32_bf16: lane kq takes indices 8 kq .. 8 kq + 7 of
+        // the chunk, 8 channels of one tap (CIN is a multiple of 16), for both
+        // operands; 9 CIN that is an odd multiple of 16 leaves 16, taken by
+        // v_mfma_f32_16x16x16_bf16 (4 per lane).
+        constexpr int KP = 9 * CIN, NK32 = KP / 32;
+        constexpr int UNR = CIN >= 48 ? 1 : 3;   // wider inputs: keep two waves per SIMD
+#pragma unroll UNR
+        for (int kk = 0; kk < NK32; ++kk) {
+            const int idx = 32 * kk + 8 * kq, tap = idx / CIN, ch = idx % CIN;
+            const int sh = ((tap / 3) * (D + 2) + tap % 3) * HC + ch;   // (dy, dx) shift and channel in the halo
+            bf16x8 a[MT], w[NTB];
 #pragma unroll
-        for (int t9 = 0; t9 < 9; ++t9) {
-            const int sh = ((t9 / 3) * (D + 2) + t9 % 3) * HC;   // (dy, dx) shift in the halo
+            for (int i = 0; i < MT; ++i) a[i] = lds8(halo + aoff[i] + sh);
 #pragma unroll
-            for (int c0 = 0; c0 < CIN; c0 += 16) {
-                bf16x4 a[MT], w[NTB];
+            for (int t = 0; t < NTB; ++t) w[t] = lds8(wl + (t * 16 + m) * WK + idx);
 #pragma unroll
-                for (int i = 0; i < MT; ++i) a[i] = *reinterpret_cast<const bf16x4*>(halo + aoff[i] + sh + c0);
+            for (int i = 0; i < MT; ++i)
 #pragma unroll
                 for (int t = 0; t < NTB; ++t)
-                    w[t] = *reinterpret_cast<const bf16x4*>(wl + (t * 16 + m) * WK + t9 * CIN + c0 + 4 * kq);
+                    acc[i][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], w[t], acc[i][t], 0, 0, 0);
+        }
+        if constexpr (KP % 32 != 0) {
+            const int idx = 32 * NK32 + 4 * kq, tap = idx / CIN, ch = idx % CIN;
+            const int sh = ((tap / 3) * (D + 2) + tap % 3) * HC + ch;
+            bf16x4 a[MT], w[NTB];
 #pragma unroll
-                for (int i = 0; i < MT; ++i)
+            for (int i = 0; i < MT; ++i) a[i] = *reinterpret_cast<const bf16x4*>(halo + aoff[i] + sh);
 #pragma unroll
-                    for (int t = 0; t < NTB; ++t)
-                        acc[i][t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], w[t], acc[i][t], 0, 0, 0);
-            }
+            for (int t = 0; t < NTB; ++t) w[t] = *reinterpret_cast<const bf16x4*>(wl + (t * 16 + m) * WK + idx);
+#pragma unroll
+            for (int i = 0; i < MT; ++i)
+#pragma unroll
+                for (int t = 0; t < NTB; ++t)
+                    acc[i][t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], w[t], acc[i][t], 0, 0, 0);
         }
         __syncthreads();
         if (pz < 2) {
