@@ -8,7 +8,8 @@ path for one batch of 16 consecutive dipole positions at one frequency: device
 re-assembly of K and M_sigma, the 16 right-hand sides, the solve of the
 16-column block by COCG preconditioned with multicolour SSOR (`--precond
 jacobi` for Jacobi) in complex64 inside complex128 iterative refinement to a
-true relative residual of 1e-9, and the total field at the receivers. Timed step k takes batch k mod 6, so 6 steps cover the survey.
+true relative residual of 1e-12, and the total field at the receivers. Timed
+step k takes batch k mod 6, so 6 steps cover the survey.
 Inputs are resident on the GPU when the timed region starts; host mesh
 preprocessing is setup and is reported separately. Beside it: plain FP64
 Jacobi GMRES(30) on a stated subset (the centre dipole at each frequency),
@@ -77,6 +78,10 @@ RTOL = 1e-9
 # out where the field has decayed by ~1e-8) need 1e-12: at 1e-10 their far
 # receivers still move by up to 1.4e-5, at 3e-11 by up to 2e-6
 RTOL_CFG4 = 1e-12
+# the survey's end dipoles (x = -3100, 3100 m) have receivers 7.1 km away:
+# their per-receiver error against the stored oracle fields was 2.8e-4, 2.5e-5,
+# 3.2e-6 and 3.3e-7 at true residuals 1e-9, 1e-10, 1e-11 and 1e-12
+RTOL_CFG3 = 1e-12
 GOLDEN_CFG2 = os.path.join(ROOT, "tests", "golden", "cfg2_receivers.npz")
 
 
@@ -332,7 +337,7 @@ def bench_cfg3(args, petgem, synth, torch):
     print(f"cfg3 setup {setup_s:.1f} s (host {S.setup_seconds:.1f} s), {S.n_dof} DOF, {S.nnz} nnz",
           file=sys.stderr, flush=True)
     sigma_dev = torch.tensor(model.sigma, device="cuda")
-    o_mix = petgem.default_opts(profile=0 if args.no_profile else 1, rtol=RTOL, method=petgem.COCG,
+    o_mix = petgem.default_opts(profile=0 if args.no_profile else 1, rtol=RTOL_CFG3, method=petgem.COCG,
                                 precision=petgem.MIXED, inner_rtol=args.inner_rtol, max_iter=args.max_iter,
                                 verbose=int(args.verbose), spmm_shape=args.spmm_shape,
                                 precond=petgem.SSOR if args.precond == "ssor" else petgem.JACOBI,
@@ -348,7 +353,7 @@ def bench_cfg3(args, petgem, synth, torch):
         sol, st, rc = S.solve(srcs, o_mix, solution=sols.get(bi), allow_not_converged=True)
         sols[bi] = sol
         E = sol.receivers(model.receivers)
-        if rc != petgem.OK or any(s_["rel_residual"] > RTOL for s_ in st):
+        if rc != petgem.OK or any(s_["rel_residual"] > RTOL_CFG3 for s_ in st):
             bad.append((bi, rc, max(s_["rel_residual"] for s_ in st)))
         print(f"cfg3 step {k}: batch {bi} ({srcs[0].freq} Hz) iters max {max(s_['iters'] for s_ in st)} "
               f"ir {st[0]['ir_steps']} solve {st[0]['t_solve_ms']:.0f} ms", file=sys.stderr, flush=True)
@@ -373,7 +378,7 @@ def bench_cfg3(args, petgem, synth, torch):
     nbytes = spmm_bytes_fp32(S.n_dof, S.nnz, B, shape)
     achieved = nbytes / (avg_ms * 1e-3) / 1e9 if n_launch else None
     kname = kernel_name("mixed", shape)
-    # accuracy: every solve converged to RTOL (gate above) and the sources with
+    # accuracy: every solve converged to RTOL_CFG3 (gate above) and the sources with
     # stored oracle fields match them
     oracle_err = {}
     for (f, i), name in CFG3_GOLDEN.items():
@@ -385,7 +390,7 @@ def bench_cfg3(args, petgem, synth, torch):
     # plain FP64 GMRES(30) on a stated subset: the centre dipole at each frequency
     picks = (16,) if args.plain_subset <= 3 else (0, 16, 31)
     sub = [f * 32 + k for f in range(3) for k in picks]
-    o_plain = petgem.default_opts(rtol=RTOL, max_iter=args.max_iter, verbose=int(args.verbose))
+    o_plain = petgem.default_opts(rtol=RTOL_CFG3, max_iter=args.max_iter, verbose=int(args.verbose))
     S.solve([model.sources[sub[0]]], o_plain, allow_not_converged=True)   # the plain path's own autotuning
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -396,7 +401,7 @@ def bench_cfg3(args, petgem, synth, torch):
     Ep = Ep.cpu().numpy()
     agree = max((rx_error(fields[k], Ep[i]) for i, k in enumerate(sub) if k in fields), default=None)
     plain_rate = len(sub) / t_plain
-    plain_ok = prc == petgem.OK and all(s_["rel_residual"] <= RTOL for s_ in pst)
+    plain_ok = prc == petgem.OK and all(s_["rel_residual"] <= RTOL_CFG3 for s_ in pst)
     value = B * args.steps / dt
     line = {
         "metric": "receiver-field solves/s at 1e-6 rel err: plain FP64 vs batched/mixed/learned",
@@ -407,7 +412,7 @@ def bench_cfg3(args, petgem, synth, torch):
                                 f"x (0.25, 0.5, 1.25) Hz = 96 sources, 101 receivers; one step = {B} dipoles at one "
                                 f"frequency as one {B}-column mixed COCG block "
                                 f"({'multicolour SSOR' if args.precond == 'ssor' else 'Jacobi'}), true relative "
-                                f"residual {RTOL:g}"),
+                                f"residual {RTOL_CFG3:g}"),
                    "form": "batched mixed", "n_dof": S.n_dof, "nnz": S.nnz, "setup_s": round(setup_s, 3),
                    "batch": B, "spmv_shape": shape, "precond": args.precond,
                    "omega": args.omega if args.precond == "ssor" else None, "parallelism": "1 GPU"},

@@ -81,6 +81,8 @@ template <> struct V2<double> { using t = double2; };
 struct ColState {
     double2 rho, alpha, beta;
     double rn2;        // inner |r|^2 (relative to the normalised start)
+    double rn2_0;      // |r|^2 at the start of the inner solve the tolerance is relative to (1, or the
+                       // split residual's of an Eisenstat solve)
     double rn2_best;   // least inner |r|^2 of the current refinement step
     double scale;      // |r64| of the current refinement step
     double bnorm;      // |b|
@@ -121,16 +123,33 @@ __device__ __forceinline__ bool stalled_now(ColState& S, double r2) {
 
 // The last refinement step of a column solves its correction only as far as
 // the target needs, with a factor 0.3 to spare (res_step). A column whose
-// inner |r| hovers just above that target without a new best for a quarter
-// of the iterations its best took (at least kRelaxIters) gives the margin
-// up: it stops once |r| is within the target without the factor. (On the
+// inner |r| hovers just above that target without a new best for half the
+// iterations its best took (at least kRelaxIters) gives the margin up: it
+// stops once |r| is within the target without the factor. (With a quarter,
+// columns that were still converging gave the margin up, missed rtol and
+// needed a fourth refinement step.) (On the
 // 6.9M-unknown survey one 0.25 Hz column reached 1.04 times its target of
 // 2.2e-2 at iteration 576 of its third step, then wandered for 4,000
 // iterations until the guard above stopped it.)
 constexpr int kRelaxIters = 100;
+// In any refinement step, a column whose |r| has had no new best for as many
+// iterations as its best took (at least kPlateauIters) stops at the first
+// iterate whose |r| is at most 0.1 of the step's start: its correction
+// still reduces the true residual tenfold, and the next refinement step
+// restarts from it. (The same 0.25 Hz survey had a column reach 1.4 times the
+// inner target 3e-5 at iteration 365 of its first step and wander between
+// 2e-4 and 7e-3 until the guard stopped it at 4,096.) A plateau as long as
+// the whole descent before it does not occur in a column that still
+// converges.
+constexpr int kPlateauIters = 200;
+__device__ __forceinline__ bool plateau_now(const ColState& S, double r2) {
+    const bool last_step = S.inner_tol2 > S.inner_rtol * S.inner_rtol;   // that one has its own rule
+    return !last_step && S.kin - S.k_best >= max(kPlateauIters, S.k_best) && r2 <= 0.01 * S.rn2_0;
+}
 __device__ __forceinline__ bool relaxed_now(const ColState& S, double r2) {
     const bool last_step = S.inner_tol2 > S.inner_rtol * S.inner_rtol;
-    return last_step && r2 <= S.inner_tol2 / (0.3 * 0.3) && S.kin - S.k_best >= max(kRelaxIters, S.k_best / 4);
+    return last_step && r2 <= S.inner_tol2 * S.rn2_0 / (0.3 * 0.3) &&
+           S.kin - S.k_best >= max(kRelaxIters, S.k_best / 2);
 }
 
 // Operator view shared by the kernels.
@@ -168,7 +187,7 @@ struct Op {
 __device__ __forceinline__ int tile_of(const Op& op, int b) { return op.tmap ? op.tmap[b] : b; }
 
 // ------------------------------------------------------------ reductions
-enum RedMode { RED_INIT = 0, RED_ALPHA = 1, RED_BETA = 2, RED_RES = 3, RED_X0 = 4 };
+enum RedMode { RED_INIT = 0, RED_ALPHA = 1, RED_BETA = 2, RED_RES = 3, RED_X0 = 4, RED_INIT_REL = 5 };
 
 __device__ __forceinline__ bool cfinite(double2 a) { return isfinite(a.x) && isfinite(a.y); }
 __device__ __forceinline__ bool czero(double2 a) { return a.x == 0.0 && a.y == 0.0; }
@@ -193,13 +212,16 @@ __device__ __forceinline__ void step_beta(ColState& S, double2 rz, double r2) {
     if (!isfinite(r2) || !cfinite(rz)) {
         S.active = 0;
         S.breakdown = 1;
-    } else if (r2 <= S.inner_tol2) {
+    } else if (r2 <= S.inner_tol2 * S.rn2_0) {
         S.active = 0;
     } else if (stalled_now(S, r2)) {
         S.active = 0;
         S.stalled += 1;
     } else if (relaxed_now(S, r2)) {
         S.active = 0;
+    } else if (plateau_now(S, r2)) {
+        S.active = 0;
+        S.stalled += 1;
     } else if (czero(S.rho)) {
         S.active = 0;
         S.breakdown = 1;
@@ -225,9 +247,10 @@ __device__ __forceinline__ void res_step(ColState& S, double rn, int first) {
 
 // The scalar step of one (segment, column) once its sums a, b are known.
 __device__ void apply_red(ColState& S, int mode, int first, double2 a, double2 b) {
-    if (mode == RED_INIT) {            // a = r^T z, b.x = |r|^2 of the normalised start
+    if (mode == RED_INIT || mode == RED_INIT_REL) {   // a = r^T z, b.x = |r|^2 of the start
         S.rho = a;
         S.rn2 = b.x;
+        S.rn2_0 = mode == RED_INIT_REL ? b.x : 1.0;   // else normalised: |r| = 1
         S.rn2_best = b.x;
         S.k_best = 0;
         S.kin = 0;
@@ -1265,6 +1288,210 @@ k_ssor_c(Op op, SsorOp so, int p0, int p1, const ColState* __restrict__ st, cons
     }
 }
 
+// Eisenstat's form of the SSOR-preconditioned COCG (many columns). With
+// D~ = D / omega, L1 = D~ + L and U1 = D~ + U = L1^T, the iteration runs on
+// the split system  L1^-1 A U1^-1 (scaled by D~^1/2 on both sides, which
+// keeps it complex symmetric and equal to COCG with M = L1 D~^-1 U1), and
+// A = L1 + U1 + (D - 2 D~) turns its product into the two triangular solves:
+//   t = U1^-1 p     (the U sweep, colours nc-1 .. 0: the forward formula on
+//                    the U entries)
+//   y = L1^-1 (p + (D - 2 D~) t)          (this kernel, colours 0 .. nc-1)
+//   q = t + y       (the product with the split operator, never formed)
+// In the variables used here (p = D~^1/2 p^, r = D~^1/2 r^) the scalars are
+//   p^T q, rho = r^T D~^-1 r, r -= alpha D~ q, x += alpha t, p = r + beta p,
+// and x is the correction itself (the sum of alpha U1^-1 p). This kernel also
+// leaves the block's partial sums of p^T (t + y) per column in part[base +
+// block] (rows of a colour: no early exit, every thread reaches the barrier).
+template <int LPR, int CPL>
+__global__ void __launch_bounds__(256)
+k_ssor_eis(Op op, SsorOp so, int p0, int p1, const ColState* __restrict__ st, const float2* __restrict__ P,
+           const float2* __restrict__ T, float2* __restrict__ Y, float omega, double2* __restrict__ part,
+           int base) {
+    constexpr int RPB = 256 / LPR;
+    constexpr int NB = 12;
+    constexpr int NH = (NB + LPR - 1) / LPR;
+    __shared__ double2 red[RPB][LPR * CPL];
+    const int slot = threadIdx.x / LPR, l = threadIdx.x % LPR;
+    const int C = op.C;
+    const float cdt = 1.f - 2.f / omega;   // (D - 2 D~) = (1 - 2 / omega) D
+    bool colok[CPL];
+#pragma unroll
+    for (int u = 0; u < CPL; ++u) {
+        const int c = l * CPL + u;
+        colok[u] = c < C && (!st || st[c].active);
+    }
+    double2 pa[CPL];
+#pragma unroll
+    for (int u = 0; u < CPL; ++u) pa[u] = make_double2(0.0, 0.0);
+    // the block strides over the colour's rows (few blocks: few partial slots
+    // for the alpha reduction); the loop bound is the same for all its threads
+    for (int pb = p0 + blockIdx.x * RPB; pb < p1; pb += gridDim.x * RPB) {
+        const int p = pb + slot;
+        const bool rowok = p < p1;   // a whole lane group of this row
+        const int i = rowok ? so.row[p] : 0;
+        bool live[CPL];
+#pragma unroll
+        for (int u = 0; u < CPL; ++u) live[u] = rowok && colok[u];
+        float2 ak[CPL], am[CPL];
+#pragma unroll
+        for (int u = 0; u < CPL; ++u) { ak[u] = f2(0.f, 0.f); am[u] = f2(0.f, 0.f); }
+        const int32_t ke = rowok ? so.rp[p + 1] : 0;
+        for (int32_t kb = rowok ? so.rp[p] : 0; kb < ke; kb += NB) {
+            int32_t cj[NH];
+            float kv[NH], mv[NH];
+#pragma unroll
+            for (int h = 0; h < NH; ++h) {
+                const int32_t k = kb + h * LPR + l;
+                const bool ok = h * LPR + l < NB && k < ke;
+                cj[h] = ok ? so.col[k] : 0;
+                kv[h] = ok ? so.K[k] : 0.f;
+                mv[h] = ok ? so.M[k] : 0.f;
+            }
+            float2 xv[NB][CPL];
+#pragma unroll
+            for (int q = 0; q < NB; ++q) {
+                const int j = __shfl(cj[q / LPR], q % LPR, LPR);
+                const bool ok = kb + q < ke;
+                const float2* yr = Y + (size_t)j * C + l * CPL;
+#pragma unroll
+                for (int u = 0; u < CPL; ++u) xv[q][u] = (ok && live[u]) ? yr[u] : f2(0.f, 0.f);
+            }
+#pragma unroll
+            for (int q = 0; q < NB; ++q) {
+                const float kq = __shfl(kv[q / LPR], q % LPR, LPR);
+                const float mq = __shfl(mv[q / LPR], q % LPR, LPR);
+#pragma unroll
+                for (int u = 0; u < CPL; ++u) {
+                    ak[u].x += kq * xv[q][u].x; ak[u].y += kq * xv[q][u].y;
+                    am[u].x += mq * xv[q][u].x; am[u].y += mq * xv[q][u].y;
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < CPL; ++u) {
+            if (!live[u]) continue;
+            const int c = l * CPL + u;
+            const double wmu = op.wmu[c];
+            // s = sum a_ij y_j = ak - i wmu am; d = Kd - i wmu Md
+            const float2 sv = f2(ak[u].x + (float)wmu * am[u].y, ak[u].y - (float)wmu * am[u].x);
+            const double dr = op.Kd[i], di = -wmu * op.Md[i];
+            const double inv = 1.0 / (dr * dr + di * di);
+            const float2 dinv = f2((float)(dr * inv), (float)(-di * inv));
+            const size_t o = (size_t)i * C + c;
+            const float2 pv = P[o], tv = T[o];
+            const float2 dt = cmulf(f2((float)dr, (float)di), tv);
+            const float2 rhs = f2(pv.x + cdt * dt.x - sv.x, pv.y + cdt * dt.y - sv.y);
+            const float2 y = cmulf(f2(omega * rhs.x, omega * rhs.y), dinv);
+            Y[o] = y;
+            const float2 qv = f2(tv.x + y.x, tv.y + y.y);
+            pa[u].x += (double)pv.x * qv.x - (double)pv.y * qv.y;
+            pa[u].y += (double)pv.x * qv.y + (double)pv.y * qv.x;
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < CPL; ++u) red[slot][l * CPL + u] = pa[u];
+    __syncthreads();
+    for (int c = threadIdx.x; c < C && c < LPR * CPL; c += 256) {
+        double2 a = make_double2(0.0, 0.0);
+        for (int r = 0; r < RPB; ++r) a = cadd(a, red[r][c]);
+        part[(size_t)(base + blockIdx.x) * C + c] = a;
+    }
+}
+
+// Start of an Eisenstat inner solve, after y = L1^-1 r0 (the forward sweep
+// into Y): r = D~ y, p = r; partials r^T y (= r^T D~^-1 r, rho) and
+// sum |r_i|^2 / |D~_i| (the squared norm of the split residual).
+__global__ void __launch_bounds__(256)
+k_eis_init(Op op, int CP, const ColState* __restrict__ st, const float2* __restrict__ Y, float2* __restrict__ R,
+           float2* __restrict__ P, float omega, double2* __restrict__ p0, double2* __restrict__ p1) {
+    __shared__ double2 ra[256], rb[256];
+    const int tile = blockIdx.x, C = op.C;
+    const int c = threadIdx.x % CP, slot = threadIdx.x / CP, RPB = 256 / CP;
+    double2 a = make_double2(0.0, 0.0), b = make_double2(0.0, 0.0);
+    if (c < C && st[c].outer) {
+        const double wmu = op.wmu[c];
+        for (int r0 = 0; r0 < kTR; r0 += RPB) {
+            const int i = tile * kTR + r0 + slot;
+            if (i >= op.nrow_valid) break;
+            const size_t o = (size_t)i * C + c;
+            const double dr = op.Kd[i] / omega, di = -wmu * op.Md[i] / omega;   // D~
+            const float2 y = Y[o];
+            const float2 r = cmulf(f2((float)dr, (float)di), y);
+            R[o] = r;
+            P[o] = r;
+            a.x += (double)r.x * y.x - (double)r.y * y.y;
+            a.y += (double)r.x * y.y + (double)r.y * y.x;
+            b.x += ((double)r.x * r.x + (double)r.y * r.y) / sqrt(dr * dr + di * di);
+        }
+    }
+    cp_sum2(a, b, CP, ra, rb);
+    if ((int)threadIdx.x < C && (int)threadIdx.x < CP) {
+        p0[(size_t)tile * C + threadIdx.x] = ra[threadIdx.x];
+        p1[(size_t)tile * C + threadIdx.x] = rb[threadIdx.x];
+    }
+}
+
+// The Eisenstat step after alpha: x += alpha t, r -= alpha D~ (t + y);
+// partials rho' = r^T D~^-1 r and sum |r_i|^2 / |D~_i|.
+__global__ void __launch_bounds__(256)
+k_eis_update(Op op, int CP, const ColState* __restrict__ st, const float2* __restrict__ T,
+             const float2* __restrict__ Y, float2* __restrict__ R, float2* __restrict__ Xi, float omega,
+             double2* __restrict__ p0, double2* __restrict__ p1) {
+    __shared__ double2 ra[256], rb[256];
+    const int tile = tile_of(op, blockIdx.x), C = op.C;
+    const int c = threadIdx.x % CP, slot = threadIdx.x / CP, RPB = 256 / CP;
+    double2 a = make_double2(0.0, 0.0), b = make_double2(0.0, 0.0);
+    if (c < C && st[c].active) {
+        const ColState& S = st[c];
+        const float ax = (float)S.alpha.x, ay = (float)S.alpha.y;
+        const double wmu = op.wmu[c];
+        for (int r0 = 0; r0 < kTR; r0 += RPB) {
+            const int i = tile * kTR + r0 + slot;
+            if (i >= op.nrow_valid) break;
+            const size_t o = (size_t)i * C + c;
+            const double dr = op.Kd[i] / omega, di = -wmu * op.Md[i] / omega;   // D~
+            const double inv = 1.0 / (dr * dr + di * di);
+            const float2 t = T[o], y = Y[o];
+            float2 x = Xi[o];
+            x.x += ax * t.x - ay * t.y;
+            x.y += ax * t.y + ay * t.x;
+            Xi[o] = x;
+            const float2 q = cmulf(f2((float)dr, (float)di), f2(t.x + y.x, t.y + y.y));   // D~ (t + y)
+            float2 r = R[o];
+            r.x -= ax * q.x - ay * q.y;
+            r.y -= ax * q.y + ay * q.x;
+            R[o] = r;
+            const float2 z = cmulf(r, f2((float)(dr * inv), (float)(-di * inv)));   // D~^-1 r
+            a.x += (double)r.x * z.x - (double)r.y * z.y;
+            a.y += (double)r.x * z.y + (double)r.y * z.x;
+            b.x += ((double)r.x * r.x + (double)r.y * r.y) * sqrt(inv);
+        }
+    }
+    cp_sum2(a, b, CP, ra, rb);
+    if ((int)threadIdx.x < C && (int)threadIdx.x < CP) {
+        p0[(size_t)tile * C + threadIdx.x] = ra[threadIdx.x];
+        p1[(size_t)tile * C + threadIdx.x] = rb[threadIdx.x];
+    }
+}
+
+// p = r + beta p for the columns still active after the beta step.
+__global__ void __launch_bounds__(256)
+k_eis_pupdate(Op op, int CP, const ColState* __restrict__ st, const float2* __restrict__ R, float2* __restrict__ P) {
+    const int tile = tile_of(op, blockIdx.x), C = op.C;
+    const int c = threadIdx.x % CP, slot = threadIdx.x / CP, RPB = 256 / CP;
+    if (c >= C) return;
+    const ColState& S = st[c];
+    if (!S.stepped || !S.active) return;
+    const float bx = (float)S.beta.x, by = (float)S.beta.y;
+    for (int r0 = 0; r0 < kTR; r0 += RPB) {
+        const int i = tile * kTR + r0 + slot;
+        if (i >= op.nrow_valid) break;
+        const size_t o = (size_t)i * C + c;
+        const float2 r = R[o], p = P[o];
+        P[o] = f2(r.x + bx * p.x - by * p.y, r.y + bx * p.y + by * p.x);
+    }
+}
+
 // Partials of r^T z per tile and column (the sweeps wrote z); with P not
 // null also p = z (the start of an inner solve). st (or null) as above; with
 // P, columns still in the refinement (outer) take part.
@@ -1490,6 +1717,9 @@ __device__ __forceinline__ void fused_scalars(ColState& S, const double2* t) {
             S.stalled += 1;
         } else if (relaxed_now(S, r2)) {
             S.active = 0;
+        } else if (plateau_now(S, r2)) {
+            S.active = 0;
+            S.stalled += 1;
         } else if (czero(rz)) {
             S.active = 0;
             S.breakdown = 1;
@@ -1978,6 +2208,7 @@ __global__ void k_init_state(ColState* st, int nsc, double inner_rtol) {
     ColState S;
     S.rho = S.alpha = S.beta = make_double2(0.0, 0.0);
     S.rn2 = 0.0;
+    S.rn2_0 = 1.0;
     S.rn2_best = 0.0;
     S.scale = 0.0;
     S.bnorm = 0.0;
@@ -2119,6 +2350,8 @@ struct BlockWork {
     int p0_slots = 0;          // SpMM partial slots per tile that p0 holds
     size_t dinv_rows = 0;
     double2 *p0 = nullptr, *p1 = nullptr, *p2 = nullptr;
+    double2* pe = nullptr;     // partials of the Eisenstat L pass, one slot per sweep block
+    size_t pe_cap = 0;
     ColState* st = nullptr;
     ColState* st2 = nullptr;   // second state slot of the in-consumer reductions
     ColState* st_h = nullptr;
@@ -2158,6 +2391,8 @@ struct BlockWork {
         dfree(Dinv);
         dinv_rows = 0;
         dfree(p0); dfree(p1); dfree(p2); dfree(st); dfree(st2); dfree(tmap); dfree(flags); dfree(wmu);
+        dfree(pe);
+        pe_cap = 0;
         dfree(seg_tile); dfree(tile_seg);
         dfree(rp); dfree(col); dfree(K64); dfree(M64); dfree(Kd); dfree(Md); dfree(K32); dfree(M32);
         cat_sell.release();
@@ -2331,36 +2566,82 @@ int ensure_ssor(petgem_system* sys, hipStream_t s) {
 
 namespace {
 
-// z = M^-1 r by the two multicolour sweeps over op's columns (Z in place; R
-// read by the forward sweep). st (or null) skips stopped columns.
-void ssor_sweeps(const Ssor& Q, const Op& op, const ColState* st, const float2* R, float2* Z, float omega,
-                 hipStream_t s) {
+// One multicolour pass of the sweep kernels over op's columns: the L entries
+// with the colours ascending, or the U entries descending; bwd picks the
+// backward formula z -= omega s / d, else z = omega (r - s) / d (a solve
+// with D~ + L, or with D~ + U on the U entries). st (or null) skips stopped
+// columns.
+void ssor_pass(const Ssor& Q, const Op& op, const ColState* st, const float2* R, float2* Z, float omega,
+               bool upper, bool bwd, hipStream_t s) {
     const int C = op.C;
-    for (int pass = 0; pass < 2; ++pass) {
-        const bool bwd = pass == 1;
-        SsorOp so{Q.row, bwd ? Q.urp : Q.lrp, bwd ? Q.ucol : Q.lcol, bwd ? Q.uK : Q.lK, bwd ? Q.uM : Q.lM};
-        for (int k = 0; k < Q.nc; ++k) {
-            const int c = bwd ? Q.nc - 1 - k : k;
-            const int p0 = Q.cptr[c], p1 = Q.cptr[c + 1];
-            if (p1 <= p0) continue;
+    SsorOp so{Q.row, upper ? Q.urp : Q.lrp, upper ? Q.ucol : Q.lcol, upper ? Q.uK : Q.lK, upper ? Q.uM : Q.lM};
+    for (int k = 0; k < Q.nc; ++k) {
+        const int c = upper ? Q.nc - 1 - k : k;
+        const int p0 = Q.cptr[c], p1 = Q.cptr[c + 1];
+        if (p1 <= p0) continue;
 #define PG_SN(G, CM) { const dim3 gr(ceil_div(p1 - p0, 256 / G)); \
-            if (bwd) hipLaunchKernelGGL((k_ssor_n<G, CM, true>), gr, dim3(256), 0, s, op, so, p0, p1, st, R, Z, omega); \
-            else hipLaunchKernelGGL((k_ssor_n<G, CM, false>), gr, dim3(256), 0, s, op, so, p0, p1, st, R, Z, omega); }
+        if (bwd) hipLaunchKernelGGL((k_ssor_n<G, CM, true>), gr, dim3(256), 0, s, op, so, p0, p1, st, R, Z, omega); \
+        else hipLaunchKernelGGL((k_ssor_n<G, CM, false>), gr, dim3(256), 0, s, op, so, p0, p1, st, R, Z, omega); }
 #define PG_SC(L, P) { const dim3 gr(ceil_div(p1 - p0, 256 / L)); \
-            if (bwd) hipLaunchKernelGGL((k_ssor_c<L, P, true>), gr, dim3(256), 0, s, op, so, p0, p1, st, R, Z, omega); \
-            else hipLaunchKernelGGL((k_ssor_c<L, P, false>), gr, dim3(256), 0, s, op, so, p0, p1, st, R, Z, omega); }
-            if (C == 1) PG_SN(8, 1)
-            else if (C == 2) PG_SN(8, 2)
-            else if (C <= 4) PG_SN(8, 4)
-            else if (C <= 8) PG_SC(8, 1)
-            else if (C <= 16) PG_SC(16, 1)
-            else if (C <= 32) PG_SC(32, 1)
-            else if (C <= 64) PG_SC(64, 1)
-            else if (C <= 128) PG_SC(64, 2)
-            else PG_SC(64, 4)
+        if (bwd) hipLaunchKernelGGL((k_ssor_c<L, P, true>), gr, dim3(256), 0, s, op, so, p0, p1, st, R, Z, omega); \
+        else hipLaunchKernelGGL((k_ssor_c<L, P, false>), gr, dim3(256), 0, s, op, so, p0, p1, st, R, Z, omega); }
+        if (C == 1) PG_SN(8, 1)
+        else if (C == 2) PG_SN(8, 2)
+        else if (C <= 4) PG_SN(8, 4)
+        else if (C <= 8) PG_SC(8, 1)
+        else if (C <= 16) PG_SC(16, 1)
+        else if (C <= 32) PG_SC(32, 1)
+        else if (C <= 64) PG_SC(64, 1)
+        else if (C <= 128) PG_SC(64, 2)
+        else PG_SC(64, 4)
 #undef PG_SN
 #undef PG_SC
-        }
+    }
+}
+
+// z = M^-1 r by the two multicolour sweeps (Z in place; R read by the
+// forward sweep).
+void ssor_sweeps(const Ssor& Q, const Op& op, const ColState* st, const float2* R, float2* Z, float omega,
+                 hipStream_t s) {
+    ssor_pass(Q, op, st, R, Z, omega, false, false, s);
+    ssor_pass(Q, op, st, R, Z, omega, true, true, s);
+}
+
+// Lanes per row of the many-column sweep kernels (C > 4).
+int eis_lpr(int C) { return C <= 8 ? 8 : C <= 16 ? 16 : C <= 32 ? 32 : 64; }
+
+// Blocks of one colour of the Eisenstat L pass: each strides over the
+// colour's rows, at most kEisBlocks of them (the partial slots stay few).
+constexpr int kEisBlocks = 2048;
+int eis_blocks(int rows, int C) { return std::min(ceil_div(rows, 256 / eis_lpr(C)), kEisBlocks); }
+
+// Blocks of one Eisenstat L pass (its partial slots).
+int eis_slots(const Ssor& Q, int C) {
+    int n = 0;
+    for (int c = 0; c < Q.nc; ++c) n += eis_blocks(Q.cptr[c + 1] - Q.cptr[c], C);
+    return n;
+}
+
+// The Eisenstat L pass (k_ssor_eis), colours ascending, block partials into
+// part in launch order.
+void eis_lpass(const Ssor& Q, const Op& op, const ColState* st, const float2* P, const float2* T, float2* Y,
+               float omega, double2* part, hipStream_t s) {
+    const int C = op.C;
+    const SsorOp so{Q.row, Q.lrp, Q.lcol, Q.lK, Q.lM};
+    int base = 0;
+    for (int c = 0; c < Q.nc; ++c) {
+        const int p0 = Q.cptr[c], p1 = Q.cptr[c + 1];
+        if (p1 <= p0) continue;
+#define PG_SE(L, PP) { const int nb = eis_blocks(p1 - p0, C); \
+        hipLaunchKernelGGL((k_ssor_eis<L, PP>), dim3(nb), dim3(256), 0, s, op, so, p0, p1, st, P, T, Y, omega, \
+                           part, base); base += nb; }
+        if (C <= 8) PG_SE(8, 1)
+        else if (C <= 16) PG_SE(16, 1)
+        else if (C <= 32) PG_SE(32, 1)
+        else if (C <= 64) PG_SE(64, 1)
+        else if (C <= 128) PG_SE(64, 2)
+        else PG_SE(64, 4)
+#undef PG_SE
     }
 }
 
@@ -2760,6 +3041,23 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
         PG_HIP(hipGetLastError());
         dinv = w->Dinv;
     }
+    // SSOR with more than four columns: Eisenstat's form (no product with A
+    // in the iteration); its L pass leaves one partial slot per block, summed
+    // by the alpha reduction as ppE slots per tile (the unused ones zero)
+    const bool eis = ssor && C > 4;
+    int ppE = 0;
+    if (eis) {
+        ppE = ceil_div(eis_slots(*sq, C), op.ntiles);
+        const size_t need = (size_t)op.ntiles * ppE * C;
+        if (w->pe_cap < need) {
+            dfree(w->pe);
+            w->pe_cap = 0;
+            PG_TRY(dalloc(&w->pe, need));
+            w->pe_cap = need;
+        }
+        hipLaunchKernelGGL(k_fill_z, dim3(ceil_div(need, 256)), dim3(256), 0, s, need, w->pe);
+        PG_HIP(hipGetLastError());
+    }
     const int nbu = ceil_div(op.ntiles, kConsumerTiles);   // blocks of the two vector kernels
     // one column per mesh otherwise (an uneven batch, or one mesh too large for
     // every block to sum its partials): the fused step with a reduction block
@@ -2918,6 +3216,19 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
                                (const float2*)w->Q, w->P, w->Xi, w->p1, w->p2);
             return;
         }
+        if (eis) {
+            ssor_pass(*sq, opi, w->st, w->P, w->Z, omega, true, false, s);   // t = U1^-1 p (into Z)
+            eis_lpass(*sq, opi, w->st, w->P, w->Z, w->Q, omega, w->pe, s);   // y (into Q), p^T (t + y)
+            hipLaunchKernelGGL(k_reduce, dim3(nsc), dim3(1024), 0, s, op, (const double2*)w->pe, ppE,
+                               (const double2*)nullptr, 1, w->st, (int)RED_ALPHA, 0);
+            hipLaunchKernelGGL(k_eis_update, dim3(opi.nlaunch), dim3(256), 0, s, opi, CP, (const ColState*)w->st,
+                               (const float2*)w->Z, (const float2*)w->Q, w->R, w->Xi, omega, w->p1, w->p2);
+            hipLaunchKernelGGL(k_reduce, dim3(nsc), dim3(1024), 0, s, op, (const double2*)w->p1, 1,
+                               (const double2*)w->p2, 1, w->st, (int)RED_BETA, 0);
+            hipLaunchKernelGGL(k_eis_pupdate, dim3(opi.nlaunch), dim3(256), 0, s, opi, CP, (const ColState*)w->st,
+                               (const float2*)w->R, w->P);
+            return;
+        }
         spmm_dispatch<float, 1>(ch, opi, w->st, ev_pair(SpmmArgs{w->P, nullptr, w->Q, w->p0}), s);
         if (in_consumer) {
             hipLaunchKernelGGL(k_update_p, dim3(nbu), dim3(256), 0, s, op, CP, kConsumerTiles, w->st, w->st2,
@@ -2953,12 +3264,12 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
             sig.insert(sig.end(), c, c + nb);
         };
         put(&opi, sizeof(opi));
-        const void* ptrs[15] = {w->Xi, w->R, w->Z, w->P, w->Q, w->p0, w->p1, w->p2, w->st, w->st2, dinv,
+        const void* ptrs[16] = {w->Xi, w->R, w->Z, w->P, w->Q, w->p0, w->p1, w->p2, w->st, w->st2, dinv,
                                 w->snap_ring, w->gcount, sq ? (const void*)sq->row : nullptr,
-                                sq ? (const void*)sq->lK : nullptr};
+                                sq ? (const void*)sq->lK : nullptr, eis ? (const void*)w->pe : nullptr};
         put(ptrs, sizeof(ptrs));
-        int chv[11] = {ch.kind, ch.a, ch.b, (int)in_consumer, opi.tmap ? tgen : 0, (int)fused, fused_u, (int)fused_seg,
-                       seg_u, (int)ssor, ssor ? (int)(o.omega * 1e6) : 0};
+        int chv[12] = {ch.kind, ch.a, ch.b, (int)in_consumer, opi.tmap ? tgen : 0, (int)fused, fused_u, (int)fused_seg,
+                       seg_u, (int)ssor, ssor ? (int)(o.omega * 1e6) : 0, ppE};
         put(chv, sizeof(chv));
         if (w->graph_sig != sig) w->release_graph();
         if (w->graphs[ng - 1] != nullptr) return PETGEM_OK;
@@ -3018,13 +3329,17 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
         // inner complex64 COCG on A d = r64 / |r64|
         hipLaunchKernelGGL(k_inner_init, dim3(op.ntiles), dim3(256), 0, s, op, CP, w->R64, w->st, dinv, w->Xi,
                            w->R, w->Z, w->P, w->p1, w->p2);
-        if (ssor) {   // z = M^-1 r, p = z and the r^T z partials by the sweeps
+        if (eis) {    // y0 = L1^-1 r0, then the split residual r = D~ y0, p = r; rho and its norm
+            ssor_pass(*sq, op, nullptr, w->R, w->Q, omega, false, false, s);
+            hipLaunchKernelGGL(k_eis_init, dim3(op.ntiles), dim3(256), 0, s, op, CP, (const ColState*)w->st,
+                               (const float2*)w->Q, w->R, w->P, omega, w->p1, w->p2);
+        } else if (ssor) {   // z = M^-1 r, p = z and the r^T z partials by the sweeps
             ssor_sweeps(*sq, op, nullptr, w->R, w->Z, omega, s);
             hipLaunchKernelGGL(k_rz, dim3(op.ntiles), dim3(256), 0, s, op, CP, (const ColState*)w->st,
                                (const float2*)w->R, (const float2*)w->Z, w->P, w->p1);
         }
         hipLaunchKernelGGL(k_reduce, dim3(nsc), dim3(1024), 0, s, op, w->p1, 1, w->p2, 1, w->st,
-                           (int)RED_INIT, 0);
+                           (int)(eis ? RED_INIT_REL : RED_INIT), 0);
         // Groups of kCheck iterations run between host checks; the number of
         // groups in a row follows the observed decrease of the worst active
         // residual (half the predicted need, at most kMaxGroups), so that the
@@ -3092,7 +3407,8 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
                 const ColState& S = sv[k];
                 if (!S.active) continue;
                 ++act;
-                if (S.rn2 > 0.0 && S.inner_tol2 > 0.0) gap = std::max(gap, std::log(S.rn2 / S.inner_tol2));
+                if (S.rn2 > 0.0 && S.inner_tol2 > 0.0)
+                    gap = std::max(gap, std::log(S.rn2 / (S.inner_tol2 * S.rn2_0)));
             }
             if (o.verbose && inner >= next_print) {
                 double worst = 0.0;

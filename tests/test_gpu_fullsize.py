@@ -87,9 +87,10 @@ def test_cfg3_block_matches_stored_oracle(pg, block, precond):
     (Jacobi GMRES(60) to 1e-12, tests/golden/cfg3_f1.25_i*.npz, written by the
     oracle only): the frequency's 32-column block (x = -3100 ... 3100 m, the
     shape the survey's sources take as one block) with Jacobi, and the batch of
-    8 dipoles holding the centre one (the benchmark's step) with multicolour
-    SSOR, both in mixed precision at a true residual of 1e-9; every column
-    with stored fields must match them within 1e-6."""
+    8 dipoles holding the centre one with multicolour SSOR, both in mixed
+    precision at a true residual of 1e-12 (the end dipole's receivers 7.1 km
+    away need it: at 1e-9 their error is 2.8e-4); every column with stored
+    fields must match them within 1e-6."""
     import os
     m = synth.config3()
     k0 = synth.CFG3_FREQS.index(1.25) * 32
@@ -104,10 +105,10 @@ def test_cfg3_block_matches_stored_oracle(pg, block, precond):
         pytest.skip("stored oracle fields missing")
     print(f"[case] cfg3 1.25 Hz block of {block}, {precond}", flush=True)
     S = pg.System.from_model(m)
-    o = pg.default_opts(method=pg.COCG, precision=pg.MIXED, rtol=1e-9,
+    o = pg.default_opts(method=pg.COCG, precision=pg.MIXED, rtol=1e-12,
                         precond=pg.SSOR if precond == "ssor" else pg.JACOBI)
     sol, st, rc = S.solve(srcs, o)
-    assert rc == pg.OK and all(s_["rel_residual"] <= 1e-9 for s_ in st)
+    assert rc == pg.OK and all(s_["rel_residual"] <= 1e-12 for s_ in st)
     E = sol.receivers(m.receivers).cpu().numpy()
     for c, g in golds.items():
         err = fem.receiver_error(E[c], g["E"])
