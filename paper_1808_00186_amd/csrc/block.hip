@@ -2622,19 +2622,30 @@ int eis_slots(const Ssor& Q, int C) {
     return n;
 }
 
+template <typename K, typename... Args>
+void launch_timed(K kernel, dim3 grid, hipStream_t s, hipEvent_t e0, hipEvent_t e1, Args... args);
+
 // The Eisenstat L pass (k_ssor_eis), colours ascending, block partials into
-// part in launch order.
+// part in launch order. evs (or null): every launch timestamps its start and
+// end into a new pair of events appended there (the profile of the solve).
 void eis_lpass(const Ssor& Q, const Op& op, const ColState* st, const float2* P, const float2* T, float2* Y,
-               float omega, double2* part, hipStream_t s) {
+               float omega, double2* part, hipStream_t s, std::vector<hipEvent_t>* evs) {
     const int C = op.C;
     const SsorOp so{Q.row, Q.lrp, Q.lcol, Q.lK, Q.lM};
     int base = 0;
     for (int c = 0; c < Q.nc; ++c) {
         const int p0 = Q.cptr[c], p1 = Q.cptr[c + 1];
         if (p1 <= p0) continue;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (evs) {
+            (void)hipEventCreate(&e0);
+            (void)hipEventCreate(&e1);
+            evs->push_back(e0);
+            evs->push_back(e1);
+        }
 #define PG_SE(L, PP) { const int nb = eis_blocks(p1 - p0, C); \
-        hipLaunchKernelGGL((k_ssor_eis<L, PP>), dim3(nb), dim3(256), 0, s, op, so, p0, p1, st, P, T, Y, omega, \
-                           part, base); base += nb; }
+        launch_timed((k_ssor_eis<L, PP>), dim3(nb), s, e0, e1, op, so, p0, p1, st, P, T, Y, omega, part, base); \
+        base += nb; }
         if (C <= 8) PG_SE(8, 1)
         else if (C <= 16) PG_SE(16, 1)
         else if (C <= 32) PG_SE(32, 1)
@@ -3218,7 +3229,7 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
         }
         if (eis) {
             ssor_pass(*sq, opi, w->st, w->P, w->Z, omega, true, false, s);   // t = U1^-1 p (into Z)
-            eis_lpass(*sq, opi, w->st, w->P, w->Z, w->Q, omega, w->pe, s);   // y (into Q), p^T (t + y)
+            eis_lpass(*sq, opi, w->st, w->P, w->Z, w->Q, omega, w->pe, s, prof ? &evs : nullptr);   // y, p^T (t + y)
             hipLaunchKernelGGL(k_reduce, dim3(nsc), dim3(1024), 0, s, op, (const double2*)w->pe, ppE,
                                (const double2*)nullptr, 1, w->st, (int)RED_ALPHA, 0);
             hipLaunchKernelGGL(k_eis_update, dim3(opi.nlaunch), dim3(256), 0, s, opi, CP, (const ColState*)w->st,
@@ -3481,7 +3492,9 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
         st->t_solve_ms = t_solve;
         st->spmv_ms = spmv_ms;
         st->spmv_launches = spmv_n;
-        st->spmv_shape = fused ? 40100 + fused_u : fused_seg ? 50100 + seg_u : 10000 * ch.kind + 100 * ch.a + ch.b;
+        st->spmv_shape = fused ? 40100 + fused_u : fused_seg ? 50100 + seg_u
+                         : eis ? 70000 + 100 * eis_lpr(C) + (C <= 64 ? 1 : C <= 128 ? 2 : 4)
+                               : 10000 * ch.kind + 100 * ch.a + ch.b;
         st->status = S.outer ? (std::isfinite(S.rnorm64) ? PETGEM_NOT_CONVERGED : PETGEM_NONFINITE) : PETGEM_OK;
         if (st->status != PETGEM_OK && status == PETGEM_OK) status = st->status;
     }
