@@ -1157,14 +1157,15 @@ struct SsorOp {
     const int32_t* col;
     const float* K;
     const float* M;
+    const double2* dg;     // {Kd, Md} of each listed row
 };
 
-__device__ __forceinline__ void ssor_row_out(const Op& op, int i, int C, int c, float2 ak, float2 am, double wmu,
+__device__ __forceinline__ void ssor_row_out(double2 kdmd, int i, int C, int c, float2 ak, float2 am, double wmu,
                                              float omega, bool bwd, const float2* __restrict__ R,
                                              float2* __restrict__ Z) {
     // s = sum a_ij v_j = ak - i wmu am; d = Kd - i wmu Md
     const float2 sv = f2(ak.x + (float)wmu * am.y, ak.y - (float)wmu * am.x);
-    const double dr = op.Kd[i], di = -wmu * op.Md[i];
+    const double dr = kdmd.x, di = -wmu * kdmd.y;
     const double inv = 1.0 / (dr * dr + di * di);
     const float2 dinv = f2((float)(dr * inv), (float)(-di * inv));
     const size_t o = (size_t)i * C + c;
@@ -1222,7 +1223,7 @@ k_ssor_n(Op op, SsorOp so, int p0, int p1, const ColState* __restrict__ st, cons
     // lane u writes column u (every lane holds the same sums)
 #pragma unroll
     for (int u = 0; u < CM; ++u)
-        if (l == u && live[u]) ssor_row_out(op, i, C, u, ak[u], am[u], op.wmu[u], omega, BWD, R, Z);
+        if (l == u && live[u]) ssor_row_out(so.dg[p], i, C, u, ak[u], am[u], op.wmu[u], omega, BWD, R, Z);
 }
 
 // More columns: LPR lanes per row, CPL consecutive columns per lane; the
@@ -1240,6 +1241,7 @@ k_ssor_c(Op op, SsorOp so, int p0, int p1, const ColState* __restrict__ st, cons
     if (p >= p1) return;   // the whole lane group of this row
     const int C = op.C;
     const int i = so.row[p];
+    const double2 dgp = so.dg[p];
     bool live[CPL];
 #pragma unroll
     for (int u = 0; u < CPL; ++u) {
@@ -1284,7 +1286,7 @@ k_ssor_c(Op op, SsorOp so, int p0, int p1, const ColState* __restrict__ st, cons
 #pragma unroll
     for (int u = 0; u < CPL; ++u) {
         const int c = l * CPL + u;
-        if (live[u]) ssor_row_out(op, i, C, c, ak[u], am[u], op.wmu[c], omega, BWD, R, Z);
+        if (live[u]) ssor_row_out(dgp, i, C, c, ak[u], am[u], op.wmu[c], omega, BWD, R, Z);
     }
 }
 
@@ -1374,7 +1376,8 @@ k_ssor_eis(Op op, SsorOp so, int p0, int p1, const ColState* __restrict__ st, co
             const double wmu = op.wmu[c];
             // s = sum a_ij y_j = ak - i wmu am; d = Kd - i wmu Md
             const float2 sv = f2(ak[u].x + (float)wmu * am[u].y, ak[u].y - (float)wmu * am[u].x);
-            const double dr = op.Kd[i], di = -wmu * op.Md[i];
+            const double2 kdmd = so.dg[p];
+            const double dr = kdmd.x, di = -wmu * kdmd.y;
             const double inv = 1.0 / (dr * dr + di * di);
             const float2 dinv = f2((float)(dr * inv), (float)(-di * inv));
             const size_t o = (size_t)i * C + c;
@@ -1490,6 +1493,14 @@ k_eis_pupdate(Op op, int CP, const ColState* __restrict__ st, const float2* __re
         const float2 r = R[o], p = P[o];
         P[o] = f2(r.x + bx * p.x - by * p.y, r.y + bx * p.y + by * p.x);
     }
+}
+
+// {Kd, Md} of each listed row of the multicolour order
+__global__ void k_ssor_dg(int n, const int32_t* __restrict__ row, const double* __restrict__ Kd,
+                          const double* __restrict__ Md, double2* __restrict__ dg) {
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    if (p >= n) return;
+    dg[p] = make_double2(Kd[row[p]], Md[row[p]]);
 }
 
 // Partials of r^T z per tile and column (the sweeps wrote z); with P not
@@ -2538,6 +2549,7 @@ int ensure_ssor(petgem_system* sys, hipStream_t s) {
         PG_TRY(dalloc(&Q.lM, (size_t)std::max<int64_t>(Q.nl, 1)));
         PG_TRY(dalloc(&Q.uK, (size_t)std::max<int64_t>(Q.nu, 1)));
         PG_TRY(dalloc(&Q.uM, (size_t)std::max<int64_t>(Q.nu, 1)));
+        PG_TRY(dalloc(&Q.dg, (size_t)n));
         PG_HIP(hipMemcpyAsync(Q.row, row.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s));
         PG_HIP(hipMemcpyAsync(Q.lrp, lrp.data(), sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice, s));
         PG_HIP(hipMemcpyAsync(Q.urp, urp.data(), sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice, s));
@@ -2558,6 +2570,8 @@ int ensure_ssor(petgem_system* sys, hipStream_t s) {
         if (Q.nu > 0)
             hipLaunchKernelGGL(k_ssor_vals, dim3(ceil_div(Q.nu, 256)), dim3(256), 0, s, Q.nu, Q.upos, sys->K32,
                                sys->Ms32, Q.uK, Q.uM);
+        hipLaunchKernelGGL(k_ssor_dg, dim3(ceil_div(n, 256)), dim3(256), 0, s, n, (const int32_t*)Q.row,
+                           (const double*)sys->Kd, (const double*)sys->Msd, Q.dg);
         PG_HIP(hipGetLastError());
         Q.values = true;
     }
@@ -2574,7 +2588,7 @@ namespace {
 void ssor_pass(const Ssor& Q, const Op& op, const ColState* st, const float2* R, float2* Z, float omega,
                bool upper, bool bwd, hipStream_t s) {
     const int C = op.C;
-    SsorOp so{Q.row, upper ? Q.urp : Q.lrp, upper ? Q.ucol : Q.lcol, upper ? Q.uK : Q.lK, upper ? Q.uM : Q.lM};
+    SsorOp so{Q.row, upper ? Q.urp : Q.lrp, upper ? Q.ucol : Q.lcol, upper ? Q.uK : Q.lK, upper ? Q.uM : Q.lM, Q.dg};
     for (int k = 0; k < Q.nc; ++k) {
         const int c = upper ? Q.nc - 1 - k : k;
         const int p0 = Q.cptr[c], p1 = Q.cptr[c + 1];
@@ -2631,7 +2645,7 @@ void launch_timed(K kernel, dim3 grid, hipStream_t s, hipEvent_t e0, hipEvent_t 
 void eis_lpass(const Ssor& Q, const Op& op, const ColState* st, const float2* P, const float2* T, float2* Y,
                float omega, double2* part, hipStream_t s, std::vector<hipEvent_t>* evs) {
     const int C = op.C;
-    const SsorOp so{Q.row, Q.lrp, Q.lcol, Q.lK, Q.lM};
+    const SsorOp so{Q.row, Q.lrp, Q.lcol, Q.lK, Q.lM, Q.dg};
     int base = 0;
     for (int c = 0; c < Q.nc; ++c) {
         const int p0 = Q.cptr[c], p1 = Q.cptr[c + 1];

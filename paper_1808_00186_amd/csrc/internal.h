@@ -92,11 +92,12 @@ struct Ssor {
     int32_t *lrp = nullptr, *lcol = nullptr, *lpos = nullptr;   // [n + 1], [nl], [nl]
     int32_t *urp = nullptr, *ucol = nullptr, *upos = nullptr;   // [n + 1], [nu], [nu]
     float *lK = nullptr, *lM = nullptr, *uK = nullptr, *uM = nullptr;
+    double2* dg = nullptr;             // [n] {Kd, Md} of each listed row (read contiguously by the sweeps)
     int64_t nl = 0, nu = 0;
-    bool values = false;               // lK .. uM current
+    bool values = false;               // lK .. uM, dg current
     void release() {
         dfree(row); dfree(lrp); dfree(lcol); dfree(lpos); dfree(urp); dfree(ucol); dfree(upos);
-        dfree(lK); dfree(lM); dfree(uK); dfree(uM);
+        dfree(lK); dfree(lM); dfree(uK); dfree(uM); dfree(dg);
         nc = 0; nl = nu = 0; values = false;
         cptr.clear(); color_h.clear();
     }
