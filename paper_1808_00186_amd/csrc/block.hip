@@ -1401,6 +1401,87 @@ k_ssor_eis(Op op, SsorOp so, int p0, int p1, const ColState* __restrict__ st, co
     }
 }
 
+// The Eisenstat U pass with the direction update folded in: for a column
+// whose beta step ran (stepped) and that is still active, p = r + beta p at
+// the row first (written back: the L pass reads it), then t = omega (p - s)/d
+// with s over the row's U entries (gathered from T), colours descending.
+template <int LPR, int CPL>
+__global__ void __launch_bounds__(256)
+k_ssor_eis_u(Op op, SsorOp so, int p0, int p1, const ColState* __restrict__ st, const float2* __restrict__ R,
+             float2* __restrict__ P, float2* __restrict__ T, float omega) {
+    constexpr int RPB = 256 / LPR;
+    constexpr int NB = 12;
+    constexpr int NH = (NB + LPR - 1) / LPR;
+    const int slot = threadIdx.x / LPR, l = threadIdx.x % LPR;
+    const int p = p0 + blockIdx.x * RPB + slot;
+    if (p >= p1) return;   // the whole lane group of this row
+    const int C = op.C;
+    const int i = so.row[p];
+    const double2 dgp = so.dg[p];
+    bool live[CPL];
+#pragma unroll
+    for (int u = 0; u < CPL; ++u) {
+        const int c = l * CPL + u;
+        live[u] = c < C && st[c].active;
+    }
+    float2 ak[CPL], am[CPL];
+#pragma unroll
+    for (int u = 0; u < CPL; ++u) { ak[u] = f2(0.f, 0.f); am[u] = f2(0.f, 0.f); }
+    const int32_t ke = so.rp[p + 1];
+    for (int32_t kb = so.rp[p]; kb < ke; kb += NB) {
+        int32_t cj[NH];
+        float kv[NH], mv[NH];
+#pragma unroll
+        for (int h = 0; h < NH; ++h) {
+            const int32_t k = kb + h * LPR + l;
+            const bool ok = h * LPR + l < NB && k < ke;
+            cj[h] = ok ? so.col[k] : 0;
+            kv[h] = ok ? so.K[k] : 0.f;
+            mv[h] = ok ? so.M[k] : 0.f;
+        }
+        float2 xv[NB][CPL];
+#pragma unroll
+        for (int q = 0; q < NB; ++q) {
+            const int j = __shfl(cj[q / LPR], q % LPR, LPR);
+            const bool ok = kb + q < ke;
+            const float2* tr = T + (size_t)j * C + l * CPL;
+#pragma unroll
+            for (int u = 0; u < CPL; ++u) xv[q][u] = (ok && live[u]) ? tr[u] : f2(0.f, 0.f);
+        }
+#pragma unroll
+        for (int q = 0; q < NB; ++q) {
+            const float kq = __shfl(kv[q / LPR], q % LPR, LPR);
+            const float mq = __shfl(mv[q / LPR], q % LPR, LPR);
+#pragma unroll
+            for (int u = 0; u < CPL; ++u) {
+                ak[u].x += kq * xv[q][u].x; ak[u].y += kq * xv[q][u].y;
+                am[u].x += mq * xv[q][u].x; am[u].y += mq * xv[q][u].y;
+            }
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < CPL; ++u) {
+        const int c = l * CPL + u;
+        if (!live[u]) continue;
+        const ColState& S = st[c];
+        const size_t o = (size_t)i * C + c;
+        float2 pv = P[o];
+        if (S.stepped) {
+            const float bx = (float)S.beta.x, by = (float)S.beta.y;
+            const float2 rv = R[o];
+            pv = f2(rv.x + bx * pv.x - by * pv.y, rv.y + bx * pv.y + by * pv.x);
+            P[o] = pv;
+        }
+        const double wmu = op.wmu[c];
+        const float2 sv = f2(ak[u].x + (float)wmu * am[u].y, ak[u].y - (float)wmu * am[u].x);
+        const double dr = dgp.x, di = -wmu * dgp.y;
+        const double inv = 1.0 / (dr * dr + di * di);
+        const float2 dinv = f2((float)(dr * inv), (float)(-di * inv));
+        const float2 t = cmulf(f2(omega * (pv.x - sv.x), omega * (pv.y - sv.y)), dinv);
+        T[o] = t;
+    }
+}
+
 // Start of an Eisenstat inner solve, after y = L1^-1 r0 (the forward sweep
 // into Y): r = D~ y, p = r; partials r^T y (= r^T D~^-1 r, rho) and
 // sum |r_i|^2 / |D~_i| (the squared norm of the split residual).
@@ -1477,23 +1558,6 @@ k_eis_update(Op op, int CP, const ColState* __restrict__ st, const float2* __res
     }
 }
 
-// p = r + beta p for the columns still active after the beta step.
-__global__ void __launch_bounds__(256)
-k_eis_pupdate(Op op, int CP, const ColState* __restrict__ st, const float2* __restrict__ R, float2* __restrict__ P) {
-    const int tile = tile_of(op, blockIdx.x), C = op.C;
-    const int c = threadIdx.x % CP, slot = threadIdx.x / CP, RPB = 256 / CP;
-    if (c >= C) return;
-    const ColState& S = st[c];
-    if (!S.stepped || !S.active) return;
-    const float bx = (float)S.beta.x, by = (float)S.beta.y;
-    for (int r0 = 0; r0 < kTR; r0 += RPB) {
-        const int i = tile * kTR + r0 + slot;
-        if (i >= op.nrow_valid) break;
-        const size_t o = (size_t)i * C + c;
-        const float2 r = R[o], p = P[o];
-        P[o] = f2(r.x + bx * p.x - by * p.y, r.y + bx * p.y + by * p.x);
-    }
-}
 
 // {Kd, Md} of each listed row of the multicolour order
 __global__ void k_ssor_dg(int n, const int32_t* __restrict__ row, const double* __restrict__ Kd,
@@ -2636,6 +2700,28 @@ int eis_slots(const Ssor& Q, int C) {
     return n;
 }
 
+// The Eisenstat U pass with the direction update (k_ssor_eis_u), colours
+// descending.
+void eis_upass(const Ssor& Q, const Op& op, const ColState* st, const float2* R, float2* P, float2* T, float omega,
+               hipStream_t s) {
+    const int C = op.C;
+    const SsorOp so{Q.row, Q.urp, Q.ucol, Q.uK, Q.uM, Q.dg};
+    for (int k = 0; k < Q.nc; ++k) {
+        const int c = Q.nc - 1 - k;
+        const int p0 = Q.cptr[c], p1 = Q.cptr[c + 1];
+        if (p1 <= p0) continue;
+#define PG_SU(L, PP) hipLaunchKernelGGL((k_ssor_eis_u<L, PP>), dim3(ceil_div(p1 - p0, 256 / L)), dim3(256), 0, s, \
+                                        op, so, p0, p1, st, R, P, T, omega);
+        if (C <= 8) PG_SU(8, 1)
+        else if (C <= 16) PG_SU(16, 1)
+        else if (C <= 32) PG_SU(32, 1)
+        else if (C <= 64) PG_SU(64, 1)
+        else if (C <= 128) PG_SU(64, 2)
+        else PG_SU(64, 4)
+#undef PG_SU
+    }
+}
+
 template <typename K, typename... Args>
 void launch_timed(K kernel, dim3 grid, hipStream_t s, hipEvent_t e0, hipEvent_t e1, Args... args);
 
@@ -3242,7 +3328,7 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
             return;
         }
         if (eis) {
-            ssor_pass(*sq, opi, w->st, w->P, w->Z, omega, true, false, s);   // t = U1^-1 p (into Z)
+            eis_upass(*sq, opi, w->st, w->R, w->P, w->Z, omega, s);   // p = r + beta p; t = U1^-1 p (into Z)
             eis_lpass(*sq, opi, w->st, w->P, w->Z, w->Q, omega, w->pe, s, prof ? &evs : nullptr);   // y, p^T (t + y)
             hipLaunchKernelGGL(k_reduce, dim3(nsc), dim3(1024), 0, s, op, (const double2*)w->pe, ppE,
                                (const double2*)nullptr, 1, w->st, (int)RED_ALPHA, 0);
@@ -3250,9 +3336,7 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
                                (const float2*)w->Z, (const float2*)w->Q, w->R, w->Xi, omega, w->p1, w->p2);
             hipLaunchKernelGGL(k_reduce, dim3(nsc), dim3(1024), 0, s, op, (const double2*)w->p1, 1,
                                (const double2*)w->p2, 1, w->st, (int)RED_BETA, 0);
-            hipLaunchKernelGGL(k_eis_pupdate, dim3(opi.nlaunch), dim3(256), 0, s, opi, CP, (const ColState*)w->st,
-                               (const float2*)w->R, w->P);
-            return;
+            return;   // p = r + beta p in the next iteration's U pass
         }
         spmm_dispatch<float, 1>(ch, opi, w->st, ev_pair(SpmmArgs{w->P, nullptr, w->Q, w->p0}), s);
         if (in_consumer) {
