@@ -72,9 +72,9 @@ MEASURED_TRAFFIC = {
         (1296681.7 * 2.0 + 435268.0) * 1024,
     "k_spmm_g<float, 8, 2, 20, 1> complex64 CSR, row entries over the lanes (K, M_sigma) @cfg3":
         (1779690.6 * 2.0 + 871820.1) * 1024,
-    # its 16-column SSOR blocks in Eisenstat's form: the L sweep, per colour launch
-    "k_ssor_eis<16, 1> complex64 Eisenstat L sweep, one colour per launch (K, M_sigma) @cfg3":
-        (557897.3 * 2.0 + 123910.2) * 1024,
+    # its 16-column SSOR blocks in Eisenstat's form: the U sweep, per colour launch
+    "k_ssor_eis_u<16, 1> complex64 Eisenstat U sweep with the direction update, one colour per launch "
+    "(K, M_sigma) @cfg3": (531322.0 * 2.0 + 244225.6) * 1024,
 }
 RTOL = 1e-9
 # the high-frequency models of the uneven batch (f up to 2 Hz, receivers 4 km
@@ -105,24 +105,24 @@ def spmm_bytes_fp32(n: int, nnz: int, cols: int, shape: int = 0) -> int:
     return 12 * nnz + n * (4 + 16 * cols + extra)
 
 
-def eis_lpass_bytes(S, cols: int) -> int:
-    """Algorithmic bytes of one launch of the Eisenstat L pass (one colour of
+def eis_upass_bytes(S, cols: int) -> int:
+    """Algorithmic bytes of one launch of the Eisenstat U pass (one colour of
     the multicolour SSOR; averaged over the colours): per entry coupling a
-    row to an earlier colour its column, K and M_sigma (4 + 4 + 4); per row
-    its position, its L range (4 + 4) and the two double diagonals (16); p
-    and t read and y written, 8 per row and column; and each row of y that
-    the colour's rows gather from earlier colours once, 8 per column."""
+    row to a later colour its column, K and M_sigma (4 + 4 + 4); per row its
+    position, its U range (4 + 4) and the two double diagonals (16); r and p
+    read, p and t written, 8 per row and column; and each row of t that the
+    colour's rows gather from later colours once, 8 per column."""
     rp, col, _, _ = S.csr()
     color = S.ssor_colors()
     n = len(rp) - 1
     cr = np.repeat(color, np.diff(rp))
     cc = color[col]
-    low = cc < cr
-    nl = int(low.sum())
+    up = cc > cr
+    nu = int(up.sum())
     gathered = 0
     for c in range(int(color.max()) + 1):
-        gathered += int(np.unique(col[low & (cr == c)]).size)
-    total = 12 * nl + n * (4 + 4 + 16) + 3 * n * cols * 8 + gathered * cols * 8
+        gathered += int(np.unique(col[up & (cr == c)]).size)
+    total = 12 * nu + n * (4 + 4 + 16) + 4 * n * cols * 8 + gathered * cols * 8
     return total // (int(color.max()) + 1)
 
 
@@ -173,7 +173,8 @@ def kernel_name(form, shape):
         return f"k_spmv<{shape}, false> complex128 CSR (A D^-1)"
     kind, a, b = shape // 10000, (shape // 100) % 100, shape % 100
     if kind == 7:
-        return f"k_ssor_eis<{a}, {b}> complex64 Eisenstat L sweep, one colour per launch (K, M_sigma)"
+        return (f"k_ssor_eis_u<{a}, {b}> complex64 Eisenstat U sweep with the direction update, one colour per "
+                f"launch (K, M_sigma)")
     if kind == 5:
         return f"k_spmm_spbs<{b}> complex64 pipelined sliced ELLPACK with beta partials, per mesh (K, M_sigma)"
     if kind == 4:
@@ -401,8 +402,8 @@ def bench_cfg3(args, petgem, synth, torch):
     n_launch = sum(o[1][0]["spmv_launches"] for o in outs)
     avg_ms = sum(o[1][0]["spmv_ms"] for o in outs) / n_launch if n_launch else float("nan")
     shape = outs[-1][1][0]["spmv_shape"]
-    # the profiled kernel: the SpMM, or in Eisenstat's form (no SpMM) its L sweep
-    nbytes = eis_lpass_bytes(S, B) if shape // 10000 == 7 else spmm_bytes_fp32(S.n_dof, S.nnz, B, shape)
+    # the profiled kernel: the SpMM, or in Eisenstat's form (no SpMM) its U sweep
+    nbytes = eis_upass_bytes(S, B) if shape // 10000 == 7 else spmm_bytes_fp32(S.n_dof, S.nnz, B, shape)
     achieved = nbytes / (avg_ms * 1e-3) / 1e9 if n_launch else None
     kname = kernel_name("mixed", shape)
     # accuracy: every solve converged to RTOL_CFG3 (gate above) and the sources with

@@ -164,9 +164,10 @@ typedef struct {
                                uneven batch (or of a mesh with too many
                                tiles for kind 4) runs for a tuned shape;
                                7 = no SpMM: Eisenstat's form of an SSOR
-                               block of more than four columns, whose L
-                               sweep (a lanes per row, b columns per lane)
-                               the profile times instead;
+                               block of more than four columns, whose U
+                               sweep (with the direction update; a lanes
+                               per row, b columns per lane) the profile
+                               times instead;
                                GMRES: the lanes per row of the complex128
                                CSR SpMV                                         */
     double  b_norm;         /* |b|_2 of the source's right-hand side            */

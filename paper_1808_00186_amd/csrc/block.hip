@@ -2700,18 +2700,30 @@ int eis_slots(const Ssor& Q, int C) {
     return n;
 }
 
+template <typename K, typename... Args>
+void launch_timed(K kernel, dim3 grid, hipStream_t s, hipEvent_t e0, hipEvent_t e1, Args... args);
+
 // The Eisenstat U pass with the direction update (k_ssor_eis_u), colours
-// descending.
+// descending. evs (or null): every launch timestamps its start and end into
+// a new pair of events appended there (the profile of the solve; this pass
+// has the largest total time of the iteration).
 void eis_upass(const Ssor& Q, const Op& op, const ColState* st, const float2* R, float2* P, float2* T, float omega,
-               hipStream_t s) {
+               hipStream_t s, std::vector<hipEvent_t>* evs) {
     const int C = op.C;
     const SsorOp so{Q.row, Q.urp, Q.ucol, Q.uK, Q.uM, Q.dg};
     for (int k = 0; k < Q.nc; ++k) {
         const int c = Q.nc - 1 - k;
         const int p0 = Q.cptr[c], p1 = Q.cptr[c + 1];
         if (p1 <= p0) continue;
-#define PG_SU(L, PP) hipLaunchKernelGGL((k_ssor_eis_u<L, PP>), dim3(ceil_div(p1 - p0, 256 / L)), dim3(256), 0, s, \
-                                        op, so, p0, p1, st, R, P, T, omega);
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (evs) {
+            (void)hipEventCreate(&e0);
+            (void)hipEventCreate(&e1);
+            evs->push_back(e0);
+            evs->push_back(e1);
+        }
+#define PG_SU(L, PP) launch_timed((k_ssor_eis_u<L, PP>), dim3(ceil_div(p1 - p0, 256 / L)), s, e0, e1, op, so, \
+                                  p0, p1, st, R, P, T, omega);
         if (C <= 8) PG_SU(8, 1)
         else if (C <= 16) PG_SU(16, 1)
         else if (C <= 32) PG_SU(32, 1)
@@ -2722,29 +2734,19 @@ void eis_upass(const Ssor& Q, const Op& op, const ColState* st, const float2* R,
     }
 }
 
-template <typename K, typename... Args>
-void launch_timed(K kernel, dim3 grid, hipStream_t s, hipEvent_t e0, hipEvent_t e1, Args... args);
-
 // The Eisenstat L pass (k_ssor_eis), colours ascending, block partials into
-// part in launch order. evs (or null): every launch timestamps its start and
-// end into a new pair of events appended there (the profile of the solve).
+// part in launch order.
 void eis_lpass(const Ssor& Q, const Op& op, const ColState* st, const float2* P, const float2* T, float2* Y,
-               float omega, double2* part, hipStream_t s, std::vector<hipEvent_t>* evs) {
+               float omega, double2* part, hipStream_t s) {
     const int C = op.C;
     const SsorOp so{Q.row, Q.lrp, Q.lcol, Q.lK, Q.lM, Q.dg};
     int base = 0;
     for (int c = 0; c < Q.nc; ++c) {
         const int p0 = Q.cptr[c], p1 = Q.cptr[c + 1];
         if (p1 <= p0) continue;
-        hipEvent_t e0 = nullptr, e1 = nullptr;
-        if (evs) {
-            (void)hipEventCreate(&e0);
-            (void)hipEventCreate(&e1);
-            evs->push_back(e0);
-            evs->push_back(e1);
-        }
 #define PG_SE(L, PP) { const int nb = eis_blocks(p1 - p0, C); \
-        launch_timed((k_ssor_eis<L, PP>), dim3(nb), s, e0, e1, op, so, p0, p1, st, P, T, Y, omega, part, base); \
+        hipLaunchKernelGGL((k_ssor_eis<L, PP>), dim3(nb), dim3(256), 0, s, op, so, p0, p1, st, P, T, Y, omega, \
+                           part, base); \
         base += nb; }
         if (C <= 8) PG_SE(8, 1)
         else if (C <= 16) PG_SE(16, 1)
@@ -3328,8 +3330,9 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
             return;
         }
         if (eis) {
-            eis_upass(*sq, opi, w->st, w->R, w->P, w->Z, omega, s);   // p = r + beta p; t = U1^-1 p (into Z)
-            eis_lpass(*sq, opi, w->st, w->P, w->Z, w->Q, omega, w->pe, s, prof ? &evs : nullptr);   // y, p^T (t + y)
+            // p = r + beta p; t = U1^-1 p (into Z)
+            eis_upass(*sq, opi, w->st, w->R, w->P, w->Z, omega, s, prof ? &evs : nullptr);
+            eis_lpass(*sq, opi, w->st, w->P, w->Z, w->Q, omega, w->pe, s);   // y (into Q), p^T (t + y)
             hipLaunchKernelGGL(k_reduce, dim3(nsc), dim3(1024), 0, s, op, (const double2*)w->pe, ppE,
                                (const double2*)nullptr, 1, w->st, (int)RED_ALPHA, 0);
             hipLaunchKernelGGL(k_eis_update, dim3(opi.nlaunch), dim3(256), 0, s, opi, CP, (const ColState*)w->st,
