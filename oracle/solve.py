@@ -107,6 +107,16 @@ def gmres(A: sp.csr_matrix, b: np.ndarray, rtol: float = 1e-12, restart: int = 6
         x = x + dinv * (V[:m].T @ y)
 
 
+def _one_blas_thread():
+    """One BLAS thread for the enclosed calls (arithmetic unchanged)."""
+    try:
+        from threadpoolctl import threadpool_limits
+        return threadpool_limits(limits=1, user_api="blas")
+    except ImportError:   # pragma: no cover - the limit is only a speed matter
+        import contextlib
+        return contextlib.nullcontext()
+
+
 def solve_system(A: sp.csr_matrix, b: np.ndarray, rtol: float = 1e-12, progress: int = 0):
     """Dense LU up to 6000 unknowns, sparse LU up to 60000, GMRES above.
     Returns (x, true relative residual, method)."""
@@ -116,10 +126,15 @@ def solve_system(A: sp.csr_matrix, b: np.ndarray, rtol: float = 1e-12, progress:
         x = np.linalg.solve(A.toarray(), b)
         method = "dense"
     elif n <= 60000:
-        x = spla.spsolve(A.tocsc(), b)
+        # SuperLU's dense kernels are small: one BLAS thread (several spin
+        # against each other and slow the factorisation down many times
+        # whenever other work shares the cores)
+        with _one_blas_thread():
+            x = spla.spsolve(A.tocsc(), b)
         method = "splu"
     else:
-        x, _, _ = gmres(A, b, rtol=rtol, progress=progress)
+        with _one_blas_thread():   # the row-block products have their own threads
+            x, _, _ = gmres(A, b, rtol=rtol, progress=progress)
         method = "gmres"
     res = np.linalg.norm(b - A @ x) / bn if bn > 0 else 0.0
     return x, res, method
