@@ -636,15 +636,25 @@ def sync_costs(args, petgem):
 def copy_calibration(args, torch):
     """A plain device copy of a known size (1 GiB read + 1 GiB written per
     launch): the FETCH_SIZE / WRITE_SIZE counters of this kernel give the
-    factor that turns the counters of the solver kernels into HBM bytes."""
+    factor that turns the counters of the solver kernels into HBM bytes. Its
+    rate (HIP events around each launch, on the stream the copy runs on) is
+    the streaming rate a plain kernel reaches, beside the 8 TB/s peak."""
     n = 1 << 30
     a = torch.empty(n, dtype=torch.uint8, device="cuda").fill_(1)
     b = torch.empty_like(a)
+    ev = []
     for _ in range(args.steps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
         b.copy_(a)
+        e1.record()
+        ev.append((e0, e1))
     torch.cuda.synchronize()
+    ms = [e0.elapsed_time(e1) for e0, e1 in ev]
+    best = min(ms[1:] if len(ms) > 1 else ms)
     return {"metric": "copy calibration", "bytes_read_per_launch": n, "bytes_written_per_launch": n,
-            "launches": args.steps}
+            "launches": args.steps, "ms_per_launch": ms,
+            "best_rate_GBps": 2 * n / (best * 1e-3) / 1e9}
 
 
 def main():

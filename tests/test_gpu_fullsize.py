@@ -81,29 +81,31 @@ def test_cfg3_sampled_rows_rhs_and_residual(pg):
 GOLDEN = __import__("os").path.join(__import__("os").path.dirname(__file__), "golden")
 
 
-@pytest.mark.parametrize("block,precond", [(32, "jacobi"), (8, "ssor")])
-def test_cfg3_block_matches_stored_oracle(pg, block, precond):
-    """The 6.9M-unknown survey at 1.25 Hz against the oracle's receiver fields
-    (Jacobi GMRES(60) to 1e-12, tests/golden/cfg3_f1.25_i*.npz, written by the
-    oracle only): the frequency's 32-column block (x = -3100 ... 3100 m, the
-    shape the survey's sources take as one block) with Jacobi, and the batch of
-    8 dipoles holding the centre one with multicolour SSOR, both in mixed
-    precision at a true residual of 1e-12 (the end dipole's receivers 7.1 km
-    away need it: at 1e-9 their error is 2.8e-4); every column with stored
-    fields must match them within 1e-6."""
+@pytest.mark.parametrize("block,precond,freq", [(32, "jacobi", 1.25), (16, "ssor", 1.25), (16, "ssor", 0.5)])
+def test_cfg3_block_matches_stored_oracle(pg, block, precond, freq):
+    """The 6.9M-unknown survey against the oracle's receiver fields (Jacobi
+    GMRES(60) to 1e-12, tests/golden/cfg3_f<freq>_i*.npz, written by the oracle
+    only), in mixed precision at a true residual of 1e-12 (the end dipole's
+    receivers 7.1 km away need it: at 1e-9 their error is 2.8e-4):
+    * at 1.25 Hz the frequency's 32-column block (x = -3100 ... 3100 m, the
+      shape the survey's sources take as one block) with Jacobi;
+    * at 1.25 and 0.5 Hz the 16-column block holding the centre dipole with
+      multicolour SSOR in Eisenstat's form, the blocks and kernels of the
+      survey benchmark's steps.
+    Every column with stored fields must match them within 1e-6."""
     import os
     m = synth.config3()
-    k0 = synth.CFG3_FREQS.index(1.25) * 32
+    k0 = synth.CFG3_FREQS.index(freq) * 32
     first = 0 if block == 32 else 16
     srcs = m.sources[k0 + first:k0 + first + block]
     golds = {}
     for i in range(first, first + block):
-        p = os.path.join(GOLDEN, f"cfg3_f1.25_i{i}.npz")
+        p = os.path.join(GOLDEN, f"cfg3_f{freq:g}_i{i}.npz")
         if os.path.exists(p):
             golds[i - first] = np.load(p)
     if not golds:
         pytest.skip("stored oracle fields missing")
-    print(f"[case] cfg3 1.25 Hz block of {block}, {precond}", flush=True)
+    print(f"[case] cfg3 {freq} Hz block of {block}, {precond}", flush=True)
     S = pg.System.from_model(m)
     o = pg.default_opts(method=pg.COCG, precision=pg.MIXED, rtol=1e-12,
                         precond=pg.SSOR if precond == "ssor" else pg.JACOBI)
