@@ -331,6 +331,60 @@ k_reduce(Op op, const double2* __restrict__ p0, int pp0, const double2* __restri
     apply_red(S, mode, first, a, b);
 }
 
+// One block per column of one system, on partials stored column by column
+// (column c's n0 slots from p0 + c * s0, likewise p1): fixed-order sums, then
+// the scalar step of that column. A block reads only its own column's slots,
+// contiguously; k_reduce's row-major slots would cost it a cache line per
+// 16-byte partial.
+__global__ void __launch_bounds__(1024)
+k_reduce_cm(const double2* __restrict__ p0, int n0, int64_t s0, const double2* __restrict__ p1, int n1, int64_t s1,
+            ColState* __restrict__ st, int mode) {
+    __shared__ double2 sa[16], sb[16];
+    const int c = blockIdx.x;
+    ColState& S = st[c];
+    if (red_skips(S, mode, 0)) {
+        if (mode == RED_BETA && threadIdx.x == 0) S.stepped = 0;   // inactive: no alpha was applied
+        return;
+    }
+    double2 a = make_double2(0.0, 0.0), b = make_double2(0.0, 0.0);
+    {
+        const double2* q = p0 + (size_t)c * s0;
+        for (int e = threadIdx.x; e < n0; e += 1024 * 8) {
+            double2 v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int k = e + 1024 * u;
+                v[u] = k < n0 ? q[k] : make_double2(0.0, 0.0);
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) a = cadd(a, v[u]);
+        }
+    }
+    if (p1) {
+        const double2* q = p1 + (size_t)c * s1;
+        for (int e = threadIdx.x; e < n1; e += 1024 * 8) {
+            double2 v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int k = e + 1024 * u;
+                v[u] = k < n1 ? q[k] : make_double2(0.0, 0.0);
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) b = cadd(b, v[u]);
+        }
+    }
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    a.x = wave_sum(a.x); a.y = wave_sum(a.y);
+    b.x = wave_sum(b.x); b.y = wave_sum(b.y);
+    if (lane == 0) { sa[wave] = a; sb[wave] = b; }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    a = sa[0];
+    b = sb[0];
+    for (int k = 1; k < 16; ++k) { a = cadd(a, sa[k]); b = cadd(b, sb[k]); }
+    apply_red(S, mode, 0, a, b);
+}
+
 // ------------------------------------------------------------------ SpMM
 // EPI 2: Y = B - A X in the template type and partial[..][c].x = sum_i |Y_ic|^2.
 // EPI 1: Y = A X and partial[..][c] = sum_i X_ic Y_ic (unconjugated).
@@ -1302,13 +1356,14 @@ k_ssor_c(Op op, SsorOp so, int p0, int p1, const ColState* __restrict__ st, cons
 // In the variables used here (p = D~^1/2 p^, r = D~^1/2 r^) the scalars are
 //   p^T q, rho = r^T D~^-1 r, r -= alpha D~ q, x += alpha t, p = r + beta p,
 // and x is the correction itself (the sum of alpha U1^-1 p). This kernel also
-// leaves the block's partial sums of p^T (t + y) per column in part[base +
-// block] (rows of a colour: no early exit, every thread reaches the barrier).
+// leaves the block's partial sums of p^T (t + y), column c's at part[c * cs +
+// base + block] (rows of a colour: no early exit, every thread reaches the
+// barrier).
 template <int LPR, int CPL>
 __global__ void __launch_bounds__(256)
 k_ssor_eis(Op op, SsorOp so, int p0, int p1, const ColState* __restrict__ st, const float2* __restrict__ P,
            const float2* __restrict__ T, float2* __restrict__ Y, float omega, double2* __restrict__ part,
-           int base) {
+           int base, int64_t cs) {
     constexpr int RPB = 256 / LPR;
     constexpr int NB = 12;
     constexpr int NH = (NB + LPR - 1) / LPR;
@@ -1397,7 +1452,7 @@ k_ssor_eis(Op op, SsorOp so, int p0, int p1, const ColState* __restrict__ st, co
     for (int c = threadIdx.x; c < C && c < LPR * CPL; c += 256) {
         double2 a = make_double2(0.0, 0.0);
         for (int r = 0; r < RPB; ++r) a = cadd(a, red[r][c]);
-        part[(size_t)(base + blockIdx.x) * C + c] = a;
+        part[(size_t)c * cs + base + blockIdx.x] = a;
     }
 }
 
@@ -1516,11 +1571,13 @@ k_eis_init(Op op, int CP, const ColState* __restrict__ st, const float2* __restr
 }
 
 // The Eisenstat step after alpha: x += alpha t, r -= alpha D~ (t + y);
-// partials rho' = r^T D~^-1 r and sum |r_i|^2 / |D~_i|.
+// partials rho' = r^T D~^-1 r and sum |r_i|^2 / |D~_i|, column by column
+// (column c's of tile t at c * ntiles + t).
 __global__ void __launch_bounds__(256)
 k_eis_update(Op op, int CP, const ColState* __restrict__ st, const float2* __restrict__ T,
              const float2* __restrict__ Y, float2* __restrict__ R, float2* __restrict__ Xi, float omega,
              double2* __restrict__ p0, double2* __restrict__ p1) {
+    const int64_t cs = op.ntiles;   // the partials column by column
     __shared__ double2 ra[256], rb[256];
     const int tile = tile_of(op, blockIdx.x), C = op.C;
     const int c = threadIdx.x % CP, slot = threadIdx.x / CP, RPB = 256 / CP;
@@ -1553,8 +1610,8 @@ k_eis_update(Op op, int CP, const ColState* __restrict__ st, const float2* __res
     }
     cp_sum2(a, b, CP, ra, rb);
     if ((int)threadIdx.x < C && (int)threadIdx.x < CP) {
-        p0[(size_t)tile * C + threadIdx.x] = ra[threadIdx.x];
-        p1[(size_t)tile * C + threadIdx.x] = rb[threadIdx.x];
+        p0[(size_t)threadIdx.x * cs + tile] = ra[threadIdx.x];
+        p1[(size_t)threadIdx.x * cs + tile] = rb[threadIdx.x];
     }
 }
 
@@ -2734,10 +2791,10 @@ void eis_upass(const Ssor& Q, const Op& op, const ColState* st, const float2* R,
     }
 }
 
-// The Eisenstat L pass (k_ssor_eis), colours ascending, block partials into
-// part in launch order.
+// The Eisenstat L pass (k_ssor_eis), colours ascending, block partials in
+// launch order, column c's from part + c * cs.
 void eis_lpass(const Ssor& Q, const Op& op, const ColState* st, const float2* P, const float2* T, float2* Y,
-               float omega, double2* part, hipStream_t s) {
+               float omega, double2* part, int64_t cs, hipStream_t s) {
     const int C = op.C;
     const SsorOp so{Q.row, Q.lrp, Q.lcol, Q.lK, Q.lM, Q.dg};
     int base = 0;
@@ -2746,7 +2803,7 @@ void eis_lpass(const Ssor& Q, const Op& op, const ColState* st, const float2* P,
         if (p1 <= p0) continue;
 #define PG_SE(L, PP) { const int nb = eis_blocks(p1 - p0, C); \
         hipLaunchKernelGGL((k_ssor_eis<L, PP>), dim3(nb), dim3(256), 0, s, op, so, p0, p1, st, P, T, Y, omega, \
-                           part, base); \
+                           part, base, cs); \
         base += nb; }
         if (C <= 8) PG_SE(8, 1)
         else if (C <= 16) PG_SE(16, 1)
@@ -3155,11 +3212,17 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
         dinv = w->Dinv;
     }
     // SSOR with more than four columns: Eisenstat's form (no product with A
-    // in the iteration); its L pass leaves one partial slot per block, summed
-    // by the alpha reduction as ppE slots per tile (the unused ones zero)
+    // in the iteration); its L pass leaves one partial slot per block and
+    // column, ntiles * ppE slots per column (the unused ones zero), and its
+    // two reductions read their partials column by column (k_reduce_cm)
     const bool eis = ssor && C > 4;
-    int ppE = 0;
+    int ppE = 0, neis = 0;
     if (eis) {
+        if (op.nseg != 1) {
+            set_error("multicolour SSOR: one system only");
+            return PETGEM_INVALID_ARG;
+        }
+        neis = eis_slots(*sq, C);
         ppE = ceil_div(eis_slots(*sq, C), op.ntiles);
         const size_t need = (size_t)op.ntiles * ppE * C;
         if (w->pe_cap < need) {
@@ -3332,13 +3395,15 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
         if (eis) {
             // p = r + beta p; t = U1^-1 p (into Z)
             eis_upass(*sq, opi, w->st, w->R, w->P, w->Z, omega, s, prof ? &evs : nullptr);
-            eis_lpass(*sq, opi, w->st, w->P, w->Z, w->Q, omega, w->pe, s);   // y (into Q), p^T (t + y)
-            hipLaunchKernelGGL(k_reduce, dim3(nsc), dim3(1024), 0, s, op, (const double2*)w->pe, ppE,
-                               (const double2*)nullptr, 1, w->st, (int)RED_ALPHA, 0);
+            const int64_t cse = (int64_t)op.ntiles * ppE;
+            eis_lpass(*sq, opi, w->st, w->P, w->Z, w->Q, omega, w->pe, cse, s);   // y (into Q), p^T (t + y)
+            hipLaunchKernelGGL(k_reduce_cm, dim3(C), dim3(1024), 0, s, (const double2*)w->pe, neis, cse,
+                               (const double2*)nullptr, 0, (int64_t)0, w->st, (int)RED_ALPHA);
             hipLaunchKernelGGL(k_eis_update, dim3(opi.nlaunch), dim3(256), 0, s, opi, CP, (const ColState*)w->st,
                                (const float2*)w->Z, (const float2*)w->Q, w->R, w->Xi, omega, w->p1, w->p2);
-            hipLaunchKernelGGL(k_reduce, dim3(nsc), dim3(1024), 0, s, op, (const double2*)w->p1, 1,
-                               (const double2*)w->p2, 1, w->st, (int)RED_BETA, 0);
+            hipLaunchKernelGGL(k_reduce_cm, dim3(C), dim3(1024), 0, s, (const double2*)w->p1, op.ntiles,
+                               (int64_t)op.ntiles, (const double2*)w->p2, op.ntiles, (int64_t)op.ntiles, w->st,
+                               (int)RED_BETA);
             return;   // p = r + beta p in the next iteration's U pass
         }
         spmm_dispatch<float, 1>(ch, opi, w->st, ev_pair(SpmmArgs{w->P, nullptr, w->Q, w->p0}), s);
