@@ -109,7 +109,8 @@ typedef struct {
     int32_t use_graph;      /* replay captured HIP graphs for the Krylov loop   */
     int32_t profile;        /* time the sparse-matrix kernels with HIP events   */
     int32_t verbose;        /* print one progress line per refinement step or
-                               per 10 GMRES cycles to stderr                    */
+                               per 10 GMRES cycles to stderr; 2 (mixed COCG):
+                               also one line per column and refinement step    */
     int32_t spmm_shape;     /* COCG: 0 = autotune the complex64 SpMM shape;
                                otherwise that shape, encoded as the
                                spmv_shape statistic (PETGEM_INVALID_ARG if it

@@ -3629,6 +3629,15 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
             fprintf(stderr, "[petgem] COCG refinement step %d: %d inner iterations, worst true residual "
                             "%.3e, %d of %d columns left, %d inner solves stopped by the stagnation guard, "
                             "%.0f ms\n", steps, inner, worst, left, nsc, stalls, t_all.ms());
+            if (o.verbose >= 2)   // each column's inner solve of this step
+                for (int k = 0; k < nsc; ++k) {
+                    const ColState& S = w->st_h[k];
+                    const double r0 = S.rn2_0 > 0.0 ? S.rn2_0 : 1.0;
+                    fprintf(stderr, "[petgem]     column %d: %d inner iterations, best %.2e at %d, last %.2e, "
+                                    "true residual %.3e, stops by the guards so far %d\n", k, S.kin,
+                            std::sqrt(S.rn2_best / r0), S.k_best, std::sqrt(S.rn2 / r0),
+                            S.bnorm > 0 ? S.rnorm64 / S.bnorm : 0.0, S.stalled);
+                }
             fflush(stderr);
         }
     }
