@@ -81,7 +81,8 @@ def test_cfg3_sampled_rows_rhs_and_residual(pg):
 GOLDEN = __import__("os").path.join(__import__("os").path.dirname(__file__), "golden")
 
 
-@pytest.mark.parametrize("block,precond,freq", [(32, "jacobi", 1.25), (16, "ssor", 1.25), (16, "ssor", 0.5)])
+@pytest.mark.parametrize("block,precond,freq", [(32, "jacobi", 1.25), (16, "ssor", 1.25), (16, "ssor", 0.5),
+                                                  (16, "ssor", 0.25)])
 def test_cfg3_block_matches_stored_oracle(pg, block, precond, freq):
     """The 6.9M-unknown survey against the oracle's receiver fields (Jacobi
     GMRES(60) to 1e-12, tests/golden/cfg3_f<freq>_i*.npz, written by the oracle
@@ -89,9 +90,9 @@ def test_cfg3_block_matches_stored_oracle(pg, block, precond, freq):
     receivers 7.1 km away need it: at 1e-9 their error is 2.8e-4):
     * at 1.25 Hz the frequency's 32-column block (x = -3100 ... 3100 m, the
       shape the survey's sources take as one block) with Jacobi;
-    * at 1.25 and 0.5 Hz the 16-column block holding the centre dipole with
-      multicolour SSOR in Eisenstat's form, the blocks and kernels of the
-      survey benchmark's steps.
+    * at 1.25, 0.5 and 0.25 Hz the 16-column block holding the centre dipole
+      with multicolour SSOR in Eisenstat's form, the blocks and kernels of
+      the survey benchmark's steps.
     Every column with stored fields must match them within 1e-6."""
     import os
     m = synth.config3()
