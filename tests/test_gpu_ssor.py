@@ -12,6 +12,9 @@ definition (oracle/precond.py). Marked `gpu`.
   relaxation factors, receivers within 1e-6 of the oracle at 1e-8, in fewer
   iterations than with Jacobi; and the 433,720-unknown marine model against
   its stored oracle fields at 1e-9.
+* Every lane shape of Eisenstat's form (more than four columns): 8, 32 and
+  64 lanes per row, the last with one, two and four columns per lane, exact
+  fits and ragged tails, each column against the oracle.
 """
 import os
 
@@ -115,3 +118,39 @@ def test_cocg_ssor_cfg2_matches_stored_oracle(pg):
           f"rx err {err:.2e} solve {st[0]['t_solve_ms']:.1f} ms", flush=True)
     assert rc == pg.OK and st[0]["rel_residual"] <= 1e-9
     assert err <= 1e-6
+
+
+@pytest.fixture(scope="module")
+def eis_pool():
+    """200 sources on the small model (67 positions along x, each at 0.5, 1.5
+    and 3 Hz, position-major) and the oracle's receiver fields of each."""
+    m = synth.config1()
+    xs = np.linspace(-400.0, 400.0, 67)
+    srcs = [synth.Dipole((float(x), 0.0, 300.0), f) for x in xs for f in (0.5, 1.5, 3.0)][:200]
+    s = fem.assemble(m.xyz, m.tets, m.sigma)
+    lus, ref = {}, []
+    for d in srcs:
+        if d.freq not in lus:
+            lus[d.freq] = spla.splu(fem.system_matrix(s, d.freq).tocsc())
+        b = fem.rhs(m.xyz, m.tets, m.sigma, m.sigma_bg, s.topo, d.pos, d.dir, d.freq, d.moment)
+        ref.append(fem.receivers_total(m.xyz, m.tets, s.topo, lus[d.freq].solve(b), m.receivers, d.pos, d.dir,
+                                       d.freq, m.sigma_bg, d.moment))
+    return m, srcs, ref
+
+
+# columns -> Eisenstat sweep shape (lanes per row x columns per lane):
+# 6 -> 8 x 1 (ragged), 32 -> 32 x 1 (exact), 64 -> 64 x 1 (exact),
+# 100 -> 64 x 2 (ragged), 200 -> 64 x 4 (ragged)
+@pytest.mark.parametrize("n_src", [6, 32, 64, 100, 200])
+def test_eisenstat_lane_shapes_match_oracle(pg, eis_pool, n_src):
+    m, pool, ref = eis_pool
+    srcs = pool[:n_src]
+    print(f"[case] cfg1 COCG SSOR (Eisenstat's form), {n_src} sources", flush=True)
+    S = pg.System.from_model(m)
+    o = pg.default_opts(method=pg.COCG, precision=pg.MIXED, rtol=1e-8, precond=pg.SSOR)
+    sol, st, rc = S.solve(srcs, o)
+    assert rc == pg.OK and all(s_["rel_residual"] <= 1e-8 for s_ in st)
+    E = sol.receivers(m.receivers).cpu().numpy()
+    errs = [fem.receiver_error(E[k], ref[k]) for k in range(n_src)]
+    print(f"  iters max {max(s_['iters'] for s_ in st)}, receiver error max {max(errs):.1e}", flush=True)
+    assert max(errs) <= 1e-6
