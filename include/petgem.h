@@ -75,6 +75,18 @@ extern "C" {
                              solve then finishes as independent mixed COCG
                              columns from the block's iterate
                              (stats.block_iters)                              */
+#define PETGEM_SQMR    3  /* symmetric QMR, the paper's single-process solver
+                             (Section 5.3, Table 2), with PETGEM_SSOR only:
+                             the COCG recurrence of the preconditioned system
+                             plus the quasi-minimal-residual smoothing of its
+                             iterate, x_Q = (1 - c^2) x_Q + c^2 x with
+                             tau^2 = tau^2 theta^2 c^2, theta = |r| / tau and
+                             c^2 = 1 / (1 + theta^2) (|r| in the norm of the
+                             inner stop test: the split residual's with more
+                             than four sources, the residual's otherwise); each
+                             inner solve stops on tau and hands x_Q to the
+                             refinement. Mixed precision, like COCG; one more
+                             vector (x_Q) is read and written per iteration    */
 #define PETGEM_FP64    0  /* every step in double precision                   */
 #define PETGEM_MIXED   1  /* complex64 Krylov solves inside a double-precision
                              iterative-refinement loop                         */
@@ -99,7 +111,8 @@ typedef struct {
 } petgem_source;
 
 typedef struct {
-    int32_t method;         /* PETGEM_GMRES, PETGEM_COCG or PETGEM_BCOCG        */
+    int32_t method;         /* PETGEM_GMRES, PETGEM_COCG, PETGEM_BCOCG or
+                               PETGEM_SQMR                                      */
     int32_t precision;      /* PETGEM_FP64 or PETGEM_MIXED                      */
     int32_t restart;        /* GMRES restart length, 1..64 (default 30)         */
     int32_t max_iter;       /* total Krylov iterations per source               */

@@ -98,6 +98,11 @@ struct ColState {
     int stepped;       // this iteration's alpha was applied to r (set at the beta step)
     int k_best;        // inner iteration of rn2_best
     int stalled;       // inner steps ended by the stagnation guard (all refinement steps)
+    // symmetric QMR (sqmr): the quasi-minimal-residual smoothing of the iterate
+    double tau2;       // tau^2, the smoothed residual's estimate (same norm as rn2)
+    double cq;         // c^2 of the latest beta step: x_Q = (1 - c^2) x_Q + c^2 x
+    double tmark;      // tau^2 at the last halving of tau (the plateau rule)
+    int sqmr;          // this solve is SQMR
 };
 
 // Stagnation guard of the inner COCG, which has no minimisation property: a
@@ -205,6 +210,54 @@ __device__ __forceinline__ void step_alpha(ColState& S, double2 pq) {
 
 // convergence test on |r|^2 and beta = rho' / rho for an active column
 // (counting the update that produced r)
+// The scalar step of SQMR (Section 5.3 names SQMR with SOR as the paper's
+// single-process solver). Its recurrence is COCG's (rho, beta as in
+// step_beta); the quasi-minimal-residual smoothing of the iterate takes, from
+// the new residual norm |r|^2 = r2, theta^2 = r2 / tau^2, c^2 = 1 / (1 +
+// theta^2) and tau^2 <- tau^2 theta^2 c^2, and the smoothed iterate is
+// x_Q = (1 - c^2) x_Q + c^2 x (written by the update kernels). tau falls
+// monotonically, so the inner solve stops once tau is within the target, or
+// once tau has not halved for as many iterations as its last halving took
+// (at least kPlateauIters). tau bounds the smoothed residual only when the
+// residuals are orthogonal; COCG's are orthogonal in the bilinear form, not
+// in the Euclidean one, and where the unsmoothed residual diverges tau still
+// falls while the smoothed residual does not (a refinement step then gains
+// nothing).
+__device__ __forceinline__ void sqmr_beta(ColState& S, double2 rz, double r2) {
+    S.iters += 1;
+    S.kin += 1;
+    S.rn2 = r2;
+    if (!isfinite(r2) || !cfinite(rz)) {
+        S.active = 0;
+        S.breakdown = 1;
+        return;
+    }
+    const double th2 = S.tau2 > 0.0 ? r2 / S.tau2 : 0.0;
+    const double c2 = 1.0 / (1.0 + th2);
+    S.tau2 = S.tau2 * th2 * c2;
+    S.cq = c2;
+    S.rn2_best = S.tau2;
+    if (S.tau2 <= S.inner_tol2 * S.rn2_0) {
+        S.active = 0;
+        return;
+    }
+    if (S.tau2 <= 0.25 * S.tmark) {
+        S.tmark = S.tau2;
+        S.k_best = S.kin;
+    } else if (S.kin - S.k_best >= max(kPlateauIters, S.k_best)) {
+        S.active = 0;
+        S.stalled += 1;
+        return;
+    }
+    if (czero(S.rho)) {
+        S.active = 0;
+        S.breakdown = 1;
+        return;
+    }
+    S.beta = cdiv(rz, S.rho);
+    S.rho = rz;
+}
+
 __device__ __forceinline__ void step_beta(ColState& S, double2 rz, double r2) {
     S.iters += 1;
     S.kin += 1;
@@ -258,11 +311,15 @@ __device__ void apply_red(ColState& S, int mode, int first, double2 a, double2 b
         S.active = S.outer && cfinite(a) && !czero(a);
         S.breakdown = 0;
         S.stepped = 0;
+        S.tau2 = b.x;                  // tau_0 = |r_0| (x_Q = x = 0)
+        S.tmark = b.x;
+        S.cq = 0.0;
     } else if (mode == RED_ALPHA) {    // a = p^T q
         step_alpha(S, a);
     } else if (mode == RED_BETA) {     // a = r^T z (new), b.x = |r|^2
         S.stepped = 1;
-        step_beta(S, a, b.x);
+        if (S.sqmr) sqmr_beta(S, a, b.x);
+        else step_beta(S, a, b.x);
     } else if (mode == RED_X0) {       // a = w^H b, b.x = |w|^2 for w = A x0
         // a zero right-hand side (its residual never formed) has x = 0; a guess
         // that already meets the tolerance is scaled all the same
@@ -1167,10 +1224,12 @@ k_update(Op op, int CP, const ColState* __restrict__ st, float2* __restrict__ R,
 }
 
 // x += alpha p for the columns whose alpha was applied to r this iteration,
-// then p = z + beta p for those still active.
+// then p = z + beta p for those still active. SQMR (XQ not null): the
+// smoothed iterate x_Q = (1 - c^2) x_Q + c^2 x with this step's c^2 (x_Q = 0
+// before the first step).
 __global__ void __launch_bounds__(256)
 k_pupdate(Op op, int CP, const ColState* __restrict__ st, const float2* __restrict__ Z, float2* __restrict__ P,
-          float2* __restrict__ Xi) {
+          float2* __restrict__ Xi, float2* __restrict__ XQ) {
     const int tile = tile_of(op, blockIdx.x), C = op.C;
     const int c = threadIdx.x % CP, slot = threadIdx.x / CP, RPB = 256 / CP;
     if (c >= C) return;
@@ -1185,7 +1244,13 @@ k_pupdate(Op op, int CP, const ColState* __restrict__ st, const float2* __restri
         if (i >= op.nrow_valid) break;
         const size_t o = (size_t)i * C + c;
         const float2 z = Z[o], p = P[o], x = Xi[o];
-        Xi[o] = f2(x.x + ax * p.x - ay * p.y, x.y + ax * p.y + ay * p.x);
+        const float2 xn = f2(x.x + ax * p.x - ay * p.y, x.y + ax * p.y + ay * p.x);
+        Xi[o] = xn;
+        if (XQ && S.sqmr) {
+            const float cq = (float)S.cq, cp = (float)(1.0 - S.cq);
+            const float2 xq = S.kin > 1 ? XQ[o] : f2(0.f, 0.f);
+            XQ[o] = f2(cp * xq.x + cq * xn.x, cp * xq.y + cq * xn.y);
+        }
         if (more) P[o] = f2(z.x + bx * p.x - by * p.y, z.y + bx * p.y + by * p.x);
     }
 }
@@ -1572,11 +1637,12 @@ k_eis_init(Op op, int CP, const ColState* __restrict__ st, const float2* __restr
 
 // The Eisenstat step after alpha: x += alpha t, r -= alpha D~ (t + y);
 // partials rho' = r^T D~^-1 r and sum |r_i|^2 / |D~_i|, column by column
-// (column c's of tile t at c * ntiles + t).
+// (column c's of tile t at c * ntiles + t). SQMR (XQ not null): first the
+// smoothing step of the previous beta step, x_Q = (1 - c^2) x_Q + c^2 x.
 __global__ void __launch_bounds__(256)
 k_eis_update(Op op, int CP, const ColState* __restrict__ st, const float2* __restrict__ T,
-             const float2* __restrict__ Y, float2* __restrict__ R, float2* __restrict__ Xi, float omega,
-             double2* __restrict__ p0, double2* __restrict__ p1) {
+             const float2* __restrict__ Y, float2* __restrict__ R, float2* __restrict__ Xi,
+             float2* __restrict__ XQ, float omega, double2* __restrict__ p0, double2* __restrict__ p1) {
     const int64_t cs = op.ntiles;   // the partials column by column
     __shared__ double2 ra[256], rb[256];
     const int tile = tile_of(op, blockIdx.x), C = op.C;
@@ -1586,6 +1652,11 @@ k_eis_update(Op op, int CP, const ColState* __restrict__ st, const float2* __res
         const ColState& S = st[c];
         const float ax = (float)S.alpha.x, ay = (float)S.alpha.y;
         const double wmu = op.wmu[c];
+        // SQMR: x is the iterate of the latest beta step, whose c^2 the state
+        // holds; x_Q takes that step here, before x moves on (the last step
+        // of an inner solve is taken by k_ir_update)
+        const bool smooth = XQ && S.sqmr && S.kin > 0;
+        const float cq = (float)S.cq, cp = (float)(1.0 - S.cq);
         for (int r0 = 0; r0 < kTR; r0 += RPB) {
             const int i = tile * kTR + r0 + slot;
             if (i >= op.nrow_valid) break;
@@ -1594,6 +1665,10 @@ k_eis_update(Op op, int CP, const ColState* __restrict__ st, const float2* __res
             const double inv = 1.0 / (dr * dr + di * di);
             const float2 t = T[o], y = Y[o];
             float2 x = Xi[o];
+            if (smooth) {
+                const float2 xq = S.kin > 1 ? XQ[o] : f2(0.f, 0.f);
+                XQ[o] = f2(cp * xq.x + cq * x.x, cp * xq.y + cq * x.y);
+            }
             x.x += ax * t.x - ay * t.y;
             x.y += ax * t.y + ay * t.x;
             Xi[o] = x;
@@ -2207,21 +2282,34 @@ k_step_seg(Op op, const ColState* __restrict__ st, float2* __restrict__ R, const
     }
 }
 
-// x64 += |r64| d for the columns still refining.
+// x64 += |r64| d for the columns still refining. d is the inner solve's
+// iterate, or for SQMR (XQ not null) its smoothed iterate x_Q: as the
+// five-kernel iteration leaves it (lag 0), or with its last step still to
+// take, x_Q = (1 - c^2) x_Q + c^2 x (lag 1, Eisenstat's form).
 __global__ void __launch_bounds__(256)
 k_ir_update(Op op, int CP, const ColState* __restrict__ st, const float2* __restrict__ Xi,
-            double2* __restrict__ X64) {
+            const float2* __restrict__ XQ, int lag, double2* __restrict__ X64) {
     const int tile = blockIdx.x, C = op.C;
     const int c = threadIdx.x % CP, slot = threadIdx.x / CP, RPB = 256 / CP;
     if (c >= C) return;
     const int seg = op.tile_seg ? op.tile_seg[tile] : 0;
     const ColState& S = st[seg * C + c];
     if (!S.outer) return;
+    const bool smooth = XQ && S.sqmr && S.kin > 0;
+    const float cq = (float)S.cq, cp = (float)(1.0 - S.cq);
     for (int r0 = 0; r0 < kTR; r0 += RPB) {
         const int i = tile * kTR + r0 + slot;
         if (i >= op.nrow_valid) break;
         const size_t o = (size_t)i * C + c;
-        const float2 d = Xi[o];
+        float2 d = Xi[o];
+        if (smooth) {
+            if (lag) {
+                const float2 xq = S.kin > 1 ? XQ[o] : f2(0.f, 0.f);
+                d = f2(cp * xq.x + cq * d.x, cp * xq.y + cq * d.y);
+            } else {
+                d = XQ[o];
+            }
+        }
         double2 x = X64[o];
         x.x += S.scale * (double)d.x;
         x.y += S.scale * (double)d.y;
@@ -2334,7 +2422,7 @@ __global__ void k_cols_in(int nr, int C, size_t r0, const double2* __restrict__ 
     dst[(r0 + i) * C + c] = src[c * lds + i];
 }
 
-__global__ void k_init_state(ColState* st, int nsc, double inner_rtol) {
+__global__ void k_init_state(ColState* st, int nsc, double inner_rtol, int sqmr) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= nsc) return;
     ColState S;
@@ -2356,6 +2444,10 @@ __global__ void k_init_state(ColState* st, int nsc, double inner_rtol) {
     S.stepped = 0;
     S.k_best = 0;
     S.stalled = 0;
+    S.tau2 = 0.0;
+    S.cq = 0.0;
+    S.tmark = 0.0;
+    S.sqmr = sqmr;
     st[k] = S;
 }
 
@@ -2484,6 +2576,8 @@ struct BlockWork {
     double2 *p0 = nullptr, *p1 = nullptr, *p2 = nullptr;
     double2* pe = nullptr;     // partials of the Eisenstat L pass, one slot per sweep block
     size_t pe_cap = 0;
+    float2* XQ = nullptr;      // SQMR: the smoothed iterate of each column's inner solve
+    size_t xq_cap = 0;
     ColState* st = nullptr;
     ColState* st2 = nullptr;   // second state slot of the in-consumer reductions
     ColState* st_h = nullptr;
@@ -2525,6 +2619,8 @@ struct BlockWork {
         dfree(p0); dfree(p1); dfree(p2); dfree(st); dfree(st2); dfree(tmap); dfree(flags); dfree(wmu);
         dfree(pe);
         pe_cap = 0;
+        dfree(XQ);
+        xq_cap = 0;
         dfree(seg_tile); dfree(tile_seg);
         dfree(rp); dfree(col); dfree(K64); dfree(M64); dfree(Kd); dfree(Md); dfree(K32); dfree(M32);
         cat_sell.release();
@@ -3131,6 +3227,8 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
     // and the beta reduction
     const bool ssor = sq != nullptr;
     const float omega = (float)o.omega;
+    // symmetric QMR: the same iteration with the smoothed iterate x_Q beside x
+    const bool sqmr = o.method == PETGEM_SQMR;
     Timer t_all;
     SpmmTuned tu;
     PG_TRY(tune_spmm(w, op, nnz, s, tu, o.verbose != 0));
@@ -3234,6 +3332,16 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
         hipLaunchKernelGGL(k_fill_z, dim3(ceil_div(need, 256)), dim3(256), 0, s, need, w->pe);
         PG_HIP(hipGetLastError());
     }
+    if (sqmr) {
+        const size_t nxq = (size_t)op.n * C;
+        if (w->xq_cap < nxq) {
+            dfree(w->XQ);
+            w->xq_cap = 0;
+            PG_TRY(dalloc(&w->XQ, nxq));
+            w->xq_cap = nxq;
+        }
+    }
+    float2* const xq = sqmr ? w->XQ : nullptr;
     const int nbu = ceil_div(op.ntiles, kConsumerTiles);   // blocks of the two vector kernels
     // one column per mesh otherwise (an uneven batch, or one mesh too large for
     // every block to sum its partials): the fused step with a reduction block
@@ -3250,7 +3358,7 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
         hipLaunchKernelGGL(k_fill_rp, dim3(1), dim3(256), 0, s, 1, 0, w->gcount);
     }
     hipLaunchKernelGGL(k_init_state, dim3(ceil_div(nsc, 64)), dim3(64), 0, s, w->st, nsc,
-                       o.inner_rtol);
+                       o.inner_rtol, (int)sqmr);
     const bool prof = o.profile != 0;
     std::vector<hipEvent_t> evs;
     // a (start, end) pair the next SpMM dispatch timestamps, or nulls
@@ -3311,7 +3419,7 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
             PG_HIP(hipMemcpyAsync(w->flags, fallback.data(), sizeof(int) * nsc, hipMemcpyHostToDevice, s));
             hipLaunchKernelGGL(k_zero_cols, dim3(op.ntiles), dim3(256), 0, s, op, CP, w->flags, w->X64);
             hipLaunchKernelGGL(k_init_state, dim3(ceil_div(nsc, 64)), dim3(64), 0, s, w->st, nsc,
-                               o.inner_rtol);
+                               o.inner_rtol, (int)sqmr);
             PG_TRY(bnorms());
             hipLaunchKernelGGL(k_set_tol, dim3(ceil_div(nsc, 64)), dim3(64), 0, s, w->st, nsc, o.rtol);
             PG_TRY(residual(0));
@@ -3400,7 +3508,7 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
             hipLaunchKernelGGL(k_reduce_cm, dim3(C), dim3(1024), 0, s, (const double2*)w->pe, neis, cse,
                                (const double2*)nullptr, 0, (int64_t)0, w->st, (int)RED_ALPHA);
             hipLaunchKernelGGL(k_eis_update, dim3(opi.nlaunch), dim3(256), 0, s, opi, CP, (const ColState*)w->st,
-                               (const float2*)w->Z, (const float2*)w->Q, w->R, w->Xi, omega, w->p1, w->p2);
+                               (const float2*)w->Z, (const float2*)w->Q, w->R, w->Xi, xq, omega, w->p1, w->p2);
             hipLaunchKernelGGL(k_reduce_cm, dim3(C), dim3(1024), 0, s, (const double2*)w->p1, op.ntiles,
                                (int64_t)op.ntiles, (const double2*)w->p2, op.ntiles, (int64_t)op.ntiles, w->st,
                                (int)RED_BETA);
@@ -3424,7 +3532,8 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
             }
             hipLaunchKernelGGL(k_reduce, dim3(nsc), dim3(1024), 0, s, op, w->p1, 1, w->p2, 1, w->st,
                                (int)RED_BETA, 0);
-            hipLaunchKernelGGL(k_pupdate, dim3(opi.nlaunch), dim3(256), 0, s, opi, CP, w->st, w->Z, w->P, w->Xi);
+            hipLaunchKernelGGL(k_pupdate, dim3(opi.nlaunch), dim3(256), 0, s, opi, CP, w->st, w->Z, w->P, w->Xi,
+                               xq);
         }
     };
     auto group = [&]() {
@@ -3441,9 +3550,10 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
             sig.insert(sig.end(), c, c + nb);
         };
         put(&opi, sizeof(opi));
-        const void* ptrs[16] = {w->Xi, w->R, w->Z, w->P, w->Q, w->p0, w->p1, w->p2, w->st, w->st2, dinv,
+        const void* ptrs[17] = {w->Xi, w->R, w->Z, w->P, w->Q, w->p0, w->p1, w->p2, w->st, w->st2, dinv,
                                 w->snap_ring, w->gcount, sq ? (const void*)sq->row : nullptr,
-                                sq ? (const void*)sq->lK : nullptr, eis ? (const void*)w->pe : nullptr};
+                                sq ? (const void*)sq->lK : nullptr, eis ? (const void*)w->pe : nullptr,
+                                (const void*)xq};
         put(ptrs, sizeof(ptrs));
         int chv[12] = {ch.kind, ch.a, ch.b, (int)in_consumer, opi.tmap ? tgen : 0, (int)fused, fused_u, (int)fused_seg,
                        seg_u, (int)ssor, ssor ? (int)(o.omega * 1e6) : 0, ppE};
@@ -3614,7 +3724,8 @@ int mrhs_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, hi
             queued = groups;
         }
         total_inner += inner;
-        hipLaunchKernelGGL(k_ir_update, dim3(op.ntiles), dim3(256), 0, s, op, CP, w->st, w->Xi, w->X64);
+        hipLaunchKernelGGL(k_ir_update, dim3(op.ntiles), dim3(256), 0, s, op, CP, w->st, w->Xi,
+                           (const float2*)xq, eis ? 1 : 0, w->X64);
         PG_TRY(residual(0));
         PG_TRY(read_state());
         ++steps;
@@ -4013,7 +4124,7 @@ int bcocg_solve(BlockWork* w, const Op& op, int64_t nnz, const petgem_opts& o, h
     PG_TRY(dalloc(&Q, nv));
     PG_TRY(dalloc(&Z, nv));
     PG_TRY(dalloc(&bs, 1));
-    hipLaunchKernelGGL(k_init_state, dim3(ceil_div(C, 64)), dim3(64), 0, s, w->st, C, o.inner_rtol);
+    hipLaunchKernelGGL(k_init_state, dim3(ceil_div(C, 64)), dim3(64), 0, s, w->st, C, o.inner_rtol, 0);
     hipLaunchKernelGGL(k_set_live, dim3(ceil_div(C, 64)), dim3(64), 0, s, w->st2, C);   // every product column live
     auto residual = [&]() -> int {
         spmm_dispatch<double, 2>(ch64, op, w->st, SpmmArgs{w->X64, w->B64, w->R64, w->p0}, s);

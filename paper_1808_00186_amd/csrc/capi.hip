@@ -287,14 +287,17 @@ int petgem_solve(petgem_system* sys, const petgem_source* src, int32_t n_src, co
         return PETGEM_INVALID_ARG;
     }
     if (o.restart < 1 || o.restart > kMaxRestart || o.max_iter < 1 || !(o.rtol > 0.0) ||
-        (o.method != PETGEM_GMRES && o.method != PETGEM_COCG && o.method != PETGEM_BCOCG) ||
+        (o.method != PETGEM_GMRES && o.method != PETGEM_COCG && o.method != PETGEM_BCOCG &&
+         o.method != PETGEM_SQMR) ||
         (o.precision != PETGEM_FP64 && o.precision != PETGEM_MIXED)) {
         set_error("invalid solver options");
         return PETGEM_INVALID_ARG;
     }
     if ((o.precond != PETGEM_JACOBI && o.precond != PETGEM_SSOR) ||
-        (o.precond == PETGEM_SSOR && (o.method != PETGEM_COCG || !(o.omega > 0.0 && o.omega < 2.0)))) {
-        set_error("precond: PETGEM_JACOBI, or PETGEM_SSOR with COCG and 0 < omega < 2");
+        (o.precond == PETGEM_SSOR && ((o.method != PETGEM_COCG && o.method != PETGEM_SQMR) ||
+                                      !(o.omega > 0.0 && o.omega < 2.0))) ||
+        (o.method == PETGEM_SQMR && o.precond != PETGEM_SSOR)) {
+        set_error("precond: PETGEM_JACOBI, or PETGEM_SSOR with COCG or SQMR and 0 < omega < 2 (SQMR takes SSOR)");
         return PETGEM_INVALID_ARG;
     }
     for (int32_t k = 0; k < n_src; ++k) PG_TRY(valid_source(src[k]));
@@ -318,7 +321,7 @@ int petgem_solve(petgem_system* sys, const petgem_source* src, int32_t n_src, co
     sol->layers = sys->layers;
     if (stats) std::memset(stats, 0, sizeof(petgem_stats) * (size_t)n_src);
     const double2* x0 = static_cast<const double2*>(x0_dev);
-    if (o.method == PETGEM_COCG || o.method == PETGEM_BCOCG) {
+    if (o.method == PETGEM_COCG || o.method == PETGEM_BCOCG || o.method == PETGEM_SQMR) {
         // A large block whose sources come in contiguous runs of one
         // frequency is solved one run at a time: the runs converge at very
         // different iteration counts (lower frequency, more iterations), and a
@@ -363,8 +366,8 @@ int petgem_solve_many(petgem_system* const* systems, const petgem_source* src, i
     if (!systems || !src || n_sys <= 0 || !sols) { set_error("systems, sources and solutions are required"); return PETGEM_INVALID_ARG; }
     petgem_opts o;
     if (opts) o = *opts; else petgem_default_opts(&o);
-    if (o.precond != PETGEM_JACOBI) {
-        set_error("the uneven batch takes the Jacobi preconditioner only");
+    if (o.precond != PETGEM_JACOBI || o.method == PETGEM_SQMR) {
+        set_error("the uneven batch takes COCG with the Jacobi preconditioner only");
         return PETGEM_INVALID_ARG;
     }
     for (int32_t k = 0; k < n_sys; ++k) {

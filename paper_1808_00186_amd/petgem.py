@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(HERE, "libpetgem.so")
 OK, INVALID_ARG, DEGENERATE_ELEMENT, MESH_TOPOLOGY = 0, -1, -2, -3
 RECEIVER_OUTSIDE, SOURCE_SINGULAR, NOT_CONVERGED, NONFINITE = -4, -5, -6, -7
 HIP_ERROR, OUT_OF_MEMORY = -8, -9
-GMRES, COCG, BCOCG = 0, 1, 2
+GMRES, COCG, BCOCG, SQMR = 0, 1, 2, 3
 JACOBI, SSOR = 0, 1
 FP64, MIXED = 0, 1
 

@@ -15,6 +15,10 @@ definition (oracle/precond.py). Marked `gpu`.
 * Every lane shape of Eisenstat's form (more than four columns): 8, 32 and
   64 lanes per row, the last with one, two and four columns per lane, exact
   fits and ragged tails, each column against the oracle.
+* SQMR (the paper's solver with the SOR family): the same solves with the
+  quasi-minimal-residual smoothing, in the explicit-product iteration (1 and
+  3 sources) and in Eisenstat's form (9 and 33), against the oracle; it takes
+  SSOR only, and the uneven batch refuses it.
 """
 import os
 
@@ -154,3 +158,26 @@ def test_eisenstat_lane_shapes_match_oracle(pg, eis_pool, n_src):
     errs = [fem.receiver_error(E[k], ref[k]) for k in range(n_src)]
     print(f"  iters max {max(s_['iters'] for s_ in st)}, receiver error max {max(errs):.1e}", flush=True)
     assert max(errs) <= 1e-6
+
+
+@pytest.mark.parametrize("n_src", [1, 3, 9, 33])
+def test_sqmr_ssor_matches_oracle(pg, eis_pool, n_src):
+    m, pool, ref = eis_pool
+    srcs = pool[:n_src]
+    print(f"[case] cfg1 SQMR SSOR, {n_src} sources", flush=True)
+    S = pg.System.from_model(m)
+    o = pg.default_opts(method=pg.SQMR, precision=pg.MIXED, rtol=1e-8, precond=pg.SSOR)
+    sol, st, rc = S.solve(srcs, o)
+    assert rc == pg.OK and all(s_["rel_residual"] <= 1e-8 for s_ in st)
+    E = sol.receivers(m.receivers).cpu().numpy()
+    errs = [fem.receiver_error(E[k], ref[k]) for k in range(n_src)]
+    oc = pg.default_opts(method=pg.COCG, precision=pg.MIXED, rtol=1e-8, precond=pg.SSOR)
+    _, stc, _ = S.solve(srcs, oc)
+    print(f"  iters SQMR {max(s_['iters'] for s_ in st)} COCG {max(s_['iters'] for s_ in stc)}, "
+          f"receiver error max {max(errs):.1e}", flush=True)
+    assert max(errs) <= 1e-6
+    if n_src == 1:
+        with pytest.raises(pg.PetgemError):   # SQMR takes SSOR
+            S.solve(srcs, pg.default_opts(method=pg.SQMR, precision=pg.MIXED))
+        with pytest.raises(pg.PetgemError):   # the uneven batch takes COCG with Jacobi
+            pg.solve_many([S], srcs, pg.default_opts(method=pg.SQMR, precision=pg.MIXED, precond=pg.SSOR))

@@ -29,6 +29,13 @@ def test_library_exports_every_declared_symbol():
     assert set(names) >= set(petgem._SIGS), set(petgem._SIGS) - set(names)
 
 
+def test_binding_constants_match_header():
+    txt = open(os.path.join(ROOT, "include", "petgem.h")).read()
+    defs = {k: int(v) for k, v in re.findall(r"#define\s+PETGEM_([A-Z0-9_]+)\s+(-?\d+)", txt)}
+    for name in ("GMRES", "COCG", "BCOCG", "SQMR", "JACOBI", "SSOR", "FP64", "MIXED", "OK"):
+        assert getattr(petgem, name) == defs[name], name
+
+
 def _oracle_pattern(xyz, tets):
     s = fem.assemble(xyz, tets, np.ones(len(tets)))
     return s.topo, s.K.tocsr()
