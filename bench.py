@@ -74,7 +74,7 @@ MEASURED_TRAFFIC = {
         (1779690.6 * 2.0 + 871820.1) * 1024,
     # its 16-column SSOR blocks in Eisenstat's form: the U sweep, per colour launch
     "k_ssor_eis_u<16, 1> complex64 Eisenstat U sweep with the direction update, one colour per launch "
-    "(K, M_sigma) @cfg3": (531322.0 * 2.0 + 244225.6) * 1024,
+    "(K, M_sigma) @cfg3": (531263.3 * 2.0 + 244225.6) * 1024,
 }
 RTOL = 1e-9
 # the high-frequency models of the uneven batch (f up to 2 Hz, receivers 4 km
